@@ -1,0 +1,168 @@
+"""Benchmark: forest-closeness estimation on one MI355X.
+
+Workload (one "step" = the whole hot path once): Barabasi-Albert graph with
+n = 200,000 and m = 5 (999,985 edges), alpha = 1, 4096 uniform spanning trees
+of G* rooted at u* sampled with Wilson's algorithm, aggregated into the
+estimated diagonal of Omega = (alpha L + I)^{-1}, forest farness and forest
+closeness of every vertex.  The CSR is resident in device memory before the
+timed region.  Prints one JSON line.
+
+value = trees per second over the timed steps (whole job, one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = {"workload": "ba_n200000_m5_alpha1_trees4096", "graph": "barabasi_albert",
+            "n": 200_000, "m_per_vertex": 5, "alpha": 1.0, "trees": 4096, "seed": 0}
+
+# Algorithmic bytes of Wilson's algorithm per unit of work (what the method
+# itself must move with a packed 8-byte per-vertex state word):
+#   walk step   : row offsets of v (8) + neighbour id (4) + read state of the
+#                 next vertex (8) + write state of v (8)            = 28 B
+#   retrace     : read + write the state word of each tree vertex    = 16 B
+#   start scan  : read the state word of each start candidate        =  8 B
+#   root        : read-modify-write of R[v] (4 + 4)                  =  8 B
+BYTES_STEP, BYTES_RETRACE, BYTES_SCAN, BYTES_ROOT = 28, 16, 8, 8
+HBM_PEAK_GBS = 8000.0
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_06192_amd", "csrc", "wilson_lane.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_lane_ba200k_traffic.txt")
+
+
+def _kernel_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != _kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(g, trees: int) -> dict:
+    import oracle
+    t0 = time.perf_counter()
+    oracle.sample(g, 1.0, 0, 0, trees)
+    dt = time.perf_counter() - t0
+    return {"value": trees / dt, "unit": "trees/s", "cores": 1, "kind": "oracle",
+            "sample": f"trees 0..{trees - 1} of the same workload, single-threaded C oracle "
+                      f"(Algorithm 3 literal), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-trees", type=int, default=320,
+                    help="trees the CPU oracle samples for the baseline (0 = skip)")
+    ap.add_argument("--no-eps", action="store_true", help="skip the time-to-eps=0.1 leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the sampler shards by tree id with no exchange "
+              "beyond one integer all-reduce, and this build runs on a single MI355X.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2101_06192_amd as fc
+    from paper_2101_06192_amd import inputs
+
+    dev = torch.device("cuda:0")
+    g = inputs.barabasi_albert(WORKLOAD["n"], WORKLOAD["m_per_vertex"], WORKLOAD["seed"])
+    dg = fc.to_device(g, dev)
+    trees = WORKLOAD["trees"]
+    alpha = WORKLOAD["alpha"]
+    torch.cuda.synchronize()
+
+    def step():
+        return fc.farness(dg, alpha=alpha, seed=WORKLOAD["seed"], tau=trees, device=dev,
+                          as_torch=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+        stats.append(out["stats"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = trees / (elapsed / args.steps)
+
+    walk_steps = stats[-1]["walk_steps"]
+    roots = stats[-1]["roots"]
+    ms_kernel = float(np.mean([s["ms_sample"] for s in stats]))
+    n = g.n
+    alg_bytes = (BYTES_STEP * walk_steps + (BYTES_RETRACE + BYTES_SCAN) * n * trees
+                 + BYTES_ROOT * roots)
+    achieved = alg_bytes / (ms_kernel / 1000.0) / 1e9
+    traffic = _traffic()
+
+    eps_leg = None
+    if not args.no_eps:
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        o = fc.diag_estimate(dg, alpha=alpha, eps=0.1, delta=0.1, seed=0, device=dev,
+                             as_torch=True)
+        torch.cuda.synchronize()
+        eps_leg = {"tau": o["tau"], "ms": 1000.0 * (time.perf_counter() - te)}
+
+    cpu = cpu_baseline(g, args.cpu_trees) if args.cpu_trees > 0 else None
+
+    line = {
+        "metric": "USTs/s and walk steps/s (GB/s vs roofline); time to eps=0.1 diag(Omega)",
+        "value": value,
+        "unit": "trees/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": WORKLOAD,
+        "walk_steps_per_s": walk_steps / (ms_per_step / 1000.0),
+        "walk_steps_per_tree": walk_steps / trees,
+        "trees_in_flight": stats[-1]["trees_in_flight"],
+        "time_to_eps0.1_diag": eps_leg,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "wilson_lane_kernel", "kernel_ms": ms_kernel,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * fc.h -- C-ABI of the forest-closeness sampling library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * What it computes (van der Grinten, Angriman, Predari, Meyerhenke, "New
+ * Approximation Algorithms for Forest Closeness Centrality -- for Individual
+ * Vertices and Vertex Groups", SDM 2021):
+ *   Omega = (alpha L + I)^{-1} is the forest matrix of a graph G (Section 2,
+ *   "Forest Distance / Closeness").  Adding a universal vertex u* joined to
+ *   every vertex with weight 1, and weighting G's edges by alpha, gives the
+ *   augmented graph G* (Section 4.1).  Sampling uniform spanning trees of G*
+ *   rooted at u* with Wilson's algorithm (Algorithm 3) and counting how often
+ *   each edge {u*, v} is in a tree estimates Omega_vv (Algorithm 1,
+ *   Prop. "unbiased"); forest farness follows from the diagonal alone
+ *   (Eq. "eq-fdistu-tr": rho(v) = n Omega_vv + tr(Omega) - 2) and forest
+ *   closeness is n / rho(v) (Definition "forest-dist-vertex").
+ *
+ * Conventions shared by every call:
+ *   - Return FC_OK (0) or a negative FC_ERR_* code; fc_last_error() gives a
+ *     message for the context's last failure.  Nothing is written to the
+ *     outputs of a failing call unless stated.
+ *   - Graphs are simple, undirected and unweighted (Section 2: finite,
+ *     simple, undirected), in CSR with both directions stored, rows sorted
+ *     strictly ascending, no self-loops.  Input that violates this is
+ *     rejected with FC_ERR_GRAPH (checked on the device for every call,
+ *     unless params.flags has FC_FLAG_TRUSTED_GRAPH).  The graph is never
+ *     modified.
+ *   - Every output array is a DEVICE pointer on the context's device, owned
+ *     by the caller (for example a torch tensor's data_ptr()).  Graph arrays
+ *     may be host or device memory (fc_graph.mem).
+ *   - All device work is enqueued on the context's stream; every call
+ *     returns only after its work has finished (the stream is synchronised).
+ *   - A context is not thread-safe; use one per host thread.  Results are a
+ *     pure function of (graph, alpha, seed, stream_id, tree range): the
+ *     output of disjoint tree ranges may be summed (checkpoint / resume).
+ *
+ * Randomness contract (the paper does not fix one; both this library and the
+ * test oracle implement it independently):
+ *   - The j-th step taken out of vertex v in tree t (j = 0, 1, ...) uses
+ *     x = Philox4x32-10(counter = (v, j, t, stream_id), key = (seed mod 2^32,
+ *     seed >> 32)) (Salmon et al., SC 2011).
+ *   - The step goes to u* iff d_v = 0 or x0 < thr(d_v), where
+ *     thr(d) = floor(2^32 * (1 / ((alpha * d) + 1))) evaluated in IEEE
+ *     binary64 with each operation rounded separately; otherwise it goes to
+ *     col_idx[row_ptr[v] + floor(x1 * d_v / 2^32)].
+ *   By Wilson's cycle-popping theorem the sampled tree and the number of
+ *   steps taken out of every vertex do not depend on the order in which
+ *   walks are started, which lets the device schedule walks freely.
+ */
+#ifndef FC_H
+#define FC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FC_API __attribute__((visibility("default")))
+
+/* return codes */
+#define FC_OK 0
+#define FC_ERR_ARG (-1)         /* invalid argument (NULL, range, alpha <= 0, ...) */
+#define FC_ERR_GRAPH (-2)       /* CSR is not simple, symmetric and sorted */
+#define FC_ERR_NOMEM (-3)       /* device allocation failed */
+#define FC_ERR_HIP (-4)         /* HIP runtime error (no device, launch failure) */
+#define FC_ERR_UNSUPPORTED (-5) /* n or nnz beyond the supported range */
+#define FC_ERR_OVERFLOW (-6)    /* a per-vertex visit counter exceeded 2^31 - 1 */
+
+/* fc_graph.mem */
+#define FC_MEM_HOST 0
+#define FC_MEM_DEVICE 1
+
+/* fc_params.estimator */
+#define FC_EST_DIRECT 0        /* Omega_vv ~ R[v] / tau */
+#define FC_EST_ALG1_LITERAL 1  /* R[v] / tau - (n+2)/(n+1)^2, see fc_diag_estimate */
+
+/* fc_params.flags */
+#define FC_FLAG_TRUSTED_GRAPH 1 /* skip the device-side CSR validation */
+
+typedef struct fc_ctx fc_ctx;
+
+/* A graph G = (V, E) with V = {0, ..., n-1}: n >= 0 vertices and nnz = 2|E|
+ * stored directed entries. row_ptr: int32[n+1], row_ptr[0] = 0,
+ * row_ptr[n] = nnz; col_idx: int32[nnz]. n < 2^31 - 1, nnz < 2^31. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    int32_t mem; /* FC_MEM_HOST or FC_MEM_DEVICE */
+} fc_graph;
+
+/* Parameters of Algorithm 1 (ApproxDiagForestMatrix(G, alpha, eps, delta)).
+ *   alpha > 0; 0 < eps < 1; 0 < delta < 1; 0 <= kappa < 1.
+ *   tau: number of trees; 0 means tau = fc_tau(m, n, eps, delta, kappa).
+ *   seed, stream_id: Philox key and counter word 3 (see the contract above). */
+typedef struct {
+    double alpha;
+    double eps;
+    double delta;
+    double kappa;
+    uint64_t seed;
+    uint32_t tau;
+    uint32_t stream_id;
+    int32_t estimator; /* FC_EST_* */
+    int32_t flags;     /* FC_FLAG_* */
+} fc_params;
+
+/* Filled by the sampling calls (any pointer may be NULL). */
+typedef struct {
+    uint32_t tau;            /* trees sampled */
+    uint32_t trees_in_flight;/* concurrent trees used by the sampler */
+    uint64_t walk_steps;     /* total random-successor calls (sum of visit counts) */
+    uint64_t roots;          /* total edges {u*, v} over all trees (= sum of R) */
+    uint64_t digest_sum;     /* sum over trees of the per-tree digest, mod 2^64 */
+    double ms_sample;        /* device time of the sampling kernel */
+    double ms_total;         /* host wall time of the call */
+} fc_stats;
+
+/* Create a context on HIP device `hip_device` that enqueues its work on
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).  The context
+ * owns its device scratch memory until fc_destroy. */
+FC_API int fc_create(fc_ctx **ctx, int hip_device, void *hip_stream);
+FC_API int fc_destroy(fc_ctx *ctx);
+/* Change the stream later calls use. */
+FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
+
+/* Sample size of Algorithm 1: tau = ceil(ln(2 max(m, n) / delta) /
+ * (2 (1 - kappa)^2 eps^2)) (Algorithm 1; proof of Theorem "time-approx":
+ * Hoeffding's bound with a union bound over the estimated entries).
+ * m = number of undirected edges.  Host-only; needs no context. */
+FC_API int fc_tau(int64_t m, int64_t n, double eps, double delta, double kappa,
+                  uint32_t *tau_out);
+
+/* Root thresholds thr(d) for d = 0..d_max as the device computes them
+ * (thr(0) = 2^32); out: host uint64[d_max + 1]. */
+FC_API int fc_thresholds(fc_ctx *ctx, double alpha, int32_t d_max, uint64_t *out);
+
+/* Sample trees t = tree_begin .. tree_begin + tree_count - 1 of G* rooted at
+ * u* (Algorithm 3, called tau times by Algorithm 1) and ACCUMULATE into the
+ * outputs (the caller zeroes them first):
+ *   root_counts  uint32[n]     R[v] += [edge {u*, v} in tree]       (required)
+ *   visit_counts uint64[n]     += steps taken out of v in the tree  (or NULL)
+ * and WRITE per-tree outputs, indexed by t - tree_begin:
+ *   tree_digests uint64[tree_count]   sum_v mix64((v << 32) | parent(v)) with
+ *                mix64 the SplitMix64 finaliser; u* has id n       (or NULL)
+ *   tree_steps   uint64[tree_count]   sum of visit counts           (or NULL)
+ *   parents      int32[tree_count*n]  parent of v, u* = n           (or NULL)
+ *   tree_visits  uint32[tree_count*n] visit count of v              (or NULL)
+ * Uses params->alpha, seed, stream_id and flags. */
+FC_API int fc_sample(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
+                     uint32_t tree_begin, uint32_t tree_count, uint32_t *root_counts,
+                     uint64_t *visit_counts, uint64_t *tree_digests, uint64_t *tree_steps,
+                     int32_t *parents, uint32_t *tree_visits, fc_stats *stats);
+
+/* Algorithm 1, ApproxDiagForestMatrix(G, alpha, eps, delta): samples tau trees
+ * (tree ids 0..tau-1) and writes diag_out[v] (double[n]):
+ *   FC_EST_DIRECT:       R[v] / tau, an unbiased estimate of Omega_vv
+ *                        (r_{G*}(u*, v) = Omega_vv; Prop. "unbiased");
+ *   FC_EST_ALG1_LITERAL: the paper's last loop, R[v]/tau - x(u*) + 2 x(v),
+ *                        with x the minimum-norm solution of
+ *                        L* x = e_{u*} - 1/(n+1) 1, which is
+ *                        R[v]/tau - (n+2)/(n+1)^2.
+ * With probability >= 1 - delta every entry is within eps of Omega_vv
+ * (Theorem "time-approx").  root_counts_out (uint32[n], or NULL) receives R. */
+FC_API int fc_diag_estimate(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
+                            double *diag_out, uint32_t *root_counts_out, fc_stats *stats);
+
+/* Forest farness and closeness of every vertex from the same sample:
+ *   farness_out[v]   = (n R[v] + S) / tau - 2, S = sum_w R[w]
+ *                      (Eq. "eq-fdistu-tr" with the estimated diagonal)
+ *   closeness_out[v] = n / farness_out[v]   (Definition "forest-dist-vertex")
+ * diag_out as in fc_diag_estimate.  Any output pointer may be NULL except
+ * farness_out. */
+FC_API int fc_farness(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
+                      double *farness_out, double *closeness_out, double *diag_out,
+                      uint32_t *root_counts_out, fc_stats *stats);
+
+/* Message for an error code / for the last failing call on a context. */
+FC_API const char *fc_error_string(int code);
+FC_API const char *fc_last_error(fc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FC_H */

@@ -226,15 +226,14 @@ def effective_resistance(Lpinv: np.ndarray, u: int, v: int) -> float:
     return float(Lpinv[u, u] + Lpinv[v, v] - 2.0 * Lpinv[u, v])
 
 
-def _spmv(g, alpha: float, x: np.ndarray) -> np.ndarray:
-    """y = (alpha L + I) x for x of shape (n,) or (n, k)."""
+def _operator(g, alpha: float):
+    """alpha L + I as a scipy sparse matrix (unit weights)."""
+    import scipy.sparse as sp
+    n = g.n
     deg = np.diff(g.row_ptr).astype(np.float64)
-    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
-    ax = np.zeros_like(x)
-    np.add.at(ax, rows, x[g.col_idx])
-    if x.ndim == 1:
-        return (1.0 + alpha * deg) * x - alpha * ax
-    return (1.0 + alpha * deg)[:, None] * x - alpha * ax
+    A = sp.csr_matrix((np.ones(g.col_idx.size), g.col_idx.astype(np.int64),
+                       g.row_ptr.astype(np.int64)), shape=(n, n))
+    return (sp.diags(1.0 + alpha * deg) - alpha * A).tocsr()
 
 
 def cg_solve(g, alpha: float, b: np.ndarray, rtol: float = 1e-9, maxiter: int = 100000):
@@ -246,6 +245,7 @@ def cg_solve(g, alpha: float, b: np.ndarray, rtol: float = 1e-9, maxiter: int = 
     B = b[:, None] if single else b
     deg = np.diff(g.row_ptr).astype(np.float64)
     minv = 1.0 / (1.0 + alpha * deg)
+    A = _operator(g, alpha)
     X = np.zeros_like(B)
     R = B.copy()
     Z = minv[:, None] * R
@@ -256,7 +256,7 @@ def cg_solve(g, alpha: float, b: np.ndarray, rtol: float = 1e-9, maxiter: int = 
     it = 0
     active = np.linalg.norm(R, axis=0) / bn > rtol
     while active.any() and it < maxiter:
-        AP = _spmv(g, alpha, P)
+        AP = A @ P
         pap = np.einsum("ij,ij->j", P, AP)
         a = np.where(active, rz / np.where(pap == 0, 1, pap), 0.0)
         X += a * P

@@ -1,0 +1,455 @@
+// Host implementation of the C-ABI declared in include/fc.h.
+//
+// The library owns device scratch (vertex records, per-tree state, staged
+// host graphs, small counters) per context and grows it on demand; callers
+// own every input and output array.  All work goes to the context's stream
+// and each call synchronises before it returns.
+#include "fc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "fc_kernels.hpp"
+
+#pragma STDC FP_CONTRACT OFF
+
+namespace {
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Small {  // device-side counters of one call
+    fc::Totals totals;
+    unsigned int queue;
+    unsigned int graph_err;
+    unsigned long long sum;
+};
+
+}  // namespace
+
+struct fc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    size_t state_budget = 0;      // bytes of per-tree state the sampler may use
+    uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
+    uint32_t max_slots = 0;       // 0 = as many trees in flight as memory allows
+};
+
+namespace {
+
+int set_err(fc_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return code;
+}
+
+int hip_fail(fc_ctx *ctx, hipError_t e, const char *what) {
+    return set_err(ctx, e == hipErrorOutOfMemory ? FC_ERR_NOMEM : FC_ERR_HIP,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FC_HIP(ctx, expr, what)                          \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+int ensure(fc_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return FC_OK;
+    if (b.ptr) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        return set_err(ctx, FC_ERR_NOMEM, std::string("allocating ") + what + " (" +
+                                              std::to_string(bytes) + " bytes) failed");
+    }
+    b.bytes = bytes;
+    return FC_OK;
+}
+
+uint32_t env_u32(const char *name, uint32_t dflt) {
+    const char *s = std::getenv(name);
+    if (!s || !*s) return dflt;
+    return static_cast<uint32_t>(std::strtoul(s, nullptr, 10));
+}
+
+bool valid_alpha(double a) { return std::isfinite(a) && a > 0.0; }
+
+// Resolved device view of a graph for one call.
+struct GraphView {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    const int32_t *row_ptr = nullptr;
+    const int32_t *col_idx = nullptr;
+};
+
+int check_graph_args(fc_ctx *ctx, const fc_graph *g) {
+    if (!g) return set_err(ctx, FC_ERR_ARG, "graph is NULL");
+    if (g->n < 0 || g->nnz < 0) return set_err(ctx, FC_ERR_ARG, "negative n or nnz");
+    if (g->n >= 0x7FFFFFFF) return set_err(ctx, FC_ERR_UNSUPPORTED, "n must be < 2^31 - 1");
+    if (g->nnz >= 0x7FFFFFFFLL) return set_err(ctx, FC_ERR_UNSUPPORTED, "nnz must be < 2^31");
+    if (g->mem != FC_MEM_HOST && g->mem != FC_MEM_DEVICE)
+        return set_err(ctx, FC_ERR_ARG, "graph.mem must be FC_MEM_HOST or FC_MEM_DEVICE");
+    if (!g->row_ptr) return set_err(ctx, FC_ERR_ARG, "row_ptr is NULL");
+    if (g->nnz > 0 && !g->col_idx) return set_err(ctx, FC_ERR_ARG, "col_idx is NULL");
+    return FC_OK;
+}
+
+// Stage (if on the host) and validate the CSR on the device.
+int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out) {
+    int rc = check_graph_args(ctx, g);
+    if (rc) return rc;
+    GraphView v;
+    v.n = g->n;
+    v.nnz = g->nnz;
+    if (g->mem == FC_MEM_HOST) {
+        if ((rc = ensure(ctx, ctx->row_ptr, sizeof(int32_t) * (static_cast<size_t>(g->n) + 1), "row_ptr")))
+            return rc;
+        if ((rc = ensure(ctx, ctx->col_idx, sizeof(int32_t) * static_cast<size_t>(g->nnz), "col_idx")))
+            return rc;
+        FC_HIP(ctx, hipMemcpyAsync(ctx->row_ptr.ptr, g->row_ptr,
+                                   sizeof(int32_t) * (static_cast<size_t>(g->n) + 1),
+                                   hipMemcpyHostToDevice, ctx->stream), "copy row_ptr");
+        if (g->nnz)
+            FC_HIP(ctx, hipMemcpyAsync(ctx->col_idx.ptr, g->col_idx,
+                                       sizeof(int32_t) * static_cast<size_t>(g->nnz),
+                                       hipMemcpyHostToDevice, ctx->stream), "copy col_idx");
+        v.row_ptr = static_cast<const int32_t *>(ctx->row_ptr.ptr);
+        v.col_idx = static_cast<const int32_t *>(ctx->col_idx.ptr);
+    } else {
+        v.row_ptr = g->row_ptr;
+        v.col_idx = g->col_idx;
+    }
+    if (!trusted) {
+        Small *sm = static_cast<Small *>(ctx->small.ptr);
+        unsigned int err = 0;
+        FC_HIP(ctx, hipMemsetAsync(&sm->graph_err, 0, sizeof(unsigned int), ctx->stream), "memset");
+        FC_HIP(ctx, fc::launch_validate_rows(v.row_ptr, v.n, v.nnz, &sm->graph_err, ctx->stream),
+               "validate_rows launch");
+        FC_HIP(ctx, hipMemcpyAsync(&err, &sm->graph_err, sizeof(err), hipMemcpyDeviceToHost,
+                                   ctx->stream), "copy error word");
+        FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "validate_rows");
+        if (err) return set_err(ctx, FC_ERR_GRAPH, "row_ptr is not monotone from 0 to nnz");
+        FC_HIP(ctx, fc::launch_validate_cols(v.row_ptr, v.col_idx, v.n, &sm->graph_err, ctx->stream),
+               "validate_cols launch");
+        FC_HIP(ctx, hipMemcpyAsync(&err, &sm->graph_err, sizeof(err), hipMemcpyDeviceToHost,
+                                   ctx->stream), "copy error word");
+        FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "validate_cols");
+        if (err) {
+            std::string m = "graph is not simple, sorted and symmetric:";
+            if (err & fc::kErrGraphColumn) m += " column out of range;";
+            if (err & fc::kErrGraphSelfLoop) m += " self-loop;";
+            if (err & fc::kErrGraphOrder) m += " row not strictly ascending;";
+            if (err & fc::kErrGraphAsymmetric) m += " missing reverse edge;";
+            return set_err(ctx, FC_ERR_GRAPH, m);
+        }
+    }
+    *out = v;
+    return FC_OK;
+}
+
+int check_params(fc_ctx *ctx, const fc_params *p) {
+    if (!p) return set_err(ctx, FC_ERR_ARG, "params is NULL");
+    if (!valid_alpha(p->alpha)) return set_err(ctx, FC_ERR_ARG, "alpha must be finite and > 0");
+    return FC_OK;
+}
+
+int tau_for(fc_ctx *ctx, const fc_params *p, const GraphView &g, uint32_t *tau) {
+    if (p->tau) {
+        *tau = p->tau;
+        return FC_OK;
+    }
+    int rc = fc_tau(g.nnz / 2, g.n, p->eps, p->delta, p->kappa, tau);
+    if (rc) return set_err(ctx, rc, "tau = 0 needs 0 < eps < 1, 0 < delta < 1, 0 <= kappa < 1");
+    return FC_OK;
+}
+
+// Runs the sampler over [tree_begin, tree_begin + tree_count).
+int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tree_begin,
+                uint32_t tree_count, uint32_t *root_counts, uint64_t *visit_counts,
+                uint64_t *tree_digests, uint64_t *tree_steps, int32_t *parents,
+                uint32_t *tree_visits, fc_stats *stats) {
+    int rc;
+    Small *sm = static_cast<Small *>(ctx->small.ptr);
+    FC_HIP(ctx, hipMemsetAsync(sm, 0, sizeof(Small), ctx->stream), "memset counters");
+    if (stats) {
+        stats->tau = tree_count;
+        stats->trees_in_flight = 0;
+        stats->walk_steps = stats->roots = stats->digest_sum = 0;
+        stats->ms_sample = 0.0;
+    }
+    if (g.n == 0 || tree_count == 0) return FC_OK;
+    if ((rc = ensure(ctx, ctx->vrec, sizeof(fc::VRec) * static_cast<size_t>(g.n), "vertex records")))
+        return rc;
+    fc::VRec *vrec = static_cast<fc::VRec *>(ctx->vrec.ptr);
+    FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, g.n, p->alpha, vrec, ctx->stream), "build_vrec");
+
+    // trees in flight: bounded by the tree count and by the state budget
+    const size_t per_slot = sizeof(uint64_t) * static_cast<size_t>(g.n);
+    size_t slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+    slots = std::min<size_t>(slots, tree_count);
+    if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
+    if ((rc = ensure(ctx, ctx->state, per_slot * slots, "per-tree state"))) return rc;
+    FC_HIP(ctx, hipMemsetAsync(ctx->state.ptr, 0, per_slot * slots, ctx->stream), "memset state");
+
+    fc::LaneArgs a{};
+    a.vrec = vrec;
+    a.col_idx = g.col_idx;
+    a.state = static_cast<uint64_t *>(ctx->state.ptr);
+    a.n = static_cast<uint32_t>(g.n);
+    a.slots = static_cast<uint32_t>(slots);
+    a.lanes_per_wave = std::max<uint32_t>(1, std::min<uint32_t>(64, ctx->lanes_per_wave));
+    a.tree_begin = tree_begin;
+    a.tree_count = tree_count;
+    a.stream_id = p->stream_id;
+    a.key0 = static_cast<uint32_t>(p->seed);
+    a.key1 = static_cast<uint32_t>(p->seed >> 32);
+    // expected steps per tree are at most n + 2 alpha m; a valid walk never
+    // comes near 256 times that, so exceeding it marks a fault, not bad luck
+    const double cap = 256.0 * (static_cast<double>(g.n) + p->alpha * static_cast<double>(g.nnz)) +
+                       1048576.0;
+    a.step_cap = cap > 4.0e18 ? 4000000000000000000ull : static_cast<unsigned long long>(cap);
+    a.queue = &sm->queue;
+    a.root_counts = root_counts;
+    a.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
+    a.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
+    a.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
+    a.parents = parents;
+    a.tree_visits = tree_visits;
+    a.totals = &sm->totals;
+
+    FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
+    FC_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+    fc::Totals tot;
+    FC_HIP(ctx, hipMemcpyAsync(&tot, &sm->totals, sizeof(tot), hipMemcpyDeviceToHost, ctx->stream),
+           "copy totals");
+    FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "sampler");
+    if (tot.error & fc::kErrStepCap)
+        return set_err(ctx, FC_ERR_HIP, "a tree exceeded the step bound (internal fault)");
+    if (tot.error & fc::kErrVisitOverflow)
+        return set_err(ctx, FC_ERR_OVERFLOW, "a per-vertex visit counter exceeded 2^31 - 1");
+    if (stats) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        stats->trees_in_flight = static_cast<uint32_t>(slots);
+        stats->walk_steps = tot.walk_steps;
+        stats->roots = tot.roots;
+        stats->digest_sum = tot.digest_sum;
+        stats->ms_sample = ms;
+    }
+    return FC_OK;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+int begin(fc_ctx *ctx) {
+    if (!ctx) return FC_ERR_ARG;
+    ctx->last_error.clear();
+    FC_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    return FC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
+    if (!out) return FC_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+        (void)hipGetLastError();
+        return FC_ERR_HIP;
+    }
+    if (hip_device < 0 || hip_device >= count) return FC_ERR_ARG;
+    if (hipSetDevice(hip_device) != hipSuccess) return FC_ERR_HIP;
+    fc_ctx *ctx = new fc_ctx();
+    ctx->device = hip_device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        ensure(ctx, ctx->small, sizeof(Small), "counters") != FC_OK) {
+        fc_destroy(ctx);
+        return FC_ERR_HIP;
+    }
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    const uint32_t gib = env_u32("FC_STATE_GIB", 0);
+    ctx->state_budget = gib ? static_cast<size_t>(gib) << 30
+                            : std::min<size_t>(free_b / 4, static_cast<size_t>(48) << 30);
+    ctx->lanes_per_wave = env_u32("FC_LANES_PER_WAVE", 64);
+    ctx->max_slots = env_u32("FC_MAX_SLOTS", 0);
+    *out = ctx;
+    return FC_OK;
+}
+
+int fc_destroy(fc_ctx *ctx) {
+    if (!ctx) return FC_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    for (DevBuf *b : {&ctx->state, &ctx->vrec, &ctx->row_ptr, &ctx->col_idx, &ctx->small,
+                      &ctx->rtmp, &ctx->thr})
+        if (b->ptr) (void)hipFree(b->ptr);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return FC_OK;
+}
+
+int fc_set_stream(fc_ctx *ctx, void *hip_stream) {
+    if (!ctx) return FC_ERR_ARG;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return FC_OK;
+}
+
+int fc_tau(int64_t m, int64_t n, double eps, double delta, double kappa, uint32_t *tau_out) {
+    if (!tau_out) return FC_ERR_ARG;
+    *tau_out = 0;
+    if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0) ||
+        !(kappa >= 0.0 && kappa < 1.0) || n < 1 || m < 0)
+        return FC_ERR_ARG;
+    // Hoeffding with a union bound over max(m, n) estimates:
+    // 2 max(m, n) exp(-2 tau ((1 - kappa) eps)^2) <= delta
+    const double events = static_cast<double>(std::max(m, n));
+    const double e1 = (1.0 - kappa) * eps;
+    const double t = std::ceil(std::log(2.0 * events / delta) / (2.0 * e1 * e1));
+    if (!(t >= 1.0) || t > 4294967295.0) return FC_ERR_ARG;
+    *tau_out = static_cast<uint32_t>(t);
+    return FC_OK;
+}
+
+int fc_thresholds(fc_ctx *ctx, double alpha, int32_t d_max, uint64_t *out) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    if (!out || d_max < 0 || !valid_alpha(alpha))
+        return set_err(ctx, FC_ERR_ARG, "need out != NULL, d_max >= 0, alpha > 0");
+    const size_t bytes = sizeof(uint64_t) * (static_cast<size_t>(d_max) + 1);
+    if ((rc = ensure(ctx, ctx->thr, bytes, "threshold table"))) return rc;
+    FC_HIP(ctx, fc::launch_thresholds(alpha, d_max, static_cast<unsigned long long *>(ctx->thr.ptr),
+                                      ctx->stream), "thresholds launch");
+    FC_HIP(ctx, hipMemcpyAsync(out, ctx->thr.ptr, bytes, hipMemcpyDeviceToHost, ctx->stream),
+           "copy thresholds");
+    FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "thresholds");
+    return FC_OK;
+}
+
+int fc_sample(fc_ctx *ctx, const fc_graph *g, const fc_params *params, uint32_t tree_begin,
+              uint32_t tree_count, uint32_t *root_counts, uint64_t *visit_counts,
+              uint64_t *tree_digests, uint64_t *tree_steps, int32_t *parents,
+              uint32_t *tree_visits, fc_stats *stats) {
+    const double t0 = now_ms();
+    int rc = begin(ctx);
+    if (rc) return rc;
+    if ((rc = check_params(ctx, params))) return rc;
+    if (!root_counts && g && g->n > 0) return set_err(ctx, FC_ERR_ARG, "root_counts is NULL");
+    if (static_cast<uint64_t>(tree_begin) + tree_count > 0x100000000ull)
+        return set_err(ctx, FC_ERR_ARG, "tree ids must stay below 2^32");
+    GraphView gv;
+    if ((rc = prepare_graph(ctx, g, params->flags & FC_FLAG_TRUSTED_GRAPH, &gv))) return rc;
+    rc = run_sampler(ctx, gv, params, tree_begin, tree_count, root_counts, visit_counts,
+                     tree_digests, tree_steps, parents, tree_visits, stats);
+    if (stats) stats->ms_total = now_ms() - t0;
+    return rc;
+}
+
+static int estimate_common(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
+                           double *diag, double *farness, double *closeness,
+                           uint32_t *root_counts_out, fc_stats *stats) {
+    const double t0 = now_ms();
+    int rc = begin(ctx);
+    if (rc) return rc;
+    if ((rc = check_params(ctx, params))) return rc;
+    if (params->estimator != FC_EST_DIRECT && params->estimator != FC_EST_ALG1_LITERAL)
+        return set_err(ctx, FC_ERR_ARG, "unknown estimator");
+    GraphView gv;
+    if ((rc = check_graph_args(ctx, g))) return rc;
+    if (g->n == 0) {  // nothing to estimate
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return FC_OK;
+    }
+    uint32_t tau = 0;
+    {
+        GraphView tmp;
+        tmp.n = g->n;
+        tmp.nnz = g->nnz;
+        if ((rc = tau_for(ctx, params, tmp, &tau))) return rc;
+    }
+    if ((rc = prepare_graph(ctx, g, params->flags & FC_FLAG_TRUSTED_GRAPH, &gv))) return rc;
+    uint32_t *R = root_counts_out;
+    if (!R) {
+        if ((rc = ensure(ctx, ctx->rtmp, sizeof(uint32_t) * static_cast<size_t>(gv.n), "root counts")))
+            return rc;
+        R = static_cast<uint32_t *>(ctx->rtmp.ptr);
+    }
+    if (gv.n)
+        FC_HIP(ctx, hipMemsetAsync(R, 0, sizeof(uint32_t) * static_cast<size_t>(gv.n), ctx->stream),
+               "memset R");
+    if ((rc = run_sampler(ctx, gv, params, 0, tau, R, nullptr, nullptr, nullptr, nullptr, nullptr,
+                          stats)))
+        return rc;
+    Small *sm = static_cast<Small *>(ctx->small.ptr);
+    FC_HIP(ctx, hipMemsetAsync(&sm->sum, 0, sizeof(unsigned long long), ctx->stream), "memset sum");
+    FC_HIP(ctx, fc::launch_sum_u32(R, gv.n, &sm->sum, ctx->stream), "sum launch");
+    FC_HIP(ctx, fc::launch_estimate(R, gv.n, tau, params->estimator == FC_EST_ALG1_LITERAL, &sm->sum,
+                                    diag, farness, closeness, ctx->stream), "estimate launch");
+    FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "estimate");
+    if (stats) stats->ms_total = now_ms() - t0;
+    return FC_OK;
+}
+
+int fc_diag_estimate(fc_ctx *ctx, const fc_graph *g, const fc_params *params, double *diag_out,
+                     uint32_t *root_counts_out, fc_stats *stats) {
+    if (ctx && !diag_out && g && g->n > 0) return set_err(ctx, FC_ERR_ARG, "diag_out is NULL");
+    return estimate_common(ctx, g, params, diag_out, nullptr, nullptr, root_counts_out, stats);
+}
+
+int fc_farness(fc_ctx *ctx, const fc_graph *g, const fc_params *params, double *farness_out,
+               double *closeness_out, double *diag_out, uint32_t *root_counts_out,
+               fc_stats *stats) {
+    if (ctx && !farness_out && g && g->n > 0) return set_err(ctx, FC_ERR_ARG, "farness_out is NULL");
+    return estimate_common(ctx, g, params, diag_out, farness_out, closeness_out, root_counts_out,
+                           stats);
+}
+
+const char *fc_error_string(int code) {
+    switch (code) {
+        case FC_OK: return "ok";
+        case FC_ERR_ARG: return "invalid argument";
+        case FC_ERR_GRAPH: return "graph violates the input contract (simple, symmetric, sorted CSR)";
+        case FC_ERR_NOMEM: return "device memory allocation failed";
+        case FC_ERR_HIP: return "HIP runtime error";
+        case FC_ERR_UNSUPPORTED: return "unsupported size";
+        case FC_ERR_OVERFLOW: return "visit counter overflow";
+        default: return "unknown error code";
+    }
+}
+
+const char *fc_last_error(fc_ctx *ctx) {
+    if (!ctx) return "no context";
+    return ctx->last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Device-side building blocks of the sampler: the Philox4x32-10 block
+// function, the per-vertex record, the packed per-tree state word and the
+// digest mixer.  gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fc {
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of two
+// 32x32->64 multiplies with the odd constants below, XOR of the high halves
+// with the other two words and the round key, then a word permutation; the
+// key advances by the 32-bit Weyl constants of the golden ratio and of
+// sqrt(3)-1 between rounds.
+struct Philox4 {
+    uint32_t x0, x1, x2, x3;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+    constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(kM0, c0), lo0 = kM0 * c0;
+        const uint32_t hi1 = __umulhi(kM1, c2), lo1 = kM1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += kW0;
+        k1 += kW1;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// SplitMix64 output function (Steele, Lea and Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Per-vertex record of G* for one alpha, 16 bytes, one dwordx4 load:
+// first CSR entry, degree, low 32 bits of the root threshold, and a flag
+// for "every step goes to u*" (threshold >= 2^32, e.g. isolated vertices).
+struct __align__(16) VRec {
+    int32_t start;
+    uint32_t deg;
+    uint32_t thr;
+    uint32_t always_root;
+};
+
+__device__ __forceinline__ VRec load_vrec(const VRec *__restrict__ vrec, uint32_t v) {
+    const uint4 q = reinterpret_cast<const uint4 *>(vrec)[v];
+    return {static_cast<int32_t>(q.x), q.y, q.z, q.w};
+}
+
+// One arrow of v: returns the successor (n = u*) given Philox words x0, x1.
+__device__ __forceinline__ uint32_t arrow_target(const VRec &r, uint32_t x0, uint32_t x1,
+                                                 const int32_t *__restrict__ col_idx,
+                                                 uint32_t n) {
+    if (r.always_root || x0 < r.thr) return n;
+    const uint32_t idx = __umulhi(x1, r.deg);
+    return static_cast<uint32_t>(col_idx[r.start + static_cast<int32_t>(idx)]);
+}
+
+// Packed per-tree state word of one vertex (lane-per-tree sampler):
+//   bits  0..30  next   successor drawn last (u* = n), valid when visited
+//   bit   31     in_tree
+//   bits 32..62  k      number of arrows drawn at the vertex in this tree
+//   bit   63     epoch  parity of the tree the word belongs to; a word of the
+//                       other parity is "fresh" (k = 0, not in the tree), so
+//                       no per-tree clearing pass is needed.
+namespace sw {
+constexpr uint64_t kNextMask = 0x7FFFFFFFull;
+constexpr uint64_t kInTree = 1ull << 31;
+constexpr uint32_t kKMask = 0x7FFFFFFFu;
+constexpr int kKShift = 32;
+constexpr int kEpochShift = 63;
+
+__device__ __forceinline__ bool current(uint64_t w, uint32_t ep) {
+    return static_cast<uint32_t>(w >> kEpochShift) == ep;
+}
+__device__ __forceinline__ bool in_tree(uint64_t w, uint32_t ep) {
+    return current(w, ep) && (w & kInTree);
+}
+__device__ __forceinline__ uint32_t visits(uint64_t w, uint32_t ep) {
+    return current(w, ep) ? static_cast<uint32_t>(w >> kKShift) & kKMask : 0u;
+}
+__device__ __forceinline__ uint32_t next(uint64_t w) {
+    return static_cast<uint32_t>(w & kNextMask);
+}
+__device__ __forceinline__ uint64_t pack(uint32_t nxt, uint32_t k, uint32_t ep) {
+    return static_cast<uint64_t>(nxt) | (static_cast<uint64_t>(k & kKMask) << kKShift) |
+           (static_cast<uint64_t>(ep) << kEpochShift);
+}
+}  // namespace sw
+
+// Error bits reported by kernels through a device word.
+constexpr uint32_t kErrVisitOverflow = 1u;
+constexpr uint32_t kErrGraphRowPtr = 2u;
+constexpr uint32_t kErrGraphColumn = 4u;
+constexpr uint32_t kErrGraphSelfLoop = 8u;
+constexpr uint32_t kErrGraphOrder = 16u;
+constexpr uint32_t kErrGraphAsymmetric = 32u;
+constexpr uint32_t kErrStepCap = 64u;
+
+// Device-side totals shared by a launch.
+struct Totals {
+    unsigned long long walk_steps;
+    unsigned long long roots;
+    unsigned long long digest_sum;
+    unsigned int error;
+    unsigned int pad;
+};
+
+}  // namespace fc

@@ -1,0 +1,62 @@
+// Host-side launch wrappers of the device kernels (one translation unit per
+// kernel family).  Every wrapper enqueues on `stream` and returns the launch
+// status; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fc_device.hpp"
+
+namespace fc {
+
+// CSR checks (input contract: simple, undirected, sorted rows).  Pass 1
+// checks row_ptr (monotone, bounds); pass 2, run only if pass 1 found
+// nothing, checks columns, self-loops, ordering and symmetry.
+hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
+                                unsigned int *err, hipStream_t stream);
+hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                                unsigned int *err, hipStream_t stream);
+
+// Per-vertex records of G* for one alpha.
+hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
+                             hipStream_t stream);
+
+// thr(d), d = 0..d_max, as the device computes it (uint64, 2^32 for "always").
+hipError_t launch_thresholds(double alpha, int32_t d_max, unsigned long long *out,
+                             hipStream_t stream);
+
+// Lane-per-tree Wilson sampler.
+struct LaneArgs {
+    const VRec *vrec;
+    const int32_t *col_idx;
+    uint64_t *state;          // slots * n words
+    uint32_t n;
+    uint32_t slots;
+    uint32_t lanes_per_wave;  // active lanes in each 64-lane wave
+    uint32_t tree_begin;
+    uint32_t tree_count;
+    uint32_t stream_id;
+    uint32_t key0, key1;
+    unsigned long long step_cap;  // per-tree bound on steps; exceeding it is an error
+    unsigned int *queue;      // next tree index (relative to tree_begin)
+    uint32_t *root_counts;
+    unsigned long long *visit_counts;
+    unsigned long long *tree_digests;
+    unsigned long long *tree_steps;
+    int32_t *parents;
+    uint32_t *tree_visits;
+    Totals *totals;
+};
+hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
+
+// S = sum of R (exact, uint64) into *sum (caller zeroes it).
+hipError_t launch_sum_u32(const uint32_t *x, int32_t n, unsigned long long *sum,
+                          hipStream_t stream);
+
+// diag / farness / closeness from R and S (any output may be null).
+hipError_t launch_estimate(const uint32_t *R, int32_t n, uint32_t tau, int literal,
+                           const unsigned long long *sum, double *diag, double *farness,
+                           double *closeness, hipStream_t stream);
+
+}  // namespace fc

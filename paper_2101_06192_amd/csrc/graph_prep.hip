@@ -1,0 +1,121 @@
+// CSR validation and the per-vertex records of the augmented graph G*.
+//
+// G* (Section 4.1 of the paper) is never materialised: u* is the id n, the
+// edges {u*, v} are implicit, and a walk leaves v to u* with probability
+// 1 / (1 + alpha d_v) (edge weight 1 against d_v edges of weight alpha).
+#include "fc_kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace fc {
+
+namespace {
+
+__global__ void validate_rows_kernel(const int32_t *__restrict__ row_ptr, int32_t n, int64_t nnz,
+                                     unsigned int *err) {
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v > n) return;
+    const int64_t a = row_ptr[v];
+    bool bad = a < 0 || a > nnz;
+    if (v == 0) bad |= (a != 0);
+    if (v == n) bad |= (a != nnz);
+    if (v < n) bad |= (row_ptr[v + 1] < a);
+    if (bad) atomicOr(err, kErrGraphRowPtr);
+}
+
+// One thread per vertex; symmetry by binary search of v in the row of each
+// neighbour (rows are sorted, which this kernel also checks).
+__global__ void validate_cols_kernel(const int32_t *__restrict__ row_ptr,
+                                     const int32_t *__restrict__ col_idx, int32_t n,
+                                     unsigned int *err) {
+    const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (v >= n) return;
+    unsigned int e = 0;
+    const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+    int32_t prev = -1;
+    for (int32_t j = a; j < b; ++j) {
+        const int32_t u = col_idx[j];
+        if (u < 0 || u >= n) {
+            e |= kErrGraphColumn;
+            break;
+        }
+        if (u == v) e |= kErrGraphSelfLoop;
+        if (u <= prev) e |= kErrGraphOrder;
+        prev = u;
+        int32_t lo = row_ptr[u], hi = row_ptr[u + 1];
+        while (lo < hi) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if (col_idx[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo >= row_ptr[u + 1] || col_idx[lo] != v) e |= kErrGraphAsymmetric;
+    }
+    if (e) atomicOr(err, e);
+}
+
+// thr(d) = floor(2^32 * (1 / ((alpha * d) + 1))), each operation rounded to
+// binary64 (IEEE division; no contraction in this file).
+__device__ __forceinline__ unsigned long long root_threshold(double alpha, uint32_t d) {
+    if (d == 0) return 1ull << 32;
+    const double ad = alpha * static_cast<double>(d);
+    const double den = ad + 1.0;
+    const double p = 1.0 / den;
+    return static_cast<unsigned long long>(p * 4294967296.0);
+}
+
+__global__ void build_vrec_kernel(const int32_t *__restrict__ row_ptr, int32_t n, double alpha,
+                                  VRec *__restrict__ vrec) {
+    const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (v >= n) return;
+    const int32_t a = row_ptr[v];
+    const uint32_t d = static_cast<uint32_t>(row_ptr[v + 1] - a);
+    const unsigned long long t = root_threshold(alpha, d);
+    VRec r;
+    r.start = a;
+    r.deg = d;
+    r.thr = static_cast<uint32_t>(t);
+    r.always_root = (t >> 32) ? 1u : 0u;
+    vrec[v] = r;
+}
+
+__global__ void thresholds_kernel(double alpha, int32_t d_max, unsigned long long *out) {
+    const int32_t d = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (d > d_max) return;
+    out[d] = root_threshold(alpha, static_cast<uint32_t>(d));
+}
+
+inline unsigned int blocks_for(int64_t items, int threads) {
+    return static_cast<unsigned int>((items + threads - 1) / threads);
+}
+
+}  // namespace
+
+hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
+                                unsigned int *err, hipStream_t stream) {
+    validate_rows_kernel<<<blocks_for(static_cast<int64_t>(n) + 1, 256), 256, 0, stream>>>(
+        row_ptr, n, nnz, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                                unsigned int *err, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    validate_cols_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, col_idx, n, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
+                             hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    build_vrec_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, n, alpha, vrec);
+    return hipGetLastError();
+}
+
+hipError_t launch_thresholds(double alpha, int32_t d_max, unsigned long long *out,
+                             hipStream_t stream) {
+    thresholds_kernel<<<blocks_for(static_cast<int64_t>(d_max) + 1, 256), 256, 0, stream>>>(
+        alpha, d_max, out);
+    return hipGetLastError();
+}
+
+}  // namespace fc

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C-ABI.
+
+Sampling is integer work, so the bar is bit-exactness: parent arrays, per
+vertex visit counts, root counts, per-tree digests and step counts.  The
+estimators are one or two correctly rounded binary64 operations on exact
+integers, so they must be bit-equal too.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_06192_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _compare(fc, g, alpha, seed, t0, count, stream=0, per_tree=True):
+    _say(f"parity {g.name or g.n} alpha={alpha} seed={seed} trees=[{t0},{t0 + count}) stream={stream}")
+    got = fc.sample(g, alpha=alpha, seed=seed, tree_begin=t0, tree_count=count, stream_id=stream,
+                    want_visits=True, want_digests=True, want_steps=True,
+                    want_parents=per_tree, want_tree_visits=per_tree)
+    ref = oracle.sample(g, alpha, seed, t0, count, stream=stream, per_tree=per_tree)
+    if per_tree:
+        for i in range(count):
+            assert np.array_equal(got["parents"][i], ref.parents[i]), f"parents differ in tree {t0 + i}"
+            assert np.array_equal(got["tree_visits"][i], ref.tree_visits[i]), f"visits differ in tree {t0 + i}"
+    assert np.array_equal(got["tree_digests"], ref.digests)
+    assert np.array_equal(got["tree_steps"], ref.steps)
+    assert np.array_equal(got["root_counts"], ref.R)
+    assert np.array_equal(got["visit_counts"], ref.visits)
+    st = got["stats"]
+    assert st["walk_steps"] == int(ref.steps.sum())
+    assert st["roots"] == int(ref.roots.sum())
+    assert st["digest_sum"] == int(ref.digests.sum(dtype=np.uint64))
+    return got, ref
+
+
+def test_thresholds_match_oracle(gpu_lib):
+    fc = gpu_lib
+    for alpha in (0.1, 0.5, 1.0, 2.0, 10.0, 1e-17, 3.3e5):
+        thr = fc.thresholds(alpha, 5000)
+        ref = np.array([oracle.root_threshold(alpha, d) for d in range(5001)], np.uint64)
+        assert np.array_equal(thr, ref), alpha
+
+
+def test_er1000_all_trees_bit_exact(gpu_lib):
+    """ER(1000, 0.01), alpha = 1, seed 0: all 2000 trees."""
+    g = inputs.erdos_renyi(1000, 0.01, 0)
+    _compare(gpu_lib, g, 1.0, 0, 0, 2000)
+
+
+def test_er1000_estimators_bit_exact(gpu_lib):
+    fc = gpu_lib
+    g = inputs.erdos_renyi(1000, 0.01, 0)
+    out = fc.farness(g, alpha=1.0, seed=0, tau=2000)
+    ref = oracle.sample(g, 1.0, 0, 0, 2000)
+    d, f, c = oracle.estimate(ref.R, 2000)
+    assert np.array_equal(out["root_counts"], ref.R)
+    assert np.array_equal(out["diag"], d)
+    assert np.array_equal(out["farness"], f)
+    assert np.array_equal(out["closeness"], c)
+    # Algorithm 1 with tau from (eps, delta) and the literal last-loop reading
+    out2 = fc.diag_estimate(g, alpha=1.0, eps=0.1, delta=0.1, seed=0, literal=True)
+    t = oracle.tau(g.m, g.n, 0.1, 0.1)
+    assert out2["tau"] == t == 576
+    ref2 = oracle.sample(g, 1.0, 0, 0, t)
+    dl, _, _ = oracle.estimate(ref2.R, t, literal=True)
+    assert np.array_equal(out2["diag"], dl)
+    # and the (eps, delta) guarantee against the dense forest matrix
+    Om = oracle.forest_matrix(g, 1.0)
+    direct = fc.diag_estimate(g, alpha=1.0, eps=0.1, delta=0.1, seed=0)
+    assert np.abs(direct["diag"] - np.diag(Om)).max() < 0.1
+
+
+@pytest.mark.parametrize("case", ["single_vertex", "isolated", "edge", "star", "path", "k6",
+                                  "triangle_isolated", "ragged_er", "two_components"])
+def test_small_and_degenerate_graphs(gpu_lib, case):
+    E = {
+        "single_vertex": (1, []),
+        "isolated": (37, []),
+        "edge": (2, [(0, 1)]),
+        "star": (65, [(0, i) for i in range(1, 65)]),
+        "path": (130, [(i, i + 1) for i in range(129)]),
+        "k6": (6, [(a, b) for a in range(6) for b in range(a + 1, 6)]),
+        "triangle_isolated": (5, [(0, 1), (1, 2), (0, 2)]),
+        "two_components": (9, [(0, 1), (1, 2), (2, 3), (5, 6), (6, 7), (7, 8), (8, 5)]),
+    }
+    if case == "ragged_er":
+        g = inputs.erdos_renyi(333, 0.03, 9)
+    else:
+        n, e = E[case]
+        g = inputs.from_edge_list(n, e, case)
+    for alpha in (0.3, 1.0, 7.0):
+        _compare(gpu_lib, g, alpha, 1234567890123, 17, 97, stream=3)
+
+
+def test_empty_graph_and_zero_trees(gpu_lib):
+    fc = gpu_lib
+    g0 = inputs.from_edge_list(0, [])
+    r = fc.sample(g0, alpha=1.0, tree_count=5, want_digests=True)
+    assert r["root_counts"].size == 0
+    out = fc.diag_estimate(g0, alpha=1.0, tau=10)
+    assert out["diag"].size == 0
+    g = inputs.erdos_renyi(50, 0.1, 2)
+    r = fc.sample(g, alpha=1.0, tree_count=0, want_visits=True)
+    assert (r["root_counts"] == 0).all() and (r["visit_counts"] == 0).all()
+
+
+def test_tree_ranges_streams_and_device_graph(gpu_lib):
+    fc = gpu_lib
+    g = inputs.barabasi_albert(3000, 4, 5)
+    a = fc.sample(g, alpha=0.8, seed=9, tree_begin=0, tree_count=40, want_digests=True)
+    b = fc.sample(g, alpha=0.8, seed=9, tree_begin=40, tree_count=25, want_digests=True)
+    c = fc.sample(g, alpha=0.8, seed=9, tree_begin=0, tree_count=65, want_digests=True)
+    assert np.array_equal(a["root_counts"] + b["root_counts"], c["root_counts"])
+    assert np.array_equal(np.concatenate([a["tree_digests"], b["tree_digests"]]), c["tree_digests"])
+    dg = fc.to_device(g)
+    d = fc.sample(dg, alpha=0.8, seed=9, tree_begin=0, tree_count=65, want_digests=True)
+    assert np.array_equal(d["tree_digests"], c["tree_digests"])
+    ref = oracle.sample(g, 0.8, 9, 0, 65, stream=0)
+    assert np.array_equal(c["root_counts"], ref.R)
+    s1 = fc.sample(g, alpha=0.8, seed=9, tree_count=10, stream_id=1, want_digests=True)
+    ref1 = oracle.sample(g, 0.8, 9, 0, 10, stream=1)
+    assert np.array_equal(s1["tree_digests"], ref1.digests)
+
+
+def test_root_test_boundary(gpu_lib):
+    """alpha chosen so that thr(1) equals x0 of vertex 0's first arrow in tree
+    0 (seed 0): both sides must take the strict comparison."""
+    x0 = int(oracle.philox4x32_10([0, 0, 0, 0], [0, 0])[0])
+    alpha = 2.0**32 / (x0 + 0.5) - 1.0
+    assert oracle.root_threshold(alpha, 1) == x0
+    g = inputs.from_edge_list(2, [(0, 1)])
+    _compare(gpu_lib, g, alpha, 0, 0, 4)
+
+
+def test_graph_validation_errors(gpu_lib):
+    fc = gpu_lib
+
+    def bad(n, rp, ci):
+        g = inputs.CSRGraph(n, np.asarray(rp, np.int32), np.asarray(ci, np.int32))
+        with pytest.raises(fc.FCError) as e:
+            fc.sample(g, alpha=1.0, tree_count=1)
+        return e.value.code
+
+    assert bad(3, [0, 1, 1, 1], [1]) == fc.FC_ERR_GRAPH            # asymmetric
+    assert bad(2, [0, 1, 2], [0, 1]) == fc.FC_ERR_GRAPH            # self-loops
+    assert bad(3, [0, 2, 3, 4], [2, 1, 0, 0]) == fc.FC_ERR_GRAPH   # unsorted row
+    assert bad(2, [0, 1, 2], [1, 5]) == fc.FC_ERR_GRAPH            # column out of range
+    assert bad(2, [0, 2, 1], [1, 0]) == fc.FC_ERR_GRAPH            # row_ptr decreasing
+    assert bad(2, [1, 1, 2], [1, 0]) == fc.FC_ERR_GRAPH            # row_ptr[0] != 0
+    with pytest.raises(fc.FCError) as e:
+        fc.sample(inputs.erdos_renyi(10, 0.3, 1), alpha=0.0, tree_count=1)
+    assert e.value.code == fc.FC_ERR_ARG
+    with pytest.raises(fc.FCError) as e:
+        fc.diag_estimate(inputs.erdos_renyi(10, 0.3, 1), alpha=1.0, eps=1.5)
+    assert e.value.code == fc.FC_ERR_ARG
+
+
+def test_ba200k_tree_subset_bit_exact(gpu_lib):
+    """BA(200000, 5), alpha = 1: the first 48 trees and a later range."""
+    g = inputs.barabasi_albert(200_000, 5, 0)
+    _compare(gpu_lib, g, 1.0, 0, 0, 48)
+    _compare(gpu_lib, g, 1.0, 0, 4000, 16, per_tree=False)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.0, 2.0])
+def test_grid_tree_subset_bit_exact(gpu_lib, alpha):
+    """1000 x 1000 grid with 12% of edges removed: 6 trees per alpha."""
+    g = inputs.grid_removed(1000, 1000, 0.12, 0)
+    _compare(gpu_lib, g, alpha, 0, 100, 6)
+
+
+def test_ba200k_full_run_sampled(gpu_lib):
+    """The benchmark's configuration (BA(200000, 5), alpha = 1, 4096 trees):
+    per-tree digests of a spread of tree ids recomputed one by one by the
+    oracle, exact totals, and the estimate against CG on sampled vertices."""
+    fc = gpu_lib
+    g = inputs.barabasi_albert(200_000, 5, 0)
+    dg = fc.to_device(g)
+    got = fc.sample(dg, alpha=1.0, seed=0, tree_begin=0, tree_count=4096, want_digests=True,
+                    want_steps=True, trusted=True)
+    for t in (0, 1, 777, 2048, 4095):
+        ref = oracle.sample(g, 1.0, 0, t, 1)
+        assert got["tree_digests"][t] == ref.digests[0], t
+        assert got["tree_steps"][t] == ref.steps[0], t
+    R = got["root_counts"].astype(np.float64)
+    assert int(R.sum()) == got["stats"]["roots"]
+    rng = np.random.default_rng(3)
+    vs = rng.choice(g.n, 32, replace=False)
+    om = oracle.omega_diag_cg(g, 1.0, vs, rtol=1e-9)
+    # Hoeffding radius at delta = 1e-6 over 32 vertices with 4096 trees
+    assert np.abs(R[vs] / 4096 - om).max() < np.sqrt(np.log(2 * 32 / 1e-6) / (2 * 4096))
