@@ -34,26 +34,26 @@ WORKLOAD = {"workload": "ba_n200000_m5_alpha1_trees4096", "graph": "barabasi_alb
 BYTES_STEP, BYTES_RETRACE, BYTES_SCAN, BYTES_ROOT = 28, 16, 8, 8
 HBM_PEAK_GBS = 8000.0
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_06192_amd", "csrc", "wilson_lane.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_lane_ba200k_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_2101_06192_amd", "csrc")
 
 
-def _kernel_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
+def _kernel_hash(sampler: str) -> str:
+    with open(os.path.join(CSRC, f"{sampler}.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic():
+def _traffic(sampler: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(ROOT, "profiles", f"{sampler}_ba200k_traffic.txt")
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != _kernel_hash():
+    if vals.get("kernel_source_sha256_16") != _kernel_hash(sampler):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--cpu-trees", type=int, default=320,
                     help="trees the CPU oracle samples for the baseline (0 = skip)")
     ap.add_argument("--no-eps", action="store_true", help="skip the time-to-eps=0.1 leg")
+    ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler shards by tree id with no exchange "
@@ -101,7 +102,7 @@ def main():
 
     def step():
         return fc.farness(dg, alpha=alpha, seed=WORKLOAD["seed"], tau=trees, device=dev,
-                          as_torch=True)
+                          as_torch=True, sampler=args.sampler)
 
     for _ in range(args.warmup):
         step()
@@ -123,14 +124,15 @@ def main():
     alg_bytes = (BYTES_STEP * walk_steps + (BYTES_RETRACE + BYTES_SCAN) * n * trees
                  + BYTES_ROOT * roots)
     achieved = alg_bytes / (ms_kernel / 1000.0) / 1e9
-    traffic = _traffic()
+    sampler = stats[-1]["sampler"]
+    traffic = _traffic(sampler)
 
     eps_leg = None
     if not args.no_eps:
         torch.cuda.synchronize()
         te = time.perf_counter()
         o = fc.diag_estimate(dg, alpha=alpha, eps=0.1, delta=0.1, seed=0, device=dev,
-                             as_torch=True)
+                             as_torch=True, sampler=args.sampler)
         torch.cuda.synchronize()
         eps_leg = {"tau": o["tau"], "ms": 1000.0 * (time.perf_counter() - te)}
 
@@ -157,7 +159,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "wilson_lane_kernel", "kernel_ms": ms_kernel,
+                     "kernel": f"{sampler}_kernel", "kernel_ms": ms_kernel,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
     }

@@ -78,6 +78,10 @@ extern "C" {
 
 /* fc_params.flags */
 #define FC_FLAG_TRUSTED_GRAPH 1 /* skip the device-side CSR validation */
+#define FC_FLAG_SAMPLER_LANE 2  /* force the lane-per-tree sampler */
+#define FC_FLAG_SAMPLER_COOP 4  /* force the workgroup-per-tree sampler */
+/* Neither sampler flag: the library picks one from n and the tree count.
+ * Both samplers produce identical results (same trees, same counts). */
 
 typedef struct fc_ctx fc_ctx;
 
@@ -117,6 +121,7 @@ typedef struct {
     uint64_t digest_sum;     /* sum over trees of the per-tree digest, mod 2^64 */
     double ms_sample;        /* device time of the sampling kernel */
     double ms_total;         /* host wall time of the call */
+    char sampler[16];        /* "wilson_lane" or "wilson_coop" */
 } fc_stats;
 
 /* Create a context on HIP device `hip_device` that enqueues its work on

@@ -35,6 +35,9 @@ FC_MEM_DEVICE = 1
 FC_EST_DIRECT = 0
 FC_EST_ALG1_LITERAL = 1
 FC_FLAG_TRUSTED_GRAPH = 1
+FC_FLAG_SAMPLER_LANE = 2
+FC_FLAG_SAMPLER_COOP = 4
+SAMPLERS = {None: 0, "auto": 0, "lane": FC_FLAG_SAMPLER_LANE, "coop": FC_FLAG_SAMPLER_COOP}
 
 
 class FCError(RuntimeError):
@@ -61,10 +64,12 @@ class fc_stats(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_uint32), ("trees_in_flight", ctypes.c_uint32),
                 ("walk_steps", ctypes.c_uint64), ("roots", ctypes.c_uint64),
                 ("digest_sum", ctypes.c_uint64), ("ms_sample", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("sampler", ctypes.c_char * 16)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["sampler"] = d["sampler"].decode()
+        return d
 
 
 _lib = None
@@ -197,10 +202,12 @@ def _graph_struct(g) -> fc_graph:
 
 
 def _params(alpha, eps=0.1, delta=0.1, kappa=0.0, seed=0, tau_=0, stream_id=0,
-            literal=False, trusted=False) -> fc_params:
+            literal=False, trusted=False, sampler=None) -> fc_params:
+    if sampler not in SAMPLERS:
+        raise ValueError(f"sampler must be one of {sorted(k for k in SAMPLERS if k)}")
+    flags = (FC_FLAG_TRUSTED_GRAPH if trusted else 0) | SAMPLERS[sampler]
     return fc_params(float(alpha), float(eps), float(delta), float(kappa), int(seed), int(tau_),
-                     int(stream_id), FC_EST_ALG1_LITERAL if literal else FC_EST_DIRECT,
-                     FC_FLAG_TRUSTED_GRAPH if trusted else 0)
+                     int(stream_id), FC_EST_ALG1_LITERAL if literal else FC_EST_DIRECT, flags)
 
 
 def _ptr(t):
@@ -226,7 +233,7 @@ def sample(g, alpha: float, seed: int = 0, tree_begin: int = 0, tree_count: int 
            stream_id: int = 0, device="cuda:0", want_visits: bool = False,
            want_digests: bool = False, want_steps: bool = False, want_parents: bool = False,
            want_tree_visits: bool = False, trusted: bool = False, as_torch: bool = False,
-           root_counts=None) -> dict:
+           root_counts=None, sampler=None) -> dict:
     """Sample trees [tree_begin, tree_begin + tree_count) (fc_sample)."""
     import torch
     ctx = context(device)
@@ -239,7 +246,7 @@ def sample(g, alpha: float, seed: int = 0, tree_begin: int = 0, tree_count: int 
     P = torch.zeros(max(tree_count * n, 1), dtype=torch.int32, device=dev) if want_parents else None
     TV = torch.zeros(max(tree_count * n, 1), dtype=torch.int32, device=dev) if want_tree_visits else None
     gs = _graph_struct(g)
-    ps = _params(alpha, seed=seed, stream_id=stream_id, trusted=trusted)
+    ps = _params(alpha, seed=seed, stream_id=stream_id, trusted=trusted, sampler=sampler)
     st = fc_stats()
     ctx.check(lib().fc_sample(ctx.handle, ctypes.byref(gs), ctypes.byref(ps), int(tree_begin),
                               int(tree_count), _ptr(R), _ptr(V), _ptr(D), _ptr(S), _ptr(P),
@@ -271,7 +278,7 @@ def sample(g, alpha: float, seed: int = 0, tree_begin: int = 0, tree_count: int 
 
 
 def _estimate(entry: str, g, alpha, eps, delta, seed, kappa, tau_, literal, device, trusted,
-              as_torch, stream_id=0):
+              as_torch, stream_id=0, sampler=None):
     import torch
     ctx = context(device)
     n = int(g.n)
@@ -279,7 +286,7 @@ def _estimate(entry: str, g, alpha, eps, delta, seed, kappa, tau_, literal, devi
     diag = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     R = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     gs = _graph_struct(g)
-    ps = _params(alpha, eps, delta, kappa, seed, tau_, stream_id, literal, trusted)
+    ps = _params(alpha, eps, delta, kappa, seed, tau_, stream_id, literal, trusted, sampler)
     st = fc_stats()
     out = {}
     if entry == "diag":
@@ -302,15 +309,17 @@ def _estimate(entry: str, g, alpha, eps, delta, seed, kappa, tau_, literal, devi
 
 def diag_estimate(g, alpha: float = 1.0, eps: float = 0.1, delta: float = 0.1, seed: int = 0,
                   kappa: float = 0.0, tau: int = 0, literal: bool = False, device="cuda:0",
-                  trusted: bool = False, as_torch: bool = False, stream_id: int = 0) -> dict:
+                  trusted: bool = False, as_torch: bool = False, stream_id: int = 0,
+                  sampler=None) -> dict:
     """Algorithm 1: (eps, delta)-estimate of diag(Omega) (fc_diag_estimate)."""
     return _estimate("diag", g, alpha, eps, delta, seed, kappa, tau, literal, device, trusted,
-                     as_torch, stream_id)
+                     as_torch, stream_id, sampler)
 
 
 def farness(g, alpha: float = 1.0, eps: float = 0.1, delta: float = 0.1, seed: int = 0,
             kappa: float = 0.0, tau: int = 0, literal: bool = False, device="cuda:0",
-            trusted: bool = False, as_torch: bool = False, stream_id: int = 0) -> dict:
+            trusted: bool = False, as_torch: bool = False, stream_id: int = 0,
+            sampler=None) -> dict:
     """Forest farness and closeness of every vertex (fc_farness)."""
     return _estimate("farness", g, alpha, eps, delta, seed, kappa, tau, literal, device, trusted,
-                     as_torch, stream_id)
+                     as_torch, stream_id, sampler)

@@ -20,6 +20,10 @@
 
 #pragma STDC FP_CONTRACT OFF
 
+static_assert(sizeof(fc_graph) == 40, "fc_graph layout");
+static_assert(sizeof(fc_params) == 56, "fc_params layout");
+static_assert(sizeof(fc_stats) == 64, "fc_stats layout");
+
 namespace {
 
 struct DevBuf {
@@ -40,11 +44,15 @@ struct fc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string last_error;
-    DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr;
+    DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
     uint32_t max_slots = 0;       // 0 = as many trees in flight as memory allows
+    uint32_t cu_count = 256;
+    uint32_t coop_threads = 256;  // threads per workgroup in the workgroup sampler
+    uint32_t coop_wg_per_cu = 4;  // resident workgroups per CU in the workgroup sampler
+    uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop (environment override)
 };
 
 namespace {
@@ -195,6 +203,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         stats->trees_in_flight = 0;
         stats->walk_steps = stats->roots = stats->digest_sum = 0;
         stats->ms_sample = 0.0;
+        stats->sampler[0] = 0;
     }
     if (g.n == 0 || tree_count == 0) return FC_OK;
     if ((rc = ensure(ctx, ctx->vrec, sizeof(fc::VRec) * static_cast<size_t>(g.n), "vertex records")))
@@ -202,42 +211,90 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::VRec *vrec = static_cast<fc::VRec *>(ctx->vrec.ptr);
     FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, g.n, p->alpha, vrec, ctx->stream), "build_vrec");
 
-    // trees in flight: bounded by the tree count and by the state budget
-    const size_t per_slot = sizeof(uint64_t) * static_cast<size_t>(g.n);
-    size_t slots = std::max<size_t>(1, ctx->state_budget / per_slot);
-    slots = std::min<size_t>(slots, tree_count);
-    if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
-    if ((rc = ensure(ctx, ctx->state, per_slot * slots, "per-tree state"))) return rc;
-    FC_HIP(ctx, hipMemsetAsync(ctx->state.ptr, 0, per_slot * slots, ctx->stream), "memset state");
-
-    fc::LaneArgs a{};
-    a.vrec = vrec;
-    a.col_idx = g.col_idx;
-    a.state = static_cast<uint64_t *>(ctx->state.ptr);
-    a.n = static_cast<uint32_t>(g.n);
-    a.slots = static_cast<uint32_t>(slots);
-    a.lanes_per_wave = std::max<uint32_t>(1, std::min<uint32_t>(64, ctx->lanes_per_wave));
-    a.tree_begin = tree_begin;
-    a.tree_count = tree_count;
-    a.stream_id = p->stream_id;
-    a.key0 = static_cast<uint32_t>(p->seed);
-    a.key1 = static_cast<uint32_t>(p->seed >> 32);
-    // expected steps per tree are at most n + 2 alpha m; a valid walk never
+    // which sampler: the lane sampler needs many trees to fill the GPU; the
+    // workgroup sampler parallelises inside each tree
+    bool use_coop;
+    if (p->flags & FC_FLAG_SAMPLER_LANE) use_coop = false;
+    else if (p->flags & FC_FLAG_SAMPLER_COOP) use_coop = true;
+    else if (ctx->force_sampler) use_coop = ctx->force_sampler == 2;
+    else use_coop = tree_count < 16u * ctx->cu_count * 64u / 4u || g.n >= 65536;
+    // expected steps per tree are at most n + 2 alpha m; a valid run never
     // comes near 256 times that, so exceeding it marks a fault, not bad luck
     const double cap = 256.0 * (static_cast<double>(g.n) + p->alpha * static_cast<double>(g.nnz)) +
                        1048576.0;
-    a.step_cap = cap > 4.0e18 ? 4000000000000000000ull : static_cast<unsigned long long>(cap);
-    a.queue = &sm->queue;
-    a.root_counts = root_counts;
-    a.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
-    a.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
-    a.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
-    a.parents = parents;
-    a.tree_visits = tree_visits;
-    a.totals = &sm->totals;
+    const unsigned long long step_cap =
+        cap > 4.0e18 ? 4000000000000000000ull : static_cast<unsigned long long>(cap);
+    size_t slots = 0;
+    const char *kname = use_coop ? "wilson_coop" : "wilson_lane";
+    fc::LaneArgs a{};
+    fc::CoopArgs c{};
+    if (use_coop) {
+        const size_t per_slot = (8u + 4u + 16u) * static_cast<size_t>(g.n) + 8u;
+        slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+        slots = std::min<size_t>(slots, tree_count);
+        slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * ctx->coop_wg_per_cu);
+        if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
+        if ((rc = ensure(ctx, ctx->cword, 8u * static_cast<size_t>(g.n) * slots, "tree words"))) return rc;
+        if ((rc = ensure(ctx, ctx->ckk, 4u * static_cast<size_t>(g.n) * slots, "draw counts"))) return rc;
+        if ((rc = ensure(ctx, ctx->clists, 4u * (4u * static_cast<size_t>(g.n) + 2u) * slots, "lists")))
+            return rc;
+        c.vrec = vrec;
+        c.col_idx = g.col_idx;
+        c.word = static_cast<uint64_t *>(ctx->cword.ptr);
+        c.kk = static_cast<uint32_t *>(ctx->ckk.ptr);
+        c.lists = static_cast<uint32_t *>(ctx->clists.ptr);
+        c.n = static_cast<uint32_t>(g.n);
+        c.slots = static_cast<uint32_t>(slots);
+        c.tree_begin = tree_begin;
+        c.tree_count = tree_count;
+        c.stream_id = p->stream_id;
+        c.key0 = static_cast<uint32_t>(p->seed);
+        c.key1 = static_cast<uint32_t>(p->seed >> 32);
+        c.max_rounds = 0x40000000u;
+        c.step_cap = step_cap;
+        c.queue = &sm->queue;
+        c.root_counts = root_counts;
+        c.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
+        c.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
+        c.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
+        c.parents = parents;
+        c.tree_visits = tree_visits;
+        c.totals = &sm->totals;
+    } else {
+        // trees in flight: bounded by the tree count and by the state budget
+        const size_t per_slot = sizeof(uint64_t) * static_cast<size_t>(g.n);
+        slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+        slots = std::min<size_t>(slots, tree_count);
+        if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
+        if ((rc = ensure(ctx, ctx->state, per_slot * slots, "per-tree state"))) return rc;
+        FC_HIP(ctx, hipMemsetAsync(ctx->state.ptr, 0, per_slot * slots, ctx->stream), "memset state");
+        a.vrec = vrec;
+        a.col_idx = g.col_idx;
+        a.state = static_cast<uint64_t *>(ctx->state.ptr);
+        a.n = static_cast<uint32_t>(g.n);
+        a.slots = static_cast<uint32_t>(slots);
+        a.lanes_per_wave = std::max<uint32_t>(1, std::min<uint32_t>(64, ctx->lanes_per_wave));
+        a.tree_begin = tree_begin;
+        a.tree_count = tree_count;
+        a.stream_id = p->stream_id;
+        a.key0 = static_cast<uint32_t>(p->seed);
+        a.key1 = static_cast<uint32_t>(p->seed >> 32);
+        a.step_cap = step_cap;
+        a.queue = &sm->queue;
+        a.root_counts = root_counts;
+        a.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
+        a.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
+        a.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
+        a.parents = parents;
+        a.tree_visits = tree_visits;
+        a.totals = &sm->totals;
+    }
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
-    FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
+    if (use_coop)
+        FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, ctx->stream), "wilson_coop launch");
+    else
+        FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
     FC_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
     fc::Totals tot;
     FC_HIP(ctx, hipMemcpyAsync(&tot, &sm->totals, sizeof(tot), hipMemcpyDeviceToHost, ctx->stream),
@@ -251,6 +308,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
         stats->trees_in_flight = static_cast<uint32_t>(slots);
+        std::snprintf(stats->sampler, sizeof(stats->sampler), "%s", kname);
         stats->walk_steps = tot.walk_steps;
         stats->roots = tot.roots;
         stats->digest_sum = tot.digest_sum;
@@ -301,6 +359,19 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
                             : std::min<size_t>(free_b / 4, static_cast<size_t>(48) << 30);
     ctx->lanes_per_wave = env_u32("FC_LANES_PER_WAVE", 64);
     ctx->max_slots = env_u32("FC_MAX_SLOTS", 0);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess &&
+        cus > 0)
+        ctx->cu_count = static_cast<uint32_t>(cus);
+    ctx->coop_threads = env_u32("FC_COOP_THREADS", 256);
+    if (ctx->coop_threads < 64 || ctx->coop_threads > 1024 || ctx->coop_threads % 64)
+        ctx->coop_threads = 256;
+    ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 4));
+    {
+        const char *fs = std::getenv("FC_SAMPLER");
+        if (fs && !std::strcmp(fs, "lane")) ctx->force_sampler = 1;
+        if (fs && !std::strcmp(fs, "coop")) ctx->force_sampler = 2;
+    }
     *out = ctx;
     return FC_OK;
 }
@@ -311,7 +382,7 @@ int fc_destroy(fc_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->state, &ctx->vrec, &ctx->row_ptr, &ctx->col_idx, &ctx->small,
-                      &ctx->rtmp, &ctx->thr})
+                      &ctx->rtmp, &ctx->thr, &ctx->cword, &ctx->ckk, &ctx->clists})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

@@ -50,6 +50,32 @@ struct LaneArgs {
 };
 hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
 
+// Workgroup-per-tree sampler (round-synchronous cycle popping).
+struct CoopArgs {
+    const VRec *vrec;
+    const int32_t *col_idx;
+    uint64_t *word;           // slots * n: arrow target | settled, in-degree counter
+    uint32_t *kk;             // slots * n: arrows drawn per vertex
+    uint32_t *lists;          // slots * (4n + 2): two unsettled lists, peel order, levels
+    uint32_t n;
+    uint32_t slots;           // workgroups (trees in flight)
+    uint32_t tree_begin;
+    uint32_t tree_count;
+    uint32_t stream_id;
+    uint32_t key0, key1;
+    uint32_t max_rounds;      // bound on popping rounds per tree; exceeding it is an error
+    unsigned long long step_cap;
+    unsigned int *queue;
+    uint32_t *root_counts;
+    unsigned long long *visit_counts;
+    unsigned long long *tree_digests;
+    unsigned long long *tree_steps;
+    int32_t *parents;
+    uint32_t *tree_visits;
+    Totals *totals;
+};
+hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, hipStream_t stream);
+
 // S = sum of R (exact, uint64) into *sum (caller zeroes it).
 hipError_t launch_sum_u32(const uint32_t *x, int32_t n, unsigned long long *sum,
                           hipStream_t stream);

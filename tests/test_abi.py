@@ -93,4 +93,4 @@ def test_struct_layouts():
     assert fc.fc_graph.nnz.offset == 8 and fc.fc_graph.mem.offset == 32
     assert ctypes.sizeof(fc.fc_params) == 56
     assert fc.fc_params.seed.offset == 32 and fc.fc_params.flags.offset == 52
-    assert ctypes.sizeof(fc.fc_stats) == 48
+    assert ctypes.sizeof(fc.fc_stats) == 64

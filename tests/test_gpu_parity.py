@@ -22,11 +22,16 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _compare(fc, g, alpha, seed, t0, count, stream=0, per_tree=True):
-    _say(f"parity {g.name or g.n} alpha={alpha} seed={seed} trees=[{t0},{t0 + count}) stream={stream}")
+SAMPLERS = ["lane", "coop"]
+
+
+def _compare(fc, g, alpha, seed, t0, count, stream=0, per_tree=True, sampler="lane"):
+    _say(f"parity {sampler} {g.name or g.n} alpha={alpha} seed={seed} "
+         f"trees=[{t0},{t0 + count}) stream={stream}")
     got = fc.sample(g, alpha=alpha, seed=seed, tree_begin=t0, tree_count=count, stream_id=stream,
                     want_visits=True, want_digests=True, want_steps=True,
-                    want_parents=per_tree, want_tree_visits=per_tree)
+                    want_parents=per_tree, want_tree_visits=per_tree, sampler=sampler)
+    assert got["stats"]["sampler"] == ("wilson_" + sampler if g.n and count else "")
     ref = oracle.sample(g, alpha, seed, t0, count, stream=stream, per_tree=per_tree)
     if per_tree:
         for i in range(count):
@@ -51,10 +56,11 @@ def test_thresholds_match_oracle(gpu_lib):
         assert np.array_equal(thr, ref), alpha
 
 
-def test_er1000_all_trees_bit_exact(gpu_lib):
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_er1000_all_trees_bit_exact(gpu_lib, sampler):
     """ER(1000, 0.01), alpha = 1, seed 0: all 2000 trees."""
     g = inputs.erdos_renyi(1000, 0.01, 0)
-    _compare(gpu_lib, g, 1.0, 0, 0, 2000)
+    _compare(gpu_lib, g, 1.0, 0, 0, 2000, sampler=sampler)
 
 
 def test_er1000_estimators_bit_exact(gpu_lib):
@@ -80,9 +86,10 @@ def test_er1000_estimators_bit_exact(gpu_lib):
     assert np.abs(direct["diag"] - np.diag(Om)).max() < 0.1
 
 
+@pytest.mark.parametrize("sampler", SAMPLERS)
 @pytest.mark.parametrize("case", ["single_vertex", "isolated", "edge", "star", "path", "k6",
                                   "triangle_isolated", "ragged_er", "two_components"])
-def test_small_and_degenerate_graphs(gpu_lib, case):
+def test_small_and_degenerate_graphs(gpu_lib, case, sampler):
     E = {
         "single_vertex": (1, []),
         "isolated": (37, []),
@@ -99,7 +106,7 @@ def test_small_and_degenerate_graphs(gpu_lib, case):
         n, e = E[case]
         g = inputs.from_edge_list(n, e, case)
     for alpha in (0.3, 1.0, 7.0):
-        _compare(gpu_lib, g, alpha, 1234567890123, 17, 97, stream=3)
+        _compare(gpu_lib, g, alpha, 1234567890123, 17, 97, stream=3, sampler=sampler)
 
 
 def test_empty_graph_and_zero_trees(gpu_lib):
@@ -132,14 +139,15 @@ def test_tree_ranges_streams_and_device_graph(gpu_lib):
     assert np.array_equal(s1["tree_digests"], ref1.digests)
 
 
-def test_root_test_boundary(gpu_lib):
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_root_test_boundary(gpu_lib, sampler):
     """alpha chosen so that thr(1) equals x0 of vertex 0's first arrow in tree
     0 (seed 0): both sides must take the strict comparison."""
     x0 = int(oracle.philox4x32_10([0, 0, 0, 0], [0, 0])[0])
     alpha = 2.0**32 / (x0 + 0.5) - 1.0
     assert oracle.root_threshold(alpha, 1) == x0
     g = inputs.from_edge_list(2, [(0, 1)])
-    _compare(gpu_lib, g, alpha, 0, 0, 4)
+    _compare(gpu_lib, g, alpha, 0, 0, 4, sampler=sampler)
 
 
 def test_graph_validation_errors(gpu_lib):
@@ -165,18 +173,29 @@ def test_graph_validation_errors(gpu_lib):
     assert e.value.code == fc.FC_ERR_ARG
 
 
-def test_ba200k_tree_subset_bit_exact(gpu_lib):
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_ba200k_tree_subset_bit_exact(gpu_lib, sampler):
     """BA(200000, 5), alpha = 1: the first 48 trees and a later range."""
     g = inputs.barabasi_albert(200_000, 5, 0)
-    _compare(gpu_lib, g, 1.0, 0, 0, 48)
-    _compare(gpu_lib, g, 1.0, 0, 4000, 16, per_tree=False)
+    _compare(gpu_lib, g, 1.0, 0, 0, 48, sampler=sampler)
+    _compare(gpu_lib, g, 1.0, 0, 4000, 16, per_tree=False, sampler=sampler)
 
 
+@pytest.mark.parametrize("sampler", SAMPLERS)
 @pytest.mark.parametrize("alpha", [0.5, 1.0, 2.0])
-def test_grid_tree_subset_bit_exact(gpu_lib, alpha):
+def test_grid_tree_subset_bit_exact(gpu_lib, alpha, sampler):
     """1000 x 1000 grid with 12% of edges removed: 6 trees per alpha."""
     g = inputs.grid_removed(1000, 1000, 0.12, 0)
-    _compare(gpu_lib, g, alpha, 0, 100, 6)
+    _compare(gpu_lib, g, alpha, 0, 100, 6, sampler=sampler)
+
+
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_rmat_heavy_tail_bit_exact(gpu_lib, sampler):
+    """R-MAT (2^15 vertices, edge factor 8) at alpha = 10 and 0.1: hubs,
+    isolated vertices and many popping rounds."""
+    g = inputs.rmat(1 << 15, 8, 11)
+    for alpha in (10.0, 0.1):
+        _compare(gpu_lib, g, alpha, 5, 0, 24, sampler=sampler)
 
 
 def test_ba200k_full_run_sampled(gpu_lib):
@@ -188,6 +207,7 @@ def test_ba200k_full_run_sampled(gpu_lib):
     dg = fc.to_device(g)
     got = fc.sample(dg, alpha=1.0, seed=0, tree_begin=0, tree_count=4096, want_digests=True,
                     want_steps=True, trusted=True)
+    _say(f"full run sampler={got['stats']['sampler']} ms={got['stats']['ms_sample']:.1f}")
     for t in (0, 1, 777, 2048, 4095):
         ref = oracle.sample(g, 1.0, 0, t, 1)
         assert got["tree_digests"][t] == ref.digests[0], t
