@@ -80,7 +80,21 @@ def main():
                     help="trees the CPU oracle samples for the baseline (0 = skip)")
     ap.add_argument("--no-eps", action="store_true", help="skip the time-to-eps=0.1 leg")
     ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop"])
+    ap.add_argument("--phase-timing", action="store_true",
+                    help="report per-phase times of the workgroup sampler (adds clock reads)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.calibrate_copy, "bytes_read": x.numel() * 4,
+                          "bytes_written": y.numel() * 4}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler shards by tree id with no exchange "
               "beyond one integer all-reduce, and this build runs on a single MI355X.",
@@ -98,6 +112,8 @@ def main():
     dg = fc.to_device(g, dev)
     trees = WORKLOAD["trees"]
     alpha = WORKLOAD["alpha"]
+    if args.phase_timing:
+        fc.set_option("phase_timing", 1, dev)
     torch.cuda.synchronize()
 
     def step():
@@ -163,6 +179,10 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
     }
+    if args.phase_timing:
+        names = ["first_arrows", "in_arrows", "peel_level0", "peel_levels", "sweep", "redraw",
+                 "output"]
+        line["phase_ms_per_workgroup"] = dict(zip(names, stats[-1]["phase_ms"]))
     print(json.dumps(line), flush=True)
 
 

@@ -122,6 +122,10 @@ typedef struct {
     double ms_sample;        /* device time of the sampling kernel */
     double ms_total;         /* host wall time of the call */
     char sampler[16];        /* "wilson_lane" or "wilson_coop" */
+    double phase_ms[8];      /* workgroup sampler with option "phase_timing": average
+                                milliseconds per workgroup spent in: first arrows,
+                                in-arrow counting, peel level 0, peel levels, reverse
+                                sweep, redraw, output; else zeros */
 } fc_stats;
 
 /* Create a context on HIP device `hip_device` that enqueues its work on
@@ -131,6 +135,17 @@ FC_API int fc_create(fc_ctx **ctx, int hip_device, void *hip_stream);
 FC_API int fc_destroy(fc_ctx *ctx);
 /* Change the stream later calls use. */
 FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
+
+/* Launch-shape options of a context (results never depend on them):
+ *   "coop_threads"    threads per workgroup of the workgroup sampler (64..1024, multiple of 64)
+ *   "coop_wg_per_cu"  workgroups per CU of the workgroup sampler (>= 1)
+ *   "coop_lds_bits"   settled bitmap in LDS: 1 when it fits, 0 never (global memory)
+ *   "coop_word32"     32-bit per-vertex tree words when they fit: 1 (default) or 0 (64-bit)
+ *   "lanes_per_wave"  active lanes per wave of the lane sampler (1..64)
+ *   "max_slots"       cap on trees in flight (0 = memory bound only)
+ *   "phase_timing"    1: the workgroup sampler reports per-phase times in fc_stats
+ * Returns FC_ERR_ARG for an unknown key or a value out of range. */
+FC_API int fc_set_option(fc_ctx *ctx, const char *key, int64_t value);
 
 /* Sample size of Algorithm 1: tau = ceil(ln(2 max(m, n) / delta) /
  * (2 (1 - kappa)^2 eps^2)) (Algorithm 1; proof of Theorem "time-approx":

@@ -64,11 +64,13 @@ class fc_stats(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_uint32), ("trees_in_flight", ctypes.c_uint32),
                 ("walk_steps", ctypes.c_uint64), ("roots", ctypes.c_uint64),
                 ("digest_sum", ctypes.c_uint64), ("ms_sample", ctypes.c_double),
-                ("ms_total", ctypes.c_double), ("sampler", ctypes.c_char * 16)]
+                ("ms_total", ctypes.c_double), ("sampler", ctypes.c_char * 16),
+                ("phase_ms", ctypes.c_double * 8)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["sampler"] = d["sampler"].decode()
+        d["phase_ms"] = list(d["phase_ms"])[:7]
         return d
 
 
@@ -90,6 +92,7 @@ def lib() -> ctypes.CDLL:
             "fc_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp]),
             "fc_destroy": (ctypes.c_int, [vp]),
             "fc_set_stream": (ctypes.c_int, [vp, vp]),
+            "fc_set_option": (ctypes.c_int, [vp, ctypes.c_char_p, i64]),
             "fc_tau": (ctypes.c_int, [i64, i64, f64, f64, f64, ctypes.POINTER(u32)]),
             "fc_thresholds": (ctypes.c_int, [vp, f64, i32, vp]),
             "fc_sample": (ctypes.c_int, [vp, gp, pp, u32, u32, vp, vp, vp, vp, vp, vp, sp]),
@@ -218,6 +221,12 @@ def _out(t, as_torch):
     if t is None:
         return None
     return t if as_torch else t.cpu().numpy()
+
+
+def set_option(key: str, value: int, device="cuda:0") -> None:
+    """Launch-shape option of the device's context (fc_set_option)."""
+    ctx = context(device)
+    ctx.check(lib().fc_set_option(ctx.handle, key.encode(), int(value)))
 
 
 def thresholds(alpha: float, d_max: int, device="cuda:0") -> np.ndarray:

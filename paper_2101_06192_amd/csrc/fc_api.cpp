@@ -22,7 +22,7 @@
 
 static_assert(sizeof(fc_graph) == 40, "fc_graph layout");
 static_assert(sizeof(fc_params) == 56, "fc_params layout");
-static_assert(sizeof(fc_stats) == 64, "fc_stats layout");
+static_assert(sizeof(fc_stats) == 128, "fc_stats layout");
 
 namespace {
 
@@ -36,6 +36,9 @@ struct Small {  // device-side counters of one call
     unsigned int queue;
     unsigned int graph_err;
     unsigned long long sum;
+    unsigned int dmax;
+    unsigned int pad;
+    unsigned long long phase_ticks[8];
 };
 
 }  // namespace
@@ -44,15 +47,20 @@ struct fc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string last_error;
-    DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists;
+    DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists, clevels, cbits;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
     uint32_t max_slots = 0;       // 0 = as many trees in flight as memory allows
     uint32_t cu_count = 256;
+    size_t max_lds = 65536;       // dynamic LDS a workgroup may use
     uint32_t coop_threads = 256;  // threads per workgroup in the workgroup sampler
     uint32_t coop_wg_per_cu = 4;  // resident workgroups per CU in the workgroup sampler
     uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop (environment override)
+    bool coop_lds_bits = true;    // settled bitmap in LDS when it fits
+    bool coop_word32 = true;      // 32-bit tree words when target and count fit
+    bool phase_timing = false;    // per-phase wall-clock ticks of the workgroup sampler
+    double wall_khz = 100000.0;   // device wall clock rate
 };
 
 namespace {
@@ -209,7 +217,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     if ((rc = ensure(ctx, ctx->vrec, sizeof(fc::VRec) * static_cast<size_t>(g.n), "vertex records")))
         return rc;
     fc::VRec *vrec = static_cast<fc::VRec *>(ctx->vrec.ptr);
-    FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, g.n, p->alpha, vrec, ctx->stream), "build_vrec");
+    FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, g.n, p->alpha, vrec, &sm->dmax, ctx->stream),
+           "build_vrec");
 
     // which sampler: the lane sampler needs many trees to fill the GPU; the
     // workgroup sampler parallelises inside each tree
@@ -228,21 +237,52 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     const char *kname = use_coop ? "wilson_coop" : "wilson_lane";
     fc::LaneArgs a{};
     fc::CoopArgs c{};
+    bool lds_bits = false, word32 = false;
+    uint32_t tshift = 32;
     if (use_coop) {
-        const size_t per_slot = (8u + 4u + 16u) * static_cast<size_t>(g.n) + 8u;
+        // 32-bit tree words when target and in-arrow count both fit (the count of
+        // a vertex never exceeds its degree)
+        unsigned int dmax = 0;
+        FC_HIP(ctx, hipMemcpyAsync(&dmax, &sm->dmax, sizeof(dmax), hipMemcpyDeviceToHost, ctx->stream),
+               "copy dmax");
+        FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "build_vrec");
+        uint32_t tb = 1, cb = 1;
+        while ((1ull << tb) <= static_cast<unsigned long long>(g.n)) ++tb;  // n < 2^tb
+        while ((1ull << cb) <= static_cast<unsigned long long>(dmax)) ++cb;  // dmax < 2^cb
+        word32 = ctx->coop_word32 && tb + cb <= 32;
+        tshift = word32 ? tb : 32;
+        const size_t wbytes = word32 ? 4u : 8u;
+        const size_t nwords = (static_cast<size_t>(g.n) + 31u) / 32u;
+        lds_bits = ctx->coop_lds_bits &&
+                   fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) + 1024u <= ctx->max_lds;
+        const size_t per_slot = (wbytes + 8u + 24u + 4u) * static_cast<size_t>(g.n) + 8u +
+                                (lds_bits ? 0u : 4u * nwords);
         slots = std::max<size_t>(1, ctx->state_budget / per_slot);
         slots = std::min<size_t>(slots, tree_count);
         slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * ctx->coop_wg_per_cu);
         if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
-        if ((rc = ensure(ctx, ctx->cword, 8u * static_cast<size_t>(g.n) * slots, "tree words"))) return rc;
-        if ((rc = ensure(ctx, ctx->ckk, 4u * static_cast<size_t>(g.n) * slots, "draw counts"))) return rc;
-        if ((rc = ensure(ctx, ctx->clists, 4u * (4u * static_cast<size_t>(g.n) + 2u) * slots, "lists")))
+        if ((rc = ensure(ctx, ctx->cword, wbytes * static_cast<size_t>(g.n) * slots, "tree words")))
+            return rc;
+        if ((rc = ensure(ctx, ctx->ckk, 8u * static_cast<size_t>(g.n) * slots, "draw counts"))) return rc;
+        // epoch-tagged draw counts: zero once per launch, then each tree of a
+        // slot uses the next epoch
+        FC_HIP(ctx, hipMemsetAsync(ctx->ckk.ptr, 0, 8u * static_cast<size_t>(g.n) * slots, ctx->stream),
+               "memset draw counts");
+        if ((rc = ensure(ctx, ctx->clists, 24u * static_cast<size_t>(g.n) * slots, "lists")))
+            return rc;
+        if ((rc = ensure(ctx, ctx->clevels, 4u * (static_cast<size_t>(g.n) + 2u) * slots, "levels")))
+            return rc;
+        if (!lds_bits &&
+            (rc = ensure(ctx, ctx->cbits, 4u * nwords * slots, "settled bitmap")))
             return rc;
         c.vrec = vrec;
         c.col_idx = g.col_idx;
-        c.word = static_cast<uint64_t *>(ctx->cword.ptr);
-        c.kk = static_cast<uint32_t *>(ctx->ckk.ptr);
-        c.lists = static_cast<uint32_t *>(ctx->clists.ptr);
+        c.word = ctx->cword.ptr;
+        c.kk = static_cast<uint64_t *>(ctx->ckk.ptr);
+        c.tshift = tshift;
+        c.lists = static_cast<uint64_t *>(ctx->clists.ptr);
+        c.levels = static_cast<uint32_t *>(ctx->clevels.ptr);
+        c.bits = lds_bits ? nullptr : static_cast<uint32_t *>(ctx->cbits.ptr);
         c.n = static_cast<uint32_t>(g.n);
         c.slots = static_cast<uint32_t>(slots);
         c.tree_begin = tree_begin;
@@ -260,6 +300,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         c.parents = parents;
         c.tree_visits = tree_visits;
         c.totals = &sm->totals;
+        c.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
     } else {
         // trees in flight: bounded by the tree count and by the state budget
         const size_t per_slot = sizeof(uint64_t) * static_cast<size_t>(g.n);
@@ -292,7 +333,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     if (use_coop)
-        FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, ctx->stream), "wilson_coop launch");
+        FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, word32, ctx->stream),
+               "wilson_coop launch");
     else
         FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
     FC_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
@@ -313,6 +355,15 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         stats->roots = tot.roots;
         stats->digest_sum = tot.digest_sum;
         stats->ms_sample = ms;
+        for (int i = 0; i < 8; ++i) stats->phase_ms[i] = 0.0;
+        if (use_coop && ctx->phase_timing) {
+            unsigned long long ticks[8];
+            FC_HIP(ctx, hipMemcpy(ticks, sm->phase_ticks, sizeof(ticks), hipMemcpyDeviceToHost),
+                   "copy phase ticks");
+            // per-workgroup average in milliseconds
+            for (int i = 0; i < 7; ++i)
+                stats->phase_ms[i] = static_cast<double>(ticks[i]) / ctx->wall_khz / static_cast<double>(slots);
+        }
     }
     return FC_OK;
 }
@@ -363,10 +414,18 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess &&
         cus > 0)
         ctx->cu_count = static_cast<uint32_t>(cus);
-    ctx->coop_threads = env_u32("FC_COOP_THREADS", 256);
+    int wclk = 0;
+    if (hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess &&
+        wclk > 0)
+        ctx->wall_khz = wclk;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) ==
+            hipSuccess && lds > 0)
+        ctx->max_lds = static_cast<size_t>(lds);
+    ctx->coop_threads = env_u32("FC_COOP_THREADS", 512);
     if (ctx->coop_threads < 64 || ctx->coop_threads > 1024 || ctx->coop_threads % 64)
         ctx->coop_threads = 256;
-    ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 4));
+    ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 2));
     {
         const char *fs = std::getenv("FC_SAMPLER");
         if (fs && !std::strcmp(fs, "lane")) ctx->force_sampler = 1;
@@ -382,7 +441,8 @@ int fc_destroy(fc_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->state, &ctx->vrec, &ctx->row_ptr, &ctx->col_idx, &ctx->small,
-                      &ctx->rtmp, &ctx->thr, &ctx->cword, &ctx->ckk, &ctx->clists})
+                      &ctx->rtmp, &ctx->thr, &ctx->cword, &ctx->ckk, &ctx->clists, &ctx->clevels,
+                      &ctx->cbits})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -393,6 +453,36 @@ int fc_destroy(fc_ctx *ctx) {
 int fc_set_stream(fc_ctx *ctx, void *hip_stream) {
     if (!ctx) return FC_ERR_ARG;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return FC_OK;
+}
+
+int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
+    if (!ctx || !key) return FC_ERR_ARG;
+    const std::string k(key);
+    if (k == "coop_threads") {
+        if (value < 64 || value > 1024 || value % 64) return set_err(ctx, FC_ERR_ARG, "coop_threads");
+        ctx->coop_threads = static_cast<uint32_t>(value);
+    } else if (k == "coop_wg_per_cu") {
+        if (value < 1 || value > 64) return set_err(ctx, FC_ERR_ARG, "coop_wg_per_cu");
+        ctx->coop_wg_per_cu = static_cast<uint32_t>(value);
+    } else if (k == "coop_lds_bits") {
+        if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_lds_bits");
+        ctx->coop_lds_bits = value == 1;
+    } else if (k == "coop_word32") {
+        if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_word32");
+        ctx->coop_word32 = value == 1;
+    } else if (k == "phase_timing") {
+        if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "phase_timing");
+        ctx->phase_timing = value == 1;
+    } else if (k == "lanes_per_wave") {
+        if (value < 1 || value > 64) return set_err(ctx, FC_ERR_ARG, "lanes_per_wave");
+        ctx->lanes_per_wave = static_cast<uint32_t>(value);
+    } else if (k == "max_slots") {
+        if (value < 0 || value > 0x7FFFFFFF) return set_err(ctx, FC_ERR_ARG, "max_slots");
+        ctx->max_slots = static_cast<uint32_t>(value);
+    } else {
+        return set_err(ctx, FC_ERR_ARG, "unknown option " + k);
+    }
     return FC_OK;
 }
 

@@ -18,9 +18,9 @@ hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
 hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
                                 unsigned int *err, hipStream_t stream);
 
-// Per-vertex records of G* for one alpha.
+// Per-vertex records of G* for one alpha; atomically maxes the degree into *dmax.
 hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
-                             hipStream_t stream);
+                             unsigned int *dmax, hipStream_t stream);
 
 // thr(d), d = 0..d_max, as the device computes it (uint64, 2^32 for "always").
 hipError_t launch_thresholds(double alpha, int32_t d_max, unsigned long long *out,
@@ -54,9 +54,12 @@ hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
 struct CoopArgs {
     const VRec *vrec;
     const int32_t *col_idx;
-    uint64_t *word;           // slots * n: arrow target | settled, in-degree counter
-    uint32_t *kk;             // slots * n: arrows drawn per vertex
-    uint32_t *lists;          // slots * (4n + 2): two unsettled lists, peel order, levels
+    void *word;               // slots * n words (u32 or u64): target | in-arrow count << tshift
+    uint64_t *kk;             // slots * n: (epoch << 32) | arrows drawn, for redrawn vertices
+    uint32_t tshift;          // bits of the target field (n < 2^tshift); 32 for u64 words
+    uint64_t *lists;          // slots * 3n: (vertex, target) pairs: two unsettled lists, peel order
+    uint32_t *levels;         // slots * (n + 2): peel level boundaries
+    uint32_t *bits;           // slots * ceil(n/32): settled bitmap when it is not kept in LDS
     uint32_t n;
     uint32_t slots;           // workgroups (trees in flight)
     uint32_t tree_begin;
@@ -73,8 +76,11 @@ struct CoopArgs {
     int32_t *parents;
     uint32_t *tree_visits;
     Totals *totals;
+    unsigned long long *phase_ticks;  // 7 wall-clock tick sums per phase, or null
 };
-hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, hipStream_t stream);
+hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool word32,
+                              hipStream_t stream);
+size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 
 // S = sum of R (exact, uint64) into *sum (caller zeroes it).
 hipError_t launch_sum_u32(const uint32_t *x, int32_t n, unsigned long long *sum,

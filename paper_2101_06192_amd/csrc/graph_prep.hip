@@ -64,11 +64,18 @@ __device__ __forceinline__ unsigned long long root_threshold(double alpha, uint3
 }
 
 __global__ void build_vrec_kernel(const int32_t *__restrict__ row_ptr, int32_t n, double alpha,
-                                  VRec *__restrict__ vrec) {
+                                  VRec *__restrict__ vrec, unsigned int *dmax) {
     const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    uint32_t d = 0;
+    int32_t a = 0;
+    if (v < n) {
+        a = row_ptr[v];
+        d = static_cast<uint32_t>(row_ptr[v + 1] - a);
+    }
+    uint32_t m = d;  // maximum degree: wave reduction, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) m = max(m, static_cast<uint32_t>(__shfl_down(m, off, 64)));
+    if ((threadIdx.x & 63u) == 0 && m) atomicMax(dmax, m);
     if (v >= n) return;
-    const int32_t a = row_ptr[v];
-    const uint32_t d = static_cast<uint32_t>(row_ptr[v + 1] - a);
     const unsigned long long t = root_threshold(alpha, d);
     VRec r;
     r.start = a;
@@ -105,9 +112,9 @@ hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, 
 }
 
 hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
-                             hipStream_t stream) {
+                             unsigned int *dmax, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    build_vrec_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, n, alpha, vrec);
+    build_vrec_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, n, alpha, vrec, dmax);
     return hipGetLastError();
 }
 

@@ -21,33 +21,35 @@
 //
 // One workgroup owns one tree at a time (tree ids come from a device
 // queue); all phase changes are workgroup barriers, with no spin-waits.
-// Per-slot device memory, n vertices:
-//   word[v] (u64)  low 32: arrow target (u* = n) | settled << 31
-//                  high 32: in-degree counter of the current round
-//   kk[v]   (u32)  arrows drawn at v (k_v)
-//   lists   (u32)  two unsettled lists (double buffer), the peel order and
-//                  the peel level boundaries.
+//
+// Memory per tree (slot), n vertices:
+//   word[v]  u32 or u64    arrow target (u* = n) in the low `tshift` bits,
+//            global        in-arrow count of the current round above it; a
+//                          32-bit word when ceil(log2(n+1)) + ceil(log2(dmax+1))
+//                          fits (the count never exceeds the degree)
+//   kk[v]    u64  global   (epoch << 32) | k_v, written only when v draws a
+//                          second arrow; a stale epoch means k_v = 1
+//   lists    u64  global   (vertex, target) pairs: two unsettled lists
+//                          (double buffer) and the peel order; plus the peel
+//                          level boundaries (u32)
+//   settled  bit  LDS      one bit per vertex when n/8 bytes fit the LDS
+//                          budget, else a per-slot global bitmap
 #include "fc_kernels.hpp"
 
 namespace fc {
 
 namespace {
 
-constexpr uint32_t kSettled = 0x80000000u;
-constexpr uint64_t kCntOne = 1ull << 32;
-
-__device__ __forceinline__ uint32_t target_of(uint64_t w) {
-    return static_cast<uint32_t>(w) & 0x7FFFFFFFu;
+__device__ __forceinline__ uint32_t lo32(uint64_t w) { return static_cast<uint32_t>(w); }
+__device__ __forceinline__ uint32_t hi32(uint64_t w) { return static_cast<uint32_t>(w >> 32); }
+__device__ __forceinline__ uint64_t pair(uint32_t v, uint32_t tg) {
+    return static_cast<uint64_t>(v) | (static_cast<uint64_t>(tg) << 32);
 }
-__device__ __forceinline__ bool settled_of(uint64_t w) {
-    return (static_cast<uint32_t>(w) & kSettled) != 0;
-}
-__device__ __forceinline__ uint32_t cnt_of(uint64_t w) { return static_cast<uint32_t>(w >> 32); }
 
-// Wave-aggregated append of `v` to `list` when `pred` holds: one LDS atomic
-// per wave.  Must be reached by every lane of the wave (uniform control flow).
-__device__ __forceinline__ void wave_append(uint32_t *__restrict__ list, uint32_t *tail,
-                                            uint32_t v, bool pred) {
+// Wave-aggregated append of `item` to `list` when `pred` holds: one LDS
+// atomic per wave.  Every lane of the wave must reach it (uniform control).
+__device__ __forceinline__ void wave_append(uint64_t *__restrict__ list, uint32_t *tail,
+                                            uint64_t item, bool pred) {
     const uint64_t mask = __ballot(pred);
     if (mask == 0) return;
     const uint32_t lane = __lane_id();
@@ -57,9 +59,23 @@ __device__ __forceinline__ void wave_append(uint32_t *__restrict__ list, uint32_
     base = __shfl(base, leader, 64);
     if (pred) {
         const uint32_t off = static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
-        list[base + off] = v;
+        list[base + off] = item;
     }
 }
+
+// The per-tree arrays belong to one workgroup for the whole launch, so their
+// atomics only need workgroup scope (no cross-XCD coherence).
+template <typename W>
+__device__ __forceinline__ W wg_fetch_add(W *p, W v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wg_fetch_or(uint32_t *p, uint32_t v) {
+    (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Per-phase wall-clock accounting (tid 0 of each workgroup), when requested.
+enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedraw, kPhOutput,
+                   kPhCount };
 
 // One arrow of v in tree t with draw index k.
 __device__ __forceinline__ uint32_t draw(const CoopArgs &a, uint32_t v, uint32_t k, uint32_t t) {
@@ -68,9 +84,11 @@ __device__ __forceinline__ uint32_t draw(const CoopArgs &a, uint32_t v, uint32_t
     return arrow_target(r, x.x0, x.x1, a.col_idx, a.n);
 }
 
+template <bool kLdsBits, typename W>
 __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
+    extern __shared__ uint32_t s_dyn[];
     __shared__ uint32_t s_tree, s_u, s_p, s_cycles;
-    __shared__ unsigned long long s_steps, s_digest, s_roots;
+    __shared__ unsigned long long s_digest, s_roots;
 
     const uint32_t n = a.n;
     const uint32_t T = blockDim.x;
@@ -78,13 +96,36 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
     const uint32_t wave_base = tid & ~63u;
     const uint32_t lane = tid & 63u;
     const size_t slot = blockIdx.x;
-    uint64_t *__restrict__ word = a.word + slot * n;
-    uint32_t *__restrict__ kk = a.kk + slot * n;
-    uint32_t *__restrict__ listA = a.lists + slot * (4ull * n + 2);
-    uint32_t *__restrict__ listB = listA + n;
-    uint32_t *__restrict__ peel = listB + n;
-    uint32_t *__restrict__ lvl = peel + n;  // n + 2 entries
+    const uint32_t nwords = (n + 31u) >> 5;
+    const uint32_t tshift = a.tshift;
+    const W tmask = (static_cast<W>(1) << tshift) - static_cast<W>(1);
+    const W cnt_one = static_cast<W>(1) << tshift;
+    const W cnt_minus_one = static_cast<W>(0) - cnt_one;
+    W *__restrict__ word = static_cast<W *>(a.word) + slot * n;
+    uint64_t *__restrict__ kk = a.kk + slot * n;
+    uint64_t *__restrict__ listA = a.lists + slot * (3ull * n);
+    uint64_t *__restrict__ listB = listA + n;
+    uint64_t *__restrict__ peel = listB + n;
+    uint32_t *__restrict__ lvl = a.levels + slot * (static_cast<size_t>(n) + 2);
+    uint32_t *__restrict__ bits = kLdsBits ? s_dyn : a.bits + slot * nwords;
     unsigned int err = 0;
+    uint32_t epoch = 0;  // per-slot tree sequence number of this launch (kk was zeroed)
+
+    auto target_of = [&](W w) -> uint32_t { return static_cast<uint32_t>(w & tmask); };
+    auto cnt_of = [&](W w) -> uint32_t { return static_cast<uint32_t>(w >> tshift); };
+    auto is_settled = [&](uint32_t v) -> bool {
+        return v >= n || ((bits[v >> 5] >> (v & 31u)) & 1u);
+    };
+    auto set_settled = [&](uint32_t v) { wg_fetch_or(&bits[v >> 5], 1u << (v & 31u)); };
+    unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned long long ph_t = a.phase_ticks ? wall_clock64() : 0ull;
+    auto mark = [&](int which) {
+        if (a.phase_ticks && tid == 0) {
+            const unsigned long long now = wall_clock64();
+            ph[which] += now - ph_t;
+            ph_t = now;
+        }
+    };
 
     for (;;) {
         __syncthreads();
@@ -93,13 +134,14 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
         const uint32_t ti = s_tree;
         if (ti >= a.tree_count) break;
         const uint32_t t = a.tree_begin + ti;
+        ++epoch;
         if (tid == 0) {
             s_u = 0;
             s_p = 0;
-            s_steps = 0;
             s_digest = 0;
             s_roots = 0;
         }
+        for (uint32_t i = tid; i < nwords; i += T) bits[i] = 0u;
         __syncthreads();
 
         // round 0: the first arrow of every vertex
@@ -108,14 +150,15 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             uint32_t tg = n;
             if (v < n) {
                 tg = draw(a, v, 0u, t);
-                word[v] = static_cast<uint64_t>(tg | (tg == n ? kSettled : 0u));
-                kk[v] = 1u;
+                word[v] = static_cast<W>(tg);
+                if (tg == n) set_settled(v);
             }
-            wave_append(listA, &s_u, v, v < n && tg != n);
+            wave_append(listA, &s_u, pair(v, tg), v < n && tg != n);
         }
         __syncthreads();
+        mark(kPhDraw0);
         uint32_t ucount = s_u;
-        uint32_t *U = listA, *Unext = listB;
+        uint64_t *U = listA, *Unext = listB;
         unsigned long long draws = n;
         uint32_t rounds = 0;
 
@@ -124,44 +167,60 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
                 err |= kErrStepCap;
                 break;
             }
-            // in-degree of each unsettled vertex from arrows of unsettled vertices
+            // in-arrows of unsettled targets from unsettled vertices (no return value:
+            // the atomics do not stall the thread)
             for (uint32_t i = tid; i < ucount; i += T) {
-                const uint32_t v = U[i];
-                const uint32_t tg = target_of(word[v]);
-                if (tg != n && !settled_of(word[tg])) atomicAdd(&word[tg], kCntOne);
+                const uint32_t tg = hi32(U[i]);
+                if (!is_settled(tg)) (void)wg_fetch_add(&word[tg], cnt_one);
             }
             if (tid == 0) s_p = 0;  // last read of s_p was followed by barriers
             __syncthreads();
-            // level 0 of the peel: in-degree zero
-            for (uint32_t base = wave_base; base < ucount; base += T) {
-                const uint32_t i = base + lane;
-                uint32_t v = 0;
-                bool leaf = false;
-                if (i < ucount) {
-                    v = U[i];
-                    leaf = cnt_of(word[v]) == 0u;
+            mark(kPhIndeg);
+            // level 0 of the peel: no in-arrows
+            for (uint32_t base = wave_base; base < ucount; base += 4 * T) {
+                uint64_t it[4];
+                bool leaf[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t i = base + q * T + lane;
+                    it[q] = i < ucount ? U[i] : 0ull;
+                    leaf[q] = false;
                 }
-                wave_append(peel, &s_p, v, leaf);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t i = base + q * T + lane;
+                    if (i < ucount) leaf[q] = cnt_of(word[lo32(it[q])]) == 0u;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wave_append(peel, &s_p, it[q], leaf[q]);
             }
             __syncthreads();
+            mark(kPhLevel0);
             uint32_t lo = 0, hi = s_p, nlev = 0;
             if (tid == 0) lvl[0] = 0;
-            // peel level by level; the arrow target of a peeled vertex loses one in-arrow
+            // peel level by level: a peeled vertex's target loses one in-arrow; the
+            // atomic returns the target's own arrow, which goes into the list with it
             while (lo < hi) {
                 if (tid == 0) lvl[nlev + 1] = hi;
-                for (uint32_t base = lo + wave_base; base < hi; base += T) {
-                    const uint32_t i = base + lane;
-                    uint32_t tg = 0;
-                    bool push = false;
-                    if (i < hi) {
-                        const uint32_t v = peel[i];
-                        tg = target_of(word[v]);
-                        if (tg != n && !settled_of(word[tg])) {
-                            const uint64_t old = atomicAdd(&word[tg], ~kCntOne + 1ull);  // -1 in the high half
-                            push = cnt_of(old) == 1u;
-                        }
+                for (uint32_t base = lo + wave_base; base < hi; base += 4 * T) {
+                    uint32_t tg[4];
+                    W old[4];
+                    bool push[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t i = base + q * T + lane;
+                        tg[q] = i < hi ? hi32(peel[i]) : n;
+                        push[q] = false;
+                        old[q] = 0;
                     }
-                    wave_append(peel, &s_p, tg, push);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (!is_settled(tg[q])) old[q] = wg_fetch_add(&word[tg[q]], cnt_minus_one);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) push[q] = !is_settled(tg[q]) && cnt_of(old[q]) == 1u;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        wave_append(peel, &s_p, pair(tg[q], target_of(old[q])), push[q]);
                 }
                 __syncthreads();
                 ++nlev;
@@ -170,103 +229,142 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
                 __syncthreads();  // every wave has read s_p before the next level appends
             }
             const uint32_t peeled = hi;
-            // reverse sweep: a vertex is settled when its arrow reaches u* or a settled vertex
+            mark(kPhPeel);
+            // reverse sweep: settled when the arrow reaches u* or a settled vertex
             for (int32_t L = static_cast<int32_t>(nlev) - 1; L >= 0; --L) {
                 const uint32_t a0 = lvl[L], a1 = lvl[L + 1];
                 for (uint32_t i = a0 + tid; i < a1; i += T) {
-                    const uint32_t v = peel[i];
-                    const uint32_t tg = target_of(word[v]);
-                    if (tg == n || settled_of(word[tg]))
-                        word[v] = static_cast<uint64_t>(tg | kSettled);
+                    const uint64_t p = peel[i];
+                    if (is_settled(hi32(p))) set_settled(lo32(p));
                 }
                 __syncthreads();
             }
+            mark(kPhSweep);
             if (peeled == ucount) {  // no cycle left: every vertex is settled
                 ucount = 0;
                 break;
             }
-            // pop every cycle: vertices that kept in-arrows draw their next arrow
+            // pop every cycle: unsettled vertices that kept in-arrows draw again
             if (tid == 0) {  // last reads of s_u / s_cycles were followed by barriers
                 s_u = 0;
                 s_cycles = 0;
             }
             __syncthreads();
             uint32_t my_cycles = 0;
-            for (uint32_t base = wave_base; base < ucount; base += T) {
-                const uint32_t i = base + lane;
-                uint32_t v = 0;
-                bool keep = false;
-                if (i < ucount) {
-                    v = U[i];
-                    const uint64_t w = word[v];
-                    if (cnt_of(w) > 0u) {
-                        const uint32_t k = kk[v];
+            for (uint32_t base = wave_base; base < ucount; base += 4 * T) {
+                uint64_t it[4];
+                W w[4];
+                bool keep[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t i = base + q * T + lane;
+                    it[q] = i < ucount ? U[i] : pair(n, n);
+                    keep[q] = false;
+                    w[q] = 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (!is_settled(lo32(it[q]))) w[q] = word[lo32(it[q])];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t v = lo32(it[q]);
+                    if (is_settled(v)) continue;
+                    if (cnt_of(w[q]) > 0u) {  // on a cycle
+                        const uint64_t kv = kk[v];
+                        const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
                         const uint32_t tg = draw(a, v, k, t);
                         if (k + 1u > 0x7FFFFFFFu) err |= kErrVisitOverflow;
-                        kk[v] = k + 1u;
-                        word[v] = static_cast<uint64_t>(tg | (tg == n ? kSettled : 0u));
-                        keep = tg != n;
+                        kk[v] = (static_cast<uint64_t>(epoch) << 32) | (k + 1u);
+                        word[v] = static_cast<W>(tg);
+                        it[q] = pair(v, tg);
+                        if (tg == n) set_settled(v);
+                        else keep[q] = true;
                         ++my_cycles;
-                    } else {
-                        keep = !settled_of(w);
+                    } else {  // hanging off a cycle: keeps its arrow, stays unsettled
+                        keep[q] = true;
                     }
                 }
-                wave_append(Unext, &s_u, v, keep);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wave_append(Unext, &s_u, it[q], keep[q]);
             }
             if (my_cycles) atomicAdd(&s_cycles, my_cycles);
             __syncthreads();
+            mark(kPhRedraw);
             draws += s_cycles;
             ucount = s_u;
-            uint32_t *tmp = U;
+            uint64_t *tmp = U;
             U = Unext;
             Unext = tmp;
         }
         __syncthreads();
         if (err & kErrStepCap) break;  // the call fails; stop this workgroup
 
-        // the tree: top arrows; R, digest, steps, optional per-tree dumps
-        unsigned long long my_steps = 0, my_digest = 0, my_roots = 0;
+        // the tree: top arrows; R, digest, optional per-tree dumps
+        unsigned long long my_digest = 0, my_roots = 0;
+        const bool want_k = a.visit_counts || a.tree_visits;
         for (uint32_t v = tid; v < n; v += T) {
             const uint32_t tg = target_of(word[v]);
-            const uint32_t k = kk[v];
-            my_steps += k;
             my_digest += mix64((static_cast<unsigned long long>(v) << 32) | tg);
             if (tg == n) {
                 ++my_roots;
                 atomicAdd(&a.root_counts[v], 1u);
             }
-            if (a.visit_counts) atomicAdd(&a.visit_counts[v], static_cast<unsigned long long>(k));
             if (a.parents) a.parents[static_cast<size_t>(ti) * n + v] = static_cast<int32_t>(tg);
-            if (a.tree_visits) a.tree_visits[static_cast<size_t>(ti) * n + v] = k;
+            if (want_k) {
+                const uint64_t kv = kk[v];
+                const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
+                if (a.visit_counts) atomicAdd(&a.visit_counts[v], static_cast<unsigned long long>(k));
+                if (a.tree_visits) a.tree_visits[static_cast<size_t>(ti) * n + v] = k;
+            }
         }
         for (int off = 32; off > 0; off >>= 1) {
-            my_steps += __shfl_down(my_steps, off, 64);
             my_digest += __shfl_down(my_digest, off, 64);
             my_roots += __shfl_down(my_roots, off, 64);
         }
         if (lane == 0) {
-            atomicAdd(&s_steps, my_steps);
             atomicAdd(&s_digest, my_digest);
             atomicAdd(&s_roots, my_roots);
         }
         __syncthreads();
         if (tid == 0) {
             if (a.tree_digests) a.tree_digests[ti] = s_digest;
-            if (a.tree_steps) a.tree_steps[ti] = s_steps;
-            atomicAdd(&a.totals->walk_steps, s_steps);
+            if (a.tree_steps) a.tree_steps[ti] = draws;
+            atomicAdd(&a.totals->walk_steps, draws);
             atomicAdd(&a.totals->roots, s_roots);
             atomicAdd(&a.totals->digest_sum, s_digest);
         }
+        mark(kPhOutput);
     }
+    if (a.phase_ticks && tid == 0)
+        for (int i = 0; i < kPhCount; ++i) atomicAdd(&a.phase_ticks[i], ph[i]);
     if (err) atomicOr(&a.totals->error, err);
 }
 
 }  // namespace
 
-hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, hipStream_t stream) {
-    if (a.n == 0 || a.tree_count == 0 || a.slots == 0) return hipSuccess;
-    wilson_coop_kernel<<<a.slots, threads, 0, stream>>>(a);
+size_t coop_lds_bytes(uint32_t n) { return 4u * ((static_cast<size_t>(n) + 31u) >> 5); }
+
+template <bool kLds, typename W>
+hipError_t launch_one(const CoopArgs &a, uint32_t threads, hipStream_t stream) {
+    const size_t lds = kLds ? coop_lds_bytes(a.n) : 0;
+    if (kLds) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_coop_kernel<kLds, W>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    wilson_coop_kernel<kLds, W><<<a.slots, threads, lds, stream>>>(a);
     return hipGetLastError();
+}
+
+hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool word32,
+                              hipStream_t stream) {
+    if (a.n == 0 || a.tree_count == 0 || a.slots == 0) return hipSuccess;
+    if (lds_bits)
+        return word32 ? launch_one<true, uint32_t>(a, threads, stream)
+                      : launch_one<true, unsigned long long>(a, threads, stream);
+    return word32 ? launch_one<false, uint32_t>(a, threads, stream)
+                  : launch_one<false, unsigned long long>(a, threads, stream);
 }
 
 }  // namespace fc

@@ -69,6 +69,7 @@ def test_null_context_arguments():
     assert L.fc_create(None, 0, None) == fc.FC_ERR_ARG
     assert L.fc_destroy(None) == fc.FC_OK
     assert L.fc_set_stream(None, None) == fc.FC_ERR_ARG
+    assert L.fc_set_option(None, b"coop_threads", 256) == fc.FC_ERR_ARG
     st = fc.fc_stats()
     gs = fc.fc_graph(1, 0, ctypes.c_void_p(1), None, 0)
     ps = fc.fc_params(1.0, 0.1, 0.1, 0.0, 0, 1, 0, 0, 0)
@@ -93,4 +94,4 @@ def test_struct_layouts():
     assert fc.fc_graph.nnz.offset == 8 and fc.fc_graph.mem.offset == 32
     assert ctypes.sizeof(fc.fc_params) == 56
     assert fc.fc_params.seed.offset == 32 and fc.fc_params.flags.offset == 52
-    assert ctypes.sizeof(fc.fc_stats) == 64
+    assert ctypes.sizeof(fc.fc_stats) == 128

@@ -189,6 +189,37 @@ def test_grid_tree_subset_bit_exact(gpu_lib, alpha, sampler):
     _compare(gpu_lib, g, alpha, 0, 100, 6, sampler=sampler)
 
 
+@pytest.mark.parametrize("shape", [(64, 1, 1, 1), (256, 3, 0, 1), (1024, 1, 1, 0), (512, 2, 0, 0)])
+def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
+    """Workgroup sampler under other launch shapes, with the settled bitmap
+    in LDS and in global memory, 32- and 64-bit tree words: identical results."""
+    fc = gpu_lib
+    threads, wg, lds, w32 = shape
+    fc.set_option("coop_threads", threads)
+    fc.set_option("coop_wg_per_cu", wg)
+    fc.set_option("coop_lds_bits", lds)
+    fc.set_option("coop_word32", w32)
+    try:
+        g = inputs.barabasi_albert(20_000, 3, 7)
+        _compare(fc, g, 1.5, 77, 9, 40, sampler="coop")
+        g2 = inputs.grid_removed(120, 90, 0.12, 3)
+        _compare(fc, g2, 2.0, 78, 0, 20, sampler="coop")
+    finally:
+        fc.set_option("coop_threads", 512)
+        fc.set_option("coop_wg_per_cu", 2)
+        fc.set_option("coop_lds_bits", 1)
+        fc.set_option("coop_word32", 1)
+
+
+def test_set_option_rejects_bad_values(gpu_lib):
+    fc = gpu_lib
+    for key, val in (("coop_threads", 100), ("coop_threads", 2048), ("coop_wg_per_cu", 0),
+                     ("lanes_per_wave", 65), ("nonsense", 1), ("coop_lds_bits", 2)):
+        with pytest.raises(fc.FCError) as e:
+            fc.set_option(key, val)
+        assert e.value.code == fc.FC_ERR_ARG
+
+
 @pytest.mark.parametrize("sampler", SAMPLERS)
 def test_rmat_heavy_tail_bit_exact(gpu_lib, sampler):
     """R-MAT (2^15 vertices, edge factor 8) at alpha = 10 and 0.1: hubs,
