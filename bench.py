@@ -80,6 +80,9 @@ def main():
                     help="trees the CPU oracle samples for the baseline (0 = skip)")
     ap.add_argument("--no-eps", action="store_true", help="skip the time-to-eps=0.1 leg")
     ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop"])
+    ap.add_argument("--config", default="ba200k",
+                    choices=["ba200k", "er1000", "grid1000", "rmat_batch", "rmat22"],
+                    help="workload; the default is the headline configuration")
     ap.add_argument("--phase-timing", action="store_true",
                     help="report per-phase times of the workgroup sampler (adds clock reads)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -108,6 +111,9 @@ def main():
     from paper_2101_06192_amd import inputs
 
     dev = torch.device("cuda:0")
+    if args.config != "ba200k":
+        other_config(args, fc, inputs, dev)
+        return
     g = inputs.barabasi_albert(WORKLOAD["n"], WORKLOAD["m_per_vertex"], WORKLOAD["seed"])
     dg = fc.to_device(g, dev)
     trees = WORKLOAD["trees"]
@@ -184,6 +190,98 @@ def main():
                  "output"]
         line["phase_ms_per_workgroup"] = dict(zip(names, stats[-1]["phase_ms"]))
     print(json.dumps(line), flush=True)
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def other_config(args, fc, inputs, dev):
+    """The non-headline workloads (same sampler, other graph families)."""
+    import numpy as np
+    res = {"metric": "trees/s", "n_gpus": 1, "data": "synthetic", "dtype": "u32",
+           "higher_is_better": True, "steps": args.steps, "warmup": args.warmup}
+    if args.config in ("er1000", "rmat22"):
+        if args.config == "er1000":
+            g, alpha, trees, name = inputs.erdos_renyi(1000, 0.01, 0), 1.0, 2000, "er_n1000_p0.01_trees2000"
+        else:
+            g, alpha, trees, name = inputs.rmat(1 << 22, 8, 0), 1.0, 1024, "rmat_n4194304_ef8_trees1024"
+        dg = fc.to_device(g, dev)
+        per = {}
+        samplers = ["lane", "coop"] if args.config == "er1000" else ["coop"]
+        for smp in samplers:
+            dt, out = _timed(lambda: fc.farness(dg, alpha=alpha, tau=trees, device=dev, as_torch=True,
+                                                sampler=smp), args.steps, args.warmup)
+            per[smp] = {"trees_per_s": trees / dt, "ms_per_step": 1000 * dt,
+                        "walk_steps_per_s": out["stats"]["walk_steps"] / dt,
+                        "kernel_ms": out["stats"]["ms_sample"]}
+        best = max(per, key=lambda k: per[k]["trees_per_s"])
+        res.update({"value": per[best]["trees_per_s"], "unit": "trees/s",
+                    "config": {"workload": name, "n": g.n, "m": g.m, "alpha": alpha, "trees": trees},
+                    "samplers": per})
+        if args.config == "rmat22":
+            te = time.perf_counter()
+            o = fc.diag_estimate(dg, alpha=alpha, eps=0.1, delta=0.1, device=dev, as_torch=True)
+            import torch
+            torch.cuda.synchronize()
+            res["time_to_eps0.1_diag"] = {"tau": o["tau"], "ms": 1000 * (time.perf_counter() - te)}
+    elif args.config == "grid1000":
+        g = inputs.grid_removed(1000, 1000, 0.12, 0)
+        dg = fc.to_device(g, dev)
+        per = {}
+        total_dt = 0.0
+        for alpha in (0.5, 1.0, 2.0):
+            dt, out = _timed(lambda: fc.farness(dg, alpha=alpha, tau=1024, device=dev, as_torch=True,
+                                                sampler=args.sampler), args.steps, args.warmup)
+            total_dt += dt
+            per[str(alpha)] = {"trees_per_s": 1024 / dt, "walk_steps_per_tree": out["stats"]["walk_steps"] / 1024,
+                               "kernel_ms": out["stats"]["ms_sample"], "sampler": out["stats"]["sampler"]}
+        res.update({"value": 3 * 1024 / total_dt, "unit": "trees/s",
+                    "config": {"workload": "grid_1000x1000_rm0.12_alpha0.5_1_2_trees1024", "n": g.n,
+                               "m": g.m}, "per_alpha": per})
+    elif args.config == "rmat_batch":
+        t0 = time.perf_counter()
+        gs = inputs.rmat_batch(256, 8, 0)
+        gen_s = time.perf_counter() - t0
+        dgs = [fc.to_device(g, dev) for g in gs]
+        alphas = (0.1, 1.0, 10.0)
+        jobs = [{"graph": dg, "alpha": a, "stream_id": gi * 3 + ai, "tree_count": 512}
+                for gi, dg in enumerate(dgs) for ai, a in enumerate(alphas)]
+        ntrees = len(jobs) * 512
+        t0 = time.perf_counter()
+        b = fc.Batch(jobs, seed=0, trusted=False, autotune=True)
+        create_s = time.perf_counter() - t0
+
+        def run_batch():
+            b.reset()
+            return b.run()
+        dt, st = _timed(run_batch, args.steps, args.warmup)
+
+        def per_job():
+            for j in jobs:
+                fc.sample(j["graph"], alpha=j["alpha"], seed=0, tree_count=512,
+                          stream_id=j["stream_id"], device=dev, as_torch=True, trusted=True)
+        dt_single, _ = _timed(per_job, 1, 0)
+        res.update({"value": ntrees / dt, "unit": "trees/s",
+                    "config": {"workload": "rmat_batch_256graphs_alpha0.1_1_10_trees512",
+                               "graphs": len(gs), "sum_n": int(sum(g.n for g in gs)),
+                               "sum_m": int(sum(g.m for g in gs)), "jobs": len(jobs), "trees": ntrees},
+                    "batched": {"ms_per_run": 1000 * dt, "kernel_ms": st["ms_sample"],
+                                "launch_shape": st["sampler"], "walk_steps_per_s": st["walk_steps"] / dt,
+                                "create_s": create_s},
+                    "per_job_launches": {"ms_total": 1000 * dt_single, "trees_per_s": ntrees / dt_single},
+                    "generation_s": gen_s})
+        b.close()
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -76,8 +76,9 @@ extern "C" {
 #define FC_EST_DIRECT 0        /* Omega_vv ~ R[v] / tau */
 #define FC_EST_ALG1_LITERAL 1  /* R[v] / tau - (n+2)/(n+1)^2, see fc_diag_estimate */
 
-/* fc_params.flags */
+/* fc_params.flags (and fc_batch_create flags) */
 #define FC_FLAG_TRUSTED_GRAPH 1 /* skip the device-side CSR validation */
+#define FC_FLAG_AUTOTUNE 8      /* fc_batch_create: time candidate launch shapes, keep the fastest */
 #define FC_FLAG_SAMPLER_LANE 2  /* force the lane-per-tree sampler */
 #define FC_FLAG_SAMPLER_COOP 4  /* force the workgroup-per-tree sampler */
 /* Neither sampler flag: the library picks one from n and the tree count.
@@ -121,7 +122,7 @@ typedef struct {
     uint64_t digest_sum;     /* sum over trees of the per-tree digest, mod 2^64 */
     double ms_sample;        /* device time of the sampling kernel */
     double ms_total;         /* host wall time of the call */
-    char sampler[16];        /* "wilson_lane" or "wilson_coop" */
+    char sampler[16];        /* "wilson_lane", "wilson_coop", or "batch:<threads>x<wg per CU>" */
     double phase_ms[8];      /* workgroup sampler with option "phase_timing": average
                                 milliseconds per workgroup spent in: first arrows,
                                 in-arrow counting, peel level 0, peel levels, reverse
@@ -197,6 +198,44 @@ FC_API int fc_diag_estimate(fc_ctx *ctx, const fc_graph *g, const fc_params *par
 FC_API int fc_farness(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
                       double *farness_out, double *closeness_out, double *diag_out,
                       uint32_t *root_counts_out, fc_stats *stats);
+
+/* ---------------------------------------------------------------------- */
+/* Batches: many (graph, alpha, tree range) jobs sampled by one persistent  */
+/* launch.  Each job is Algorithm 3 applied tree_count times to its own G*  */
+/* (Section 4.1 with that job's alpha); the jobs share nothing but the      */
+/* launch.  A job's results are identical to fc_sample on the same graph,  */
+/* alpha, seed, stream_id and tree range.                                   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    fc_graph graph;         /* mem must be FC_MEM_DEVICE */
+    double alpha;           /* > 0 */
+    uint32_t stream_id;     /* Philox counter word 3 of this job's trees */
+    uint32_t tree_begin;    /* first tree id */
+    uint32_t tree_count;    /* number of trees */
+    uint32_t pad;
+    uint32_t *root_counts;  /* device uint32[n]: R[v] += ..., accumulated (caller zeroes) */
+    uint64_t *tree_digests; /* device uint64[tree_count] (as in fc_sample) or NULL */
+} fc_job;
+
+typedef struct fc_batch fc_batch;
+
+/* Prepare a batch of n_jobs jobs under one Philox key (seed): validates every
+ * distinct graph (unless FC_FLAG_TRUSTED_GRAPH), builds each job's vertex
+ * records of G*, orders the work items (trees) largest graph first, sizes
+ * the per-slot scratch for the largest graph, optionally autotunes the
+ * launch shape (FC_FLAG_AUTOTUNE; results do not depend on it) and captures
+ * the sampling launch as a HIP graph.  The job array is copied; the graphs
+ * and output buffers it points to must stay valid until fc_batch_destroy.
+ * Returns FC_ERR_ARG for a job with a host graph, alpha <= 0, a NULL
+ * root_counts, or more than 2^32 - 1 trees in total. */
+FC_API int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t seed,
+                           int32_t flags, fc_batch **out);
+/* Sample every tree of every job (one replay of the captured launch on the
+ * context's stream) and accumulate into the jobs' root_counts; writes
+ * tree_digests where given.  stats: totals over the batch; ms_sample is the
+ * device time of the launch. */
+FC_API int fc_batch_run(fc_batch *batch, fc_stats *stats);
+FC_API int fc_batch_destroy(fc_batch *batch);
 
 /* Message for an error code / for the last failing call on a context. */
 FC_API const char *fc_error_string(int code);

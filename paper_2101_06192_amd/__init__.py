@@ -74,6 +74,15 @@ class fc_stats(ctypes.Structure):
         return d
 
 
+class fc_job(ctypes.Structure):
+    _fields_ = [("graph", fc_graph), ("alpha", ctypes.c_double), ("stream_id", ctypes.c_uint32),
+                ("tree_begin", ctypes.c_uint32), ("tree_count", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("root_counts", ctypes.c_void_p),
+                ("tree_digests", ctypes.c_void_p)]
+
+
+FC_FLAG_AUTOTUNE = 8
+
 _lib = None
 
 
@@ -98,6 +107,10 @@ def lib() -> ctypes.CDLL:
             "fc_sample": (ctypes.c_int, [vp, gp, pp, u32, u32, vp, vp, vp, vp, vp, vp, sp]),
             "fc_diag_estimate": (ctypes.c_int, [vp, gp, pp, vp, vp, sp]),
             "fc_farness": (ctypes.c_int, [vp, gp, pp, vp, vp, vp, vp, sp]),
+            "fc_batch_create": (ctypes.c_int, [vp, ctypes.POINTER(fc_job), i32, ctypes.c_uint64,
+                                               i32, ctypes.POINTER(vp)]),
+            "fc_batch_run": (ctypes.c_int, [vp, sp]),
+            "fc_batch_destroy": (ctypes.c_int, [vp]),
             "fc_error_string": (ctypes.c_char_p, [ctypes.c_int]),
             "fc_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -332,3 +345,65 @@ def farness(g, alpha: float = 1.0, eps: float = 0.1, delta: float = 0.1, seed: i
     """Forest farness and closeness of every vertex (fc_farness)."""
     return _estimate("farness", g, alpha, eps, delta, seed, kappa, tau, literal, device, trusted,
                      as_torch, stream_id, sampler)
+
+
+class Batch:
+    """Many (graph, alpha, tree range) jobs sampled by one persistent launch
+    (fc_batch_create / fc_batch_run).  ``jobs`` is a list of dicts with keys
+    graph (a DeviceGraph), alpha, tree_count, and optionally stream_id,
+    tree_begin and digests (bool).  Each job's root counts accumulate in a
+    device tensor (``self.root_counts[i]``); ``reset()`` zeroes them."""
+
+    def __init__(self, jobs, seed: int = 0, device="cuda:0", trusted: bool = False,
+                 autotune: bool = False):
+        import torch
+        self.ctx = context(device)
+        dev = self.ctx.device
+        self.graphs = [j["graph"] for j in jobs]
+        for g in self.graphs:
+            if not isinstance(g, DeviceGraph):
+                raise TypeError("batch jobs need device graphs (to_device)")
+        self.root_counts = [torch.zeros(max(j["graph"].n, 1), dtype=torch.int32, device=dev)
+                            for j in jobs]
+        self.digests = [torch.zeros(max(j["tree_count"], 1), dtype=torch.int64, device=dev)
+                        if j.get("digests") else None for j in jobs]
+        arr = (fc_job * max(len(jobs), 1))()
+        for i, j in enumerate(jobs):
+            arr[i] = fc_job(_graph_struct(j["graph"]), float(j["alpha"]), int(j.get("stream_id", 0)),
+                            int(j.get("tree_begin", 0)), int(j["tree_count"]), 0,
+                            ctypes.c_void_p(self.root_counts[i].data_ptr()),
+                            _ptr(self.digests[i]))
+        flags = (FC_FLAG_TRUSTED_GRAPH if trusted else 0) | (FC_FLAG_AUTOTUNE if autotune else 0)
+        h = ctypes.c_void_p()
+        self.ctx.check(lib().fc_batch_create(self.ctx.handle, arr, len(jobs), int(seed), flags,
+                                             ctypes.byref(h)))
+        self.handle = h
+        self.n_jobs = len(jobs)
+
+    def run(self) -> dict:
+        self.ctx.sync_stream()
+        st = fc_stats()
+        self.ctx.check(lib().fc_batch_run(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset(self):
+        for r in self.root_counts:
+            r.zero_()
+
+    def result(self, i: int) -> dict:
+        n = self.graphs[i].n
+        out = {"root_counts": self.root_counts[i][:n].cpu().numpy().view(np.uint32)}
+        if self.digests[i] is not None:
+            out["tree_digests"] = self.digests[i].cpu().numpy().view(np.uint64)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

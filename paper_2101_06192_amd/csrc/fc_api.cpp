@@ -16,54 +16,16 @@
 #include <cstring>
 #include <string>
 
-#include "fc_kernels.hpp"
+#include "fc_internal.hpp"
 
 #pragma STDC FP_CONTRACT OFF
 
 static_assert(sizeof(fc_graph) == 40, "fc_graph layout");
 static_assert(sizeof(fc_params) == 56, "fc_params layout");
 static_assert(sizeof(fc_stats) == 128, "fc_stats layout");
+static_assert(sizeof(fc_job) == 80, "fc_job layout");
 
-namespace {
-
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
-
-struct Small {  // device-side counters of one call
-    fc::Totals totals;
-    unsigned int queue;
-    unsigned int graph_err;
-    unsigned long long sum;
-    unsigned int dmax;
-    unsigned int pad;
-    unsigned long long phase_ticks[8];
-};
-
-}  // namespace
-
-struct fc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string last_error;
-    DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists, clevels, cbits;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    size_t state_budget = 0;      // bytes of per-tree state the sampler may use
-    uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
-    uint32_t max_slots = 0;       // 0 = as many trees in flight as memory allows
-    uint32_t cu_count = 256;
-    size_t max_lds = 65536;       // dynamic LDS a workgroup may use
-    uint32_t coop_threads = 256;  // threads per workgroup in the workgroup sampler
-    uint32_t coop_wg_per_cu = 4;  // resident workgroups per CU in the workgroup sampler
-    uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop (environment override)
-    bool coop_lds_bits = true;    // settled bitmap in LDS when it fits
-    bool coop_word32 = true;      // 32-bit tree words when target and count fit
-    bool phase_timing = false;    // per-phase wall-clock ticks of the workgroup sampler
-    double wall_khz = 100000.0;   // device wall clock rate
-};
-
-namespace {
+namespace fc_host {
 
 int set_err(fc_ctx *ctx, int code, const std::string &msg) {
     if (ctx) ctx->last_error = msg;
@@ -74,12 +36,6 @@ int hip_fail(fc_ctx *ctx, hipError_t e, const char *what) {
     return set_err(ctx, e == hipErrorOutOfMemory ? FC_ERR_NOMEM : FC_ERR_HIP,
                    std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define FC_HIP(ctx, expr, what)                          \
-    do {                                                 \
-        hipError_t e_ = (expr);                          \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
-    } while (0)
 
 int ensure(fc_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
     if (bytes == 0) bytes = 16;
@@ -109,13 +65,6 @@ uint32_t env_u32(const char *name, uint32_t dflt) {
 
 bool valid_alpha(double a) { return std::isfinite(a) && a > 0.0; }
 
-// Resolved device view of a graph for one call.
-struct GraphView {
-    int32_t n = 0;
-    int64_t nnz = 0;
-    const int32_t *row_ptr = nullptr;
-    const int32_t *col_idx = nullptr;
-};
 
 int check_graph_args(fc_ctx *ctx, const fc_graph *g) {
     if (!g) return set_err(ctx, FC_ERR_ARG, "graph is NULL");
@@ -129,7 +78,6 @@ int check_graph_args(fc_ctx *ctx, const fc_graph *g) {
     return FC_OK;
 }
 
-// Stage (if on the host) and validate the CSR on the device.
 int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out) {
     int rc = check_graph_args(ctx, g);
     if (rc) return rc;
@@ -246,11 +194,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         FC_HIP(ctx, hipMemcpyAsync(&dmax, &sm->dmax, sizeof(dmax), hipMemcpyDeviceToHost, ctx->stream),
                "copy dmax");
         FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "build_vrec");
-        uint32_t tb = 1, cb = 1;
-        while ((1ull << tb) <= static_cast<unsigned long long>(g.n)) ++tb;  // n < 2^tb
-        while ((1ull << cb) <= static_cast<unsigned long long>(dmax)) ++cb;  // dmax < 2^cb
-        word32 = ctx->coop_word32 && tb + cb <= 32;
-        tshift = word32 ? tb : 32;
+        word_layout(static_cast<uint32_t>(g.n), dmax, ctx->coop_word32, &tshift, &word32);
         const size_t wbytes = word32 ? 4u : 8u;
         const size_t nwords = (static_cast<size_t>(g.n) + 31u) / 32u;
         lds_bits = ctx->coop_lds_bits &&
@@ -275,31 +219,36 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         if (!lds_bits &&
             (rc = ensure(ctx, ctx->cbits, 4u * nwords * slots, "settled bitmap")))
             return rc;
-        c.vrec = vrec;
-        c.col_idx = g.col_idx;
         c.word = ctx->cword.ptr;
         c.kk = static_cast<uint64_t *>(ctx->ckk.ptr);
-        c.tshift = tshift;
         c.lists = static_cast<uint64_t *>(ctx->clists.ptr);
         c.levels = static_cast<uint32_t *>(ctx->clevels.ptr);
         c.bits = lds_bits ? nullptr : static_cast<uint32_t *>(ctx->cbits.ptr);
-        c.n = static_cast<uint32_t>(g.n);
+        c.n_max = static_cast<uint32_t>(g.n);
         c.slots = static_cast<uint32_t>(slots);
-        c.tree_begin = tree_begin;
-        c.tree_count = tree_count;
-        c.stream_id = p->stream_id;
+        c.item_count = tree_count;
         c.key0 = static_cast<uint32_t>(p->seed);
         c.key1 = static_cast<uint32_t>(p->seed >> 32);
         c.max_rounds = 0x40000000u;
-        c.step_cap = step_cap;
         c.queue = &sm->queue;
-        c.root_counts = root_counts;
-        c.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
-        c.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
-        c.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
-        c.parents = parents;
-        c.tree_visits = tree_visits;
         c.totals = &sm->totals;
+        c.jobs = nullptr;
+        c.item_job = nullptr;
+        fc::CoopJob &j = c.single;
+        j.vrec = vrec;
+        j.col_idx = g.col_idx;
+        j.n = static_cast<uint32_t>(g.n);
+        j.tshift = tshift;
+        j.stream_id = p->stream_id;
+        j.tree_begin = tree_begin;
+        j.first_item = 0;
+        j.step_cap = step_cap;
+        j.root_counts = root_counts;
+        j.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
+        j.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
+        j.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
+        j.parents = parents;
+        j.tree_visits = tree_visits;
         c.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
     } else {
         // trees in flight: bounded by the tree count and by the state budget
@@ -332,9 +281,11 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     }
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
-    if (use_coop)
+    if (use_coop) {
+        FC_HIP(ctx, fc::coop_set_lds_limit(lds_bits, word32, c.n_max), "coop LDS limit");
         FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, word32, ctx->stream),
                "wilson_coop launch");
+    }
     else
         FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
     FC_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
@@ -374,6 +325,14 @@ double now_ms() {
         .count();
 }
 
+void word_layout(uint32_t n, uint32_t dmax, bool allow32, uint32_t *tshift, bool *word32) {
+    uint32_t tb = 1, cb = 1;
+    while ((1ull << tb) <= static_cast<unsigned long long>(n)) ++tb;     // n < 2^tb
+    while ((1ull << cb) <= static_cast<unsigned long long>(dmax)) ++cb;  // dmax < 2^cb
+    *word32 = allow32 && tb + cb <= 32;
+    *tshift = *word32 ? tb : 32;
+}
+
 int begin(fc_ctx *ctx) {
     if (!ctx) return FC_ERR_ARG;
     ctx->last_error.clear();
@@ -381,7 +340,9 @@ int begin(fc_ctx *ctx) {
     return FC_OK;
 }
 
-}  // namespace
+}  // namespace fc_host
+
+using namespace fc_host;
 
 extern "C" {
 
@@ -425,7 +386,7 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     ctx->coop_threads = env_u32("FC_COOP_THREADS", 512);
     if (ctx->coop_threads < 64 || ctx->coop_threads > 1024 || ctx->coop_threads % 64)
         ctx->coop_threads = 256;
-    ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 2));
+    ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 4));
     {
         const char *fs = std::getenv("FC_SAMPLER");
         if (fs && !std::strcmp(fs, "lane")) ctx->force_sampler = 1;

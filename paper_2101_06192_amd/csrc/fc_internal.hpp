@@ -1,0 +1,81 @@
+// Host-side internals shared by the C-ABI translation units: the context,
+// device buffers and the graph preparation helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "fc.h"
+#include "fc_kernels.hpp"
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Small {  // device-side counters of one call
+    fc::Totals totals;
+    unsigned int queue;
+    unsigned int graph_err;
+    unsigned long long sum;
+    unsigned int dmax;
+    unsigned int pad;
+    unsigned long long phase_ticks[8];
+};
+
+struct fc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists, clevels, cbits;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    size_t state_budget = 0;      // bytes of per-tree state the sampler may use
+    uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
+    uint32_t max_slots = 0;       // 0 = as many trees in flight as memory allows
+    uint32_t cu_count = 256;
+    size_t max_lds = 65536;       // dynamic LDS a workgroup may use
+    uint32_t coop_threads = 512;  // threads per workgroup in the workgroup sampler
+    uint32_t coop_wg_per_cu = 4;  // resident workgroups per CU in the workgroup sampler
+    uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop (environment override)
+    bool coop_lds_bits = true;    // settled bitmap in LDS when it fits
+    bool coop_word32 = true;      // 32-bit tree words when target and count fit
+    bool phase_timing = false;    // per-phase wall-clock ticks of the workgroup sampler
+    double wall_khz = 100000.0;   // device wall clock rate
+};
+
+
+#define FC_HIP(ctx, expr, what)                          \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+
+namespace fc_host {
+
+int set_err(fc_ctx *ctx, int code, const std::string &msg);
+int hip_fail(fc_ctx *ctx, hipError_t e, const char *what);
+// Grow-only device buffer: (re)allocates when `bytes` exceeds its size.
+int ensure(fc_ctx *ctx, DevBuf &b, size_t bytes, const char *what);
+uint32_t env_u32(const char *name, uint32_t dflt);
+bool valid_alpha(double a);
+
+// Resolved device view of a graph for one call.
+struct GraphView {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    const int32_t *row_ptr = nullptr;
+    const int32_t *col_idx = nullptr;
+};
+
+int check_graph_args(fc_ctx *ctx, const fc_graph *g);
+// Stage (if on the host) and validate the CSR on the device.
+int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out);
+double now_ms();
+int begin(fc_ctx *ctx);
+// Bits of the target field so that n < 2^tshift, and whether a 32-bit tree
+// word also holds an in-arrow count up to dmax.
+void word_layout(uint32_t n, uint32_t dmax, bool allow32, uint32_t *tshift, bool *word32);
+
+}  // namespace fc_host

@@ -50,37 +50,54 @@ struct LaneArgs {
 };
 hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
 
-// Workgroup-per-tree sampler (round-synchronous cycle popping).
-struct CoopArgs {
+// Workgroup-per-tree sampler (round-synchronous cycle popping).  A job is
+// one (graph, alpha, stream) with a range of trees and its own outputs.
+struct CoopJob {
     const VRec *vrec;
     const int32_t *col_idx;
-    void *word;               // slots * n words (u32 or u64): target | in-arrow count << tshift
-    uint64_t *kk;             // slots * n: (epoch << 32) | arrows drawn, for redrawn vertices
-    uint32_t tshift;          // bits of the target field (n < 2^tshift); 32 for u64 words
-    uint64_t *lists;          // slots * 3n: (vertex, target) pairs: two unsettled lists, peel order
-    uint32_t *levels;         // slots * (n + 2): peel level boundaries
-    uint32_t *bits;           // slots * ceil(n/32): settled bitmap when it is not kept in LDS
     uint32_t n;
-    uint32_t slots;           // workgroups (trees in flight)
-    uint32_t tree_begin;
-    uint32_t tree_count;
+    uint32_t tshift;          // bits of the target field in a tree word
     uint32_t stream_id;
-    uint32_t key0, key1;
-    uint32_t max_rounds;      // bound on popping rounds per tree; exceeding it is an error
-    unsigned long long step_cap;
-    unsigned int *queue;
+    uint32_t tree_begin;
+    uint32_t first_item;      // work item of the job's first tree
+    uint32_t pad;
+    unsigned long long step_cap;  // per-tree bound on draws; exceeding it is an error
     uint32_t *root_counts;
     unsigned long long *visit_counts;
     unsigned long long *tree_digests;
     unsigned long long *tree_steps;
     int32_t *parents;
     uint32_t *tree_visits;
+};
+
+struct CoopArgs {
+    void *word;               // slots * n_max words (u32 or u64): target | in-arrow count << tshift
+    uint64_t *kk;             // slots * n_max: (epoch << 32) | arrows drawn, for redrawn vertices
+    uint64_t *lists;          // slots * 3 n_max: (vertex, target) pairs: two unsettled lists, peel order
+    uint32_t *levels;         // slots * (n_max + 2): peel level boundaries
+    uint32_t *bits;           // slots * ceil(n_max/32): settled bitmap when it is not kept in LDS
+    uint32_t n_max;           // largest n of any job (per-slot stride)
+    uint32_t slots;           // workgroups (trees in flight)
+    uint32_t item_count;      // trees over all jobs
+    uint32_t key0, key1;
+    uint32_t max_rounds;      // bound on popping rounds per tree; exceeding it is an error
+    unsigned int *queue;
     Totals *totals;
     unsigned long long *phase_ticks;  // 7 wall-clock tick sums per phase, or null
+    CoopJob single;           // the job of a single-graph launch (jobs == null)
+    const CoopJob *jobs;      // batch: device job table
+    const uint32_t *item_job; // batch: job index of each work item
 };
 hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool word32,
                               hipStream_t stream);
+// Raise the kernel's dynamic-LDS limit for a bitmap of n_max bits (call
+// before launching, outside stream capture).
+hipError_t coop_set_lds_limit(bool lds_bits, bool word32, uint32_t n_max);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
+
+// p[0..count) = value (a kernel, so that it can sit in a captured HIP graph).
+hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,
+                           hipStream_t stream);
 
 // S = sum of R (exact, uint64) into *sum (caller zeroes it).
 hipError_t launch_sum_u32(const uint32_t *x, int32_t n, unsigned long long *sum,

@@ -54,7 +54,24 @@ __global__ __launch_bounds__(256) void estimate_kernel(const uint32_t *__restric
     }
 }
 
+// Plain fills (used instead of memset nodes inside captured HIP graphs).
+__global__ void fill_u64_kernel(unsigned long long *__restrict__ p, size_t count,
+                                unsigned long long value) {
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[i] = value;
+}
+
 }  // namespace
+
+hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,
+                           hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    fill_u64_kernel<<<static_cast<unsigned int>(blocks), 256, 0, stream>>>(p, count, value);
+    return hipGetLastError();
+}
 
 hipError_t launch_sum_u32(const uint32_t *x, int32_t n, unsigned long long *sum,
                           hipStream_t stream) {

@@ -78,45 +78,38 @@ enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedr
                    kPhCount };
 
 // One arrow of v in tree t with draw index k.
-__device__ __forceinline__ uint32_t draw(const CoopArgs &a, uint32_t v, uint32_t k, uint32_t t) {
-    const VRec r = load_vrec(a.vrec, v);
-    const Philox4 x = philox4x32_10(v, k, t, a.stream_id, a.key0, a.key1);
-    return arrow_target(r, x.x0, x.x1, a.col_idx, a.n);
+__device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32_t key1,
+                                         uint32_t v, uint32_t k, uint32_t t) {
+    const VRec r = load_vrec(j.vrec, v);
+    const Philox4 x = philox4x32_10(v, k, t, j.stream_id, key0, key1);
+    return arrow_target(r, x.x0, x.x1, j.col_idx, j.n);
 }
 
+// Work items are trees; a single-graph launch has one implicit job, a batch
+// launch maps item w to job item_job[w] and tree w - job.first_item.
 template <bool kLdsBits, typename W>
 __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_dyn[];
-    __shared__ uint32_t s_tree, s_u, s_p, s_cycles;
+    __shared__ uint32_t s_item, s_u, s_p, s_cycles;
     __shared__ unsigned long long s_digest, s_roots;
 
-    const uint32_t n = a.n;
     const uint32_t T = blockDim.x;
     const uint32_t tid = threadIdx.x;
     const uint32_t wave_base = tid & ~63u;
     const uint32_t lane = tid & 63u;
     const size_t slot = blockIdx.x;
-    const uint32_t nwords = (n + 31u) >> 5;
-    const uint32_t tshift = a.tshift;
-    const W tmask = (static_cast<W>(1) << tshift) - static_cast<W>(1);
-    const W cnt_one = static_cast<W>(1) << tshift;
-    const W cnt_minus_one = static_cast<W>(0) - cnt_one;
-    W *__restrict__ word = static_cast<W *>(a.word) + slot * n;
-    uint64_t *__restrict__ kk = a.kk + slot * n;
-    uint64_t *__restrict__ listA = a.lists + slot * (3ull * n);
-    uint64_t *__restrict__ listB = listA + n;
-    uint64_t *__restrict__ peel = listB + n;
-    uint32_t *__restrict__ lvl = a.levels + slot * (static_cast<size_t>(n) + 2);
-    uint32_t *__restrict__ bits = kLdsBits ? s_dyn : a.bits + slot * nwords;
+    const size_t stride = a.n_max;
+    const size_t bstride = (stride + 31u) >> 5;
+    W *__restrict__ word = static_cast<W *>(a.word) + slot * stride;
+    uint64_t *__restrict__ kk = a.kk + slot * stride;
+    uint64_t *__restrict__ listA = a.lists + slot * (3ull * stride);
+    uint64_t *__restrict__ listB = listA + stride;
+    uint64_t *__restrict__ peel = listB + stride;
+    uint32_t *__restrict__ lvl = a.levels + slot * (stride + 2);
+    uint32_t *__restrict__ bits = kLdsBits ? s_dyn : a.bits + slot * bstride;
     unsigned int err = 0;
     uint32_t epoch = 0;  // per-slot tree sequence number of this launch (kk was zeroed)
 
-    auto target_of = [&](W w) -> uint32_t { return static_cast<uint32_t>(w & tmask); };
-    auto cnt_of = [&](W w) -> uint32_t { return static_cast<uint32_t>(w >> tshift); };
-    auto is_settled = [&](uint32_t v) -> bool {
-        return v >= n || ((bits[v >> 5] >> (v & 31u)) & 1u);
-    };
-    auto set_settled = [&](uint32_t v) { wg_fetch_or(&bits[v >> 5], 1u << (v & 31u)); };
     unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0};
     unsigned long long ph_t = a.phase_ticks ? wall_clock64() : 0ull;
     auto mark = [&](int which) {
@@ -129,11 +122,26 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
 
     for (;;) {
         __syncthreads();
-        if (tid == 0) s_tree = atomicAdd(a.queue, 1u);
+        if (tid == 0) s_item = atomicAdd(a.queue, 1u);
         __syncthreads();
-        const uint32_t ti = s_tree;
-        if (ti >= a.tree_count) break;
-        const uint32_t t = a.tree_begin + ti;
+        const uint32_t item = s_item;
+        if (item >= a.item_count) break;
+        const CoopJob job = a.jobs ? a.jobs[a.item_job[item]] : a.single;
+        const uint32_t ti = item - job.first_item;
+        const uint32_t t = job.tree_begin + ti;
+        const uint32_t n = job.n;
+        const uint32_t nwords = (n + 31u) >> 5;
+        const uint32_t tshift = job.tshift;
+        const W tmask = (static_cast<W>(1) << tshift) - static_cast<W>(1);
+        const W cnt_one = static_cast<W>(1) << tshift;
+        const W cnt_minus_one = static_cast<W>(0) - cnt_one;
+        auto target_of = [&](W w) -> uint32_t { return static_cast<uint32_t>(w & tmask); };
+        auto cnt_of = [&](W w) -> uint32_t { return static_cast<uint32_t>(w >> tshift); };
+        auto is_settled = [&](uint32_t v) -> bool {
+            return v >= n || ((bits[v >> 5] >> (v & 31u)) & 1u);
+        };
+        auto set_settled = [&](uint32_t v) { wg_fetch_or(&bits[v >> 5], 1u << (v & 31u)); };
+
         ++epoch;
         if (tid == 0) {
             s_u = 0;
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             const uint32_t v = base + lane;
             uint32_t tg = n;
             if (v < n) {
-                tg = draw(a, v, 0u, t);
+                tg = draw(job, a.key0, a.key1, v, 0u, t);
                 word[v] = static_cast<W>(tg);
                 if (tg == n) set_settled(v);
             }
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
         uint32_t rounds = 0;
 
         while (ucount > 0) {
-            if (++rounds > a.max_rounds || draws > a.step_cap) {
+            if (++rounds > a.max_rounds || draws > job.step_cap) {
                 err |= kErrStepCap;
                 break;
             }
@@ -272,7 +280,7 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
                     if (cnt_of(w[q]) > 0u) {  // on a cycle
                         const uint64_t kv = kk[v];
                         const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
-                        const uint32_t tg = draw(a, v, k, t);
+                        const uint32_t tg = draw(job, a.key0, a.key1, v, k, t);
                         if (k + 1u > 0x7FFFFFFFu) err |= kErrVisitOverflow;
                         kk[v] = (static_cast<uint64_t>(epoch) << 32) | (k + 1u);
                         word[v] = static_cast<W>(tg);
@@ -301,20 +309,20 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
 
         // the tree: top arrows; R, digest, optional per-tree dumps
         unsigned long long my_digest = 0, my_roots = 0;
-        const bool want_k = a.visit_counts || a.tree_visits;
+        const bool want_k = job.visit_counts || job.tree_visits;
         for (uint32_t v = tid; v < n; v += T) {
             const uint32_t tg = target_of(word[v]);
             my_digest += mix64((static_cast<unsigned long long>(v) << 32) | tg);
             if (tg == n) {
                 ++my_roots;
-                atomicAdd(&a.root_counts[v], 1u);
+                atomicAdd(&job.root_counts[v], 1u);
             }
-            if (a.parents) a.parents[static_cast<size_t>(ti) * n + v] = static_cast<int32_t>(tg);
+            if (job.parents) job.parents[static_cast<size_t>(ti) * n + v] = static_cast<int32_t>(tg);
             if (want_k) {
                 const uint64_t kv = kk[v];
                 const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
-                if (a.visit_counts) atomicAdd(&a.visit_counts[v], static_cast<unsigned long long>(k));
-                if (a.tree_visits) a.tree_visits[static_cast<size_t>(ti) * n + v] = k;
+                if (job.visit_counts) atomicAdd(&job.visit_counts[v], static_cast<unsigned long long>(k));
+                if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + v] = k;
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
@@ -327,8 +335,8 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
         }
         __syncthreads();
         if (tid == 0) {
-            if (a.tree_digests) a.tree_digests[ti] = s_digest;
-            if (a.tree_steps) a.tree_steps[ti] = draws;
+            if (job.tree_digests) job.tree_digests[ti] = s_digest;
+            if (job.tree_steps) job.tree_steps[ti] = draws;
             atomicAdd(&a.totals->walk_steps, draws);
             atomicAdd(&a.totals->roots, s_roots);
             atomicAdd(&a.totals->digest_sum, s_digest);
@@ -346,20 +354,22 @@ size_t coop_lds_bytes(uint32_t n) { return 4u * ((static_cast<size_t>(n) + 31u) 
 
 template <bool kLds, typename W>
 hipError_t launch_one(const CoopArgs &a, uint32_t threads, hipStream_t stream) {
-    const size_t lds = kLds ? coop_lds_bytes(a.n) : 0;
-    if (kLds) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_coop_kernel<kLds, W>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-    }
+    const size_t lds = kLds ? coop_lds_bytes(a.n_max) : 0;
     wilson_coop_kernel<kLds, W><<<a.slots, threads, lds, stream>>>(a);
     return hipGetLastError();
 }
 
+hipError_t coop_set_lds_limit(bool lds_bits, bool word32, uint32_t n_max) {
+    if (!lds_bits) return hipSuccess;
+    const int lds = static_cast<int>(coop_lds_bytes(n_max));
+    const void *f = word32 ? reinterpret_cast<const void *>(&wilson_coop_kernel<true, uint32_t>)
+                           : reinterpret_cast<const void *>(&wilson_coop_kernel<true, unsigned long long>);
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool word32,
                               hipStream_t stream) {
-    if (a.n == 0 || a.tree_count == 0 || a.slots == 0) return hipSuccess;
+    if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
     if (lds_bits)
         return word32 ? launch_one<true, uint32_t>(a, threads, stream)
                       : launch_one<true, unsigned long long>(a, threads, stream);

@@ -95,3 +95,4 @@ def test_struct_layouts():
     assert ctypes.sizeof(fc.fc_params) == 56
     assert fc.fc_params.seed.offset == 32 and fc.fc_params.flags.offset == 52
     assert ctypes.sizeof(fc.fc_stats) == 128
+    assert ctypes.sizeof(fc.fc_job) == 80 and fc.fc_job.root_counts.offset == 64

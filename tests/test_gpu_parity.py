@@ -250,3 +250,87 @@ def test_ba200k_full_run_sampled(gpu_lib):
     om = oracle.omega_diag_cg(g, 1.0, vs, rtol=1e-9)
     # Hoeffding radius at delta = 1e-6 over 32 vertices with 4096 trees
     assert np.abs(R[vs] / 4096 - om).max() < np.sqrt(np.log(2 * 32 / 1e-6) / (2 * 4096))
+
+
+# --------------------------------------------------------------------------
+# Batches (many graphs x alphas in one persistent launch)
+# --------------------------------------------------------------------------
+def _batch_graphs():
+    sizes = inputs.rmat_batch_sizes(6, 5, lo_exp=7.0, hi_exp=12.0)
+    gs = [inputs.rmat(nn, 8, 100 + i) for i, nn in enumerate(sizes)]
+    gs.append(inputs.barabasi_albert(5000, 3, 2))
+    gs.append(inputs.grid_removed(40, 50, 0.12, 1))
+    gs.append(inputs.from_edge_list(3, [(0, 1)], "edge_plus_isolated"))
+    return gs
+
+
+def test_batch_matches_oracle_and_single_runs(gpu_lib):
+    fc = gpu_lib
+    gs = _batch_graphs()
+    dgs = [fc.to_device(g) for g in gs]
+    alphas = (0.1, 1.0, 10.0)
+    jobs = []
+    for gi, dg in enumerate(dgs):
+        for ai, a in enumerate(alphas):
+            jobs.append({"graph": dg, "alpha": a, "stream_id": gi * len(alphas) + ai,
+                         "tree_begin": 3 * ai, "tree_count": 20 + 5 * ai, "digests": True})
+    # edge jobs: no trees, and an empty graph
+    jobs.append({"graph": dgs[0], "alpha": 1.0, "tree_count": 0})
+    jobs.append({"graph": fc.to_device(inputs.from_edge_list(0, [])), "alpha": 1.0, "tree_count": 4})
+    b = fc.Batch(jobs, seed=4242)
+    st = b.run()
+    _say(f"batch run: {st['sampler']} ms={st['ms_sample']:.2f} trees={st['tau']}")
+    total_steps = 0
+    for i, j in enumerate(jobs[:-2]):
+        g = gs[i // len(alphas)]
+        ref = oracle.sample(g, j["alpha"], 4242, j["tree_begin"], j["tree_count"],
+                            stream=j["stream_id"])
+        got = b.result(i)
+        assert np.array_equal(got["root_counts"], ref.R), i
+        assert np.array_equal(got["tree_digests"], ref.digests), i
+        total_steps += int(ref.steps.sum())
+        one = fc.sample(dgs[i // len(alphas)], alpha=j["alpha"], seed=4242,
+                        tree_begin=j["tree_begin"], tree_count=j["tree_count"],
+                        stream_id=j["stream_id"], want_digests=True, sampler="coop")
+        assert np.array_equal(one["root_counts"], got["root_counts"])
+    assert st["walk_steps"] == total_steps
+    b.close()
+
+
+def test_batch_graph_replays_and_autotune(gpu_lib):
+    """Replays of the captured launch, with eager work and synchronisation
+    between them, each equal to the eager single-job result."""
+    import torch
+    fc = gpu_lib
+    gs = _batch_graphs()[:4]
+    dgs = [fc.to_device(g) for g in gs]
+    jobs = [{"graph": dg, "alpha": 1.0, "stream_id": i, "tree_count": 33, "digests": True}
+            for i, dg in enumerate(dgs)]
+    eager = [fc.sample(dg, alpha=1.0, seed=7, tree_count=33, stream_id=i, want_digests=True)
+             for i, dg in enumerate(dgs)]
+    for tune in (False, True):
+        b = fc.Batch(jobs, seed=7, autotune=tune)
+        for rep in range(3):
+            b.reset()
+            x = torch.randn(1 << 20, device="cuda:0")  # unrelated eager work in between
+            x.mul_(2.0).sum().item()
+            torch.cuda.synchronize()
+            b.run()
+            for i in range(len(jobs)):
+                got = b.result(i)
+                assert np.array_equal(got["root_counts"], eager[i]["root_counts"]), (tune, rep, i)
+                assert np.array_equal(got["tree_digests"], eager[i]["tree_digests"]), (tune, rep, i)
+        # without a reset the counts accumulate
+        b.run()
+        assert np.array_equal(b.result(0)["root_counts"], 2 * eager[0]["root_counts"])
+        b.close()
+
+
+def test_batch_rejects_host_graphs_and_bad_alpha(gpu_lib):
+    fc = gpu_lib
+    g = inputs.erdos_renyi(30, 0.2, 1)
+    with pytest.raises(TypeError):
+        fc.Batch([{"graph": g, "alpha": 1.0, "tree_count": 2}])
+    with pytest.raises(fc.FCError) as e:
+        fc.Batch([{"graph": fc.to_device(g), "alpha": -1.0, "tree_count": 2}])
+    assert e.value.code == fc.FC_ERR_ARG
