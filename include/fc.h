@@ -237,6 +237,31 @@ FC_API int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint
 FC_API int fc_batch_run(fc_batch *batch, fc_stats *stats);
 FC_API int fc_batch_destroy(fc_batch *batch);
 
+/* ---------------------------------------------------------------------- */
+/* Linear solves with the forest matrix system (alpha L + I) X = B.          */
+/* ---------------------------------------------------------------------- */
+#define FC_PREC_FP64 0          /* Jacobi-preconditioned CG in binary64 */
+#define FC_PREC_FP32_REFINED 1  /* binary32 CG inside binary64 iterative refinement */
+
+/* Solve (alpha L + I) X = B for 1 <= nrhs <= 64 right-hand sides: the system
+ * behind the forest matrix Omega = (alpha L + I)^{-1} (Section 2), the solve of
+ * Algorithm 1 (via its grounded form) and the CG ground truth of the
+ * experiments (Section 6.1).
+ *   B, X  device double[n * nrhs], row-major (X[v * nrhs + j]); X holds the
+ *         initial guess on entry (zero it for a cold start), the solution on exit.
+ *   Stops when every column has ||B_j - A X_j||_2 <= rtol ||B_j||_2 (residual
+ *   always evaluated in binary64), or after max_iters inner CG iterations.
+ *   FC_PREC_FP64: one CG on the correction, all in binary64.
+ *   FC_PREC_FP32_REFINED: repeat { R = B - A X (binary64); solve A D = R/|R|
+ *   with binary32 CG to a relative residual of 1e-4; X += |R| D (binary64) }.
+ *   iters_out (host, or NULL): inner CG iterations; relres_out (host double[nrhs],
+ *   or NULL): final relative residuals.  Returns FC_OK also when max_iters
+ *   ran out; check relres_out.  FC_ERR_UNSUPPORTED for nrhs > 64.
+ *   flags: FC_FLAG_TRUSTED_GRAPH. */
+FC_API int fc_solve(fc_ctx *ctx, const fc_graph *g, double alpha, const double *B, double *X,
+                    int32_t nrhs, double rtol, int32_t precision, int32_t max_iters, int32_t flags,
+                    int32_t *iters_out, double *relres_out);
+
 /* Message for an error code / for the last failing call on a context. */
 FC_API const char *fc_error_string(int code);
 FC_API const char *fc_last_error(fc_ctx *ctx);

@@ -82,6 +82,8 @@ class fc_job(ctypes.Structure):
 
 
 FC_FLAG_AUTOTUNE = 8
+FC_PREC_FP64 = 0
+FC_PREC_FP32_REFINED = 1
 
 _lib = None
 
@@ -107,6 +109,8 @@ def lib() -> ctypes.CDLL:
             "fc_sample": (ctypes.c_int, [vp, gp, pp, u32, u32, vp, vp, vp, vp, vp, vp, sp]),
             "fc_diag_estimate": (ctypes.c_int, [vp, gp, pp, vp, vp, sp]),
             "fc_farness": (ctypes.c_int, [vp, gp, pp, vp, vp, vp, vp, sp]),
+            "fc_solve": (ctypes.c_int, [vp, gp, f64, vp, vp, i32, f64, i32, i32, i32,
+                                        ctypes.POINTER(i32), vp]),
             "fc_batch_create": (ctypes.c_int, [vp, ctypes.POINTER(fc_job), i32, ctypes.c_uint64,
                                                i32, ctypes.POINTER(vp)]),
             "fc_batch_run": (ctypes.c_int, [vp, sp]),
@@ -407,3 +411,30 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def solve(g, alpha: float, B, X0=None, rtol: float = 1e-9, precision: str = "fp32_refined",
+          max_iters: int = 20000, device="cuda:0", trusted: bool = False, as_torch: bool = False) -> dict:
+    """(alpha L + I) X = B for up to 64 right-hand sides (fc_solve).  B: (n, k)
+    array or tensor; X0: initial guess (zeros if None).  precision "fp64" or
+    "fp32_refined"."""
+    import torch
+    ctx = context(device)
+    dev = ctx.device
+    Bt = torch.as_tensor(B, dtype=torch.float64).to(dev)
+    if Bt.dim() == 1:
+        Bt = Bt[:, None]
+    Bt = Bt.contiguous()
+    n, k = Bt.shape
+    X = (torch.zeros_like(Bt) if X0 is None
+         else torch.as_tensor(X0, dtype=torch.float64).to(dev).reshape(n, k).contiguous().clone())
+    prec = {"fp64": FC_PREC_FP64, "fp32_refined": FC_PREC_FP32_REFINED}[precision]
+    gs = _graph_struct(g)
+    it = ctypes.c_int32(0)
+    rel = np.zeros(max(k, 1), np.float64)
+    ctx.check(lib().fc_solve(ctx.handle, ctypes.byref(gs), float(alpha),
+                             ctypes.c_void_p(Bt.data_ptr()), ctypes.c_void_p(X.data_ptr()), int(k),
+                             float(rtol), prec, int(max_iters),
+                             FC_FLAG_TRUSTED_GRAPH if trusted else 0, ctypes.byref(it),
+                             ctypes.c_void_p(rel.ctypes.data)))
+    return {"X": X if as_torch else X.cpu().numpy(), "iters": int(it.value), "relres": rel[:k]}

@@ -108,4 +108,29 @@ hipError_t launch_estimate(const uint32_t *R, int32_t n, uint32_t tau, int liter
                            const unsigned long long *sum, double *diag, double *farness,
                            double *closeness, hipStream_t stream);
 
+// Block CG on (alpha L + I) X = B, row-major n x k, k <= 64.
+struct CgWork {
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    uint32_t n, k;
+    double alpha;
+    uint32_t max_blocks;
+    const double *B;        // n x k right-hand sides
+    double *X;              // n x k solution (binary64)
+    double *R64;            // n x k binary64 residual B - A X
+    void *r, *z, *p, *q, *d;  // n x k inner vectors in the inner precision
+    double *partial_a, *partial_b;  // max_blocks x 64 partial sums
+    double *scalars;        // 8 x 64: rz, rz_new, pq, rr, tol2, step, beta, active
+    double *scale;          // 64: residual norms the inner solve is scaled by
+    double *res_rr, *res_bb;  // 64: |R_j|^2 and |B_j|^2
+    unsigned int *any;      // device flag: some column still active
+};
+// Inner Jacobi-preconditioned CG on A d = R64 / scale (per column), then
+// X += scale * d.  Stops a column when |r_j|^2 <= tol2_j (scalars[256 + j]).
+template <typename T>
+hipError_t cg_inner(const CgWork &w, uint32_t max_iters, uint32_t poll, uint32_t *iters,
+                    hipStream_t stream);
+// R64 = B - A X and |R_j|^2 into res_rr (and |B_j|^2 into res_bb).
+hipError_t cg_residual(const CgWork &w, bool with_b, hipStream_t stream);
+
 }  // namespace fc

@@ -334,3 +334,69 @@ def test_batch_rejects_host_graphs_and_bad_alpha(gpu_lib):
     with pytest.raises(fc.FCError) as e:
         fc.Batch([{"graph": fc.to_device(g), "alpha": -1.0, "tree_count": 2}])
     assert e.value.code == fc.FC_ERR_ARG
+
+
+# --------------------------------------------------------------------------
+# Linear solves (alpha L + I) X = B, binary64 and binary32-refined
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("k", [1, 5, 37, 64])
+def test_solve_matches_dense(gpu_lib, precision, k):
+    fc = gpu_lib
+    g = inputs.barabasi_albert(700, 3, 4)
+    alpha = 1.3
+    B = inputs.gaussian(g.n * k, 10 + k).reshape(g.n, k)
+    out = fc.solve(g, alpha, B, rtol=1e-10, precision=precision)
+    A = alpha * oracle.laplacian(g) + np.eye(g.n)
+    Xd = np.linalg.solve(A, B)
+    assert (out["relres"] <= 1e-10).all(), out["relres"]
+    # relative residual bound -> error bound: |x - x*| <= cond(A) rtol |x*|
+    cond = np.linalg.cond(A)
+    err = np.abs(out["X"] - Xd).max() / np.abs(Xd).max()
+    assert err <= 2 * cond * 1e-10, (err, cond)
+    # the residual reported is the true binary64 residual
+    R = B - A @ out["X"]
+    assert np.allclose(np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0), out["relres"],
+                       rtol=1e-3, atol=1e-15)
+
+
+def test_solve_precisions_agree_and_initial_guess(gpu_lib):
+    fc = gpu_lib
+    g = inputs.grid_removed(30, 40, 0.12, 2)
+    B = inputs.gaussian(g.n * 8, 3).reshape(g.n, 8)
+    a = fc.solve(g, 2.0, B, rtol=1e-11, precision="fp64")
+    b = fc.solve(g, 2.0, B, rtol=1e-11, precision="fp32_refined")
+    assert np.abs(a["X"] - b["X"]).max() < 1e-8 * np.abs(a["X"]).max()
+    # warm start from the solution: no iterations needed
+    c = fc.solve(g, 2.0, B, X0=a["X"], rtol=1e-9, precision="fp32_refined")
+    assert c["iters"] == 0 and (c["relres"] <= 1e-9).all()
+    # zero right-hand side column stays zero
+    B[:, 3] = 0.0
+    d = fc.solve(g, 2.0, B, rtol=1e-9)
+    assert (d["X"][:, 3] == 0.0).all()
+
+
+def test_solve_omega_diagonal(gpu_lib):
+    """Columns e_v give Omega e_v: the diagonal matches the dense forest matrix."""
+    fc = gpu_lib
+    g = inputs.erdos_renyi(1000, 0.01, 0)
+    vs = np.arange(0, 1000, 16)[:64]
+    B = np.zeros((g.n, len(vs)))
+    B[vs, np.arange(len(vs))] = 1.0
+    out = fc.solve(g, 1.0, B, rtol=1e-9, precision="fp32_refined")
+    Om = oracle.forest_matrix(g, 1.0)
+    assert np.abs(out["X"][vs, np.arange(len(vs))] - np.diag(Om)[vs]).max() < 1e-8
+
+
+def test_solve_argument_errors(gpu_lib):
+    fc = gpu_lib
+    g = inputs.erdos_renyi(50, 0.1, 1)
+    with pytest.raises(fc.FCError) as e:
+        fc.solve(g, 1.0, np.ones((50, 65)))
+    assert e.value.code == fc.FC_ERR_UNSUPPORTED
+    with pytest.raises(fc.FCError) as e:
+        fc.solve(g, 0.0, np.ones((50, 2)))
+    assert e.value.code == fc.FC_ERR_ARG
+    with pytest.raises(fc.FCError) as e:
+        fc.solve(g, 1.0, np.ones((50, 2)), rtol=0.0)
+    assert e.value.code == fc.FC_ERR_ARG
