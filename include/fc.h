@@ -142,6 +142,7 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "coop_wg_per_cu"  workgroups per CU of the workgroup sampler (>= 1)
  *   "coop_lds_bits"   settled bitmap in LDS: 1 when it fits, 0 never (global memory)
  *   "coop_word32"     32-bit per-vertex tree words when they fit: 1 (default) or 0 (64-bit)
+ *   "coop_in_bits"    second LDS bitmap (vertices with in-arrows) when it fits: 1 (default) or 0
  *   "lanes_per_wave"  active lanes per wave of the lane sampler (1..64)
  *   "max_slots"       cap on trees in flight (0 = memory bound only)
  *   "phase_timing"    1: the workgroup sampler reports per-phase times in fc_stats
@@ -253,7 +254,7 @@ FC_API int fc_batch_destroy(fc_batch *batch);
  *   always evaluated in binary64), or after max_iters inner CG iterations.
  *   FC_PREC_FP64: one CG on the correction, all in binary64.
  *   FC_PREC_FP32_REFINED: repeat { R = B - A X (binary64); solve A D = R/|R|
- *   with binary32 CG to a relative residual of 1e-4; X += |R| D (binary64) }.
+ *   with binary32 CG to a relative residual of 1e-5; X += |R| D (binary64) }.
  *   iters_out (host, or NULL): inner CG iterations; relres_out (host double[nrhs],
  *   or NULL): final relative residuals.  Returns FC_OK also when max_iters
  *   ran out; check relres_out.  FC_ERR_UNSUPPORTED for nrhs > 64.

@@ -40,6 +40,23 @@ __device__ __forceinline__ void row_range(uint32_t kk, uint32_t *first_group, ui
     (void)kk;
 }
 
+// sum over the neighbours u of v of X[u][col], four independent gathers in flight.
+template <typename T>
+__device__ __forceinline__ T neighbour_sum(const int32_t *__restrict__ col_idx, int32_t b, int32_t e,
+                                           const T *__restrict__ X, uint32_t k, uint32_t col) {
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int32_t q = b;
+    for (; q + 4 <= e; q += 4) {
+        const int32_t u0 = col_idx[q], u1 = col_idx[q + 1], u2 = col_idx[q + 2], u3 = col_idx[q + 3];
+        s0 += X[static_cast<size_t>(u0) * k + col];
+        s1 += X[static_cast<size_t>(u1) * k + col];
+        s2 += X[static_cast<size_t>(u2) * k + col];
+        s3 += X[static_cast<size_t>(u3) * k + col];
+    }
+    for (; q < e; ++q) s0 += X[static_cast<size_t>(col_idx[q]) * k + col];
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Block-level per-column reduction of `acc` into partial[blockIdx.x * k + col].
 template <typename A>
 __device__ __forceinline__ void block_column_sum(A acc, const Lane &ln, uint32_t k, A *partial,
@@ -73,8 +90,7 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(const int32_t *__restri
         const uint32_t v = g * rows_per_group + ln.rsub;
         if (v < n && ln.valid) {
             const int32_t b = row_ptr[v], e = row_ptr[v + 1];
-            T s = T(0);
-            for (int32_t q = b; q < e; ++q) s += X[static_cast<size_t>(col_idx[q]) * k + ln.col];
+            const T s = neighbour_sum<T>(col_idx, b, e, X, k, ln.col);
             const T x = X[static_cast<size_t>(v) * k + ln.col];
             const T d = static_cast<T>(e - b);
             const T y = (T(1) + a * d) * x - a * s;
@@ -104,8 +120,7 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const int32_t *__res
         const uint32_t v = g * rows_per_group + ln.rsub;
         if (v < n && ln.valid) {
             const int32_t b = row_ptr[v], e = row_ptr[v + 1];
-            double s = 0.0;
-            for (int32_t q = b; q < e; ++q) s += X[static_cast<size_t>(col_idx[q]) * k + ln.col];
+            const double s = neighbour_sum<double>(col_idx, b, e, X, k, ln.col);
             const size_t i = static_cast<size_t>(v) * k + ln.col;
             const double ax = (1.0 + alpha * static_cast<double>(e - b)) * X[i] - alpha * s;
             const double r = B[i] - ax;

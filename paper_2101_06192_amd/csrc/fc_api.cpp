@@ -185,7 +185,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     const char *kname = use_coop ? "wilson_coop" : "wilson_lane";
     fc::LaneArgs a{};
     fc::CoopArgs c{};
-    bool lds_bits = false, word32 = false;
+    bool lds_bits = false, in_bits = false, word32 = false;
     uint32_t tshift = 32;
     if (use_coop) {
         // 32-bit tree words when target and in-arrow count both fit (the count of
@@ -199,6 +199,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         const size_t nwords = (static_cast<size_t>(g.n) + 31u) / 32u;
         lds_bits = ctx->coop_lds_bits &&
                    fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) + 1024u <= ctx->max_lds;
+        in_bits = lds_bits && ctx->coop_in_bits &&
+                  2 * fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) + 1024u <= ctx->max_lds;
         const size_t per_slot = (wbytes + 8u + 24u + 4u) * static_cast<size_t>(g.n) + 8u +
                                 (lds_bits ? 0u : 4u * nwords);
         slots = std::max<size_t>(1, ctx->state_budget / per_slot);
@@ -282,8 +284,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     if (use_coop) {
-        FC_HIP(ctx, fc::coop_set_lds_limit(lds_bits, word32, c.n_max), "coop LDS limit");
-        FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, word32, ctx->stream),
+        FC_HIP(ctx, fc::coop_set_lds_limit(lds_bits, in_bits, word32, c.n_max), "coop LDS limit");
+        FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, ctx->stream),
                "wilson_coop launch");
     }
     else
@@ -387,6 +389,7 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     if (ctx->coop_threads < 64 || ctx->coop_threads > 1024 || ctx->coop_threads % 64)
         ctx->coop_threads = 256;
     ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 4));
+    ctx->coop_in_bits = env_u32("FC_COOP_IN_BITS", 1) != 0;
     {
         const char *fs = std::getenv("FC_SAMPLER");
         if (fs && !std::strcmp(fs, "lane")) ctx->force_sampler = 1;
@@ -403,7 +406,8 @@ int fc_destroy(fc_ctx *ctx) {
     else (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->state, &ctx->vrec, &ctx->row_ptr, &ctx->col_idx, &ctx->small,
                       &ctx->rtmp, &ctx->thr, &ctx->cword, &ctx->ckk, &ctx->clists, &ctx->clevels,
-                      &ctx->cbits})
+                      &ctx->cbits, &ctx->s_r64, &ctx->s_r, &ctx->s_z, &ctx->s_p, &ctx->s_q,
+                      &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -429,6 +433,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "coop_lds_bits") {
         if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_lds_bits");
         ctx->coop_lds_bits = value == 1;
+    } else if (k == "coop_in_bits") {
+        if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_in_bits");
+        ctx->coop_in_bits = value == 1;
     } else if (k == "coop_word32") {
         if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_word32");
         ctx->coop_word32 = value == 1;

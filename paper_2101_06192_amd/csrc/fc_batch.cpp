@@ -28,7 +28,7 @@ struct fc_batch {
     DevBuf vrec, jobtab, item_job, word, kk, lists, levels, bits, small, dmax, scratch_r;
     uint32_t n_max = 0, item_count = 0, slots = 0, threads = 512, wg_per_cu = 4;
     size_t ntab = 0;  // entries of the device job table (jobs that have trees)
-    bool lds_bits = false, word32 = true;
+    bool lds_bits = false, in_bits = false, word32 = true;
     size_t kk_words = 0;
     fc::CoopArgs args{};
     hipStream_t stream = nullptr;
@@ -61,7 +61,7 @@ hipError_t enqueue_run(fc_batch *b, const fc::CoopArgs &a, uint32_t threads, hip
     if (e != hipSuccess) return e;
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(b->kk.ptr), b->kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
-    return fc::launch_wilson_coop(a, threads, b->lds_bits, b->word32, stream);
+    return fc::launch_wilson_coop(a, threads, b->lds_bits, b->in_bits, b->word32, stream);
 }
 
 // Size the scratch for `slots` workgroups and point the launch arguments at it.
@@ -258,6 +258,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         b->word32 = b->word32 && w32;
     }
     b->lds_bits = ctx->coop_lds_bits && fc::coop_lds_bytes(n_max) + 1024u <= ctx->max_lds;
+    b->in_bits = b->lds_bits && ctx->coop_in_bits &&
+                 2 * fc::coop_lds_bytes(n_max) + 1024u <= ctx->max_lds;
 
     // job table and item -> job map
     std::vector<fc::CoopJob> tab(order.size());
@@ -306,7 +308,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     a.phase_ticks = nullptr;
     a.jobs = static_cast<const fc::CoopJob *>(b->jobtab.ptr);
     a.item_job = static_cast<const uint32_t *>(b->item_job.ptr);
-    FC_HIP(ctx, fc::coop_set_lds_limit(b->lds_bits, b->word32, n_max), "coop LDS limit");
+    FC_HIP(ctx, fc::coop_set_lds_limit(b->lds_bits, b->in_bits, b->word32, n_max), "coop LDS limit");
 
     if ((flags & FC_FLAG_AUTOTUNE) && (rc = autotune(b))) return fail(rc);
     if ((rc = size_scratch(b, slots_for(b, b->wg_per_cu)))) return fail(rc);

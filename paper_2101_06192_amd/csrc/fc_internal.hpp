@@ -29,6 +29,7 @@ struct fc_ctx {
     hipStream_t stream = nullptr;
     std::string last_error;
     DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists, clevels, cbits;
+    DevBuf s_r64, s_r, s_z, s_p, s_q, s_d, s_pa, s_pb, s_small;  // solver workspace
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
@@ -40,6 +41,7 @@ struct fc_ctx {
     uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop (environment override)
     bool coop_lds_bits = true;    // settled bitmap in LDS when it fits
     bool coop_word32 = true;      // 32-bit tree words when target and count fit
+    bool coop_in_bits = true;     // in-arrow bitmap in LDS when both bitmaps fit
     bool phase_timing = false;    // per-phase wall-clock ticks of the workgroup sampler
     double wall_khz = 100000.0;   // device wall clock rate
 };

@@ -88,11 +88,13 @@ struct CoopArgs {
     const CoopJob *jobs;      // batch: device job table
     const uint32_t *item_job; // batch: job index of each work item
 };
-hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool word32,
-                              hipStream_t stream);
-// Raise the kernel's dynamic-LDS limit for a bitmap of n_max bits (call
+// lds_bits: settled bitmap in LDS; in_bits (needs lds_bits): second LDS bitmap of
+// vertices with in-arrows.
+hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
+                              bool word32, hipStream_t stream);
+// Raise the kernel's dynamic-LDS limit for the bitmaps of n_max bits (call
 // before launching, outside stream capture).
-hipError_t coop_set_lds_limit(bool lds_bits, bool word32, uint32_t n_max);
+hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 
 // p[0..count) = value (a kernel, so that it can sit in a captured HIP graph).

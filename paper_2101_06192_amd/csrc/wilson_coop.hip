@@ -87,7 +87,11 @@ __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32
 
 // Work items are trees; a single-graph launch has one implicit job, a batch
 // launch maps item w to job item_job[w] and tree w - job.first_item.
-template <bool kLdsBits, typename W>
+// kInBits (with kLdsBits): a second LDS bitmap marks unsettled vertices that
+// still have in-arrows in the current round -- set while counting, cleared
+// when the vertex is peeled -- so peel level 0 and cycle detection read LDS
+// instead of the global tree words.
+template <bool kLdsBits, typename W, bool kInBits>
 __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_dyn[];
     __shared__ uint32_t s_item, s_u, s_p, s_cycles;
@@ -107,6 +111,7 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
     uint64_t *__restrict__ peel = listB + stride;
     uint32_t *__restrict__ lvl = a.levels + slot * (stride + 2);
     uint32_t *__restrict__ bits = kLdsBits ? s_dyn : a.bits + slot * bstride;
+    uint32_t *__restrict__ inb = s_dyn + bstride;  // used only when kInBits
     unsigned int err = 0;
     uint32_t epoch = 0;  // per-slot tree sequence number of this launch (kk was zeroed)
 
@@ -141,6 +146,9 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             return v >= n || ((bits[v >> 5] >> (v & 31u)) & 1u);
         };
         auto set_settled = [&](uint32_t v) { wg_fetch_or(&bits[v >> 5], 1u << (v & 31u)); };
+        auto has_in = [&](uint32_t v) -> bool { return (inb[v >> 5] >> (v & 31u)) & 1u; };
+        auto set_in = [&](uint32_t v) { atomicOr(&inb[v >> 5], 1u << (v & 31u)); };
+        auto clear_in = [&](uint32_t v) { atomicAnd(&inb[v >> 5], ~(1u << (v & 31u))); };
 
         ++epoch;
         if (tid == 0) {
@@ -149,7 +157,10 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             s_digest = 0;
             s_roots = 0;
         }
-        for (uint32_t i = tid; i < nwords; i += T) bits[i] = 0u;
+        for (uint32_t i = tid; i < nwords; i += T) {
+            bits[i] = 0u;
+            if (kInBits) inb[i] = 0u;
+        }
         __syncthreads();
 
         // round 0: the first arrow of every vertex
@@ -179,7 +190,10 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             // the atomics do not stall the thread)
             for (uint32_t i = tid; i < ucount; i += T) {
                 const uint32_t tg = hi32(U[i]);
-                if (!is_settled(tg)) (void)wg_fetch_add(&word[tg], cnt_one);
+                if (!is_settled(tg)) {
+                    (void)wg_fetch_add(&word[tg], cnt_one);
+                    if (kInBits) set_in(tg);
+                }
             }
             if (tid == 0) s_p = 0;  // last read of s_p was followed by barriers
             __syncthreads();
@@ -197,7 +211,8 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t i = base + q * T + lane;
-                    if (i < ucount) leaf[q] = cnt_of(word[lo32(it[q])]) == 0u;
+                    if (i < ucount)
+                        leaf[q] = kInBits ? !has_in(lo32(it[q])) : cnt_of(word[lo32(it[q])]) == 0u;
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) wave_append(peel, &s_p, it[q], leaf[q]);
@@ -225,7 +240,10 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
                     for (int q = 0; q < 4; ++q)
                         if (!is_settled(tg[q])) old[q] = wg_fetch_add(&word[tg[q]], cnt_minus_one);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) push[q] = !is_settled(tg[q]) && cnt_of(old[q]) == 1u;
+                    for (int q = 0; q < 4; ++q) {
+                        push[q] = !is_settled(tg[q]) && cnt_of(old[q]) == 1u;
+                        if (kInBits && push[q]) clear_in(tg[q]);
+                    }
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         wave_append(peel, &s_p, pair(tg[q], target_of(old[q])), push[q]);
@@ -238,6 +256,10 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             }
             const uint32_t peeled = hi;
             mark(kPhPeel);
+            if (peeled == ucount) {  // no cycle left: every vertex reaches u*, the tree is done
+                ucount = 0;
+                break;
+            }
             // reverse sweep: settled when the arrow reaches u* or a settled vertex
             for (int32_t L = static_cast<int32_t>(nlev) - 1; L >= 0; --L) {
                 const uint32_t a0 = lvl[L], a1 = lvl[L + 1];
@@ -248,10 +270,6 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
                 __syncthreads();
             }
             mark(kPhSweep);
-            if (peeled == ucount) {  // no cycle left: every vertex is settled
-                ucount = 0;
-                break;
-            }
             // pop every cycle: unsettled vertices that kept in-arrows draw again
             if (tid == 0) {  // last reads of s_u / s_cycles were followed by barriers
                 s_u = 0;
@@ -272,12 +290,14 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (!is_settled(lo32(it[q]))) w[q] = word[lo32(it[q])];
+                    if (!kInBits && !is_settled(lo32(it[q]))) w[q] = word[lo32(it[q])];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t v = lo32(it[q]);
                     if (is_settled(v)) continue;
-                    if (cnt_of(w[q]) > 0u) {  // on a cycle
+                    const bool on_cycle = kInBits ? has_in(v) : cnt_of(w[q]) > 0u;
+                    if (on_cycle) {
+                        if (kInBits) clear_in(v);
                         const uint64_t kv = kk[v];
                         const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
                         const uint32_t tg = draw(job, a.key0, a.key1, v, k, t);
@@ -352,29 +372,39 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
 
 size_t coop_lds_bytes(uint32_t n) { return 4u * ((static_cast<size_t>(n) + 31u) >> 5); }
 
-template <bool kLds, typename W>
+template <bool kLds, typename W, bool kIn>
 hipError_t launch_one(const CoopArgs &a, uint32_t threads, hipStream_t stream) {
-    const size_t lds = kLds ? coop_lds_bytes(a.n_max) : 0;
-    wilson_coop_kernel<kLds, W><<<a.slots, threads, lds, stream>>>(a);
+    const size_t lds = kLds ? (kIn ? 2 : 1) * coop_lds_bytes(a.n_max) : 0;
+    wilson_coop_kernel<kLds, W, kIn><<<a.slots, threads, lds, stream>>>(a);
     return hipGetLastError();
 }
 
-hipError_t coop_set_lds_limit(bool lds_bits, bool word32, uint32_t n_max) {
+template <typename W>
+const void *kernel_of(bool lds_bits, bool in_bits) {
+    if (!lds_bits) return reinterpret_cast<const void *>(&wilson_coop_kernel<false, W, false>);
+    return in_bits ? reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, true>)
+                   : reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, false>);
+}
+
+hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t n_max) {
     if (!lds_bits) return hipSuccess;
-    const int lds = static_cast<int>(coop_lds_bytes(n_max));
-    const void *f = word32 ? reinterpret_cast<const void *>(&wilson_coop_kernel<true, uint32_t>)
-                           : reinterpret_cast<const void *>(&wilson_coop_kernel<true, unsigned long long>);
+    const int lds = static_cast<int>((in_bits ? 2 : 1) * coop_lds_bytes(n_max));
+    const void *f = word32 ? kernel_of<uint32_t>(true, in_bits)
+                           : kernel_of<unsigned long long>(true, in_bits);
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool word32,
-                              hipStream_t stream) {
+hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
+                              bool word32, hipStream_t stream) {
     if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
+    if (lds_bits && in_bits)
+        return word32 ? launch_one<true, uint32_t, true>(a, threads, stream)
+                      : launch_one<true, unsigned long long, true>(a, threads, stream);
     if (lds_bits)
-        return word32 ? launch_one<true, uint32_t>(a, threads, stream)
-                      : launch_one<true, unsigned long long>(a, threads, stream);
-    return word32 ? launch_one<false, uint32_t>(a, threads, stream)
-                  : launch_one<false, unsigned long long>(a, threads, stream);
+        return word32 ? launch_one<true, uint32_t, false>(a, threads, stream)
+                      : launch_one<true, unsigned long long, false>(a, threads, stream);
+    return word32 ? launch_one<false, uint32_t, false>(a, threads, stream)
+                  : launch_one<false, unsigned long long, false>(a, threads, stream);
 }
 
 }  // namespace fc

@@ -189,16 +189,19 @@ def test_grid_tree_subset_bit_exact(gpu_lib, alpha, sampler):
     _compare(gpu_lib, g, alpha, 0, 100, 6, sampler=sampler)
 
 
-@pytest.mark.parametrize("shape", [(64, 1, 1, 1), (256, 3, 0, 1), (1024, 1, 1, 0), (512, 2, 0, 0)])
+@pytest.mark.parametrize("shape", [(64, 1, 1, 1, 1), (256, 3, 0, 1, 1), (1024, 1, 1, 0, 0),
+                                   (512, 2, 0, 0, 0), (512, 4, 1, 1, 0), (256, 2, 1, 0, 1)])
 def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
     """Workgroup sampler under other launch shapes, with the settled bitmap
-    in LDS and in global memory, 32- and 64-bit tree words: identical results."""
+    in LDS or global memory, with or without the in-arrow bitmap, 32- and
+    64-bit tree words: identical results."""
     fc = gpu_lib
-    threads, wg, lds, w32 = shape
+    threads, wg, lds, w32, inb = shape
     fc.set_option("coop_threads", threads)
     fc.set_option("coop_wg_per_cu", wg)
     fc.set_option("coop_lds_bits", lds)
     fc.set_option("coop_word32", w32)
+    fc.set_option("coop_in_bits", inb)
     try:
         g = inputs.barabasi_albert(20_000, 3, 7)
         _compare(fc, g, 1.5, 77, 9, 40, sampler="coop")
@@ -206,9 +209,10 @@ def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
         _compare(fc, g2, 2.0, 78, 0, 20, sampler="coop")
     finally:
         fc.set_option("coop_threads", 512)
-        fc.set_option("coop_wg_per_cu", 2)
+        fc.set_option("coop_wg_per_cu", 4)
         fc.set_option("coop_lds_bits", 1)
         fc.set_option("coop_word32", 1)
+        fc.set_option("coop_in_bits", 1)
 
 
 def test_set_option_rejects_bad_values(gpu_lib):
