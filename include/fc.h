@@ -138,7 +138,7 @@ FC_API int fc_destroy(fc_ctx *ctx);
 FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
 
 /* Launch-shape options of a context (results never depend on them):
- *   "coop_threads"    threads per workgroup of the workgroup sampler (64..1024, multiple of 64)
+ *   "coop_threads"    threads per workgroup of the workgroup sampler (64..512, multiple of 64)
  *   "coop_wg_per_cu"  workgroups per CU of the workgroup sampler (>= 1)
  *   "coop_lds_bits"   settled bitmap in LDS: 1 when it fits, 0 never (global memory)
  *   "coop_word32"     32-bit per-vertex tree words when they fit: 1 (default) or 0 (64-bit)

@@ -205,7 +205,15 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                                 (lds_bits ? 0u : 4u * nwords);
         slots = std::max<size_t>(1, ctx->state_budget / per_slot);
         slots = std::min<size_t>(slots, tree_count);
-        slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * ctx->coop_wg_per_cu);
+        // persistent workgroups: as many as requested per CU, but never more
+        // than fit at once (a workgroup that starts late finds the queue empty)
+        FC_HIP(ctx, fc::coop_set_lds_limit(lds_bits, in_bits, word32, static_cast<uint32_t>(g.n)),
+               "coop LDS limit");
+        uint32_t per_cu = ctx->coop_wg_per_cu;
+        const int fit = fc::coop_max_active(ctx->coop_threads, lds_bits, in_bits, word32,
+                                            static_cast<uint32_t>(g.n));
+        if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
+        slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
         if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
         if ((rc = ensure(ctx, ctx->cword, wbytes * static_cast<size_t>(g.n) * slots, "tree words")))
             return rc;
@@ -284,7 +292,6 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     if (use_coop) {
-        FC_HIP(ctx, fc::coop_set_lds_limit(lds_bits, in_bits, word32, c.n_max), "coop LDS limit");
         FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, ctx->stream),
                "wilson_coop launch");
     }
@@ -386,9 +393,9 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
             hipSuccess && lds > 0)
         ctx->max_lds = static_cast<size_t>(lds);
     ctx->coop_threads = env_u32("FC_COOP_THREADS", 512);
-    if (ctx->coop_threads < 64 || ctx->coop_threads > 1024 || ctx->coop_threads % 64)
-        ctx->coop_threads = 256;
-    ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 4));
+    if (ctx->coop_threads < 64 || ctx->coop_threads > 512 || ctx->coop_threads % 64)
+        ctx->coop_threads = 512;
+    ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 3));
     ctx->coop_in_bits = env_u32("FC_COOP_IN_BITS", 1) != 0;
     {
         const char *fs = std::getenv("FC_SAMPLER");
@@ -425,7 +432,7 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     if (!ctx || !key) return FC_ERR_ARG;
     const std::string k(key);
     if (k == "coop_threads") {
-        if (value < 64 || value > 1024 || value % 64) return set_err(ctx, FC_ERR_ARG, "coop_threads");
+        if (value < 64 || value > 512 || value % 64) return set_err(ctx, FC_ERR_ARG, "coop_threads");
         ctx->coop_threads = static_cast<uint32_t>(value);
     } else if (k == "coop_wg_per_cu") {
         if (value < 1 || value > 64) return set_err(ctx, FC_ERR_ARG, "coop_wg_per_cu");

@@ -87,8 +87,10 @@ int size_scratch(fc_batch *b, uint32_t slots) {
     return FC_OK;
 }
 
-uint32_t slots_for(fc_batch *b, uint32_t wg_per_cu) {
+uint32_t slots_for(fc_batch *b, uint32_t threads, uint32_t wg_per_cu) {
     const size_t n = b->n_max;
+    const int fit = fc::coop_max_active(threads, b->lds_bits, b->in_bits, b->word32, b->n_max);
+    if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
     const size_t per_slot = ((b->word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
                             (b->lds_bits ? 0 : 4 * ((n + 31) / 32));
     size_t slots = std::max<size_t>(1, b->ctx->state_budget / per_slot);
@@ -102,7 +104,7 @@ uint32_t slots_for(fc_batch *b, uint32_t wg_per_cu) {
 int autotune(fc_batch *b) {
     fc_ctx *ctx = b->ctx;
     int rc;
-    const uint32_t cand[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+    const uint32_t cand[][2] = {{256, 3}, {256, 6}, {512, 2}, {512, 3}, {128, 12}};
     // throw-away job table: same graphs and records, outputs into one scratch R
     std::vector<fc::CoopJob> tab(b->ntab);
     FC_HIP(ctx, hipMemcpy(tab.data(), b->jobtab.ptr, sizeof(fc::CoopJob) * tab.size(),
@@ -125,7 +127,7 @@ int autotune(fc_batch *b) {
     float best = 1e30f;
     uint32_t best_t = b->threads, best_w = b->wg_per_cu;
     for (const auto &c : cand) {
-        const uint32_t slots = slots_for(b, c[1]);
+        const uint32_t slots = slots_for(b, c[0], c[1]);
         if ((rc = size_scratch(b, slots))) break;
         fc::CoopArgs a = b->args;
         a.jobs = static_cast<const fc::CoopJob *>(tmp_tab.ptr);
@@ -311,7 +313,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     FC_HIP(ctx, fc::coop_set_lds_limit(b->lds_bits, b->in_bits, b->word32, n_max), "coop LDS limit");
 
     if ((flags & FC_FLAG_AUTOTUNE) && (rc = autotune(b))) return fail(rc);
-    if ((rc = size_scratch(b, slots_for(b, b->wg_per_cu)))) return fail(rc);
+    if ((rc = size_scratch(b, slots_for(b, b->threads, b->wg_per_cu)))) return fail(rc);
 
     // capture the run: counter reset, epoch reset, sampling kernel
     FC_HIP(ctx, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");

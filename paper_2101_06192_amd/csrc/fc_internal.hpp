@@ -37,7 +37,7 @@ struct fc_ctx {
     uint32_t cu_count = 256;
     size_t max_lds = 65536;       // dynamic LDS a workgroup may use
     uint32_t coop_threads = 512;  // threads per workgroup in the workgroup sampler
-    uint32_t coop_wg_per_cu = 4;  // resident workgroups per CU in the workgroup sampler
+    uint32_t coop_wg_per_cu = 3;  // resident workgroups per CU in the workgroup sampler
     uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop (environment override)
     bool coop_lds_bits = true;    // settled bitmap in LDS when it fits
     bool coop_word32 = true;      // 32-bit tree words when target and count fit

@@ -95,6 +95,8 @@ hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits
 // Raise the kernel's dynamic-LDS limit for the bitmaps of n_max bits (call
 // before launching, outside stream capture).
 hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
+// Workgroups of the chosen variant that fit on one CU at once (0 if unknown).
+int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 
 // p[0..count) = value (a kernel, so that it can sit in a captured HIP graph).

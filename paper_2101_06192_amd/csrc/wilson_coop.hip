@@ -77,6 +77,10 @@ __device__ __forceinline__ void wg_fetch_or(uint32_t *p, uint32_t v) {
 enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedraw, kPhOutput,
                    kPhCount };
 
+// A value read from LDS that every lane of the wave holds: tell the compiler,
+// so that what depends on it lives in scalar registers.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // One arrow of v in tree t with draw index k.
 __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32_t key1,
                                          uint32_t v, uint32_t k, uint32_t t) {
@@ -92,7 +96,10 @@ __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32
 // when the vertex is peeled -- so peel level 0 and cycle detection read LDS
 // instead of the global tree words.
 template <bool kLdsBits, typename W, bool kInBits>
-__global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
+// At most 512 threads, and registers for six waves per SIMD (24 per CU):
+// the phases are latency bound, so resident waves matter more than unrolling.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6)))
+void wilson_coop_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_dyn[];
     __shared__ uint32_t s_item, s_u, s_p, s_cycles;
     __shared__ unsigned long long s_digest, s_roots;
@@ -115,13 +122,18 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
     unsigned int err = 0;
     uint32_t epoch = 0;  // per-slot tree sequence number of this launch (kk was zeroed)
 
-    unsigned long long ph[kPhCount] = {0, 0, 0, 0, 0, 0, 0};
-    unsigned long long ph_t = a.phase_ticks ? wall_clock64() : 0ull;
+    // phase accounting lives in LDS (thread 0 only) to keep it out of registers
+    __shared__ unsigned long long s_ph[kPhCount + 1];
+    const bool timing = a.phase_ticks != nullptr;
+    if (timing && tid == 0) {
+        for (int i = 0; i < kPhCount; ++i) s_ph[i] = 0;
+        s_ph[kPhCount] = wall_clock64();
+    }
     auto mark = [&](int which) {
-        if (a.phase_ticks && tid == 0) {
+        if (timing && tid == 0) {
             const unsigned long long now = wall_clock64();
-            ph[which] += now - ph_t;
-            ph_t = now;
+            s_ph[which] += now - s_ph[kPhCount];
+            s_ph[kPhCount] = now;
         }
     };
 
@@ -129,9 +141,9 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
         __syncthreads();
         if (tid == 0) s_item = atomicAdd(a.queue, 1u);
         __syncthreads();
-        const uint32_t item = s_item;
+        const uint32_t item = uniform(s_item);
         if (item >= a.item_count) break;
-        const CoopJob job = a.jobs ? a.jobs[a.item_job[item]] : a.single;
+        const CoopJob job = a.jobs ? a.jobs[uniform(a.item_job[item])] : a.single;
         const uint32_t ti = item - job.first_item;
         const uint32_t t = job.tree_begin + ti;
         const uint32_t n = job.n;
@@ -176,7 +188,7 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
         }
         __syncthreads();
         mark(kPhDraw0);
-        uint32_t ucount = s_u;
+        uint32_t ucount = uniform(s_u);
         uint64_t *U = listA, *Unext = listB;
         unsigned long long draws = n;
         uint32_t rounds = 0;
@@ -199,59 +211,59 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             __syncthreads();
             mark(kPhIndeg);
             // level 0 of the peel: no in-arrows
-            for (uint32_t base = wave_base; base < ucount; base += 4 * T) {
-                uint64_t it[4];
-                bool leaf[4];
+            for (uint32_t base = wave_base; base < ucount; base += 2 * T) {
+                uint64_t it[2];
+                bool leaf[2];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 2; ++q) {
                     const uint32_t i = base + q * T + lane;
                     it[q] = i < ucount ? U[i] : 0ull;
                     leaf[q] = false;
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 2; ++q) {
                     const uint32_t i = base + q * T + lane;
                     if (i < ucount)
                         leaf[q] = kInBits ? !has_in(lo32(it[q])) : cnt_of(word[lo32(it[q])]) == 0u;
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) wave_append(peel, &s_p, it[q], leaf[q]);
+                for (int q = 0; q < 2; ++q) wave_append(peel, &s_p, it[q], leaf[q]);
             }
             __syncthreads();
             mark(kPhLevel0);
-            uint32_t lo = 0, hi = s_p, nlev = 0;
+            uint32_t lo = 0, hi = uniform(s_p), nlev = 0;
             if (tid == 0) lvl[0] = 0;
             // peel level by level: a peeled vertex's target loses one in-arrow; the
             // atomic returns the target's own arrow, which goes into the list with it
             while (lo < hi) {
                 if (tid == 0) lvl[nlev + 1] = hi;
-                for (uint32_t base = lo + wave_base; base < hi; base += 4 * T) {
-                    uint32_t tg[4];
-                    W old[4];
-                    bool push[4];
+                for (uint32_t base = lo + wave_base; base < hi; base += 2 * T) {
+                    uint32_t tg[2];
+                    W old[2];
+                    bool push[2];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < 2; ++q) {
                         const uint32_t i = base + q * T + lane;
                         tg[q] = i < hi ? hi32(peel[i]) : n;
                         push[q] = false;
                         old[q] = 0;
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < 2; ++q)
                         if (!is_settled(tg[q])) old[q] = wg_fetch_add(&word[tg[q]], cnt_minus_one);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < 2; ++q) {
                         push[q] = !is_settled(tg[q]) && cnt_of(old[q]) == 1u;
                         if (kInBits && push[q]) clear_in(tg[q]);
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < 2; ++q)
                         wave_append(peel, &s_p, pair(tg[q], target_of(old[q])), push[q]);
                 }
                 __syncthreads();
                 ++nlev;
                 lo = hi;
-                hi = s_p;
+                hi = uniform(s_p);
                 __syncthreads();  // every wave has read s_p before the next level appends
             }
             const uint32_t peeled = hi;
@@ -262,7 +274,7 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             }
             // reverse sweep: settled when the arrow reaches u* or a settled vertex
             for (int32_t L = static_cast<int32_t>(nlev) - 1; L >= 0; --L) {
-                const uint32_t a0 = lvl[L], a1 = lvl[L + 1];
+                const uint32_t a0 = uniform(lvl[L]), a1 = uniform(lvl[L + 1]);
                 for (uint32_t i = a0 + tid; i < a1; i += T) {
                     const uint64_t p = peel[i];
                     if (is_settled(hi32(p))) set_settled(lo32(p));
@@ -277,22 +289,22 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
             }
             __syncthreads();
             uint32_t my_cycles = 0;
-            for (uint32_t base = wave_base; base < ucount; base += 4 * T) {
-                uint64_t it[4];
-                W w[4];
-                bool keep[4];
+            for (uint32_t base = wave_base; base < ucount; base += 2 * T) {
+                uint64_t it[2];
+                W w[2];
+                bool keep[2];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 2; ++q) {
                     const uint32_t i = base + q * T + lane;
                     it[q] = i < ucount ? U[i] : pair(n, n);
                     keep[q] = false;
                     w[q] = 0;
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 2; ++q)
                     if (!kInBits && !is_settled(lo32(it[q]))) w[q] = word[lo32(it[q])];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 2; ++q) {
                     const uint32_t v = lo32(it[q]);
                     if (is_settled(v)) continue;
                     const bool on_cycle = kInBits ? has_in(v) : cnt_of(w[q]) > 0u;
@@ -313,13 +325,13 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) wave_append(Unext, &s_u, it[q], keep[q]);
+                for (int q = 0; q < 2; ++q) wave_append(Unext, &s_u, it[q], keep[q]);
             }
             if (my_cycles) atomicAdd(&s_cycles, my_cycles);
             __syncthreads();
             mark(kPhRedraw);
-            draws += s_cycles;
-            ucount = s_u;
+            draws += uniform(s_cycles);
+            ucount = uniform(s_u);
             uint64_t *tmp = U;
             U = Unext;
             Unext = tmp;
@@ -363,8 +375,8 @@ __global__ __launch_bounds__(1024) void wilson_coop_kernel(CoopArgs a) {
         }
         mark(kPhOutput);
     }
-    if (a.phase_ticks && tid == 0)
-        for (int i = 0; i < kPhCount; ++i) atomicAdd(&a.phase_ticks[i], ph[i]);
+    if (timing && tid == 0)
+        for (int i = 0; i < kPhCount; ++i) atomicAdd(&a.phase_ticks[i], s_ph[i]);
     if (err) atomicOr(&a.totals->error, err);
 }
 
@@ -384,6 +396,17 @@ const void *kernel_of(bool lds_bits, bool in_bits) {
     if (!lds_bits) return reinterpret_cast<const void *>(&wilson_coop_kernel<false, W, false>);
     return in_bits ? reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, true>)
                    : reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, false>);
+}
+
+int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max) {
+    const size_t lds = lds_bits ? (in_bits ? 2 : 1) * coop_lds_bytes(n_max) : 0;
+    const void *f = word32 ? kernel_of<uint32_t>(lds_bits, in_bits)
+                           : kernel_of<unsigned long long>(lds_bits, in_bits);
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, static_cast<int>(threads), lds) !=
+        hipSuccess)
+        return 0;
+    return blocks;
 }
 
 hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t n_max) {

@@ -189,7 +189,7 @@ def test_grid_tree_subset_bit_exact(gpu_lib, alpha, sampler):
     _compare(gpu_lib, g, alpha, 0, 100, 6, sampler=sampler)
 
 
-@pytest.mark.parametrize("shape", [(64, 1, 1, 1, 1), (256, 3, 0, 1, 1), (1024, 1, 1, 0, 0),
+@pytest.mark.parametrize("shape", [(64, 1, 1, 1, 1), (256, 3, 0, 1, 1), (448, 1, 1, 0, 0),
                                    (512, 2, 0, 0, 0), (512, 4, 1, 1, 0), (256, 2, 1, 0, 1)])
 def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
     """Workgroup sampler under other launch shapes, with the settled bitmap
@@ -209,7 +209,7 @@ def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
         _compare(fc, g2, 2.0, 78, 0, 20, sampler="coop")
     finally:
         fc.set_option("coop_threads", 512)
-        fc.set_option("coop_wg_per_cu", 4)
+        fc.set_option("coop_wg_per_cu", 3)
         fc.set_option("coop_lds_bits", 1)
         fc.set_option("coop_word32", 1)
         fc.set_option("coop_in_bits", 1)
@@ -217,7 +217,7 @@ def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
 
 def test_set_option_rejects_bad_values(gpu_lib):
     fc = gpu_lib
-    for key, val in (("coop_threads", 100), ("coop_threads", 2048), ("coop_wg_per_cu", 0),
+    for key, val in (("coop_threads", 100), ("coop_threads", 1024), ("coop_wg_per_cu", 0),
                      ("lanes_per_wave", 65), ("nonsense", 1), ("coop_lds_bits", 2)):
         with pytest.raises(fc.FCError) as e:
             fc.set_option(key, val)
