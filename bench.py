@@ -160,6 +160,14 @@ def main():
 
     cpu = cpu_baseline(g, args.cpu_trees) if args.cpu_trees > 0 else None
 
+    # the random-access ceiling the sampler runs against: independent random
+    # 4-byte loads and atomic adds over a 4 GiB footprint (far beyond caches)
+    ceiling = None
+    if not args.no_eps:
+        ceiling = {"footprint_bytes": 4 << 30,
+                   "random_loads_per_s": fc.probe_random_access(4 << 30, False, dev),
+                   "random_atomics_per_s": fc.probe_random_access(4 << 30, True, dev)}
+
     line = {
         "metric": "USTs/s and walk steps/s (GB/s vs roofline); time to eps=0.1 diag(Omega)",
         "value": value,
@@ -182,7 +190,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": f"{sampler}_kernel", "kernel_ms": ms_kernel,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "random_access_ceiling": ceiling},
         "cpu_baseline": cpu,
     }
     if args.phase_timing:

@@ -263,6 +263,15 @@ FC_API int fc_solve(fc_ctx *ctx, const fc_graph *g, double alpha, const double *
                     int32_t nrhs, double rtol, int32_t precision, int32_t max_iters, int32_t flags,
                     int32_t *iters_out, double *relres_out);
 
+/* Measurement utility (not part of the method): rate of independent random
+ * 4-byte accesses -- loads (atomics = 0) or atomic adds (atomics = 1) -- over
+ * a device footprint of footprint_bytes (rounded down to a power of two,
+ * >= 4 KiB), in accesses per second, into *rate_out.  The library allocates
+ * and frees the footprint.  The sampler's random gathers and in-arrow
+ * atomics are bounded by these rates. */
+FC_API int fc_probe_random_access(fc_ctx *ctx, uint64_t footprint_bytes, int32_t atomics,
+                                  double *rate_out);
+
 /* Message for an error code / for the last failing call on a context. */
 FC_API const char *fc_error_string(int code);
 FC_API const char *fc_last_error(fc_ctx *ctx);

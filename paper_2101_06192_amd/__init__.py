@@ -115,6 +115,8 @@ def lib() -> ctypes.CDLL:
                                                i32, ctypes.POINTER(vp)]),
             "fc_batch_run": (ctypes.c_int, [vp, sp]),
             "fc_batch_destroy": (ctypes.c_int, [vp]),
+            "fc_probe_random_access": (ctypes.c_int, [vp, ctypes.c_uint64, i32,
+                                                      ctypes.POINTER(ctypes.c_double)]),
             "fc_error_string": (ctypes.c_char_p, [ctypes.c_int]),
             "fc_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -438,3 +440,12 @@ def solve(g, alpha: float, B, X0=None, rtol: float = 1e-9, precision: str = "fp3
                              FC_FLAG_TRUSTED_GRAPH if trusted else 0, ctypes.byref(it),
                              ctypes.c_void_p(rel.ctypes.data)))
     return {"X": X if as_torch else X.cpu().numpy(), "iters": int(it.value), "relres": rel[:k]}
+
+
+def probe_random_access(footprint_bytes: int, atomics: bool = False, device="cuda:0") -> float:
+    """Random 4-byte accesses per second over a footprint (fc_probe_random_access)."""
+    ctx = context(device)
+    out = ctypes.c_double(0.0)
+    ctx.check(lib().fc_probe_random_access(ctx.handle, int(footprint_bytes), int(bool(atomics)),
+                                           ctypes.byref(out)))
+    return float(out.value)

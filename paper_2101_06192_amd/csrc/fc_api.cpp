@@ -570,6 +570,41 @@ int fc_farness(fc_ctx *ctx, const fc_graph *g, const fc_params *params, double *
                            stats);
 }
 
+int fc_probe_random_access(fc_ctx *ctx, uint64_t footprint_bytes, int32_t atomics,
+                           double *rate_out) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    if (!rate_out || footprint_bytes < 4096 || (atomics != 0 && atomics != 1))
+        return set_err(ctx, FC_ERR_ARG, "need rate_out, footprint >= 4 KiB, atomics 0 or 1");
+    uint64_t words = 1;
+    while (words * 2 * 4 <= footprint_bytes && words < (1ull << 31)) words *= 2;
+    DevBuf buf;
+    if ((rc = ensure(ctx, buf, 4 * words + 64, "probe footprint"))) return rc;
+    uint32_t *data = static_cast<uint32_t *>(buf.ptr);
+    auto done = [&](int code) {
+        (void)hipFree(buf.ptr);
+        return code;
+    };
+    if (hipMemsetAsync(data, 0, 4 * words + 64, ctx->stream) != hipSuccess)
+        return done(set_err(ctx, FC_ERR_HIP, "probe memset"));
+    const uint32_t blocks = ctx->cu_count * 32, iters = 64;
+    const double accesses = static_cast<double>(blocks) * 256.0 * iters * 8.0;
+    uint32_t *sink = data + words;
+    hipError_t e = fc::launch_random_access(data, static_cast<uint32_t>(words), 4, atomics, blocks,
+                                            sink, ctx->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = fc::launch_random_access(data, static_cast<uint32_t>(words), iters, atomics, blocks, sink,
+                                     ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return done(hip_fail(ctx, e, "probe"));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    *rate_out = ms > 0.f ? accesses / (ms / 1000.0) : 0.0;
+    return done(FC_OK);
+}
+
 const char *fc_error_string(int code) {
     switch (code) {
         case FC_OK: return "ok";

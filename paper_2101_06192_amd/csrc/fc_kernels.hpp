@@ -103,6 +103,11 @@ size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,
                            hipStream_t stream);
 
+// Memory probe: blocks x 256 threads, each issuing iters x 8 random 4-byte
+// loads (or atomic adds) into data[0 .. words_pow2), words_pow2 a power of two.
+hipError_t launch_random_access(uint32_t *data, uint32_t words_pow2, uint32_t iters, bool atomics,
+                                uint32_t blocks, uint32_t *sink, hipStream_t stream);
+
 // S = sum of R (exact, uint64) into *sum (caller zeroes it).
 hipError_t launch_sum_u32(const uint32_t *x, int32_t n, unsigned long long *sum,
                           hipStream_t stream);
