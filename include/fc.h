@@ -80,9 +80,14 @@ extern "C" {
 #define FC_FLAG_TRUSTED_GRAPH 1 /* skip the device-side CSR validation */
 #define FC_FLAG_AUTOTUNE 8      /* fc_batch_create: time candidate launch shapes, keep the fastest */
 #define FC_FLAG_SAMPLER_LANE 2  /* force the lane-per-tree sampler */
-#define FC_FLAG_SAMPLER_COOP 4  /* force the workgroup-per-tree sampler */
-/* Neither sampler flag: the library picks one from n and the tree count.
- * Both samplers produce identical results (same trees, same counts). */
+#define FC_FLAG_SAMPLER_COOP 4  /* force the workgroup-per-tree sampler, counters in global memory */
+#define FC_FLAG_SAMPLER_LDS 16  /* force the workgroup-per-tree sampler with every in-arrow
+                                   counter in LDS; FC_ERR_UNSUPPORTED when one tree's
+                                   counters and settled bitmap do not fit */
+/* No sampler flag: the library picks lane or workgroup from n and the tree
+ * count, and for the workgroup sampler LDS counters whenever they fit (option
+ * "coop_lds_counts").  All samplers produce identical results (same trees,
+ * same counts). */
 
 typedef struct fc_ctx fc_ctx;
 
@@ -122,7 +127,9 @@ typedef struct {
     uint64_t digest_sum;     /* sum over trees of the per-tree digest, mod 2^64 */
     double ms_sample;        /* device time of the sampling kernel */
     double ms_total;         /* host wall time of the call */
-    char sampler[16];        /* "wilson_lane", "wilson_coop", or "batch:<threads>x<wg per CU>" */
+    char sampler[16];        /* "wilson_lane", "wilson_coop", "wilson_lds" (workgroup sampler,
+                                counters in LDS), or for a batch "batch:<threads>x<wg per CU>"
+                                ("ldsbatch:..." with counters in LDS) */
     double phase_ms[8];      /* workgroup sampler with option "phase_timing": average
                                 milliseconds per workgroup spent in: first arrows,
                                 in-arrow counting, peel level 0, peel levels, reverse
@@ -143,6 +150,10 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "coop_lds_bits"   settled bitmap in LDS: 1 when it fits, 0 never (global memory)
  *   "coop_word32"     32-bit per-vertex tree words when they fit: 1 (default) or 0 (64-bit)
  *   "coop_in_bits"    second LDS bitmap (vertices with in-arrows) when it fits: 1 (default) or 0
+ *   "coop_lds_counts" 1 (default): the workgroup sampler keeps every in-arrow counter of a
+ *                     tree in LDS (degree-sized fields on degree-class relabelled ids) when
+ *                     they and the settled bitmap fit; 0: counters in global tree words
+ *   "lds_threads"     threads per workgroup of that LDS-counter variant (64..1024, multiple of 64)
  *   "lanes_per_wave"  active lanes per wave of the lane sampler (1..64)
  *   "max_slots"       cap on trees in flight (0 = memory bound only)
  *   "phase_timing"    1: the workgroup sampler reports per-phase times in fc_stats

@@ -37,7 +37,9 @@ FC_EST_ALG1_LITERAL = 1
 FC_FLAG_TRUSTED_GRAPH = 1
 FC_FLAG_SAMPLER_LANE = 2
 FC_FLAG_SAMPLER_COOP = 4
-SAMPLERS = {None: 0, "auto": 0, "lane": FC_FLAG_SAMPLER_LANE, "coop": FC_FLAG_SAMPLER_COOP}
+FC_FLAG_SAMPLER_LDS = 16
+SAMPLERS = {None: 0, "auto": 0, "lane": FC_FLAG_SAMPLER_LANE, "coop": FC_FLAG_SAMPLER_COOP,
+            "lds": FC_FLAG_SAMPLER_LDS}
 
 
 class FCError(RuntimeError):

@@ -170,11 +170,14 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
 
     // which sampler: the lane sampler needs many trees to fill the GPU; the
     // workgroup sampler parallelises inside each tree
-    bool use_coop;
-    if (p->flags & FC_FLAG_SAMPLER_LANE) use_coop = false;
-    else if (p->flags & FC_FLAG_SAMPLER_COOP) use_coop = true;
-    else if (ctx->force_sampler) use_coop = ctx->force_sampler == 2;
-    else use_coop = tree_count < 16u * ctx->cu_count * 64u / 4u || g.n >= 65536;
+    // mode: 1 lane, 2 workgroup with global counters, 3 workgroup with LDS counters
+    uint32_t mode = 0;
+    if (p->flags & FC_FLAG_SAMPLER_LANE) mode = 1;
+    else if (p->flags & FC_FLAG_SAMPLER_COOP) mode = 2;
+    else if (p->flags & FC_FLAG_SAMPLER_LDS) mode = 3;
+    else mode = ctx->force_sampler;
+    const bool use_coop = mode == 0 ? tree_count < 16u * ctx->cu_count * 64u / 4u || g.n >= 65536
+                                    : mode >= 2;
     // expected steps per tree are at most n + 2 alpha m; a valid run never
     // comes near 256 times that, so exceeding it marks a fault, not bad luck
     const double cap = 256.0 * (static_cast<double>(g.n) + p->alpha * static_cast<double>(g.nnz)) +
@@ -186,14 +189,119 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::LaneArgs a{};
     fc::CoopArgs c{};
     bool lds_bits = false, in_bits = false, word32 = false;
+    bool use_lds = false;
+    uint32_t lds_words = 0;
     uint32_t tshift = 32;
+    unsigned int dmax = 0;
     if (use_coop) {
+        // LDS-counter variant when the degree-class count fields and the settled
+        // bitmap of one tree fit in LDS (at least 4 + 1 bits per vertex)
+        const bool try_lds = (mode == 3 || (mode == 0 && ctx->coop_lds_counts)) &&
+                             static_cast<size_t>(g.n) * 5u <= 8u * ctx->max_lds;
+        const uint32_t nb = fc::relabel_blocks(static_cast<uint32_t>(g.n));
+        if (try_lds) {
+            if ((rc = ensure(ctx, ctx->rl_blk, 16u * nb, "class counts")) ||
+                (rc = ensure(ctx, ctx->rl_base, 16u * nb, "class offsets")))
+                return rc;
+            FC_HIP(ctx, fc::launch_class_bounds(g.row_ptr, static_cast<uint32_t>(g.n),
+                                                static_cast<uint32_t *>(ctx->rl_blk.ptr),
+                                                static_cast<uint32_t *>(ctx->rl_base.ptr),
+                                                sm->class_bounds, ctx->stream),
+                   "class bounds");
+        }
         // 32-bit tree words when target and in-arrow count both fit (the count of
         // a vertex never exceeds its degree)
-        unsigned int dmax = 0;
+        unsigned int cb[4] = {0, 0, 0, 0};
         FC_HIP(ctx, hipMemcpyAsync(&dmax, &sm->dmax, sizeof(dmax), hipMemcpyDeviceToHost, ctx->stream),
                "copy dmax");
+        if (try_lds)
+            FC_HIP(ctx, hipMemcpyAsync(cb, sm->class_bounds, sizeof(cb), hipMemcpyDeviceToHost,
+                                       ctx->stream), "copy class bounds");
         FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "build_vrec");
+        if (try_lds) {
+            const fc::CountLayout L = fc::count_layout(static_cast<uint32_t>(g.n), cb[0], cb[1], cb[2]);
+            if (4u * static_cast<size_t>(L.words) + kLdsStaticBytes <= ctx->max_lds) {
+                use_lds = true;
+                lds_words = L.words;
+            }
+        }
+        if (mode == 3 && !use_lds)
+            return set_err(ctx, FC_ERR_UNSUPPORTED,
+                           "the in-arrow counters of one tree do not fit in LDS");
+        if (use_lds) {
+            kname = "wilson_lds";
+            const size_t n = static_cast<size_t>(g.n);
+            if ((rc = ensure(ctx, ctx->rl_inv, 4u * n, "relabel inverse")) ||
+                (rc = ensure(ctx, ctx->rl_orig, 4u * n, "relabel ids")) ||
+                (rc = ensure(ctx, ctx->rl_vrec, sizeof(fc::VRec) * n, "relabelled records")) ||
+                (rc = ensure(ctx, ctx->rl_adj, 8u * static_cast<size_t>(g.nnz), "relabelled adjacency")))
+                return rc;
+            FC_HIP(ctx, fc::launch_relabel_graph(g.row_ptr, g.col_idx, static_cast<uint32_t>(g.n),
+                                                 g.nnz, static_cast<const uint32_t *>(ctx->rl_base.ptr),
+                                                 static_cast<uint32_t *>(ctx->rl_inv.ptr),
+                                                 static_cast<uint32_t *>(ctx->rl_orig.ptr),
+                                                 static_cast<unsigned long long *>(ctx->rl_adj.ptr),
+                                                 ctx->stream),
+                   "relabel");
+            FC_HIP(ctx, fc::launch_relabel_vrec(vrec, static_cast<const uint32_t *>(ctx->rl_inv.ptr),
+                                                static_cast<uint32_t>(g.n),
+                                                static_cast<fc::VRec *>(ctx->rl_vrec.ptr), ctx->stream),
+                   "relabel records");
+            const size_t per_slot = (8u + 8u + 24u + 4u) * n + 8u;
+            slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+            slots = std::min<size_t>(slots, tree_count);
+            FC_HIP(ctx, fc::lds_set_limit(lds_words), "LDS limit");
+            uint32_t per_cu = ctx->coop_wg_per_cu;
+            const int fit = fc::lds_max_active(ctx->lds_threads, lds_words);
+            if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
+            slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
+            if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
+            if ((rc = ensure(ctx, ctx->cword, 8u * n * slots, "tree words")) ||
+                (rc = ensure(ctx, ctx->ckk, 8u * n * slots, "draw counts")) ||
+                (rc = ensure(ctx, ctx->clists, 24u * n * slots, "lists")) ||
+                (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")))
+                return rc;
+            FC_HIP(ctx, hipMemsetAsync(ctx->ckk.ptr, 0, 8u * n * slots, ctx->stream),
+                   "memset draw counts");
+            c.word = ctx->cword.ptr;
+            c.kk = static_cast<uint64_t *>(ctx->ckk.ptr);
+            c.lists = static_cast<uint64_t *>(ctx->clists.ptr);
+            c.levels = static_cast<uint32_t *>(ctx->clevels.ptr);
+            c.bits = nullptr;
+            c.n_max = static_cast<uint32_t>(g.n);
+            c.slots = static_cast<uint32_t>(slots);
+            c.item_count = tree_count;
+            c.key0 = static_cast<uint32_t>(p->seed);
+            c.key1 = static_cast<uint32_t>(p->seed >> 32);
+            c.max_rounds = 0x40000000u;
+            c.queue = &sm->queue;
+            c.totals = &sm->totals;
+            c.jobs = nullptr;
+            c.item_job = nullptr;
+            fc::CoopJob &j = c.single;
+            j.vrec = static_cast<const fc::VRec *>(ctx->rl_vrec.ptr);
+            j.col_idx = g.col_idx;
+            j.adj = static_cast<const unsigned long long *>(ctx->rl_adj.ptr);
+            j.orig = static_cast<const uint32_t *>(ctx->rl_orig.ptr);
+            j.n = static_cast<uint32_t>(g.n);
+            j.n0 = cb[0];
+            j.n1 = cb[1];
+            j.n2 = cb[2];
+            j.tshift = 32;
+            j.stream_id = p->stream_id;
+            j.tree_begin = tree_begin;
+            j.first_item = 0;
+            j.step_cap = step_cap;
+            j.root_counts = root_counts;
+            j.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
+            j.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
+            j.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
+            j.parents = parents;
+            j.tree_visits = tree_visits;
+            c.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
+        }
+    }
+    if (use_coop && !use_lds) {
         word_layout(static_cast<uint32_t>(g.n), dmax, ctx->coop_word32, &tshift, &word32);
         const size_t wbytes = word32 ? 4u : 8u;
         const size_t nwords = (static_cast<size_t>(g.n) + 31u) / 32u;
@@ -260,7 +368,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         j.parents = parents;
         j.tree_visits = tree_visits;
         c.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
-    } else {
+    } else if (!use_coop) {
         // trees in flight: bounded by the tree count and by the state budget
         const size_t per_slot = sizeof(uint64_t) * static_cast<size_t>(g.n);
         slots = std::max<size_t>(1, ctx->state_budget / per_slot);
@@ -291,11 +399,13 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     }
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
-    if (use_coop) {
+    if (use_lds) {
+        FC_HIP(ctx, fc::launch_wilson_lds(c, ctx->lds_threads, lds_words, ctx->stream),
+               "wilson_lds launch");
+    } else if (use_coop) {
         FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, ctx->stream),
                "wilson_coop launch");
-    }
-    else
+    } else
         FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
     FC_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
     fc::Totals tot;
@@ -316,7 +426,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         stats->digest_sum = tot.digest_sum;
         stats->ms_sample = ms;
         for (int i = 0; i < 8; ++i) stats->phase_ms[i] = 0.0;
-        if (use_coop && ctx->phase_timing) {
+        if ((use_coop || use_lds) && ctx->phase_timing) {
             unsigned long long ticks[8];
             FC_HIP(ctx, hipMemcpy(ticks, sm->phase_ticks, sizeof(ticks), hipMemcpyDeviceToHost),
                    "copy phase ticks");
@@ -397,10 +507,15 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
         ctx->coop_threads = 512;
     ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 3));
     ctx->coop_in_bits = env_u32("FC_COOP_IN_BITS", 1) != 0;
+    ctx->coop_lds_counts = env_u32("FC_COOP_LDS_COUNTS", 1) != 0;
+    ctx->lds_threads = env_u32("FC_LDS_THREADS", 1024);
+    if (ctx->lds_threads < 64 || ctx->lds_threads > 1024 || ctx->lds_threads % 64)
+        ctx->lds_threads = 1024;
     {
         const char *fs = std::getenv("FC_SAMPLER");
         if (fs && !std::strcmp(fs, "lane")) ctx->force_sampler = 1;
         if (fs && !std::strcmp(fs, "coop")) ctx->force_sampler = 2;
+        if (fs && !std::strcmp(fs, "lds")) ctx->force_sampler = 3;
     }
     *out = ctx;
     return FC_OK;
@@ -414,7 +529,8 @@ int fc_destroy(fc_ctx *ctx) {
     for (DevBuf *b : {&ctx->state, &ctx->vrec, &ctx->row_ptr, &ctx->col_idx, &ctx->small,
                       &ctx->rtmp, &ctx->thr, &ctx->cword, &ctx->ckk, &ctx->clists, &ctx->clevels,
                       &ctx->cbits, &ctx->s_r64, &ctx->s_r, &ctx->s_z, &ctx->s_p, &ctx->s_q,
-                      &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small})
+                      &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small, &ctx->rl_blk,
+                      &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -446,6 +562,12 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "coop_word32") {
         if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_word32");
         ctx->coop_word32 = value == 1;
+    } else if (k == "coop_lds_counts") {
+        if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_lds_counts");
+        ctx->coop_lds_counts = value == 1;
+    } else if (k == "lds_threads") {
+        if (value < 64 || value > 1024 || value % 64) return set_err(ctx, FC_ERR_ARG, "lds_threads");
+        ctx->lds_threads = static_cast<uint32_t>(value);
     } else if (k == "phase_timing") {
         if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "phase_timing");
         ctx->phase_timing = value == 1;

@@ -10,6 +10,7 @@
 // HIP graph made of two fill kernels (counters, epoch-tagged draw counts)
 // and the sampling kernel.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,9 +27,12 @@ struct fc_batch {
     uint64_t seed = 0;
     int32_t flags = 0;
     DevBuf vrec, jobtab, item_job, word, kk, lists, levels, bits, small, dmax, scratch_r;
+    DevBuf rl_blk, rl_base, rl_bounds, rl_inv, rl_orig, rl_adj, rl_vrec;  // degree-class relabelling
     uint32_t n_max = 0, item_count = 0, slots = 0, threads = 512, wg_per_cu = 4;
     size_t ntab = 0;  // entries of the device job table (jobs that have trees)
     bool lds_bits = false, in_bits = false, word32 = true;
+    bool use_lds = false;     // LDS-counter kernel
+    uint32_t lds_words = 0;   // its dynamic LDS (largest graph of the batch)
     size_t kk_words = 0;
     fc::CoopArgs args{};
     hipStream_t stream = nullptr;
@@ -45,7 +49,8 @@ int free_batch(fc_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (DevBuf *d : {&b->vrec, &b->jobtab, &b->item_job, &b->word, &b->kk, &b->lists, &b->levels,
-                      &b->bits, &b->small, &b->dmax, &b->scratch_r})
+                      &b->bits, &b->small, &b->dmax, &b->scratch_r, &b->rl_blk, &b->rl_base,
+                      &b->rl_bounds, &b->rl_inv, &b->rl_orig, &b->rl_adj, &b->rl_vrec})
         if (d->ptr) (void)hipFree(d->ptr);
     for (hipEvent_t e : {b->ev_in, b->ev0, b->ev1})
         if (e) (void)hipEventDestroy(e);
@@ -61,6 +66,7 @@ hipError_t enqueue_run(fc_batch *b, const fc::CoopArgs &a, uint32_t threads, hip
     if (e != hipSuccess) return e;
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(b->kk.ptr), b->kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
+    if (b->use_lds) return fc::launch_wilson_lds(a, threads, b->lds_words, stream);
     return fc::launch_wilson_coop(a, threads, b->lds_bits, b->in_bits, b->word32, stream);
 }
 
@@ -69,12 +75,14 @@ int size_scratch(fc_batch *b, uint32_t slots) {
     fc_ctx *ctx = b->ctx;
     int rc;
     const size_t n = b->n_max, nwords = (n + 31) / 32;
-    const size_t wbytes = b->word32 ? 4 : 8;
+    const size_t wbytes = b->word32 && !b->use_lds ? 4 : 8;
     if ((rc = ensure(ctx, b->word, wbytes * n * slots, "batch tree words"))) return rc;
     if ((rc = ensure(ctx, b->kk, 8 * n * slots, "batch draw counts"))) return rc;
     if ((rc = ensure(ctx, b->lists, 24 * n * slots, "batch lists"))) return rc;
     if ((rc = ensure(ctx, b->levels, 4 * (n + 2) * slots, "batch levels"))) return rc;
-    if (!b->lds_bits && (rc = ensure(ctx, b->bits, 4 * nwords * slots, "batch bitmap"))) return rc;
+    if (!b->use_lds && !b->lds_bits &&
+        (rc = ensure(ctx, b->bits, 4 * nwords * slots, "batch bitmap")))
+        return rc;
     b->kk_words = n * slots;
     b->slots = slots;
     fc::CoopArgs &a = b->args;
@@ -82,17 +90,20 @@ int size_scratch(fc_batch *b, uint32_t slots) {
     a.kk = static_cast<uint64_t *>(b->kk.ptr);
     a.lists = static_cast<uint64_t *>(b->lists.ptr);
     a.levels = static_cast<uint32_t *>(b->levels.ptr);
-    a.bits = b->lds_bits ? nullptr : static_cast<uint32_t *>(b->bits.ptr);
+    a.bits = b->lds_bits || b->use_lds ? nullptr : static_cast<uint32_t *>(b->bits.ptr);
     a.slots = slots;
     return FC_OK;
 }
 
 uint32_t slots_for(fc_batch *b, uint32_t threads, uint32_t wg_per_cu) {
     const size_t n = b->n_max;
-    const int fit = fc::coop_max_active(threads, b->lds_bits, b->in_bits, b->word32, b->n_max);
+    const int fit = b->use_lds ? fc::lds_max_active(threads, b->lds_words)
+                               : fc::coop_max_active(threads, b->lds_bits, b->in_bits, b->word32,
+                                                     b->n_max);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
-    const size_t per_slot = ((b->word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
-                            (b->lds_bits ? 0 : 4 * ((n + 31) / 32));
+    const size_t per_slot = b->use_lds ? (8 + 8 + 24 + 4) * n + 8
+                                       : ((b->word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
+                                             (b->lds_bits ? 0 : 4 * ((n + 31) / 32));
     size_t slots = std::max<size_t>(1, b->ctx->state_budget / per_slot);
     slots = std::min<size_t>(slots, static_cast<size_t>(b->ctx->cu_count) * wg_per_cu);
     slots = std::min<size_t>(slots, b->item_count);
@@ -104,7 +115,14 @@ uint32_t slots_for(fc_batch *b, uint32_t threads, uint32_t wg_per_cu) {
 int autotune(fc_batch *b) {
     fc_ctx *ctx = b->ctx;
     int rc;
-    const uint32_t cand[][2] = {{256, 3}, {256, 6}, {512, 2}, {512, 3}, {128, 12}};
+    static const uint32_t cand_coop[][2] = {{256, 3}, {256, 6}, {512, 2}, {512, 3}, {128, 12}};
+    static const uint32_t cand_lds[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {1024, 1},
+                                           {1024, 2}};
+    std::vector<std::array<uint32_t, 2>> cand;
+    if (b->use_lds)
+        for (const auto &c : cand_lds) cand.push_back({c[0], c[1]});
+    else
+        for (const auto &c : cand_coop) cand.push_back({c[0], c[1]});
     // throw-away job table: same graphs and records, outputs into one scratch R
     std::vector<fc::CoopJob> tab(b->ntab);
     FC_HIP(ctx, hipMemcpy(tab.data(), b->jobtab.ptr, sizeof(fc::CoopJob) * tab.size(),
@@ -246,10 +264,81 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         FC_HIP(ctx, fc::launch_build_vrec(j.graph.row_ptr, j.graph.n, j.alpha, vrec + voff[k],
                                           dmax_d + k, b->stream), "build_vrec");
     }
+    // degree classes of each distinct graph, for the LDS-counter kernel
+    struct GInfo {
+        const int32_t *rp, *ci;
+        uint32_t n;
+        int64_t nnz;
+        size_t off_n, off_e, off_b;
+    };
+    std::vector<GInfo> gs;
+    std::vector<uint32_t> gof(order.size());
+    size_t tn = 0, te = 0, tb = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        const fc_graph &gr = b->jobs[order[k]].graph;
+        size_t f = 0;
+        while (f < gs.size() && !(gs[f].rp == gr.row_ptr && gs[f].ci == gr.col_idx &&
+                                  gs[f].n == static_cast<uint32_t>(gr.n)))
+            ++f;
+        if (f == gs.size()) {
+            gs.push_back({gr.row_ptr, gr.col_idx, static_cast<uint32_t>(gr.n), gr.nnz, tn, te, tb});
+            tn += static_cast<size_t>(gr.n);
+            te += static_cast<size_t>(gr.nnz);
+            tb += fc::relabel_blocks(static_cast<uint32_t>(gr.n));
+        }
+        gof[k] = static_cast<uint32_t>(f);
+    }
+    const bool try_lds = ctx->coop_lds_counts && !order.empty() &&
+                         static_cast<size_t>(n_max) * 5u <= 8u * ctx->max_lds;
+    std::vector<unsigned int> bounds(4 * gs.size(), 0u);
+    if (try_lds) {
+        if ((rc = ensure(ctx, b->rl_blk, 16 * tb, "class counts")) ||
+            (rc = ensure(ctx, b->rl_base, 16 * tb, "class offsets")) ||
+            (rc = ensure(ctx, b->rl_bounds, 16 * gs.size(), "class bounds")))
+            return fail(rc);
+        uint32_t *blk = static_cast<uint32_t *>(b->rl_blk.ptr);
+        uint32_t *base = static_cast<uint32_t *>(b->rl_base.ptr);
+        uint32_t *bnd = static_cast<uint32_t *>(b->rl_bounds.ptr);
+        for (size_t f = 0; f < gs.size(); ++f)
+            FC_HIP(ctx, fc::launch_class_bounds(gs[f].rp, gs[f].n, blk + 4 * gs[f].off_b,
+                                                base + 4 * gs[f].off_b, bnd + 4 * f, b->stream),
+                   "class bounds");
+        FC_HIP(ctx, hipMemcpyAsync(bounds.data(), bnd, 16 * gs.size(), hipMemcpyDeviceToHost,
+                                   b->stream), "copy class bounds");
+    }
     std::vector<unsigned int> dmax(order.size());
     FC_HIP(ctx, hipMemcpyAsync(dmax.data(), dmax_d, 4 * order.size(), hipMemcpyDeviceToHost, b->stream),
            "copy degrees");
     FC_HIP(ctx, hipStreamSynchronize(b->stream), "batch preparation");
+    if (try_lds) {
+        uint32_t words = 0;
+        for (size_t f = 0; f < gs.size(); ++f)
+            words = std::max(words, fc::count_layout(gs[f].n, bounds[4 * f], bounds[4 * f + 1],
+                                                     bounds[4 * f + 2]).words);
+        b->use_lds = 4u * static_cast<size_t>(words) + kLdsStaticBytes <= ctx->max_lds;
+        b->lds_words = words;
+    }
+    if (b->use_lds) {
+        if ((rc = ensure(ctx, b->rl_inv, 4 * tn, "relabel inverse")) ||
+            (rc = ensure(ctx, b->rl_orig, 4 * tn, "relabel ids")) ||
+            (rc = ensure(ctx, b->rl_adj, 8 * te, "relabelled adjacency")) ||
+            (rc = ensure(ctx, b->rl_vrec, sizeof(fc::VRec) * vtotal, "relabelled records")))
+            return fail(rc);
+        const uint32_t *base = static_cast<const uint32_t *>(b->rl_base.ptr);
+        uint32_t *inv = static_cast<uint32_t *>(b->rl_inv.ptr);
+        uint32_t *orig = static_cast<uint32_t *>(b->rl_orig.ptr);
+        unsigned long long *adj = static_cast<unsigned long long *>(b->rl_adj.ptr);
+        for (const GInfo &gi : gs)
+            FC_HIP(ctx, fc::launch_relabel_graph(gi.rp, gi.ci, gi.n, gi.nnz, base + 4 * gi.off_b,
+                                                 inv + gi.off_n, orig + gi.off_n, adj + gi.off_e,
+                                                 b->stream), "relabel");
+        fc::VRec *vr = static_cast<fc::VRec *>(b->rl_vrec.ptr);
+        for (size_t k = 0; k < order.size(); ++k)
+            FC_HIP(ctx, fc::launch_relabel_vrec(vrec + voff[k], inv + gs[gof[k]].off_n,
+                                                static_cast<uint32_t>(b->jobs[order[k]].graph.n),
+                                                vr + voff[k], b->stream), "relabel records");
+        b->threads = ctx->lds_threads;
+    }
 
     // one word width for the whole launch
     b->word32 = ctx->coop_word32;
@@ -274,6 +363,15 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         c.vrec = vrec + voff[k];
         c.col_idx = j.graph.col_idx;
         c.n = static_cast<uint32_t>(j.graph.n);
+        if (b->use_lds) {
+            const GInfo &gi = gs[gof[k]];
+            c.vrec = static_cast<const fc::VRec *>(b->rl_vrec.ptr) + voff[k];
+            c.adj = static_cast<const unsigned long long *>(b->rl_adj.ptr) + gi.off_e;
+            c.orig = static_cast<const uint32_t *>(b->rl_orig.ptr) + gi.off_n;
+            c.n0 = bounds[4 * gof[k]];
+            c.n1 = bounds[4 * gof[k] + 1];
+            c.n2 = bounds[4 * gof[k] + 2];
+        }
         bool w32;
         word_layout(c.n, dmax[k], b->word32, &c.tshift, &w32);
         c.stream_id = j.stream_id;
@@ -310,7 +408,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     a.phase_ticks = nullptr;
     a.jobs = static_cast<const fc::CoopJob *>(b->jobtab.ptr);
     a.item_job = static_cast<const uint32_t *>(b->item_job.ptr);
-    FC_HIP(ctx, fc::coop_set_lds_limit(b->lds_bits, b->in_bits, b->word32, n_max), "coop LDS limit");
+    if (b->use_lds) FC_HIP(ctx, fc::lds_set_limit(b->lds_words), "LDS limit");
+    else FC_HIP(ctx, fc::coop_set_lds_limit(b->lds_bits, b->in_bits, b->word32, n_max), "coop LDS limit");
 
     if ((flags & FC_FLAG_AUTOTUNE) && (rc = autotune(b))) return fail(rc);
     if ((rc = size_scratch(b, slots_for(b, b->threads, b->wg_per_cu)))) return fail(rc);
@@ -335,7 +434,8 @@ int fc_batch_run(fc_batch *b, fc_stats *stats) {
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->tau = b->item_count;
-        std::snprintf(stats->sampler, sizeof(stats->sampler), "batch:%ux%u", b->threads, b->wg_per_cu);
+        std::snprintf(stats->sampler, sizeof(stats->sampler), "%s:%ux%u",
+                      b->use_lds ? "ldsbatch" : "batch", b->threads, b->wg_per_cu);
     }
     if (b->item_count == 0) return FC_OK;
     // order after the caller's earlier work on the context stream, and make the

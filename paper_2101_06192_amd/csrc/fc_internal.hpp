@@ -22,6 +22,7 @@ struct Small {  // device-side counters of one call
     unsigned int dmax;
     unsigned int pad;
     unsigned long long phase_ticks[8];
+    unsigned int class_bounds[4];  // n0, n1, n2 of the degree-class relabelling
 };
 
 struct fc_ctx {
@@ -30,6 +31,7 @@ struct fc_ctx {
     std::string last_error;
     DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists, clevels, cbits;
     DevBuf s_r64, s_r, s_z, s_p, s_q, s_d, s_pa, s_pb, s_small;  // solver workspace
+    DevBuf rl_blk, rl_base, rl_inv, rl_orig, rl_vrec, rl_adj;     // degree-class relabelling
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
@@ -38,11 +40,13 @@ struct fc_ctx {
     size_t max_lds = 65536;       // dynamic LDS a workgroup may use
     uint32_t coop_threads = 512;  // threads per workgroup in the workgroup sampler
     uint32_t coop_wg_per_cu = 3;  // resident workgroups per CU in the workgroup sampler
-    uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop (environment override)
+    uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop, 3 lds (environment override)
     bool coop_lds_bits = true;    // settled bitmap in LDS when it fits
     bool coop_word32 = true;      // 32-bit tree words when target and count fit
     bool coop_in_bits = true;     // in-arrow bitmap in LDS when both bitmaps fit
     bool phase_timing = false;    // per-phase wall-clock ticks of the workgroup sampler
+    bool coop_lds_counts = true;  // in-arrow counters in LDS when the tree's fields fit
+    uint32_t lds_threads = 1024;  // threads per workgroup of the LDS-counter sampler
     double wall_khz = 100000.0;   // device wall clock rate
 };
 
@@ -55,6 +59,9 @@ struct fc_ctx {
 
 
 namespace fc_host {
+
+// static LDS of the LDS-counter kernel (item, tails, totals, phase clocks) with margin
+constexpr size_t kLdsStaticBytes = 256;
 
 int set_err(fc_ctx *ctx, int code, const std::string &msg);
 int hip_fail(fc_ctx *ctx, hipError_t e, const char *what);

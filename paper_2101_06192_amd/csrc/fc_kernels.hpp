@@ -52,10 +52,17 @@ hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
 
 // Workgroup-per-tree sampler (round-synchronous cycle popping).  A job is
 // one (graph, alpha, stream) with a range of trees and its own outputs.
+// The LDS-counter variant reads the degree-class relabelled graph instead:
+// vrec and adj on internal ids (vrec.always_root = original id | flag << 31),
+// orig maps internal ids back, and [0, n0), [n0, n1), [n1, n2), [n2, n) are
+// the internal ids of the 4-, 8-, 16- and 32-bit counter classes.
 struct CoopJob {
     const VRec *vrec;
     const int32_t *col_idx;
+    const unsigned long long *adj;  // LDS variant: internal | original << 32 per CSR entry
+    const uint32_t *orig;           // LDS variant: original id of each internal id
     uint32_t n;
+    uint32_t n0, n1, n2;            // LDS variant: class boundaries
     uint32_t tshift;          // bits of the target field in a tree word
     uint32_t stream_id;
     uint32_t tree_begin;
@@ -98,6 +105,44 @@ hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t
 // Workgroups of the chosen variant that fit on one CU at once (0 if unknown).
 int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
+
+// LDS-counter variant: the per-tree arrays are word (u64: internal target |
+// original target << 32), kk, lists and levels as above; the settled bitmap
+// and all in-arrow counters live in LDS.
+hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
+                             hipStream_t stream);
+hipError_t lds_set_limit(uint32_t lds_words);
+int lds_max_active(uint32_t threads, uint32_t lds_words);
+
+// LDS word offsets of one tree's counter classes and settled bitmap.
+struct CountLayout {
+    uint32_t o1, o2, o3, ob, words;
+};
+__host__ __device__ inline CountLayout count_layout(uint32_t n, uint32_t n0, uint32_t n1,
+                                                    uint32_t n2) {
+    CountLayout L;
+    L.o1 = (n0 + 7u) >> 3;
+    L.o2 = L.o1 + ((n1 - n0 + 3u) >> 2);
+    L.o3 = L.o2 + ((n2 - n1 + 1u) >> 1);
+    L.ob = L.o3 + (n - n2);
+    L.words = L.ob + ((n + 31u) >> 5);
+    return L;
+}
+
+// Degree-class relabelling (blocks of 1024 vertices): per-block class counts
+// into blk (4 per block), first internal id per block and class into base,
+// and bounds[0..2] = n0, n1, n2.
+uint32_t relabel_blocks(uint32_t n);
+hipError_t launch_class_bounds(const int32_t *row_ptr, uint32_t n, uint32_t *blk, uint32_t *base,
+                               uint32_t *bounds, hipStream_t stream);
+// inv/orig permutations and relabelled adjacency of one graph (base from
+// launch_class_bounds).
+hipError_t launch_relabel_graph(const int32_t *row_ptr, const int32_t *col_idx, uint32_t n,
+                                int64_t nnz, const uint32_t *base, uint32_t *inv, uint32_t *orig,
+                                unsigned long long *adj, hipStream_t stream);
+// Relabelled records of one G* (from the original-id records vrec).
+hipError_t launch_relabel_vrec(const VRec *vrec, const uint32_t *inv, uint32_t n, VRec *vrec_r,
+                               hipStream_t stream);
 
 // p[0..count) = value (a kernel, so that it can sit in a captured HIP graph).
 hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,

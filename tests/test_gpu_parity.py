@@ -22,7 +22,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-SAMPLERS = ["lane", "coop"]
+SAMPLERS = ["lane", "coop", "lds"]
 
 
 def _compare(fc, g, alpha, seed, t0, count, stream=0, per_tree=True, sampler="lane"):
@@ -181,12 +181,59 @@ def test_ba200k_tree_subset_bit_exact(gpu_lib, sampler):
     _compare(gpu_lib, g, 1.0, 0, 4000, 16, per_tree=False, sampler=sampler)
 
 
-@pytest.mark.parametrize("sampler", SAMPLERS)
+@pytest.mark.parametrize("sampler", ["lane", "coop"])
 @pytest.mark.parametrize("alpha", [0.5, 1.0, 2.0])
 def test_grid_tree_subset_bit_exact(gpu_lib, alpha, sampler):
     """1000 x 1000 grid with 12% of edges removed: 6 trees per alpha."""
     g = inputs.grid_removed(1000, 1000, 0.12, 0)
     _compare(gpu_lib, g, alpha, 0, 100, 6, sampler=sampler)
+
+
+def test_lds_sampler_rejects_graphs_too_large_and_auto_falls_back(gpu_lib):
+    """10^6 vertices need at least 610 KiB of 4-bit counters: forcing the
+    LDS-counter sampler fails cleanly, the automatic choice uses global
+    counters."""
+    fc = gpu_lib
+    g = inputs.grid_removed(1000, 1000, 0.12, 0)
+    with pytest.raises(fc.FCError) as e:
+        fc.sample(g, alpha=1.0, seed=0, tree_begin=0, tree_count=2, sampler="lds")
+    assert e.value.code == fc.FC_ERR_UNSUPPORTED
+    got = fc.sample(g, alpha=1.0, seed=0, tree_begin=0, tree_count=2, want_digests=True)
+    assert got["stats"]["sampler"] == "wilson_coop"
+    ref = oracle.sample(g, 1.0, 0, 0, 2, per_tree=False)
+    assert np.array_equal(got["tree_digests"], ref.digests)
+
+
+@pytest.mark.parametrize("threads,wg", [(64, 8), (256, 2), (512, 1), (1024, 2)])
+def test_lds_launch_shapes_bit_exact(gpu_lib, threads, wg):
+    """LDS-counter sampler with other workgroup sizes and residency caps."""
+    fc = gpu_lib
+    fc.set_option("lds_threads", threads)
+    fc.set_option("coop_wg_per_cu", wg)
+    try:
+        g = inputs.barabasi_albert(20_000, 3, 7)
+        _compare(fc, g, 1.5, 77, 9, 40, sampler="lds")
+        g2 = inputs.grid_removed(120, 90, 0.12, 3)
+        _compare(fc, g2, 2.0, 78, 0, 20, sampler="lds")
+    finally:
+        fc.set_option("lds_threads", 1024)
+        fc.set_option("coop_wg_per_cu", 3)
+
+
+def test_auto_choice_prefers_lds_counters(gpu_lib):
+    """Without a sampler flag a tree that fits uses LDS counters; the option
+    turns that off."""
+    fc = gpu_lib
+    g = inputs.barabasi_albert(70_000, 4, 5)
+    got = fc.sample(g, alpha=1.0, seed=3, tree_begin=0, tree_count=8, want_digests=True)
+    assert got["stats"]["sampler"] == "wilson_lds"
+    fc.set_option("coop_lds_counts", 0)
+    try:
+        got2 = fc.sample(g, alpha=1.0, seed=3, tree_begin=0, tree_count=8, want_digests=True)
+        assert got2["stats"]["sampler"] == "wilson_coop"
+    finally:
+        fc.set_option("coop_lds_counts", 1)
+    assert np.array_equal(got["tree_digests"], got2["tree_digests"])
 
 
 @pytest.mark.parametrize("shape", [(64, 1, 1, 1, 1), (256, 3, 0, 1, 1), (448, 1, 1, 0, 0),
@@ -218,7 +265,8 @@ def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
 def test_set_option_rejects_bad_values(gpu_lib):
     fc = gpu_lib
     for key, val in (("coop_threads", 100), ("coop_threads", 1024), ("coop_wg_per_cu", 0),
-                     ("lanes_per_wave", 65), ("nonsense", 1), ("coop_lds_bits", 2)):
+                     ("lanes_per_wave", 65), ("nonsense", 1), ("coop_lds_bits", 2),
+                     ("coop_lds_counts", 2), ("lds_threads", 1088), ("lds_threads", 96)):
         with pytest.raises(fc.FCError) as e:
             fc.set_option(key, val)
         assert e.value.code == fc.FC_ERR_ARG
@@ -268,7 +316,16 @@ def _batch_graphs():
     return gs
 
 
-def test_batch_matches_oracle_and_single_runs(gpu_lib):
+@pytest.fixture(params=[1, 0], ids=["lds_counters", "global_counters"])
+def counters(request, gpu_lib):
+    """Runs a test with the workgroup kernels' in-arrow counters in LDS (the
+    default) and in global tree words."""
+    gpu_lib.set_option("coop_lds_counts", request.param)
+    yield "ldsbatch" if request.param else "batch"
+    gpu_lib.set_option("coop_lds_counts", 1)
+
+
+def test_batch_matches_oracle_and_single_runs(gpu_lib, counters):
     fc = gpu_lib
     gs = _batch_graphs()
     dgs = [fc.to_device(g) for g in gs]
@@ -284,6 +341,7 @@ def test_batch_matches_oracle_and_single_runs(gpu_lib):
     b = fc.Batch(jobs, seed=4242)
     st = b.run()
     _say(f"batch run: {st['sampler']} ms={st['ms_sample']:.2f} trees={st['tau']}")
+    assert st["sampler"].split(":")[0] == counters
     total_steps = 0
     for i, j in enumerate(jobs[:-2]):
         g = gs[i // len(alphas)]
@@ -301,7 +359,7 @@ def test_batch_matches_oracle_and_single_runs(gpu_lib):
     b.close()
 
 
-def test_batch_graph_replays_and_autotune(gpu_lib):
+def test_batch_graph_replays_and_autotune(gpu_lib, counters):
     """Replays of the captured launch, with eager work and synchronisation
     between them, each equal to the eager single-job result."""
     import torch
@@ -314,6 +372,7 @@ def test_batch_graph_replays_and_autotune(gpu_lib):
              for i, dg in enumerate(dgs)]
     for tune in (False, True):
         b = fc.Batch(jobs, seed=7, autotune=tune)
+        assert b.run()["sampler"].split(":")[0] == counters
         for rep in range(3):
             b.reset()
             x = torch.randn(1 << 20, device="cuda:0")  # unrelated eager work in between
