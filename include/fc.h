@@ -66,7 +66,8 @@ extern "C" {
 #define FC_ERR_NOMEM (-3)       /* device allocation failed */
 #define FC_ERR_HIP (-4)         /* HIP runtime error (no device, launch failure) */
 #define FC_ERR_UNSUPPORTED (-5) /* n or nnz beyond the supported range */
-#define FC_ERR_OVERFLOW (-6)    /* a per-vertex visit counter exceeded 2^31 - 1 */
+#define FC_ERR_OVERFLOW (-6)    /* a per-vertex draw count in one tree exceeded 2^31 - 1
+                                   (2^28 - 1 with the LDS-counter sampler) */
 
 /* fc_graph.mem */
 #define FC_MEM_HOST 0
@@ -129,11 +130,16 @@ typedef struct {
     double ms_total;         /* host wall time of the call */
     char sampler[16];        /* "wilson_lane", "wilson_coop", "wilson_lds" (workgroup sampler,
                                 counters in LDS), or for a batch "batch:<threads>x<wg per CU>"
-                                ("ldsbatch:..." with counters in LDS) */
+                                ("lbatch:..." with counters in LDS) */
     double phase_ms[8];      /* workgroup sampler with option "phase_timing": average
-                                milliseconds per workgroup spent in: first arrows,
-                                in-arrow counting, peel level 0, peel levels, reverse
-                                sweep, redraw, output; else zeros */
+                                milliseconds per workgroup spent in
+                                wilson_coop: first arrows, in-arrow counting, peel
+                                  level 0, peel levels, reverse sweep, redraw, output;
+                                wilson_lds: first arrows, in-arrow counting with peel
+                                  level 0, wide peel levels, single-wave peel levels,
+                                  reverse sweep, split of the unsettled list, cycle
+                                  popping, output;
+                                else zeros */
 } fc_stats;
 
 /* Create a context on HIP device `hip_device` that enqueues its work on
@@ -153,10 +159,16 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "coop_lds_counts" 1 (default): the workgroup sampler keeps every in-arrow counter of a
  *                     tree in LDS (degree-sized fields on degree-class relabelled ids) when
  *                     they and the settled bitmap fit; 0: counters in global tree words
- *   "lds_threads"     threads per workgroup of that LDS-counter variant (64..1024, multiple of 64)
+ *   "lds_threads"     threads per workgroup of that LDS-counter variant (64..1024, multiple
+ *                     of 64; 0, the default: 1024 when LDS holds at most two trees per
+ *                     CU, else narrower (down to 256) as the trees per CU grow)
+ *   "lds_wg_per_cu"   cap on its resident workgroups per CU (0, the default: as many as fit)
  *   "lanes_per_wave"  active lanes per wave of the lane sampler (1..64)
  *   "max_slots"       cap on trees in flight (0 = memory bound only)
  *   "phase_timing"    1: the workgroup sampler reports per-phase times in fc_stats
+ *   "max_draws"       cap on the arrows one vertex may draw in one tree, below each
+ *                     sampler's own limit (0, the default: no extra cap); a call that
+ *                     exceeds it returns FC_ERR_OVERFLOW (exercises that error path)
  * Returns FC_ERR_ARG for an unknown key or a value out of range. */
 FC_API int fc_set_option(fc_ctx *ctx, const char *key, int64_t value);
 

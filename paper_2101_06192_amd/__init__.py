@@ -72,7 +72,7 @@ class fc_stats(ctypes.Structure):
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["sampler"] = d["sampler"].decode()
-        d["phase_ms"] = list(d["phase_ms"])[:7]
+        d["phase_ms"] = list(d["phase_ms"])
         return d
 
 

@@ -190,13 +190,14 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::CoopArgs c{};
     bool lds_bits = false, in_bits = false, word32 = false;
     bool use_lds = false;
-    uint32_t lds_words = 0;
+    uint32_t lds_words = 0, lds_threads = 1024;
     uint32_t tshift = 32;
     unsigned int dmax = 0;
     if (use_coop) {
         // LDS-counter variant when the degree-class count fields and the settled
         // bitmap of one tree fit in LDS (at least 4 + 1 bits per vertex)
         const bool try_lds = (mode == 3 || (mode == 0 && ctx->coop_lds_counts)) &&
+                             g.n < (1 << fc::kRelabelIdBits) &&
                              static_cast<size_t>(g.n) * 5u <= 8u * ctx->max_lds;
         const uint32_t nb = fc::relabel_blocks(static_cast<uint32_t>(g.n));
         if (try_lds) {
@@ -247,24 +248,23 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                                                 static_cast<uint32_t>(g.n),
                                                 static_cast<fc::VRec *>(ctx->rl_vrec.ptr), ctx->stream),
                    "relabel records");
-            const size_t per_slot = (8u + 8u + 24u + 4u) * n + 8u;
+            const size_t per_slot = (8u + 24u + 4u) * n + 8u;
             slots = std::max<size_t>(1, ctx->state_budget / per_slot);
             slots = std::min<size_t>(slots, tree_count);
             FC_HIP(ctx, fc::lds_set_limit(lds_words), "LDS limit");
-            uint32_t per_cu = ctx->coop_wg_per_cu;
-            const int fit = fc::lds_max_active(ctx->lds_threads, lds_words);
+            lds_threads = lds_threads_for(ctx, tree_count, lds_words);
+            uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
+            const int fit = fc::lds_max_active(lds_threads, lds_words);
             if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
+            else per_cu = 1;
             slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
             if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
             if ((rc = ensure(ctx, ctx->cword, 8u * n * slots, "tree words")) ||
-                (rc = ensure(ctx, ctx->ckk, 8u * n * slots, "draw counts")) ||
                 (rc = ensure(ctx, ctx->clists, 24u * n * slots, "lists")) ||
                 (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")))
                 return rc;
-            FC_HIP(ctx, hipMemsetAsync(ctx->ckk.ptr, 0, 8u * n * slots, ctx->stream),
-                   "memset draw counts");
             c.word = ctx->cword.ptr;
-            c.kk = static_cast<uint64_t *>(ctx->ckk.ptr);
+            c.kk = nullptr;  // draw counts travel in the tree words
             c.lists = static_cast<uint64_t *>(ctx->clists.ptr);
             c.levels = static_cast<uint32_t *>(ctx->clevels.ptr);
             c.bits = nullptr;
@@ -274,6 +274,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             c.key0 = static_cast<uint32_t>(p->seed);
             c.key1 = static_cast<uint32_t>(p->seed >> 32);
             c.max_rounds = 0x40000000u;
+            c.k_limit = ctx->max_draws ? ctx->max_draws : 0xFFFFFFFFu;
             c.queue = &sm->queue;
             c.totals = &sm->totals;
             c.jobs = nullptr;
@@ -348,6 +349,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         c.key0 = static_cast<uint32_t>(p->seed);
         c.key1 = static_cast<uint32_t>(p->seed >> 32);
         c.max_rounds = 0x40000000u;
+        c.k_limit = ctx->max_draws ? ctx->max_draws : 0x7FFFFFFFu;
         c.queue = &sm->queue;
         c.totals = &sm->totals;
         c.jobs = nullptr;
@@ -388,6 +390,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         a.key0 = static_cast<uint32_t>(p->seed);
         a.key1 = static_cast<uint32_t>(p->seed >> 32);
         a.step_cap = step_cap;
+        a.k_limit = ctx->max_draws ? ctx->max_draws : 0x7FFFFFFFu;
         a.queue = &sm->queue;
         a.root_counts = root_counts;
         a.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
@@ -400,7 +403,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     if (use_lds) {
-        FC_HIP(ctx, fc::launch_wilson_lds(c, ctx->lds_threads, lds_words, ctx->stream),
+        FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, ctx->stream),
                "wilson_lds launch");
     } else if (use_coop) {
         FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, ctx->stream),
@@ -415,7 +418,11 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     if (tot.error & fc::kErrStepCap)
         return set_err(ctx, FC_ERR_HIP, "a tree exceeded the step bound (internal fault)");
     if (tot.error & fc::kErrVisitOverflow)
-        return set_err(ctx, FC_ERR_OVERFLOW, "a per-vertex visit counter exceeded 2^31 - 1");
+        return set_err(ctx, FC_ERR_OVERFLOW,
+                       ctx->max_draws ? "a per-vertex draw count exceeded option max_draws"
+                       : use_lds ? "a per-vertex draw count exceeded 2^28 - 1 (the LDS-counter "
+                                   "sampler's limit; option coop_lds_counts = 0 allows 2^31 - 1)"
+                                 : "a per-vertex visit counter exceeded 2^31 - 1");
     if (stats) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
@@ -431,7 +438,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             FC_HIP(ctx, hipMemcpy(ticks, sm->phase_ticks, sizeof(ticks), hipMemcpyDeviceToHost),
                    "copy phase ticks");
             // per-workgroup average in milliseconds
-            for (int i = 0; i < 7; ++i)
+            for (int i = 0; i < 8; ++i)
                 stats->phase_ms[i] = static_cast<double>(ticks[i]) / ctx->wall_khz / static_cast<double>(slots);
         }
     }
@@ -450,6 +457,20 @@ void word_layout(uint32_t n, uint32_t dmax, bool allow32, uint32_t *tshift, bool
     while ((1ull << cb) <= static_cast<unsigned long long>(dmax)) ++cb;  // dmax < 2^cb
     *word32 = allow32 && tb + cb <= 32;
     *tshift = *word32 ? tb : 32;
+}
+
+uint32_t lds_threads_for(const fc_ctx *ctx, uint64_t trees, uint32_t lds_words) {
+    if (ctx->lds_threads) return ctx->lds_threads;
+    // A CU holds at most 2048 threads.  When LDS admits only one or two trees
+    // per CU, each gets the widest workgroup; otherwise narrow the workgroups
+    // until the CUs hold as many trees as there are (per CU) or LDS admits.
+    const size_t per_tree = 4u * static_cast<size_t>(lds_words) + kLdsStaticBytes;
+    const uint64_t fit_lds = ctx->max_lds / per_tree;
+    if (fit_lds <= 2) return 1024u;
+    const uint64_t per_cu = std::min<uint64_t>((trees + ctx->cu_count - 1) / ctx->cu_count, fit_lds);
+    uint32_t t = 1024u;
+    while (t > 256u && 2048u / t < per_cu) t /= 2;
+    return t;
 }
 
 int begin(fc_ctx *ctx) {
@@ -508,9 +529,9 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     ctx->coop_wg_per_cu = std::max<uint32_t>(1, env_u32("FC_COOP_WG_PER_CU", 3));
     ctx->coop_in_bits = env_u32("FC_COOP_IN_BITS", 1) != 0;
     ctx->coop_lds_counts = env_u32("FC_COOP_LDS_COUNTS", 1) != 0;
-    ctx->lds_threads = env_u32("FC_LDS_THREADS", 1024);
-    if (ctx->lds_threads < 64 || ctx->lds_threads > 1024 || ctx->lds_threads % 64)
-        ctx->lds_threads = 1024;
+    ctx->lds_threads = env_u32("FC_LDS_THREADS", 0);
+    if (ctx->lds_threads > 1024 || ctx->lds_threads % 64) ctx->lds_threads = 0;
+    ctx->lds_wg_per_cu = std::min<uint32_t>(64, env_u32("FC_LDS_WG_PER_CU", 0));
     {
         const char *fs = std::getenv("FC_SAMPLER");
         if (fs && !std::strcmp(fs, "lane")) ctx->force_sampler = 1;
@@ -566,8 +587,14 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
         if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "coop_lds_counts");
         ctx->coop_lds_counts = value == 1;
     } else if (k == "lds_threads") {
-        if (value < 64 || value > 1024 || value % 64) return set_err(ctx, FC_ERR_ARG, "lds_threads");
+        if (value < 0 || value > 1024 || value % 64) return set_err(ctx, FC_ERR_ARG, "lds_threads");
         ctx->lds_threads = static_cast<uint32_t>(value);
+    } else if (k == "lds_wg_per_cu") {
+        if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
+        ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
+    } else if (k == "max_draws") {
+        if (value < 0 || value > 0x7FFFFFFF) return set_err(ctx, FC_ERR_ARG, "max_draws");
+        ctx->max_draws = static_cast<uint32_t>(value);
     } else if (k == "phase_timing") {
         if (value != 0 && value != 1) return set_err(ctx, FC_ERR_ARG, "phase_timing");
         ctx->phase_timing = value == 1;

@@ -64,9 +64,9 @@ hipError_t enqueue_run(fc_batch *b, const fc::CoopArgs &a, uint32_t threads, hip
     hipError_t e = fc::launch_fill_u64(static_cast<unsigned long long *>(b->small.ptr),
                                        sizeof(Small) / 8, 0ull, stream);
     if (e != hipSuccess) return e;
+    if (b->use_lds) return fc::launch_wilson_lds(a, threads, b->lds_words, stream);
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(b->kk.ptr), b->kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
-    if (b->use_lds) return fc::launch_wilson_lds(a, threads, b->lds_words, stream);
     return fc::launch_wilson_coop(a, threads, b->lds_bits, b->in_bits, b->word32, stream);
 }
 
@@ -77,7 +77,7 @@ int size_scratch(fc_batch *b, uint32_t slots) {
     const size_t n = b->n_max, nwords = (n + 31) / 32;
     const size_t wbytes = b->word32 && !b->use_lds ? 4 : 8;
     if ((rc = ensure(ctx, b->word, wbytes * n * slots, "batch tree words"))) return rc;
-    if ((rc = ensure(ctx, b->kk, 8 * n * slots, "batch draw counts"))) return rc;
+    if (!b->use_lds && (rc = ensure(ctx, b->kk, 8 * n * slots, "batch draw counts"))) return rc;
     if ((rc = ensure(ctx, b->lists, 24 * n * slots, "batch lists"))) return rc;
     if ((rc = ensure(ctx, b->levels, 4 * (n + 2) * slots, "batch levels"))) return rc;
     if (!b->use_lds && !b->lds_bits &&
@@ -87,7 +87,7 @@ int size_scratch(fc_batch *b, uint32_t slots) {
     b->slots = slots;
     fc::CoopArgs &a = b->args;
     a.word = b->word.ptr;
-    a.kk = static_cast<uint64_t *>(b->kk.ptr);
+    a.kk = b->use_lds ? nullptr : static_cast<uint64_t *>(b->kk.ptr);
     a.lists = static_cast<uint64_t *>(b->lists.ptr);
     a.levels = static_cast<uint32_t *>(b->levels.ptr);
     a.bits = b->lds_bits || b->use_lds ? nullptr : static_cast<uint32_t *>(b->bits.ptr);
@@ -101,7 +101,7 @@ uint32_t slots_for(fc_batch *b, uint32_t threads, uint32_t wg_per_cu) {
                                : fc::coop_max_active(threads, b->lds_bits, b->in_bits, b->word32,
                                                      b->n_max);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
-    const size_t per_slot = b->use_lds ? (8 + 8 + 24 + 4) * n + 8
+    const size_t per_slot = b->use_lds ? (8 + 24 + 4) * n + 8
                                        : ((b->word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
                                              (b->lds_bits ? 0 : 4 * ((n + 31) / 32));
     size_t slots = std::max<size_t>(1, b->ctx->state_budget / per_slot);
@@ -116,8 +116,7 @@ int autotune(fc_batch *b) {
     fc_ctx *ctx = b->ctx;
     int rc;
     static const uint32_t cand_coop[][2] = {{256, 3}, {256, 6}, {512, 2}, {512, 3}, {128, 12}};
-    static const uint32_t cand_lds[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {1024, 1},
-                                           {1024, 2}};
+    static const uint32_t cand_lds[][2] = {{256, 64}, {512, 64}, {1024, 64}, {256, 4}, {512, 2}};
     std::vector<std::array<uint32_t, 2>> cand;
     if (b->use_lds)
         for (const auto &c : cand_lds) cand.push_back({c[0], c[1]});
@@ -289,6 +288,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         gof[k] = static_cast<uint32_t>(f);
     }
     const bool try_lds = ctx->coop_lds_counts && !order.empty() &&
+                         n_max < (1u << fc::kRelabelIdBits) &&
                          static_cast<size_t>(n_max) * 5u <= 8u * ctx->max_lds;
     std::vector<unsigned int> bounds(4 * gs.size(), 0u);
     if (try_lds) {
@@ -337,7 +337,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
             FC_HIP(ctx, fc::launch_relabel_vrec(vrec + voff[k], inv + gs[gof[k]].off_n,
                                                 static_cast<uint32_t>(b->jobs[order[k]].graph.n),
                                                 vr + voff[k], b->stream), "relabel records");
-        b->threads = ctx->lds_threads;
+        b->threads = lds_threads_for(ctx, b->item_count, b->lds_words);
+        b->wg_per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
     }
 
     // one word width for the whole launch
@@ -402,6 +403,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     a.key0 = static_cast<uint32_t>(seed);
     a.key1 = static_cast<uint32_t>(seed >> 32);
     a.max_rounds = 0x40000000u;
+    a.k_limit = ctx->max_draws ? ctx->max_draws : b->use_lds ? 0xFFFFFFFFu : 0x7FFFFFFFu;
     Small *sm = static_cast<Small *>(b->small.ptr);
     a.queue = &sm->queue;
     a.totals = &sm->totals;
@@ -435,7 +437,7 @@ int fc_batch_run(fc_batch *b, fc_stats *stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->tau = b->item_count;
         std::snprintf(stats->sampler, sizeof(stats->sampler), "%s:%ux%u",
-                      b->use_lds ? "ldsbatch" : "batch", b->threads, b->wg_per_cu);
+                      b->use_lds ? "lbatch" : "batch", b->threads, b->wg_per_cu);
     }
     if (b->item_count == 0) return FC_OK;
     // order after the caller's earlier work on the context stream, and make the
@@ -453,7 +455,9 @@ int fc_batch_run(fc_batch *b, fc_stats *stats) {
     if (sm.totals.error & fc::kErrStepCap)
         return set_err(ctx, FC_ERR_HIP, "a tree exceeded the step bound (internal fault)");
     if (sm.totals.error & fc::kErrVisitOverflow)
-        return set_err(ctx, FC_ERR_OVERFLOW, "a per-vertex visit counter exceeded 2^31 - 1");
+        return set_err(ctx, FC_ERR_OVERFLOW,
+                       b->use_lds ? "a per-vertex draw count exceeded 2^28 - 1 (LDS counters)"
+                                  : "a per-vertex visit counter exceeded 2^31 - 1");
     if (stats) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);

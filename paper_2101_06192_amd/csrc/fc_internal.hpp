@@ -45,8 +45,10 @@ struct fc_ctx {
     bool coop_word32 = true;      // 32-bit tree words when target and count fit
     bool coop_in_bits = true;     // in-arrow bitmap in LDS when both bitmaps fit
     bool phase_timing = false;    // per-phase wall-clock ticks of the workgroup sampler
+    uint32_t max_draws = 0;       // per-vertex draw limit in one tree (0: each sampler's own)
     bool coop_lds_counts = true;  // in-arrow counters in LDS when the tree's fields fit
-    uint32_t lds_threads = 1024;  // threads per workgroup of the LDS-counter sampler
+    uint32_t lds_threads = 0;     // threads per workgroup of the LDS-counter sampler (0: by n)
+    uint32_t lds_wg_per_cu = 0;   // its resident workgroups per CU (0: as many as fit)
     double wall_khz = 100000.0;   // device wall clock rate
 };
 
@@ -61,7 +63,7 @@ struct fc_ctx {
 namespace fc_host {
 
 // static LDS of the LDS-counter kernel (item, tails, totals, phase clocks) with margin
-constexpr size_t kLdsStaticBytes = 256;
+constexpr size_t kLdsStaticBytes = 1024;
 
 int set_err(fc_ctx *ctx, int code, const std::string &msg);
 int hip_fail(fc_ctx *ctx, hipError_t e, const char *what);
@@ -83,6 +85,9 @@ int check_graph_args(fc_ctx *ctx, const fc_graph *g);
 int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out);
 double now_ms();
 int begin(fc_ctx *ctx);
+// Threads per workgroup of the LDS-counter sampler for `trees` trees whose
+// counters and bitmap take lds_words words of LDS.
+uint32_t lds_threads_for(const fc_ctx *ctx, uint64_t trees, uint32_t lds_words);
 // Bits of the target field so that n < 2^tshift, and whether a 32-bit tree
 // word also holds an in-arrow count up to dmax.
 void word_layout(uint32_t n, uint32_t dmax, bool allow32, uint32_t *tshift, bool *word32);

@@ -39,6 +39,7 @@ struct LaneArgs {
     uint32_t stream_id;
     uint32_t key0, key1;
     unsigned long long step_cap;  // per-tree bound on steps; exceeding it is an error
+    uint32_t k_limit;         // largest per-vertex draw count in one tree; beyond it is an error
     unsigned int *queue;      // next tree index (relative to tree_begin)
     uint32_t *root_counts;
     unsigned long long *visit_counts;
@@ -59,7 +60,7 @@ hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
 struct CoopJob {
     const VRec *vrec;
     const int32_t *col_idx;
-    const unsigned long long *adj;  // LDS variant: internal | original << 32 per CSR entry
+    const unsigned long long *adj;  // LDS variant: internal | original << 18 per CSR entry
     const uint32_t *orig;           // LDS variant: original id of each internal id
     uint32_t n;
     uint32_t n0, n1, n2;            // LDS variant: class boundaries
@@ -88,6 +89,7 @@ struct CoopArgs {
     uint32_t item_count;      // trees over all jobs
     uint32_t key0, key1;
     uint32_t max_rounds;      // bound on popping rounds per tree; exceeding it is an error
+    uint32_t k_limit;         // largest per-vertex draw count in one tree; beyond it is an error
     unsigned int *queue;
     Totals *totals;
     unsigned long long *phase_ticks;  // 7 wall-clock tick sums per phase, or null
@@ -106,9 +108,10 @@ hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t
 int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 
-// LDS-counter variant: the per-tree arrays are word (u64: internal target |
-// original target << 32), kk, lists and levels as above; the settled bitmap
-// and all in-arrow counters live in LDS.
+// LDS-counter variant (n < 2^kRelabelIdBits): the per-tree arrays are word
+// (u64: internal target | original target << 18 | draw count << 36), lists
+// and levels as above (no kk); the settled bitmap and all in-arrow counters
+// live in LDS.
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
                              hipStream_t stream);
 hipError_t lds_set_limit(uint32_t lds_words);
@@ -128,6 +131,10 @@ __host__ __device__ inline CountLayout count_layout(uint32_t n, uint32_t n0, uin
     L.words = L.ob + ((n + 31u) >> 5);
     return L;
 }
+
+// Id width of the relabelled adjacency entries (internal | original << bits)
+// and of the LDS-counter sampler's packed words: graphs need n < 2^bits.
+constexpr uint32_t kRelabelIdBits = 18;
 
 // Degree-class relabelling (blocks of 1024 vertices): per-block class counts
 // into blk (4 per block), first internal id per block and class into base,

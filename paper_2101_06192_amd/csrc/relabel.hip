@@ -8,8 +8,9 @@
 // which makes a field's LDS word and shift plain arithmetic on the internal
 // id.  Randomness and every output stay on original ids: the relabelled
 // vertex record carries the original id, and the relabelled adjacency holds
-// (internal, original) pairs of each neighbour at the same CSR positions, so
-// the neighbour chosen by a draw is the one the original CSR gives.
+// (internal, original) pairs of each neighbour at the same CSR positions
+// (internal id in the low kRelabelIdBits bits, original id above), so the
+// neighbour chosen by a draw is the one the original CSR gives.
 #include "fc_kernels.hpp"
 
 namespace fc {
@@ -99,7 +100,7 @@ __global__ void relabel_adj_kernel(const int32_t *__restrict__ col_idx, int64_t 
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const uint32_t u = static_cast<uint32_t>(col_idx[e]);
         adj[e] = static_cast<unsigned long long>(inv[u]) |
-                 (static_cast<unsigned long long>(u) << 32);
+                 (static_cast<unsigned long long>(u) << kRelabelIdBits);
     }
 }
 

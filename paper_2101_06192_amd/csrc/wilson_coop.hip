@@ -313,7 +313,7 @@ void wilson_coop_kernel(CoopArgs a) {
                         const uint64_t kv = kk[v];
                         const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
                         const uint32_t tg = draw(job, a.key0, a.key1, v, k, t);
-                        if (k + 1u > 0x7FFFFFFFu) err |= kErrVisitOverflow;
+                        if (k + 1u > a.k_limit) err |= kErrVisitOverflow;
                         kk[v] = (static_cast<uint64_t>(epoch) << 32) | (k + 1u);
                         word[v] = static_cast<W>(tg);
                         it[q] = pair(v, tg);

@@ -14,7 +14,8 @@
 //   level 0  v with cnt[v] == 0 starts the peel list
 //   peel     a peeled x decrements cnt[target(x)]; the one that drops it to 0
 //            appends (target, its own target) to the list (a global load of
-//            the target's tree word)
+//            the target's tree word); levels of at most 64 vertices (the long
+//            tail) are peeled by one wave without workgroup barriers
 //   sweep    peel levels in reverse: x is settled when its target is
 //   redraw   what is left with cnt[v] == 1 lies on a cycle: v draws its next
 //            arrow (cnt[v] back to 0); vertices hanging off a cycle keep theirs
@@ -25,22 +26,35 @@
 // Counts of settled vertices are never read again; they stay at most the
 // degree, so no field overflows into its neighbour.
 //
-// Memory per tree (slot), n vertices:
-//   word[v]  u64 global  internal target | original target << 32 (u* = n)
-//   kk[v]    u64 global  (epoch << 32) | k_v for redrawn vertices
-//   lists    u64 global  (v, target) pairs: two unsettled lists, peel order
+// Ids fit in 18 bits (a tree whose fields fit in LDS has n < 2^18), which
+// leaves room to carry each vertex's draw count k_v with its arrow:
+//   word[v]  u64 global  internal target | original target << 18 | k_v << 36
+//                        (u* = n in both numberings)
+//   lists    u64 global  v | internal target << 18 | k_v << 36: two unsettled
+//                        lists and the peel order (k unused there)
 //   levels   u32 global  peel level boundaries
 //   LDS      count fields (4/8/16/32 bits by class), then the settled bitmap
+// so redrawing a cycle vertex touches no per-vertex array besides its word.
 #include "fc_kernels.hpp"
 
 namespace fc {
 
 namespace {
 
-__device__ __forceinline__ uint32_t lo32(uint64_t w) { return static_cast<uint32_t>(w); }
-__device__ __forceinline__ uint32_t hi32(uint64_t w) { return static_cast<uint32_t>(w >> 32); }
-__device__ __forceinline__ uint64_t pair(uint32_t v, uint32_t tg) {
-    return static_cast<uint64_t>(v) | (static_cast<uint64_t>(tg) << 32);
+constexpr uint32_t kIdBits = kRelabelIdBits;
+constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
+constexpr uint32_t kKShift = 2 * kIdBits;
+constexpr uint32_t kKMax = (1u << (64 - kKShift)) - 1u;  // largest draw count a word holds
+
+// list entry / tree word fields
+__device__ __forceinline__ uint32_t f_lo(uint64_t w) { return static_cast<uint32_t>(w) & kIdMask; }
+__device__ __forceinline__ uint32_t f_mid(uint64_t w) {
+    return static_cast<uint32_t>(w >> kIdBits) & kIdMask;
+}
+__device__ __forceinline__ uint32_t f_k(uint64_t w) { return static_cast<uint32_t>(w >> kKShift); }
+__device__ __forceinline__ uint64_t pack(uint32_t lo, uint32_t mid, uint32_t k) {
+    return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(mid) << kIdBits) |
+           (static_cast<uint64_t>(k) << kKShift);
 }
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -67,8 +81,17 @@ __device__ __forceinline__ void wave_append(uint64_t *__restrict__ list, uint32_
     }
 }
 
-enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedraw, kPhOutput,
-                   kPhCount };
+// Order this wave's LDS accesses before and after (single-wave phases).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Per-phase clock sums: first arrows, in-arrow count + peel level 0, wide peel
+// levels, narrow (single-wave) peel levels, reverse sweep, split of the
+// unsettled list, cycle popping, output.
+enum Phase : int { kPhDraw0 = 0, kPhLevel0, kPhPeel, kPhTail, kPhSweep, kPhSplit, kPhCycles,
+                   kPhOutput, kPhCount };
 
 // Counter field of internal id x: LDS word, shift and mask.
 struct Field {
@@ -90,20 +113,27 @@ __device__ __forceinline__ Field field_of(const Classes &c, uint32_t x) {
     return {c.o3 + (x - c.n2), 0u, 0xFFFFFFFFu};
 }
 
-// One arrow of internal vertex v (record r) with draw index k in tree t:
-// internal | original target, (n | n << 32) for u*.
+// Arrow number k (0-based) of the vertex with record r in tree t: its tree
+// word with draw count k + 1 (internal | original target; u* = n in both).
 __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32_t key0,
                                          uint32_t key1, uint32_t k, uint32_t t) {
     const uint32_t orig = r.always_root & 0x7FFFFFFFu;
     const Philox4 x = philox4x32_10(orig, k, t, j.stream_id, key0, key1);
-    if ((r.always_root >> 31) || x.x0 < r.thr) return pair(j.n, j.n);
+    const uint64_t kbits = static_cast<uint64_t>(k + 1u) << kKShift;
+    if ((r.always_root >> 31) || x.x0 < r.thr) return pack(j.n, j.n, 0u) | kbits;
     const uint32_t idx = __umulhi(x.x1, r.deg);
-    return j.adj[r.start + static_cast<int32_t>(idx)];
+    return j.adj[r.start + static_cast<int32_t>(idx)] | kbits;
 }
+
+// Items per lane per pass iteration (independent loads in flight per lane):
+// streaming passes, and passes that also draw arrows (more registers each).
+constexpr int kR = 4;
+constexpr int kRD = 2;
 
 __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_lds[];
-    __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over;
+    __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev;
+    __shared__ uint64_t s_tail[64];
     __shared__ unsigned long long s_digest, s_roots;
     __shared__ unsigned long long s_ph[kPhCount + 1];
 
@@ -114,13 +144,11 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     const size_t slot = blockIdx.x;
     const size_t stride = a.n_max;
     uint64_t *__restrict__ word = static_cast<uint64_t *>(a.word) + slot * stride;
-    uint64_t *__restrict__ kk = a.kk + slot * stride;
     uint64_t *__restrict__ listA = a.lists + slot * (3ull * stride);
     uint64_t *__restrict__ listB = listA + stride;
     uint64_t *__restrict__ peel = listB + stride;
     uint32_t *__restrict__ lvl = a.levels + slot * (stride + 2);
     unsigned int err = 0;
-    uint32_t epoch = 0;
 
     const bool timing = a.phase_ticks != nullptr;
     if (tid == 0) s_over = 0;
@@ -168,7 +196,6 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             return (atomicAdd(&s_lds[f.w], 0u - (1u << f.sh)) >> f.sh) & f.mask;
         };
 
-        ++epoch;
         if (tid == 0) {
             s_u = 0;
             s_p = 0;
@@ -181,18 +208,34 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         // round 0: the first arrow of every vertex, and the first in-arrow count
         // (arrows into vertices that turn out settled are counted too; those
         // counts are never read)
-        for (uint32_t base = wave_base; base < n; base += T) {
-            const uint32_t v = base + lane;
-            uint32_t tg = n;
-            if (v < n) {
-                const VRec r = load_vrec(job.vrec, v);
-                const uint64_t w = draw(job, r, a.key0, a.key1, 0u, t);
-                word[v] = w;
-                tg = lo32(w);
-                if (tg == n) set_settled(v);
-                else count_add(tg);
+        for (uint32_t base = wave_base; base < n; base += kRD * T) {
+            VRec r[kRD];
+            uint64_t w[kRD];
+#pragma unroll
+            for (int q = 0; q < kRD; ++q) {
+                const uint32_t v = base + q * T + lane;
+                if (v < n) r[q] = load_vrec(job.vrec, v);
             }
-            wave_append(listA, &s_u, n, &s_over, pair(v, tg), v < n && tg != n);
+#pragma unroll
+            for (int q = 0; q < kRD; ++q) {
+                const uint32_t v = base + q * T + lane;
+                w[q] = v < n ? draw(job, r[q], a.key0, a.key1, 0u, t) : pack(n, n, 0u);
+            }
+#pragma unroll
+            for (int q = 0; q < kRD; ++q) {
+                const uint32_t v = base + q * T + lane;
+                if (v < n) {
+                    word[v] = w[q];
+                    if (f_lo(w[q]) == n) set_settled(v);
+                    else count_add(f_lo(w[q]));
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kRD; ++q) {
+                const uint32_t v = base + q * T + lane;
+                wave_append(listA, &s_u, n, &s_over, pack(v, f_lo(w[q]), 1u),
+                            v < n && f_lo(w[q]) != n);
+            }
         }
         __syncthreads();
         mark(kPhDraw0);
@@ -209,51 +252,54 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             }
             if (!counted) {
                 for (uint32_t i = tid; i < ucount; i += T) {
-                    const uint32_t tg = hi32(U[i]);
+                    const uint32_t tg = f_mid(U[i]);
                     if (!is_settled(tg)) count_add(tg);
                 }
                 __syncthreads();
             }
             counted = false;
             if (tid == 0) s_p = 0;
-            mark(kPhIndeg);
             // level 0 of the peel: no in-arrows
-            for (uint32_t base = wave_base; base < ucount; base += 2 * T) {
-                uint64_t it[2];
-                bool leaf[2];
+            for (uint32_t base = wave_base; base < ucount; base += kR * T) {
+                uint64_t it[kR];
+                bool leaf[kR];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < kR; ++q) {
                     const uint32_t i = base + q * T + lane;
                     it[q] = i < ucount ? U[i] : 0ull;
-                    leaf[q] = i < ucount && count_of(lo32(it[q])) == 0u;
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) wave_append(peel, &s_p, n, &s_over, it[q], leaf[q]);
+                for (int q = 0; q < kR; ++q) {
+                    const uint32_t i = base + q * T + lane;
+                    leaf[q] = i < ucount && count_of(f_lo(it[q])) == 0u;
+                }
+#pragma unroll
+                for (int q = 0; q < kR; ++q) wave_append(peel, &s_p, n, &s_over, it[q], leaf[q]);
             }
             __syncthreads();
             mark(kPhLevel0);
             uint32_t lo = 0, hi = min(uniform(s_p), n), nlev = 0;
             if (tid == 0) lvl[0] = 0;
-            while (lo < hi) {
+            while (hi - lo > 64u) {
                 if (tid == 0) lvl[nlev + 1] = hi;
-                for (uint32_t base = lo + wave_base; base < hi; base += 2 * T) {
-                    uint32_t tg[2];
-                    bool push[2];
-                    uint64_t nx[2];
+                for (uint32_t base = lo + wave_base; base < hi; base += kR * T) {
+                    uint32_t tg[kR];
+                    bool push[kR];
+                    uint64_t nx[kR];
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < kR; ++q) {
                         const uint32_t i = base + q * T + lane;
-                        tg[q] = i < hi ? hi32(peel[i]) : n;
+                        tg[q] = i < hi ? f_mid(peel[i]) : n;
                         push[q] = false;
                     }
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < kR; ++q)
                         if (!is_settled(tg[q])) push[q] = count_dec(tg[q]) == 1u;
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) nx[q] = push[q] ? word[tg[q]] : 0ull;
+                    for (int q = 0; q < kR; ++q) nx[q] = push[q] ? word[tg[q]] : 0ull;
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
-                        wave_append(peel, &s_p, n, &s_over, pair(tg[q], lo32(nx[q])), push[q]);
+                    for (int q = 0; q < kR; ++q)
+                        wave_append(peel, &s_p, n, &s_over, pack(tg[q], f_lo(nx[q]), 0u), push[q]);
                 }
                 __syncthreads();
                 ++nlev;
@@ -261,64 +307,155 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 hi = min(uniform(s_p), n);
                 __syncthreads();  // every wave has read s_p before the next level appends
             }
-            const uint32_t peeled = hi;
+            // No level is larger than the one before it (a peeled vertex frees at
+            // most its own target), so once a level fits in one wave, wave 0 peels
+            // the rest alone, without workgroup barriers: the frontier stays in
+            // registers (compacted through LDS) and is also appended to the list
+            // for the sweep.
+            const uint32_t tail0 = nlev;
             mark(kPhPeel);
+            if (lo < hi) {
+                if (wave_base == 0) {
+                    uint32_t cnt = hi - lo, pos = hi, nl = nlev;
+                    uint64_t it = lane < cnt ? peel[lo + lane] : 0ull;
+                    while (cnt > 0) {
+                        if (lane == 0) lvl[nl + 1] = pos;
+                        const uint32_t tg = f_mid(it);
+                        bool push = false;
+                        if (lane < cnt && !is_settled(tg)) push = count_dec(tg) == 1u;
+                        const uint64_t nx = push ? pack(tg, f_lo(word[tg]), 0u) : 0ull;
+                        const uint64_t mask = __ballot(push);
+                        const uint32_t m = static_cast<uint32_t>(__popcll(mask));
+                        if (pos + m > n) {
+                            if (lane == 0) s_over = 1u;
+                            break;
+                        }
+                        if (push) {
+                            const uint32_t r =
+                                static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
+                            s_tail[r] = nx;
+                            peel[pos + r] = nx;
+                        }
+                        wave_sync();
+                        it = lane < m ? s_tail[lane] : 0ull;
+                        wave_sync();
+                        pos += m;
+                        cnt = m;
+                        ++nl;
+                    }
+                    if (lane == 0) {
+                        s_p = pos;
+                        s_nlev = nl;
+                    }
+                }
+                __syncthreads();
+                hi = uniform(s_p);
+                nlev = uniform(s_nlev);
+            }
+            const uint32_t peeled = hi;
+            mark(kPhTail);
             if (peeled == ucount) {  // no cycle: every unsettled vertex reaches u*
                 ucount = 0;
                 break;
             }
-            for (int32_t Lv = static_cast<int32_t>(nlev) - 1; Lv >= 0; --Lv) {
+            // reverse sweep; the narrow tail levels first, by wave 0 alone (level
+            // boundaries fetched 63 at a time), then the wide ones
+            if (wave_base == 0 && nlev > tail0) {
+                for (int32_t top = static_cast<int32_t>(nlev) - 1; top >= static_cast<int32_t>(tail0);
+                     top -= 63) {
+                    const int32_t li = top + 1 - static_cast<int32_t>(lane);  // lane j: lvl[top + 1 - j]
+                    const uint32_t bnd = li >= static_cast<int32_t>(tail0) ? lvl[li] : 0u;
+                    const int32_t levels = min(63, top - static_cast<int32_t>(tail0) + 1);
+                    for (int32_t j = 0; j < levels; ++j) {
+                        const uint32_t a1 = __shfl(bnd, j, 64), a0 = __shfl(bnd, j + 1, 64);
+                        if (lane < a1 - a0) {
+                            const uint64_t p = peel[a0 + lane];
+                            if (is_settled(f_mid(p))) set_settled(f_lo(p));
+                        }
+                        wave_sync();
+                    }
+                }
+            }
+            __syncthreads();
+            for (int32_t Lv = static_cast<int32_t>(tail0) - 1; Lv >= 0; --Lv) {
                 const uint32_t a0 = uniform(lvl[Lv]), a1 = uniform(lvl[Lv + 1]);
                 for (uint32_t i = a0 + tid; i < a1; i += T) {
                     const uint64_t p = peel[i];
-                    if (is_settled(hi32(p))) set_settled(lo32(p));
+                    if (is_settled(f_mid(p))) set_settled(f_lo(p));
                 }
                 __syncthreads();
             }
             mark(kPhSweep);
+            // split the unsettled vertices: hanging ones keep their arrow (next
+            // list), cycle vertices (count 1) go to a cycle list in the dead peel
+            // buffer
             if (tid == 0) {
                 s_u = 0;
                 s_cycles = 0;
             }
             __syncthreads();
-            uint32_t my_cycles = 0;
-            for (uint32_t base = wave_base; base < ucount; base += 2 * T) {
-                uint64_t it[2];
-                bool keep[2];
+            uint64_t *__restrict__ cyc = peel;
+            for (uint32_t base = wave_base; base < ucount; base += kR * T) {
+                uint64_t it[kR];
+                bool keep[kR], pop[kR];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < kR; ++q) {
                     const uint32_t i = base + q * T + lane;
-                    it[q] = i < ucount ? U[i] : pair(n, n);
-                    keep[q] = false;
+                    it[q] = i < ucount ? U[i] : pack(n, n, 0u);
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const uint32_t v = lo32(it[q]);
-                    if (is_settled(v)) continue;
-                    if (count_of(v) != 0u) {  // on a cycle: pop it
-                        (void)count_dec(v);
-                        const uint64_t kv = kk[v];
-                        const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
-                        const VRec r = load_vrec(job.vrec, v);
-                        const uint64_t w = draw(job, r, a.key0, a.key1, k, t);
-                        if (k + 1u > 0x7FFFFFFFu) err |= kErrVisitOverflow;
-                        kk[v] = (static_cast<uint64_t>(epoch) << 32) | (k + 1u);
-                        word[v] = w;
-                        it[q] = pair(v, lo32(w));
-                        if (lo32(w) == n) set_settled(v);
-                        else keep[q] = true;
-                        ++my_cycles;
-                    } else {  // hanging off a cycle
-                        keep[q] = true;
+                for (int q = 0; q < kR; ++q) {
+                    const uint32_t v = f_lo(it[q]);
+                    const bool live = !is_settled(v);
+                    pop[q] = live && count_of(v) != 0u;
+                    keep[q] = live && !pop[q];
+                }
+#pragma unroll
+                for (int q = 0; q < kR; ++q) {
+                    wave_append(Unext, &s_u, n, &s_over, it[q], keep[q]);
+                    wave_append(cyc, &s_cycles, n, &s_over, it[q], pop[q]);
+                }
+            }
+            __syncthreads();
+            mark(kPhSplit);
+            // pop every cycle: each cycle vertex draws its next arrow
+            const uint32_t ccount = min(uniform(s_cycles), n);
+            for (uint32_t base = wave_base; base < ccount; base += kRD * T) {
+                uint32_t v[kRD], k[kRD];
+                VRec r[kRD];
+                uint64_t w[kRD];
+#pragma unroll
+                for (int q = 0; q < kRD; ++q) {
+                    const uint32_t i = base + q * T + lane;
+                    const uint64_t e = i < ccount ? cyc[i] : pack(n, n, 0u);
+                    v[q] = f_lo(e);
+                    k[q] = f_k(e);
+                    if (v[q] < n) r[q] = load_vrec(job.vrec, v[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < kRD; ++q) {
+                    if (v[q] < n && k[q] >= min(kKMax, a.k_limit)) {  // count past the limit
+                        err |= kErrVisitOverflow;
+                        v[q] = n;
+                    }
+                    w[q] = v[q] < n ? draw(job, r[q], a.key0, a.key1, k[q], t) : pack(n, n, 0u);
+                }
+#pragma unroll
+                for (int q = 0; q < kRD; ++q) {
+                    if (v[q] < n) {
+                        (void)count_dec(v[q]);  // the cycle's arrow into v is gone
+                        word[v[q]] = w[q];
+                        if (f_lo(w[q]) == n) set_settled(v[q]);
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) wave_append(Unext, &s_u, n, &s_over, it[q], keep[q]);
+                for (int q = 0; q < kRD; ++q)
+                    wave_append(Unext, &s_u, n, &s_over, pack(v[q], f_lo(w[q]), f_k(w[q])),
+                                v[q] < n && f_lo(w[q]) != n);
             }
-            if (my_cycles) atomicAdd(&s_cycles, my_cycles);
             __syncthreads();
-            mark(kPhRedraw);
-            draws += uniform(s_cycles);
+            mark(kPhCycles);
+            draws += ccount;
             ucount = min(uniform(s_u), n);
             uint64_t *tmp = U;
             U = Unext;
@@ -332,16 +469,15 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         for (uint32_t v = tid; v < n; v += T) {
             const uint64_t w = word[v];
             const uint32_t ov = job.orig[v];
-            const uint32_t otg = hi32(w);
+            const uint32_t otg = f_mid(w);
             my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | otg);
-            if (lo32(w) == n) {
+            if (f_lo(w) == n) {
                 ++my_roots;
                 atomicAdd(&job.root_counts[ov], 1u);
             }
             if (job.parents) job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(otg);
             if (want_k) {
-                const uint64_t kv = kk[v];
-                const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
+                const uint32_t k = f_k(w);
                 if (job.visit_counts)
                     atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(k));
                 if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = k;

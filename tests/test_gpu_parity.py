@@ -184,9 +184,32 @@ def test_ba200k_tree_subset_bit_exact(gpu_lib, sampler):
 @pytest.mark.parametrize("sampler", ["lane", "coop"])
 @pytest.mark.parametrize("alpha", [0.5, 1.0, 2.0])
 def test_grid_tree_subset_bit_exact(gpu_lib, alpha, sampler):
-    """1000 x 1000 grid with 12% of edges removed: 6 trees per alpha."""
+    """1000 x 1000 grid with 12% of edges removed: 16 trees per alpha."""
     g = inputs.grid_removed(1000, 1000, 0.12, 0)
-    _compare(gpu_lib, g, alpha, 0, 100, 6, sampler=sampler)
+    _compare(gpu_lib, g, alpha, 0, 100, 16, per_tree=sampler == "coop", sampler=sampler)
+
+
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_draw_limit_reports_overflow(gpu_lib, sampler):
+    """The per-vertex draw-count limit (forced down with option max_draws)
+    turns into FC_ERR_OVERFLOW; at the largest count the oracle sees, the run
+    succeeds and matches it."""
+    fc = gpu_lib
+    g = inputs.erdos_renyi(200, 0.05, 3)
+    ref = oracle.sample(g, 1.0, 9, 0, 8, per_tree=True)
+    kmax = int(ref.tree_visits.max())
+    assert kmax >= 2
+    fc.set_option("max_draws", kmax - 1)
+    try:
+        with pytest.raises(fc.FCError) as e:
+            fc.sample(g, alpha=1.0, seed=9, tree_begin=0, tree_count=8, sampler=sampler)
+        assert e.value.code == fc.FC_ERR_OVERFLOW
+        fc.set_option("max_draws", kmax)
+        got = fc.sample(g, alpha=1.0, seed=9, tree_begin=0, tree_count=8, want_digests=True,
+                        sampler=sampler)
+        assert np.array_equal(got["tree_digests"], ref.digests)
+    finally:
+        fc.set_option("max_draws", 0)
 
 
 def test_lds_sampler_rejects_graphs_too_large_and_auto_falls_back(gpu_lib):
@@ -204,20 +227,20 @@ def test_lds_sampler_rejects_graphs_too_large_and_auto_falls_back(gpu_lib):
     assert np.array_equal(got["tree_digests"], ref.digests)
 
 
-@pytest.mark.parametrize("threads,wg", [(64, 8), (256, 2), (512, 1), (1024, 2)])
+@pytest.mark.parametrize("threads,wg", [(64, 8), (256, 2), (512, 1), (1024, 2), (128, 0)])
 def test_lds_launch_shapes_bit_exact(gpu_lib, threads, wg):
     """LDS-counter sampler with other workgroup sizes and residency caps."""
     fc = gpu_lib
     fc.set_option("lds_threads", threads)
-    fc.set_option("coop_wg_per_cu", wg)
+    fc.set_option("lds_wg_per_cu", wg)
     try:
         g = inputs.barabasi_albert(20_000, 3, 7)
         _compare(fc, g, 1.5, 77, 9, 40, sampler="lds")
         g2 = inputs.grid_removed(120, 90, 0.12, 3)
         _compare(fc, g2, 2.0, 78, 0, 20, sampler="lds")
     finally:
-        fc.set_option("lds_threads", 1024)
-        fc.set_option("coop_wg_per_cu", 3)
+        fc.set_option("lds_threads", 0)
+        fc.set_option("lds_wg_per_cu", 0)
 
 
 def test_auto_choice_prefers_lds_counters(gpu_lib):
@@ -266,7 +289,9 @@ def test_set_option_rejects_bad_values(gpu_lib):
     fc = gpu_lib
     for key, val in (("coop_threads", 100), ("coop_threads", 1024), ("coop_wg_per_cu", 0),
                      ("lanes_per_wave", 65), ("nonsense", 1), ("coop_lds_bits", 2),
-                     ("coop_lds_counts", 2), ("lds_threads", 1088), ("lds_threads", 96)):
+                     ("coop_lds_counts", 2), ("lds_threads", 1088), ("lds_threads", 96),
+                     ("lds_wg_per_cu", -1), ("lds_wg_per_cu", 65), ("max_draws", -1),
+                     ("max_draws", 1 << 31)):
         with pytest.raises(fc.FCError) as e:
             fc.set_option(key, val)
         assert e.value.code == fc.FC_ERR_ARG
@@ -321,7 +346,7 @@ def counters(request, gpu_lib):
     """Runs a test with the workgroup kernels' in-arrow counters in LDS (the
     default) and in global tree words."""
     gpu_lib.set_option("coop_lds_counts", request.param)
-    yield "ldsbatch" if request.param else "batch"
+    yield "lbatch" if request.param else "batch"
     gpu_lib.set_option("coop_lds_counts", 1)
 
 
