@@ -246,6 +246,8 @@ def other_config(args, fc, inputs, dev):
     import numpy as np
     res = {"metric": "trees/s", "n_gpus": 1, "data": "synthetic", "dtype": "u32",
            "higher_is_better": True, "steps": args.steps, "warmup": args.warmup}
+    if args.phase_timing:
+        fc.set_option("phase_timing", 1, dev)
     if args.config in ("er1000", "rmat22"):
         if args.config == "er1000":
             g, alpha, trees, name = inputs.erdos_renyi(1000, 0.01, 0), 1.0, 2000, "er_n1000_p0.01_trees2000"
@@ -260,6 +262,8 @@ def other_config(args, fc, inputs, dev):
             per[smp] = {"trees_per_s": trees / dt, "ms_per_step": 1000 * dt,
                         "walk_steps_per_s": out["stats"]["walk_steps"] / dt,
                         "kernel_ms": out["stats"]["ms_sample"]}
+            if args.phase_timing:
+                per[smp]["phase_ms"] = out["stats"]["phase_ms"]
         best = max(per, key=lambda k: per[k]["trees_per_s"])
         res.update({"value": per[best]["trees_per_s"], "unit": "trees/s",
                     "config": {"workload": name, "n": g.n, "m": g.m, "alpha": alpha, "trees": trees},
@@ -281,6 +285,8 @@ def other_config(args, fc, inputs, dev):
             total_dt += dt
             per[str(alpha)] = {"trees_per_s": 1024 / dt, "walk_steps_per_tree": out["stats"]["walk_steps"] / 1024,
                                "kernel_ms": out["stats"]["ms_sample"], "sampler": out["stats"]["sampler"]}
+            if args.phase_timing:
+                per[str(alpha)]["phase_ms"] = out["stats"]["phase_ms"]
         res.update({"value": 3 * 1024 / total_dt, "unit": "trees/s",
                     "config": {"workload": "grid_1000x1000_rm0.12_alpha0.5_1_2_trees1024", "n": g.n,
                                "m": g.m}, "per_alpha": per})

@@ -112,7 +112,8 @@ int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out) 
                                    ctx->stream), "copy error word");
         FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "validate_rows");
         if (err) return set_err(ctx, FC_ERR_GRAPH, "row_ptr is not monotone from 0 to nnz");
-        FC_HIP(ctx, fc::launch_validate_cols(v.row_ptr, v.col_idx, v.n, &sm->graph_err, ctx->stream),
+        FC_HIP(ctx, fc::launch_validate_cols(v.row_ptr, v.col_idx, v.n, v.nnz, &sm->graph_err,
+                                             ctx->stream),
                "validate_cols launch");
         FC_HIP(ctx, hipMemcpyAsync(&err, &sm->graph_err, sizeof(err), hipMemcpyDeviceToHost,
                                    ctx->stream), "copy error word");

@@ -16,7 +16,7 @@ namespace fc {
 hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
                                 unsigned int *err, hipStream_t stream);
 hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
-                                unsigned int *err, hipStream_t stream);
+                                int64_t nnz, unsigned int *err, hipStream_t stream);
 
 // Per-vertex records of G* for one alpha; atomically maxes the degree into *dmax.
 hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,

@@ -23,32 +23,49 @@ __global__ void validate_rows_kernel(const int32_t *__restrict__ row_ptr, int32_
     if (bad) atomicOr(err, kErrGraphRowPtr);
 }
 
-// One thread per vertex; symmetry by binary search of v in the row of each
-// neighbour (rows are sorted, which this kernel also checks).
+// Edge-parallel: each thread checks kColChunk consecutive CSR entries.  It
+// finds the row of its first entry by binary search over row_ptr, then walks
+// rows forward; every entry is checked for range, self-loop, strict order
+// against the previous entry of its row, and symmetry by binary search of the
+// row vertex in the row of the neighbour (rows are sorted, which this kernel
+// also checks).  Work is proportional to nnz whatever the degree spread.
+constexpr int64_t kColChunk = 16;
+
 __global__ void validate_cols_kernel(const int32_t *__restrict__ row_ptr,
-                                     const int32_t *__restrict__ col_idx, int32_t n,
+                                     const int32_t *__restrict__ col_idx, int32_t n, int64_t nnz,
                                      unsigned int *err) {
-    const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (v >= n) return;
+    const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * kColChunk;
+    if (e0 >= nnz) return;
+    const int64_t e1 = e0 + kColChunk < nnz ? e0 + kColChunk : nnz;
+    // row v with row_ptr[v] <= e0 < row_ptr[v + 1] (row_ptr is monotone: pass 1)
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (row_ptr[mid] <= e0) lo = mid;
+        else hi = mid - 1;
+    }
+    int32_t v = lo;
+    int64_t row_end = row_ptr[v + 1];
     unsigned int e = 0;
-    const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-    int32_t prev = -1;
-    for (int32_t j = a; j < b; ++j) {
+    for (int64_t j = e0; j < e1; ++j) {
+        while (j >= row_end) {  // skip to the row holding entry j (empty rows included)
+            ++v;
+            row_end = row_ptr[v + 1];
+        }
         const int32_t u = col_idx[j];
         if (u < 0 || u >= n) {
             e |= kErrGraphColumn;
-            break;
+            continue;
         }
         if (u == v) e |= kErrGraphSelfLoop;
-        if (u <= prev) e |= kErrGraphOrder;
-        prev = u;
-        int32_t lo = row_ptr[u], hi = row_ptr[u + 1];
-        while (lo < hi) {
-            const int32_t mid = lo + ((hi - lo) >> 1);
-            if (col_idx[mid] < v) lo = mid + 1;
-            else hi = mid;
+        if (j > row_ptr[v] && col_idx[j - 1] >= u) e |= kErrGraphOrder;
+        int32_t a = row_ptr[u], b = row_ptr[u + 1];
+        while (a < b) {
+            const int32_t mid = a + ((b - a) >> 1);
+            if (col_idx[mid] < v) a = mid + 1;
+            else b = mid;
         }
-        if (lo >= row_ptr[u + 1] || col_idx[lo] != v) e |= kErrGraphAsymmetric;
+        if (a >= row_ptr[u + 1] || col_idx[a] != v) e |= kErrGraphAsymmetric;
     }
     if (e) atomicOr(err, e);
 }
@@ -105,9 +122,10 @@ hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
 }
 
 hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
-                                unsigned int *err, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    validate_cols_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, col_idx, n, err);
+                                int64_t nnz, unsigned int *err, hipStream_t stream) {
+    if (n == 0 || nnz == 0) return hipSuccess;
+    validate_cols_kernel<<<blocks_for((nnz + kColChunk - 1) / kColChunk, 256), 256, 0, stream>>>(
+        row_ptr, col_idx, n, nnz, err);
     return hipGetLastError();
 }
 

@@ -73,6 +73,15 @@ __device__ __forceinline__ void wg_fetch_or(uint32_t *p, uint32_t v) {
     (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Order this wave's LDS accesses before and after (single-wave phases).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Items per lane per iteration of the streaming passes (loads in flight).
+constexpr int kR = 2;
+
 // Per-phase wall-clock accounting (tid 0 of each workgroup), when requested.
 enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedraw, kPhOutput,
                    kPhCount };
@@ -101,7 +110,8 @@ template <bool kLdsBits, typename W, bool kInBits>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6)))
 void wilson_coop_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_dyn[];
-    __shared__ uint32_t s_item, s_u, s_p, s_cycles;
+    __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev;
+    __shared__ uint64_t s_tail[64];
     __shared__ unsigned long long s_digest, s_roots;
 
     const uint32_t T = blockDim.x;
@@ -125,6 +135,7 @@ void wilson_coop_kernel(CoopArgs a) {
     // phase accounting lives in LDS (thread 0 only) to keep it out of registers
     __shared__ unsigned long long s_ph[kPhCount + 1];
     const bool timing = a.phase_ticks != nullptr;
+    if (tid == 0) s_over = 0;
     if (timing && tid == 0) {
         for (int i = 0; i < kPhCount; ++i) s_ph[i] = 0;
         s_ph[kPhCount] = wall_clock64();
@@ -176,15 +187,26 @@ void wilson_coop_kernel(CoopArgs a) {
         __syncthreads();
 
         // round 0: the first arrow of every vertex
-        for (uint32_t base = wave_base; base < n; base += T) {
-            const uint32_t v = base + lane;
-            uint32_t tg = n;
-            if (v < n) {
-                tg = draw(job, a.key0, a.key1, v, 0u, t);
-                word[v] = static_cast<W>(tg);
-                if (tg == n) set_settled(v);
+        for (uint32_t base = wave_base; base < n; base += 2 * T) {
+            uint32_t tg[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t v = base + q * T + lane;
+                tg[q] = v < n ? draw(job, a.key0, a.key1, v, 0u, t) : n;
             }
-            wave_append(listA, &s_u, pair(v, tg), v < n && tg != n);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t v = base + q * T + lane;
+                if (v < n) {
+                    word[v] = static_cast<W>(tg[q]);
+                    if (tg[q] == n) set_settled(v);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t v = base + q * T + lane;
+                wave_append(listA, &s_u, pair(v, tg[q]), v < n && tg[q] != n);
+            }
         }
         __syncthreads();
         mark(kPhDraw0);
@@ -194,77 +216,133 @@ void wilson_coop_kernel(CoopArgs a) {
         uint32_t rounds = 0;
 
         while (ucount > 0) {
-            if (++rounds > a.max_rounds || draws > job.step_cap) {
+            if (++rounds > a.max_rounds || draws > job.step_cap || s_over) {
                 err |= kErrStepCap;
                 break;
             }
             // in-arrows of unsettled targets from unsettled vertices (no return value:
             // the atomics do not stall the thread)
-            for (uint32_t i = tid; i < ucount; i += T) {
-                const uint32_t tg = hi32(U[i]);
-                if (!is_settled(tg)) {
-                    (void)wg_fetch_add(&word[tg], cnt_one);
-                    if (kInBits) set_in(tg);
+            for (uint32_t base = tid; base < ucount; base += kR * T) {
+                uint32_t tg[kR];
+#pragma unroll
+                for (int q = 0; q < kR; ++q) {
+                    const uint32_t i = base + q * T;
+                    tg[q] = i < ucount ? hi32(U[i]) : n;
+                }
+#pragma unroll
+                for (int q = 0; q < kR; ++q) {
+                    if (!is_settled(tg[q])) {
+                        (void)wg_fetch_add(&word[tg[q]], cnt_one);
+                        if (kInBits) set_in(tg[q]);
+                    }
                 }
             }
             if (tid == 0) s_p = 0;  // last read of s_p was followed by barriers
             __syncthreads();
             mark(kPhIndeg);
             // level 0 of the peel: no in-arrows
-            for (uint32_t base = wave_base; base < ucount; base += 2 * T) {
-                uint64_t it[2];
-                bool leaf[2];
+            for (uint32_t base = wave_base; base < ucount; base += kR * T) {
+                uint64_t it[kR];
+                bool leaf[kR];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < kR; ++q) {
                     const uint32_t i = base + q * T + lane;
                     it[q] = i < ucount ? U[i] : 0ull;
                     leaf[q] = false;
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < kR; ++q) {
                     const uint32_t i = base + q * T + lane;
                     if (i < ucount)
                         leaf[q] = kInBits ? !has_in(lo32(it[q])) : cnt_of(word[lo32(it[q])]) == 0u;
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) wave_append(peel, &s_p, it[q], leaf[q]);
+                for (int q = 0; q < kR; ++q) wave_append(peel, &s_p, it[q], leaf[q]);
             }
             __syncthreads();
             mark(kPhLevel0);
-            uint32_t lo = 0, hi = uniform(s_p), nlev = 0;
+            uint32_t lo = 0, hi = min(uniform(s_p), n), nlev = 0;
             if (tid == 0) lvl[0] = 0;
             // peel level by level: a peeled vertex's target loses one in-arrow; the
             // atomic returns the target's own arrow, which goes into the list with it
-            while (lo < hi) {
+            while (hi - lo > 64u) {
                 if (tid == 0) lvl[nlev + 1] = hi;
-                for (uint32_t base = lo + wave_base; base < hi; base += 2 * T) {
-                    uint32_t tg[2];
-                    W old[2];
-                    bool push[2];
+                for (uint32_t base = lo + wave_base; base < hi; base += kR * T) {
+                    uint32_t tg[kR];
+                    W old[kR];
+                    bool push[kR];
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < kR; ++q) {
                         const uint32_t i = base + q * T + lane;
                         tg[q] = i < hi ? hi32(peel[i]) : n;
                         push[q] = false;
                         old[q] = 0;
                     }
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < kR; ++q)
                         if (!is_settled(tg[q])) old[q] = wg_fetch_add(&word[tg[q]], cnt_minus_one);
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < kR; ++q) {
                         push[q] = !is_settled(tg[q]) && cnt_of(old[q]) == 1u;
                         if (kInBits && push[q]) clear_in(tg[q]);
                     }
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < kR; ++q)
                         wave_append(peel, &s_p, pair(tg[q], target_of(old[q])), push[q]);
                 }
                 __syncthreads();
                 ++nlev;
                 lo = hi;
-                hi = uniform(s_p);
+                hi = min(uniform(s_p), n);
                 __syncthreads();  // every wave has read s_p before the next level appends
+            }
+            // No level is larger than the one before it (a peeled vertex frees at
+            // most its own target): once a level fits in one wave, wave 0 peels the
+            // rest alone, without workgroup barriers, the frontier compacted
+            // through LDS and appended to the list for the sweep.
+            const uint32_t tail0 = nlev;
+            if (lo < hi) {
+                if (wave_base == 0) {
+                    uint32_t cnt = hi - lo, pos = hi, nl = nlev;
+                    uint64_t it = lane < cnt ? peel[lo + lane] : 0ull;
+                    while (cnt > 0) {
+                        if (lane == 0) lvl[nl + 1] = pos;
+                        const uint32_t tg = hi32(it);
+                        bool push = false;
+                        W old = 0;
+                        if (lane < cnt && !is_settled(tg)) {
+                            old = wg_fetch_add(&word[tg], cnt_minus_one);
+                            push = cnt_of(old) == 1u;
+                            if (kInBits && push) clear_in(tg);
+                        }
+                        const uint64_t mask = __ballot(push);
+                        const uint32_t m = static_cast<uint32_t>(__popcll(mask));
+                        if (pos + m > n) {  // only with counts a valid graph cannot produce
+                            if (lane == 0) s_over = 1u;
+                            break;
+                        }
+                        if (push) {
+                            const uint32_t r =
+                                static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
+                            const uint64_t nx = pair(tg, target_of(old));
+                            s_tail[r] = nx;
+                            peel[pos + r] = nx;
+                        }
+                        wave_sync();
+                        it = lane < m ? s_tail[lane] : 0ull;
+                        wave_sync();
+                        pos += m;
+                        cnt = m;
+                        ++nl;
+                    }
+                    if (lane == 0) {
+                        s_p = pos;
+                        s_nlev = nl;
+                    }
+                }
+                __syncthreads();
+                hi = uniform(s_p);
+                nlev = uniform(s_nlev);
             }
             const uint32_t peeled = hi;
             mark(kPhPeel);
@@ -272,8 +350,26 @@ void wilson_coop_kernel(CoopArgs a) {
                 ucount = 0;
                 break;
             }
-            // reverse sweep: settled when the arrow reaches u* or a settled vertex
-            for (int32_t L = static_cast<int32_t>(nlev) - 1; L >= 0; --L) {
+            // reverse sweep: settled when the arrow reaches u* or a settled vertex;
+            // the narrow tail levels first by wave 0 alone, then the wide ones
+            if (wave_base == 0 && nlev > tail0) {
+                for (int32_t top = static_cast<int32_t>(nlev) - 1; top >= static_cast<int32_t>(tail0);
+                     top -= 63) {
+                    const int32_t li = top + 1 - static_cast<int32_t>(lane);  // lane j: lvl[top + 1 - j]
+                    const uint32_t bnd = li >= static_cast<int32_t>(tail0) ? lvl[li] : 0u;
+                    const int32_t levels = min(63, top - static_cast<int32_t>(tail0) + 1);
+                    for (int32_t j = 0; j < levels; ++j) {
+                        const uint32_t a1 = __shfl(bnd, j, 64), a0 = __shfl(bnd, j + 1, 64);
+                        if (lane < a1 - a0) {
+                            const uint64_t p = peel[a0 + lane];
+                            if (is_settled(hi32(p))) set_settled(lo32(p));
+                        }
+                        wave_sync();
+                    }
+                }
+            }
+            __syncthreads();
+            for (int32_t L = static_cast<int32_t>(tail0) - 1; L >= 0; --L) {
                 const uint32_t a0 = uniform(lvl[L]), a1 = uniform(lvl[L + 1]);
                 for (uint32_t i = a0 + tid; i < a1; i += T) {
                     const uint64_t p = peel[i];
@@ -282,56 +378,77 @@ void wilson_coop_kernel(CoopArgs a) {
                 __syncthreads();
             }
             mark(kPhSweep);
-            // pop every cycle: unsettled vertices that kept in-arrows draw again
+            // split the unsettled vertices: those hanging off a cycle keep their
+            // arrow (next list); cycle vertices (in-arrows left) go to a cycle
+            // list in the dead peel buffer
             if (tid == 0) {  // last reads of s_u / s_cycles were followed by barriers
                 s_u = 0;
                 s_cycles = 0;
             }
             __syncthreads();
-            uint32_t my_cycles = 0;
-            for (uint32_t base = wave_base; base < ucount; base += 2 * T) {
-                uint64_t it[2];
-                W w[2];
-                bool keep[2];
+            uint64_t *__restrict__ cyc = peel;
+            for (uint32_t base = wave_base; base < ucount; base += kR * T) {
+                uint64_t it[kR];
+                W w[kR];
+                bool keep[kR], pop[kR];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < kR; ++q) {
                     const uint32_t i = base + q * T + lane;
                     it[q] = i < ucount ? U[i] : pair(n, n);
-                    keep[q] = false;
                     w[q] = 0;
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
+                for (int q = 0; q < kR; ++q)
                     if (!kInBits && !is_settled(lo32(it[q]))) w[q] = word[lo32(it[q])];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < kR; ++q) {
                     const uint32_t v = lo32(it[q]);
-                    if (is_settled(v)) continue;
-                    const bool on_cycle = kInBits ? has_in(v) : cnt_of(w[q]) > 0u;
-                    if (on_cycle) {
-                        if (kInBits) clear_in(v);
-                        const uint64_t kv = kk[v];
-                        const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
-                        const uint32_t tg = draw(job, a.key0, a.key1, v, k, t);
-                        if (k + 1u > a.k_limit) err |= kErrVisitOverflow;
-                        kk[v] = (static_cast<uint64_t>(epoch) << 32) | (k + 1u);
-                        word[v] = static_cast<W>(tg);
-                        it[q] = pair(v, tg);
-                        if (tg == n) set_settled(v);
-                        else keep[q] = true;
-                        ++my_cycles;
-                    } else {  // hanging off a cycle: keeps its arrow, stays unsettled
-                        keep[q] = true;
+                    const bool live = !is_settled(v);
+                    pop[q] = live && (kInBits ? has_in(v) : cnt_of(w[q]) > 0u);
+                    keep[q] = live && !pop[q];
+                }
+#pragma unroll
+                for (int q = 0; q < kR; ++q) {
+                    wave_append(Unext, &s_u, it[q], keep[q]);
+                    wave_append(cyc, &s_cycles, it[q], pop[q]);
+                }
+            }
+            __syncthreads();
+            // pop every cycle: each cycle vertex draws its next arrow
+            const uint32_t ccount = min(uniform(s_cycles), n);
+            for (uint32_t base = wave_base; base < ccount; base += 2 * T) {
+                uint32_t v[2], k[2], tg[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint32_t i = base + q * T + lane;
+                    v[q] = i < ccount ? lo32(cyc[i]) : n;
+                    k[q] = 1u;
+                    if (v[q] < n) {
+                        const uint64_t kv = kk[v[q]];
+                        if (hi32(kv) == epoch) k[q] = lo32(kv);
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) wave_append(Unext, &s_u, it[q], keep[q]);
+                for (int q = 0; q < 2; ++q)
+                    tg[q] = v[q] < n ? draw(job, a.key0, a.key1, v[q], k[q], t) : n;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    if (v[q] < n) {
+                        if (kInBits) clear_in(v[q]);
+                        if (k[q] + 1u > a.k_limit) err |= kErrVisitOverflow;
+                        kk[v[q]] = (static_cast<uint64_t>(epoch) << 32) | (k[q] + 1u);
+                        word[v[q]] = static_cast<W>(tg[q]);  // count back to 0 with it
+                        if (tg[q] == n) set_settled(v[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    wave_append(Unext, &s_u, pair(v[q], tg[q]), v[q] < n && tg[q] != n);
             }
-            if (my_cycles) atomicAdd(&s_cycles, my_cycles);
             __syncthreads();
             mark(kPhRedraw);
-            draws += uniform(s_cycles);
-            ucount = uniform(s_u);
+            draws += ccount;
+            ucount = min(uniform(s_u), n);
             uint64_t *tmp = U;
             U = Unext;
             Unext = tmp;
