@@ -252,7 +252,6 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             const size_t per_slot = (8u + 24u + 4u) * n + 8u;
             slots = std::max<size_t>(1, ctx->state_budget / per_slot);
             slots = std::min<size_t>(slots, tree_count);
-            FC_HIP(ctx, fc::lds_set_limit(lds_words), "LDS limit");
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
             uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
             const int fit = fc::lds_max_active(lds_threads, lds_words);
@@ -317,8 +316,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         slots = std::min<size_t>(slots, tree_count);
         // persistent workgroups: as many as requested per CU, but never more
         // than fit at once (a workgroup that starts late finds the queue empty)
-        FC_HIP(ctx, fc::coop_set_lds_limit(lds_bits, in_bits, word32, static_cast<uint32_t>(g.n)),
-               "coop LDS limit");
+
         uint32_t per_cu = ctx->coop_wg_per_cu;
         const int fit = fc::coop_max_active(ctx->coop_threads, lds_bits, in_bits, word32,
                                             static_cast<uint32_t>(g.n));
@@ -524,6 +522,14 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) ==
             hipSuccess && lds > 0)
         ctx->max_lds = static_cast<size_t>(lds);
+    // dynamic LDS: allow the workgroup kernels up to the device limit once;
+    // each launch passes what it uses
+    if (fc::coop_set_lds_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess ||
+        fc::lds_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fc_destroy(ctx);
+        return FC_ERR_HIP;
+    }
     ctx->coop_threads = env_u32("FC_COOP_THREADS", 512);
     if (ctx->coop_threads < 64 || ctx->coop_threads > 512 || ctx->coop_threads % 64)
         ctx->coop_threads = 512;

@@ -1,13 +1,16 @@
 // Batches of sampling jobs (fc_batch_create / fc_batch_run / fc_batch_destroy).
 //
-// A batch turns many (graph, alpha, tree range) jobs into one list of work
-// items (trees), ordered largest graph first so that the longest trees start
-// early, and samples them with the workgroup-per-tree kernel in a single
-// persistent launch whose workgroups pull items from a device queue.  The
-// per-slot scratch is sized for the largest graph.  Everything that does not
-// change between runs (validation, vertex records, item order, scratch,
-// launch shape) happens once in fc_batch_create; a run replays a captured
-// HIP graph made of two fill kernels (counters, epoch-tagged draw counts)
+// A batch turns many (graph, alpha, tree range) jobs into lists of work items
+// (trees), ordered largest graph first so that the longest trees start early,
+// and samples each list with a workgroup-per-tree kernel in one persistent
+// launch whose workgroups pull items from a device queue.  With LDS counters
+// the jobs fall into up to two launch groups: graphs whose counter fields take
+// at most a quarter of a CU's LDS ("narrow": several trees per CU, narrower
+// workgroups) and the rest ("wide": one or two trees per CU).  Each group's
+// per-slot scratch is sized for its largest graph.  Everything that does not
+// change between runs (validation, vertex records, relabelling, item order,
+// scratch, launch shapes) happens once in fc_batch_create; a run replays one
+// captured HIP graph: per group, fill kernels (counters, draw-count epochs)
 // and the sampling kernel.
 #include <algorithm>
 #include <array>
@@ -21,20 +24,32 @@
 
 using namespace fc_host;
 
+namespace {
+
+// One persistent launch: its jobs (batch job indices, largest graph first),
+// device job table and item map, scratch, counters and launch shape.
+struct Group {
+    std::vector<int32_t> jobs;
+    DevBuf jobtab, item_job, word, kk, lists, levels, bits, small, scratch_r;
+    fc::CoopArgs args{};
+    uint32_t n_max = 0, item_count = 0, slots = 0, threads = 512, wg_per_cu = 4;
+    size_t ntab = 0, kk_words = 0;
+    bool use_lds = false, lds_bits = false, in_bits = false, word32 = true;
+    uint32_t lds_words = 0;  // dynamic LDS of the LDS-counter kernel (largest graph)
+};
+
+}  // namespace
+
 struct fc_batch {
     fc_ctx *ctx = nullptr;
     std::vector<fc_job> jobs;
     uint64_t seed = 0;
     int32_t flags = 0;
-    DevBuf vrec, jobtab, item_job, word, kk, lists, levels, bits, small, dmax, scratch_r;
+    DevBuf vrec, dmax;
     DevBuf rl_blk, rl_base, rl_bounds, rl_inv, rl_orig, rl_adj, rl_vrec;  // degree-class relabelling
-    uint32_t n_max = 0, item_count = 0, slots = 0, threads = 512, wg_per_cu = 4;
-    size_t ntab = 0;  // entries of the device job table (jobs that have trees)
-    bool lds_bits = false, in_bits = false, word32 = true;
-    bool use_lds = false;     // LDS-counter kernel
-    uint32_t lds_words = 0;   // its dynamic LDS (largest graph of the batch)
-    size_t kk_words = 0;
-    fc::CoopArgs args{};
+    Group grp[2];
+    int ngroups = 0;
+    uint32_t item_count = 0;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -48,10 +63,13 @@ int free_batch(fc_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (DevBuf *d : {&b->vrec, &b->jobtab, &b->item_job, &b->word, &b->kk, &b->lists, &b->levels,
-                      &b->bits, &b->small, &b->dmax, &b->scratch_r, &b->rl_blk, &b->rl_base,
-                      &b->rl_bounds, &b->rl_inv, &b->rl_orig, &b->rl_adj, &b->rl_vrec})
+    for (DevBuf *d : {&b->vrec, &b->dmax, &b->rl_blk, &b->rl_base, &b->rl_bounds, &b->rl_inv,
+                      &b->rl_orig, &b->rl_adj, &b->rl_vrec})
         if (d->ptr) (void)hipFree(d->ptr);
+    for (Group &g : b->grp)
+        for (DevBuf *d : {&g.jobtab, &g.item_job, &g.word, &g.kk, &g.lists, &g.levels, &g.bits,
+                          &g.small, &g.scratch_r})
+            if (d->ptr) (void)hipFree(d->ptr);
     for (hipEvent_t e : {b->ev_in, b->ev0, b->ev1})
         if (e) (void)hipEventDestroy(e);
     if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -59,118 +77,124 @@ int free_batch(fc_batch *b) {
     return FC_OK;
 }
 
-// Enqueue one run on `stream`: reset counters and draw-count epochs, then sample.
-hipError_t enqueue_run(fc_batch *b, const fc::CoopArgs &a, uint32_t threads, hipStream_t stream) {
-    hipError_t e = fc::launch_fill_u64(static_cast<unsigned long long *>(b->small.ptr),
+// Enqueue one run of a group on `stream`: reset its counters (and draw-count
+// epochs for the global-counter kernel), then sample.
+hipError_t enqueue_group(const Group &g, const fc::CoopArgs &a, uint32_t threads,
+                         hipStream_t stream) {
+    hipError_t e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.small.ptr),
                                        sizeof(Small) / 8, 0ull, stream);
     if (e != hipSuccess) return e;
-    if (b->use_lds) return fc::launch_wilson_lds(a, threads, b->lds_words, stream);
-    e = fc::launch_fill_u64(static_cast<unsigned long long *>(b->kk.ptr), b->kk_words, 0ull, stream);
+    if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, stream);
+    e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.kk.ptr), g.kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
-    return fc::launch_wilson_coop(a, threads, b->lds_bits, b->in_bits, b->word32, stream);
+    return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, stream);
 }
 
-// Size the scratch for `slots` workgroups and point the launch arguments at it.
-int size_scratch(fc_batch *b, uint32_t slots) {
-    fc_ctx *ctx = b->ctx;
+// Size a group's scratch for `slots` workgroups and point its arguments at it.
+int size_scratch(fc_ctx *ctx, Group &g, uint32_t slots) {
     int rc;
-    const size_t n = b->n_max, nwords = (n + 31) / 32;
-    const size_t wbytes = b->word32 && !b->use_lds ? 4 : 8;
-    if ((rc = ensure(ctx, b->word, wbytes * n * slots, "batch tree words"))) return rc;
-    if (!b->use_lds && (rc = ensure(ctx, b->kk, 8 * n * slots, "batch draw counts"))) return rc;
-    if ((rc = ensure(ctx, b->lists, 24 * n * slots, "batch lists"))) return rc;
-    if ((rc = ensure(ctx, b->levels, 4 * (n + 2) * slots, "batch levels"))) return rc;
-    if (!b->use_lds && !b->lds_bits &&
-        (rc = ensure(ctx, b->bits, 4 * nwords * slots, "batch bitmap")))
+    const size_t n = g.n_max, nwords = (n + 31) / 32;
+    const size_t wbytes = g.word32 && !g.use_lds ? 4 : 8;
+    if ((rc = ensure(ctx, g.word, wbytes * n * slots, "batch tree words"))) return rc;
+    if (!g.use_lds && (rc = ensure(ctx, g.kk, 8 * n * slots, "batch draw counts"))) return rc;
+    if ((rc = ensure(ctx, g.lists, 24 * n * slots, "batch lists"))) return rc;
+    if ((rc = ensure(ctx, g.levels, 4 * (n + 2) * slots, "batch levels"))) return rc;
+    if (!g.use_lds && !g.lds_bits && (rc = ensure(ctx, g.bits, 4 * nwords * slots, "batch bitmap")))
         return rc;
-    b->kk_words = n * slots;
-    b->slots = slots;
-    fc::CoopArgs &a = b->args;
-    a.word = b->word.ptr;
-    a.kk = b->use_lds ? nullptr : static_cast<uint64_t *>(b->kk.ptr);
-    a.lists = static_cast<uint64_t *>(b->lists.ptr);
-    a.levels = static_cast<uint32_t *>(b->levels.ptr);
-    a.bits = b->lds_bits || b->use_lds ? nullptr : static_cast<uint32_t *>(b->bits.ptr);
+    g.kk_words = n * slots;
+    g.slots = slots;
+    fc::CoopArgs &a = g.args;
+    a.word = g.word.ptr;
+    a.kk = g.use_lds ? nullptr : static_cast<uint64_t *>(g.kk.ptr);
+    a.lists = static_cast<uint64_t *>(g.lists.ptr);
+    a.levels = static_cast<uint32_t *>(g.levels.ptr);
+    a.bits = g.lds_bits || g.use_lds ? nullptr : static_cast<uint32_t *>(g.bits.ptr);
     a.slots = slots;
     return FC_OK;
 }
 
-uint32_t slots_for(fc_batch *b, uint32_t threads, uint32_t wg_per_cu) {
-    const size_t n = b->n_max;
-    const int fit = b->use_lds ? fc::lds_max_active(threads, b->lds_words)
-                               : fc::coop_max_active(threads, b->lds_bits, b->in_bits, b->word32,
-                                                     b->n_max);
+uint32_t slots_for(const fc_ctx *ctx, const Group &g, uint32_t threads, uint32_t wg_per_cu) {
+    const size_t n = g.n_max;
+    const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words)
+                              : fc::coop_max_active(threads, g.lds_bits, g.in_bits, g.word32, g.n_max);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
-    const size_t per_slot = b->use_lds ? (8 + 24 + 4) * n + 8
-                                       : ((b->word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
-                                             (b->lds_bits ? 0 : 4 * ((n + 31) / 32));
-    size_t slots = std::max<size_t>(1, b->ctx->state_budget / per_slot);
-    slots = std::min<size_t>(slots, static_cast<size_t>(b->ctx->cu_count) * wg_per_cu);
-    slots = std::min<size_t>(slots, b->item_count);
+    const size_t per_slot = g.use_lds ? (8 + 24 + 4) * n + 8
+                                      : ((g.word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
+                                            (g.lds_bits ? 0 : 4 * ((n + 31) / 32));
+    size_t slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+    slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * wg_per_cu);
+    slots = std::min<size_t>(slots, g.item_count);
     return static_cast<uint32_t>(std::max<size_t>(slots, 1));
 }
 
-// Launch-shape autotuning on a prefix of the work items with throw-away
-// outputs: results never depend on the shape, only the time does.
-int autotune(fc_batch *b) {
+// Launch-shape autotuning of one group on a prefix of its work items with
+// throw-away outputs: results never depend on the shape, only the time does.
+int autotune(fc_batch *b, Group &g) {
     fc_ctx *ctx = b->ctx;
-    int rc;
+    int rc = FC_OK;
     static const uint32_t cand_coop[][2] = {{256, 3}, {256, 6}, {512, 2}, {512, 3}, {128, 12}};
     static const uint32_t cand_lds[][2] = {{256, 64}, {512, 64}, {1024, 64}, {256, 4}, {512, 2}};
     std::vector<std::array<uint32_t, 2>> cand;
-    if (b->use_lds)
+    if (g.use_lds)
         for (const auto &c : cand_lds) cand.push_back({c[0], c[1]});
     else
         for (const auto &c : cand_coop) cand.push_back({c[0], c[1]});
     // throw-away job table: same graphs and records, outputs into one scratch R
-    std::vector<fc::CoopJob> tab(b->ntab);
-    FC_HIP(ctx, hipMemcpy(tab.data(), b->jobtab.ptr, sizeof(fc::CoopJob) * tab.size(),
+    std::vector<fc::CoopJob> tab(g.ntab);
+    FC_HIP(ctx, hipMemcpy(tab.data(), g.jobtab.ptr, sizeof(fc::CoopJob) * tab.size(),
                           hipMemcpyDeviceToHost), "read job table");
-    if ((rc = ensure(ctx, b->scratch_r, 4 * static_cast<size_t>(b->n_max), "tuning outputs"))) return rc;
-    DevBuf tmp_tab;
+    if ((rc = ensure(ctx, g.scratch_r, 4 * static_cast<size_t>(g.n_max), "tuning outputs"))) return rc;
     for (auto &j : tab) {
-        j.root_counts = static_cast<uint32_t *>(b->scratch_r.ptr);
+        j.root_counts = static_cast<uint32_t *>(g.scratch_r.ptr);
         j.visit_counts = nullptr;
         j.tree_digests = nullptr;
         j.tree_steps = nullptr;
         j.parents = nullptr;
         j.tree_visits = nullptr;
     }
+    DevBuf tmp_tab;
     if ((rc = ensure(ctx, tmp_tab, sizeof(fc::CoopJob) * tab.size(), "tuning job table"))) return rc;
-    FC_HIP(ctx, hipMemcpy(tmp_tab.ptr, tab.data(), sizeof(fc::CoopJob) * tab.size(),
-                          hipMemcpyHostToDevice), "write tuning table");
-    const uint32_t prefix = std::min<uint32_t>(b->item_count,
-                                               std::max<uint32_t>(b->item_count / 16, 4096));
+    const uint32_t prefix = std::min<uint32_t>(g.item_count,
+                                               std::max<uint32_t>(g.item_count / 16, 4096));
     float best = 1e30f;
-    uint32_t best_t = b->threads, best_w = b->wg_per_cu;
-    for (const auto &c : cand) {
-        const uint32_t slots = slots_for(b, c[0], c[1]);
-        if ((rc = size_scratch(b, slots))) break;
-        fc::CoopArgs a = b->args;
+    uint32_t best_t = g.threads, best_w = g.wg_per_cu;
+    hipError_t he = hipMemcpy(tmp_tab.ptr, tab.data(), sizeof(fc::CoopJob) * tab.size(),
+                              hipMemcpyHostToDevice);
+    if (he != hipSuccess) rc = hip_fail(ctx, he, "write tuning table");
+    for (size_t c = 0; rc == FC_OK && c < cand.size(); ++c) {
+        const uint32_t slots = slots_for(ctx, g, cand[c][0], cand[c][1]);
+        if ((rc = size_scratch(ctx, g, slots))) break;
+        fc::CoopArgs a = g.args;
         a.jobs = static_cast<const fc::CoopJob *>(tmp_tab.ptr);
         a.item_count = prefix;
-        FC_HIP(ctx, hipEventRecord(b->ev0, b->stream), "event");
-        FC_HIP(ctx, enqueue_run(b, a, c[0], b->stream), "tuning launch");
-        FC_HIP(ctx, hipEventRecord(b->ev1, b->stream), "event");
-        FC_HIP(ctx, hipStreamSynchronize(b->stream), "tuning run");
+        if ((he = hipEventRecord(b->ev0, b->stream)) != hipSuccess ||
+            (he = enqueue_group(g, a, cand[c][0], b->stream)) != hipSuccess ||
+            (he = hipEventRecord(b->ev1, b->stream)) != hipSuccess ||
+            (he = hipStreamSynchronize(b->stream)) != hipSuccess) {
+            rc = hip_fail(ctx, he, "tuning run");
+            break;
+        }
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
         Small sm;
-        FC_HIP(ctx, hipMemcpy(&sm, b->small.ptr, sizeof(sm), hipMemcpyDeviceToHost), "read counters");
+        if ((he = hipMemcpy(&sm, g.small.ptr, sizeof(sm), hipMemcpyDeviceToHost)) != hipSuccess) {
+            rc = hip_fail(ctx, he, "read counters");
+            break;
+        }
         if (sm.totals.error) {
             rc = set_err(ctx, FC_ERR_HIP, "autotuning run reported a kernel error");
             break;
         }
         if (ms < best) {
             best = ms;
-            best_t = c[0];
-            best_w = c[1];
+            best_t = cand[c][0];
+            best_w = cand[c][1];
         }
     }
     if (tmp_tab.ptr) (void)hipFree(tmp_tab.ptr);
     if (rc) return rc;
-    b->threads = best_t;
-    b->wg_per_cu = best_w;
+    g.threads = best_t;
+    g.wg_per_cu = best_w;
     return FC_OK;
 }
 
@@ -209,19 +233,20 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     b->jobs.assign(jobs, jobs + n_jobs);
     b->seed = seed;
     b->flags = flags;
-    b->n_max = n_max;
     b->item_count = static_cast<uint32_t>(items);
-    b->threads = ctx->coop_threads;
-    b->wg_per_cu = ctx->coop_wg_per_cu;
     auto fail = [&](int code) {
         free_batch(b);
         return code;
     };
+#define FB_HIP(expr, what)                                          \
+    do {                                                            \
+        hipError_t e_ = (expr);                                     \
+        if (e_ != hipSuccess) return fail(hip_fail(ctx, e_, what)); \
+    } while (0)
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&b->ev_in) != hipSuccess || hipEventCreate(&b->ev0) != hipSuccess ||
         hipEventCreate(&b->ev1) != hipSuccess)
         return fail(set_err(ctx, FC_ERR_HIP, "creating the batch stream and events failed"));
-    if ((rc = ensure(ctx, b->small, sizeof(Small), "batch counters"))) return fail(rc);
     if (items == 0) {
         *out = b;
         return FC_OK;
@@ -245,6 +270,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return b->jobs[x].graph.n > b->jobs[y].graph.n;
     });
+    std::vector<size_t> pos(n_jobs, 0);  // job index -> place in `order`
+    for (size_t k = 0; k < order.size(); ++k) pos[order[k]] = k;
 
     // vertex records of every job's G* and each graph's maximum degree
     std::vector<size_t> voff(order.size());
@@ -255,14 +282,15 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     }
     if ((rc = ensure(ctx, b->vrec, sizeof(fc::VRec) * vtotal, "batch vertex records"))) return fail(rc);
     if ((rc = ensure(ctx, b->dmax, 4 * order.size(), "batch degrees"))) return fail(rc);
-    FC_HIP(ctx, hipMemsetAsync(b->dmax.ptr, 0, 4 * order.size(), b->stream), "memset degrees");
+    FB_HIP(hipMemsetAsync(b->dmax.ptr, 0, 4 * order.size(), b->stream), "memset degrees");
     fc::VRec *vrec = static_cast<fc::VRec *>(b->vrec.ptr);
     unsigned int *dmax_d = static_cast<unsigned int *>(b->dmax.ptr);
     for (size_t k = 0; k < order.size(); ++k) {
         const fc_job &j = b->jobs[order[k]];
-        FC_HIP(ctx, fc::launch_build_vrec(j.graph.row_ptr, j.graph.n, j.alpha, vrec + voff[k],
-                                          dmax_d + k, b->stream), "build_vrec");
+        FB_HIP(fc::launch_build_vrec(j.graph.row_ptr, j.graph.n, j.alpha, vrec + voff[k], dmax_d + k,
+                                     b->stream), "build_vrec");
     }
+
     // degree classes of each distinct graph, for the LDS-counter kernel
     struct GInfo {
         const int32_t *rp, *ci;
@@ -300,25 +328,28 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         uint32_t *base = static_cast<uint32_t *>(b->rl_base.ptr);
         uint32_t *bnd = static_cast<uint32_t *>(b->rl_bounds.ptr);
         for (size_t f = 0; f < gs.size(); ++f)
-            FC_HIP(ctx, fc::launch_class_bounds(gs[f].rp, gs[f].n, blk + 4 * gs[f].off_b,
-                                                base + 4 * gs[f].off_b, bnd + 4 * f, b->stream),
+            FB_HIP(fc::launch_class_bounds(gs[f].rp, gs[f].n, blk + 4 * gs[f].off_b,
+                                           base + 4 * gs[f].off_b, bnd + 4 * f, b->stream),
                    "class bounds");
-        FC_HIP(ctx, hipMemcpyAsync(bounds.data(), bnd, 16 * gs.size(), hipMemcpyDeviceToHost,
-                                   b->stream), "copy class bounds");
+        FB_HIP(hipMemcpyAsync(bounds.data(), bnd, 16 * gs.size(), hipMemcpyDeviceToHost, b->stream),
+               "copy class bounds");
     }
     std::vector<unsigned int> dmax(order.size());
-    FC_HIP(ctx, hipMemcpyAsync(dmax.data(), dmax_d, 4 * order.size(), hipMemcpyDeviceToHost, b->stream),
+    FB_HIP(hipMemcpyAsync(dmax.data(), dmax_d, 4 * order.size(), hipMemcpyDeviceToHost, b->stream),
            "copy degrees");
-    FC_HIP(ctx, hipStreamSynchronize(b->stream), "batch preparation");
+    FB_HIP(hipStreamSynchronize(b->stream), "batch preparation");
+    std::vector<uint32_t> gwords(gs.size(), 0);
+    bool use_lds = false;
     if (try_lds) {
         uint32_t words = 0;
-        for (size_t f = 0; f < gs.size(); ++f)
-            words = std::max(words, fc::count_layout(gs[f].n, bounds[4 * f], bounds[4 * f + 1],
-                                                     bounds[4 * f + 2]).words);
-        b->use_lds = 4u * static_cast<size_t>(words) + kLdsStaticBytes <= ctx->max_lds;
-        b->lds_words = words;
+        for (size_t f = 0; f < gs.size(); ++f) {
+            gwords[f] =
+                fc::count_layout(gs[f].n, bounds[4 * f], bounds[4 * f + 1], bounds[4 * f + 2]).words;
+            words = std::max(words, gwords[f]);
+        }
+        use_lds = 4u * static_cast<size_t>(words) + kLdsStaticBytes <= ctx->max_lds;
     }
-    if (b->use_lds) {
+    if (use_lds) {
         if ((rc = ensure(ctx, b->rl_inv, 4 * tn, "relabel inverse")) ||
             (rc = ensure(ctx, b->rl_orig, 4 * tn, "relabel ids")) ||
             (rc = ensure(ctx, b->rl_adj, 8 * te, "relabelled adjacency")) ||
@@ -329,100 +360,125 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         uint32_t *orig = static_cast<uint32_t *>(b->rl_orig.ptr);
         unsigned long long *adj = static_cast<unsigned long long *>(b->rl_adj.ptr);
         for (const GInfo &gi : gs)
-            FC_HIP(ctx, fc::launch_relabel_graph(gi.rp, gi.ci, gi.n, gi.nnz, base + 4 * gi.off_b,
-                                                 inv + gi.off_n, orig + gi.off_n, adj + gi.off_e,
-                                                 b->stream), "relabel");
+            FB_HIP(fc::launch_relabel_graph(gi.rp, gi.ci, gi.n, gi.nnz, base + 4 * gi.off_b,
+                                            inv + gi.off_n, orig + gi.off_n, adj + gi.off_e,
+                                            b->stream), "relabel");
         fc::VRec *vr = static_cast<fc::VRec *>(b->rl_vrec.ptr);
         for (size_t k = 0; k < order.size(); ++k)
-            FC_HIP(ctx, fc::launch_relabel_vrec(vrec + voff[k], inv + gs[gof[k]].off_n,
-                                                static_cast<uint32_t>(b->jobs[order[k]].graph.n),
-                                                vr + voff[k], b->stream), "relabel records");
-        b->threads = lds_threads_for(ctx, b->item_count, b->lds_words);
-        b->wg_per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
+            FB_HIP(fc::launch_relabel_vrec(vrec + voff[k], inv + gs[gof[k]].off_n,
+                                           static_cast<uint32_t>(b->jobs[order[k]].graph.n),
+                                           vr + voff[k], b->stream), "relabel records");
     }
 
-    // one word width for the whole launch
-    b->word32 = ctx->coop_word32;
+    // launch groups: with LDS counters, jobs whose fields take at most a quarter
+    // of the LDS form the narrow group; everything else is one group
     for (size_t k = 0; k < order.size(); ++k) {
-        uint32_t ts;
-        bool w32;
-        word_layout(static_cast<uint32_t>(b->jobs[order[k]].graph.n), dmax[k], true, &ts, &w32);
-        b->word32 = b->word32 && w32;
+        const bool narrow = use_lds && 4u * static_cast<size_t>(gwords[gof[k]]) + kLdsStaticBytes <=
+                                           ctx->max_lds / 4;
+        b->grp[narrow ? 1 : 0].jobs.push_back(order[k]);
     }
-    b->lds_bits = ctx->coop_lds_bits && fc::coop_lds_bytes(n_max) + 1024u <= ctx->max_lds;
-    b->in_bits = b->lds_bits && ctx->coop_in_bits &&
-                 2 * fc::coop_lds_bytes(n_max) + 1024u <= ctx->max_lds;
+    if (b->grp[0].jobs.empty()) std::swap(b->grp[0].jobs, b->grp[1].jobs);
+    b->ngroups = b->grp[1].jobs.empty() ? 1 : 2;
 
-    // job table and item -> job map
-    std::vector<fc::CoopJob> tab(order.size());
-    std::vector<uint32_t> item_job(b->item_count);
-    uint32_t first = 0;
-    for (size_t k = 0; k < order.size(); ++k) {
-        const fc_job &j = b->jobs[order[k]];
-        fc::CoopJob &c = tab[k];
-        std::memset(&c, 0, sizeof(c));
-        c.vrec = vrec + voff[k];
-        c.col_idx = j.graph.col_idx;
-        c.n = static_cast<uint32_t>(j.graph.n);
-        if (b->use_lds) {
-            const GInfo &gi = gs[gof[k]];
-            c.vrec = static_cast<const fc::VRec *>(b->rl_vrec.ptr) + voff[k];
-            c.adj = static_cast<const unsigned long long *>(b->rl_adj.ptr) + gi.off_e;
-            c.orig = static_cast<const uint32_t *>(b->rl_orig.ptr) + gi.off_n;
-            c.n0 = bounds[4 * gof[k]];
-            c.n1 = bounds[4 * gof[k] + 1];
-            c.n2 = bounds[4 * gof[k] + 2];
+    for (int gi = 0; gi < b->ngroups; ++gi) {
+        Group &g = b->grp[gi];
+        if ((rc = ensure(ctx, g.small, sizeof(Small), "batch counters"))) return fail(rc);
+        g.use_lds = use_lds;
+        g.word32 = ctx->coop_word32;
+        for (int32_t j : g.jobs) {
+            const size_t k = pos[j];
+            g.n_max = std::max<uint32_t>(g.n_max, static_cast<uint32_t>(b->jobs[j].graph.n));
+            g.item_count += b->jobs[j].tree_count;
+            if (use_lds) g.lds_words = std::max(g.lds_words, gwords[gof[k]]);
+            uint32_t ts;
+            bool w32;
+            word_layout(static_cast<uint32_t>(b->jobs[j].graph.n), dmax[k], true, &ts, &w32);
+            g.word32 = g.word32 && w32;
         }
-        bool w32;
-        word_layout(c.n, dmax[k], b->word32, &c.tshift, &w32);
-        c.stream_id = j.stream_id;
-        c.tree_begin = j.tree_begin;
-        c.first_item = first;
-        const double cap = 256.0 * (static_cast<double>(j.graph.n) +
-                                    j.alpha * static_cast<double>(j.graph.nnz)) + 1048576.0;
-        c.step_cap = cap > 4.0e18 ? 4000000000000000000ull : static_cast<unsigned long long>(cap);
-        c.root_counts = j.root_counts;
-        c.tree_digests = reinterpret_cast<unsigned long long *>(j.tree_digests);
-        std::fill(item_job.begin() + first, item_job.begin() + first + j.tree_count,
-                  static_cast<uint32_t>(k));
-        first += j.tree_count;
+        g.lds_bits = !use_lds && ctx->coop_lds_bits &&
+                     fc::coop_lds_bytes(g.n_max) + 1024u <= ctx->max_lds;
+        g.in_bits = g.lds_bits && ctx->coop_in_bits &&
+                    2 * fc::coop_lds_bytes(g.n_max) + 1024u <= ctx->max_lds;
+
+        // job table and item -> job map
+        std::vector<fc::CoopJob> tab(g.jobs.size());
+        std::vector<uint32_t> item_job(g.item_count);
+        uint32_t first = 0;
+        for (size_t t = 0; t < g.jobs.size(); ++t) {
+            const fc_job &j = b->jobs[g.jobs[t]];
+            const size_t k = pos[g.jobs[t]];
+            fc::CoopJob &c = tab[t];
+            std::memset(&c, 0, sizeof(c));
+            c.vrec = vrec + voff[k];
+            c.col_idx = j.graph.col_idx;
+            c.n = static_cast<uint32_t>(j.graph.n);
+            if (use_lds) {
+                const GInfo &gf = gs[gof[k]];
+                c.vrec = static_cast<const fc::VRec *>(b->rl_vrec.ptr) + voff[k];
+                c.adj = static_cast<const unsigned long long *>(b->rl_adj.ptr) + gf.off_e;
+                c.orig = static_cast<const uint32_t *>(b->rl_orig.ptr) + gf.off_n;
+                c.n0 = bounds[4 * gof[k]];
+                c.n1 = bounds[4 * gof[k] + 1];
+                c.n2 = bounds[4 * gof[k] + 2];
+            }
+            bool w32;
+            word_layout(c.n, dmax[k], g.word32, &c.tshift, &w32);
+            c.stream_id = j.stream_id;
+            c.tree_begin = j.tree_begin;
+            c.first_item = first;
+            const double cap = 256.0 * (static_cast<double>(j.graph.n) +
+                                        j.alpha * static_cast<double>(j.graph.nnz)) + 1048576.0;
+            c.step_cap = cap > 4.0e18 ? 4000000000000000000ull : static_cast<unsigned long long>(cap);
+            c.root_counts = j.root_counts;
+            c.tree_digests = reinterpret_cast<unsigned long long *>(j.tree_digests);
+            std::fill(item_job.begin() + first, item_job.begin() + first + j.tree_count,
+                      static_cast<uint32_t>(t));
+            first += j.tree_count;
+        }
+        g.ntab = tab.size();
+        if ((rc = ensure(ctx, g.jobtab, sizeof(fc::CoopJob) * tab.size(), "job table"))) return fail(rc);
+        if ((rc = ensure(ctx, g.item_job, 4 * item_job.size(), "item map"))) return fail(rc);
+        FB_HIP(hipMemcpyAsync(g.jobtab.ptr, tab.data(), sizeof(fc::CoopJob) * tab.size(),
+                              hipMemcpyHostToDevice, b->stream), "copy job table");
+        FB_HIP(hipMemcpyAsync(g.item_job.ptr, item_job.data(), 4 * item_job.size(),
+                              hipMemcpyHostToDevice, b->stream), "copy item map");
+        FB_HIP(hipStreamSynchronize(b->stream), "batch tables");
+
+        fc::CoopArgs &a = g.args;
+        std::memset(&a, 0, sizeof(a));
+        a.n_max = g.n_max;
+        a.item_count = g.item_count;
+        a.key0 = static_cast<uint32_t>(seed);
+        a.key1 = static_cast<uint32_t>(seed >> 32);
+        a.max_rounds = 0x40000000u;
+        a.k_limit = ctx->max_draws ? ctx->max_draws : use_lds ? 0xFFFFFFFFu : 0x7FFFFFFFu;
+        Small *sm = static_cast<Small *>(g.small.ptr);
+        a.queue = &sm->queue;
+        a.totals = &sm->totals;
+        a.phase_ticks = nullptr;
+        a.jobs = static_cast<const fc::CoopJob *>(g.jobtab.ptr);
+        a.item_job = static_cast<const uint32_t *>(g.item_job.ptr);
+        if (use_lds) {
+            g.threads = lds_threads_for(ctx, g.item_count, g.lds_words);
+            g.wg_per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
+        } else {
+            g.threads = ctx->coop_threads;
+            g.wg_per_cu = ctx->coop_wg_per_cu;
+        }
+        if ((flags & FC_FLAG_AUTOTUNE) && (rc = autotune(b, g))) return fail(rc);
+        if ((rc = size_scratch(ctx, g, slots_for(ctx, g, g.threads, g.wg_per_cu)))) return fail(rc);
     }
-    b->ntab = tab.size();
-    if ((rc = ensure(ctx, b->jobtab, sizeof(fc::CoopJob) * tab.size(), "job table"))) return fail(rc);
-    if ((rc = ensure(ctx, b->item_job, 4 * item_job.size(), "item map"))) return fail(rc);
-    FC_HIP(ctx, hipMemcpyAsync(b->jobtab.ptr, tab.data(), sizeof(fc::CoopJob) * tab.size(),
-                               hipMemcpyHostToDevice, b->stream), "copy job table");
-    FC_HIP(ctx, hipMemcpyAsync(b->item_job.ptr, item_job.data(), 4 * item_job.size(),
-                               hipMemcpyHostToDevice, b->stream), "copy item map");
-    FC_HIP(ctx, hipStreamSynchronize(b->stream), "batch tables");
 
-    fc::CoopArgs &a = b->args;
-    std::memset(&a, 0, sizeof(a));
-    a.n_max = n_max;
-    a.item_count = b->item_count;
-    a.key0 = static_cast<uint32_t>(seed);
-    a.key1 = static_cast<uint32_t>(seed >> 32);
-    a.max_rounds = 0x40000000u;
-    a.k_limit = ctx->max_draws ? ctx->max_draws : b->use_lds ? 0xFFFFFFFFu : 0x7FFFFFFFu;
-    Small *sm = static_cast<Small *>(b->small.ptr);
-    a.queue = &sm->queue;
-    a.totals = &sm->totals;
-    a.phase_ticks = nullptr;
-    a.jobs = static_cast<const fc::CoopJob *>(b->jobtab.ptr);
-    a.item_job = static_cast<const uint32_t *>(b->item_job.ptr);
-    if (b->use_lds) FC_HIP(ctx, fc::lds_set_limit(b->lds_words), "LDS limit");
-    else FC_HIP(ctx, fc::coop_set_lds_limit(b->lds_bits, b->in_bits, b->word32, n_max), "coop LDS limit");
-
-    if ((flags & FC_FLAG_AUTOTUNE) && (rc = autotune(b))) return fail(rc);
-    if ((rc = size_scratch(b, slots_for(b, b->threads, b->wg_per_cu)))) return fail(rc);
-
-    // capture the run: counter reset, epoch reset, sampling kernel
-    FC_HIP(ctx, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t ce = enqueue_run(b, b->args, b->threads, b->stream);
+    // capture the run: per group, counter resets and the sampling kernel
+    FB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t ce = hipSuccess;
+    for (int gi = 0; gi < b->ngroups && ce == hipSuccess; ++gi)
+        ce = enqueue_group(b->grp[gi], b->grp[gi].args, b->grp[gi].threads, b->stream);
     hipError_t ee = hipStreamEndCapture(b->stream, &b->graph);
     if (ce != hipSuccess) return fail(hip_fail(ctx, ce, "capturing the batch launch"));
     if (ee != hipSuccess) return fail(hip_fail(ctx, ee, "end capture"));
-    FC_HIP(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate graph");
+    FB_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate graph");
+#undef FB_HIP
     *out = b;
     return FC_OK;
 }
@@ -436,8 +492,13 @@ int fc_batch_run(fc_batch *b, fc_stats *stats) {
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->tau = b->item_count;
-        std::snprintf(stats->sampler, sizeof(stats->sampler), "%s:%ux%u",
-                      b->use_lds ? "lbatch" : "batch", b->threads, b->wg_per_cu);
+        const Group &g = b->grp[0];
+        if (b->ngroups == 2)
+            std::snprintf(stats->sampler, sizeof(stats->sampler), "%s:%u+%u",
+                          g.use_lds ? "lbatch" : "batch", g.threads, b->grp[1].threads);
+        else
+            std::snprintf(stats->sampler, sizeof(stats->sampler), "%s:%ux%u",
+                          g.use_lds ? "lbatch" : "batch", g.threads, g.wg_per_cu);
     }
     if (b->item_count == 0) return FC_OK;
     // order after the caller's earlier work on the context stream, and make the
@@ -447,24 +508,33 @@ int fc_batch_run(fc_batch *b, fc_stats *stats) {
     FC_HIP(ctx, hipEventRecord(b->ev0, b->stream), "event");
     FC_HIP(ctx, hipGraphLaunch(b->exec, b->stream), "graph launch");
     FC_HIP(ctx, hipEventRecord(b->ev1, b->stream), "event");
-    Small sm;
-    FC_HIP(ctx, hipMemcpyAsync(&sm, b->small.ptr, sizeof(sm), hipMemcpyDeviceToHost, b->stream),
-           "copy counters");
+    Small sm[2];
+    for (int gi = 0; gi < b->ngroups; ++gi)
+        FC_HIP(ctx, hipMemcpyAsync(&sm[gi], b->grp[gi].small.ptr, sizeof(Small),
+                                   hipMemcpyDeviceToHost, b->stream), "copy counters");
     FC_HIP(ctx, hipStreamSynchronize(b->stream), "batch run");
     FC_HIP(ctx, hipStreamWaitEvent(ctx->stream, b->ev1, 0), "wait");
-    if (sm.totals.error & fc::kErrStepCap)
+    unsigned int error = 0;
+    unsigned long long steps = 0, roots = 0, digests = 0;
+    for (int gi = 0; gi < b->ngroups; ++gi) {
+        error |= sm[gi].totals.error;
+        steps += sm[gi].totals.walk_steps;
+        roots += sm[gi].totals.roots;
+        digests += sm[gi].totals.digest_sum;
+    }
+    if (error & fc::kErrStepCap)
         return set_err(ctx, FC_ERR_HIP, "a tree exceeded the step bound (internal fault)");
-    if (sm.totals.error & fc::kErrVisitOverflow)
+    if (error & fc::kErrVisitOverflow)
         return set_err(ctx, FC_ERR_OVERFLOW,
-                       b->use_lds ? "a per-vertex draw count exceeded 2^28 - 1 (LDS counters)"
-                                  : "a per-vertex visit counter exceeded 2^31 - 1");
+                       b->grp[0].use_lds ? "a per-vertex draw count exceeded 2^28 - 1 (LDS counters)"
+                                         : "a per-vertex visit counter exceeded 2^31 - 1");
     if (stats) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
-        stats->trees_in_flight = b->slots;
-        stats->walk_steps = sm.totals.walk_steps;
-        stats->roots = sm.totals.roots;
-        stats->digest_sum = sm.totals.digest_sum;
+        stats->trees_in_flight = b->grp[0].slots + (b->ngroups == 2 ? b->grp[1].slots : 0u);
+        stats->walk_steps = steps;
+        stats->roots = roots;
+        stats->digest_sum = digests;
         stats->ms_sample = ms;
         stats->ms_total = now_ms() - t0;
     }

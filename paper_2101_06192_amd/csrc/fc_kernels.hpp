@@ -101,9 +101,9 @@ struct CoopArgs {
 // vertices with in-arrows.
 hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
                               bool word32, hipStream_t stream);
-// Raise the kernel's dynamic-LDS limit for the bitmaps of n_max bits (call
-// before launching, outside stream capture).
-hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
+// Allow up to `bytes` of dynamic LDS per workgroup for every variant (set once
+// per device to the device limit; launches pass what they need).
+hipError_t coop_set_lds_limit(size_t bytes);
 // Workgroups of the chosen variant that fit on one CU at once (0 if unknown).
 int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
@@ -114,7 +114,7 @@ size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 // live in LDS.
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
                              hipStream_t stream);
-hipError_t lds_set_limit(uint32_t lds_words);
+hipError_t lds_set_limit(size_t bytes);  // as coop_set_lds_limit, for the LDS-counter kernel
 int lds_max_active(uint32_t threads, uint32_t lds_words);
 
 // LDS word offsets of one tree's counter classes and settled bitmap.

@@ -526,12 +526,17 @@ int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, 
     return blocks;
 }
 
-hipError_t coop_set_lds_limit(bool lds_bits, bool in_bits, bool word32, uint32_t n_max) {
-    if (!lds_bits) return hipSuccess;
-    const int lds = static_cast<int>((in_bits ? 2 : 1) * coop_lds_bytes(n_max));
-    const void *f = word32 ? kernel_of<uint32_t>(true, in_bits)
-                           : kernel_of<unsigned long long>(true, in_bits);
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+hipError_t coop_set_lds_limit(size_t bytes) {
+    const int lim = static_cast<int>(bytes);
+    const void *fs[] = {kernel_of<uint32_t>(false, false), kernel_of<uint32_t>(true, false),
+                        kernel_of<uint32_t>(true, true), kernel_of<unsigned long long>(false, false),
+                        kernel_of<unsigned long long>(true, false),
+                        kernel_of<unsigned long long>(true, true)};
+    for (const void *f : fs) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,

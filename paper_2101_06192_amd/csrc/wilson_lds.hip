@@ -508,10 +508,9 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 
 }  // namespace
 
-hipError_t lds_set_limit(uint32_t lds_words) {
+hipError_t lds_set_limit(size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_lds_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               static_cast<int>(4u * lds_words));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
 int lds_max_active(uint32_t threads, uint32_t lds_words) {

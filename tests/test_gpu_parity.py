@@ -243,6 +243,24 @@ def test_lds_launch_shapes_bit_exact(gpu_lib, threads, wg):
         fc.set_option("lds_wg_per_cu", 0)
 
 
+def test_lds_counter_classes_and_size_limit(gpu_lib):
+    """A star whose centre has degree 70000 needs a 32-bit field (the widest
+    class); BA(250000, 3) needs 161.8 KB of fields and bitmap, just inside
+    gfx950's 160 KiB of LDS; BA(262000, 3) is beyond it and runs on global
+    counters.  All three match the oracle tree for tree."""
+    fc = gpu_lib
+    star = inputs.from_edge_list(70001, [(0, i) for i in range(1, 70001)], "star70000")
+    got, _ = _compare(fc, star, 0.5, 21, 0, 12, per_tree=True, sampler="lds")
+    near = inputs.barabasi_albert(250_000, 3, 1)
+    got = fc.sample(near, alpha=1.0, seed=2, tree_begin=0, tree_count=8, want_digests=True)
+    assert got["stats"]["sampler"] == "wilson_lds"
+    assert np.array_equal(got["tree_digests"], oracle.sample(near, 1.0, 2, 0, 8).digests)
+    over = inputs.barabasi_albert(262_000, 3, 1)
+    got = fc.sample(over, alpha=1.0, seed=2, tree_begin=0, tree_count=8, want_digests=True)
+    assert got["stats"]["sampler"] == "wilson_coop"
+    assert np.array_equal(got["tree_digests"], oracle.sample(over, 1.0, 2, 0, 8).digests)
+
+
 def test_auto_choice_prefers_lds_counters(gpu_lib):
     """Without a sampler flag a tree that fits uses LDS counters; the option
     turns that off."""
@@ -336,6 +354,9 @@ def _batch_graphs():
     sizes = inputs.rmat_batch_sizes(6, 5, lo_exp=7.0, hi_exp=12.0)
     gs = [inputs.rmat(nn, 8, 100 + i) for i, nn in enumerate(sizes)]
     gs.append(inputs.barabasi_albert(5000, 3, 2))
+    # 80000 vertices need more than a quarter of the LDS for their counters:
+    # with LDS counters the batch runs as two launch groups
+    gs.append(inputs.barabasi_albert(80_000, 3, 4))
     gs.append(inputs.grid_removed(40, 50, 0.12, 1))
     gs.append(inputs.from_edge_list(3, [(0, 1)], "edge_plus_isolated"))
     return gs
@@ -367,6 +388,8 @@ def test_batch_matches_oracle_and_single_runs(gpu_lib, counters):
     st = b.run()
     _say(f"batch run: {st['sampler']} ms={st['ms_sample']:.2f} trees={st['tau']}")
     assert st["sampler"].split(":")[0] == counters
+    if counters == "lbatch":
+        assert "+" in st["sampler"]  # two launch groups
     total_steps = 0
     for i, j in enumerate(jobs[:-2]):
         g = gs[i // len(alphas)]
@@ -389,7 +412,8 @@ def test_batch_graph_replays_and_autotune(gpu_lib, counters):
     between them, each equal to the eager single-job result."""
     import torch
     fc = gpu_lib
-    gs = _batch_graphs()[:4]
+    all_gs = _batch_graphs()
+    gs = all_gs[:4] + [all_gs[7]]  # small R-MAT graphs and BA(80000, 3): two launch groups
     dgs = [fc.to_device(g) for g in gs]
     jobs = [{"graph": dg, "alpha": 1.0, "stream_id": i, "tree_count": 33, "digests": True}
             for i, dg in enumerate(dgs)]
