@@ -166,7 +166,10 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     if ((rc = ensure(ctx, ctx->vrec, sizeof(fc::VRec) * static_cast<size_t>(g.n), "vertex records")))
         return rc;
     fc::VRec *vrec = static_cast<fc::VRec *>(ctx->vrec.ptr);
-    FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, g.n, p->alpha, vrec, &sm->dmax, ctx->stream),
+    if ((rc = ensure(ctx, ctx->iso, 4u * ((static_cast<size_t>(g.n) + 31u) / 32u), "isolated bitmap")))
+        return rc;
+    FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, g.n, p->alpha, vrec, &sm->dmax,
+                                      static_cast<uint32_t *>(ctx->iso.ptr), ctx->stream),
            "build_vrec");
 
     // which sampler: the lane sampler needs many trees to fill the GPU; the
@@ -197,13 +200,13 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     if (use_coop) {
         // LDS-counter variant when the degree-class count fields and the settled
         // bitmap of one tree fit in LDS (at least 4 + 1 bits per vertex)
+        // (isolated vertices need no LDS, so only the id width bounds n here)
         const bool try_lds = (mode == 3 || (mode == 0 && ctx->coop_lds_counts)) &&
-                             g.n < (1 << fc::kRelabelIdBits) &&
-                             static_cast<size_t>(g.n) * 5u <= 8u * ctx->max_lds;
+                             g.n < (1 << fc::kRelabelIdBits);
         const uint32_t nb = fc::relabel_blocks(static_cast<uint32_t>(g.n));
         if (try_lds) {
-            if ((rc = ensure(ctx, ctx->rl_blk, 16u * nb, "class counts")) ||
-                (rc = ensure(ctx, ctx->rl_base, 16u * nb, "class offsets")))
+            if ((rc = ensure(ctx, ctx->rl_blk, 4u * fc::kRelabelClasses * nb, "class counts")) ||
+                (rc = ensure(ctx, ctx->rl_base, 4u * fc::kRelabelClasses * nb, "class offsets")))
                 return rc;
             FC_HIP(ctx, fc::launch_class_bounds(g.row_ptr, static_cast<uint32_t>(g.n),
                                                 static_cast<uint32_t *>(ctx->rl_blk.ptr),
@@ -221,7 +224,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                                        ctx->stream), "copy class bounds");
         FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "build_vrec");
         if (try_lds) {
-            const fc::CountLayout L = fc::count_layout(static_cast<uint32_t>(g.n), cb[0], cb[1], cb[2]);
+            const fc::CountLayout L = fc::count_layout(cb[3], cb[0], cb[1], cb[2]);
             if (4u * static_cast<size_t>(L.words) + kLdsStaticBytes <= ctx->max_lds) {
                 use_lds = true;
                 lds_words = L.words;
@@ -288,6 +291,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             j.n0 = cb[0];
             j.n1 = cb[1];
             j.n2 = cb[2];
+            j.n3 = cb[3];
+            j.tree_count = tree_count;
             j.tshift = 32;
             j.stream_id = p->stream_id;
             j.tree_begin = tree_begin;
@@ -356,6 +361,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         fc::CoopJob &j = c.single;
         j.vrec = vrec;
         j.col_idx = g.col_idx;
+        j.iso = static_cast<const uint32_t *>(ctx->iso.ptr);
+        j.tree_count = tree_count;
         j.n = static_cast<uint32_t>(g.n);
         j.tshift = tshift;
         j.stream_id = p->stream_id;
@@ -558,7 +565,8 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->rtmp, &ctx->thr, &ctx->cword, &ctx->ckk, &ctx->clists, &ctx->clevels,
                       &ctx->cbits, &ctx->s_r64, &ctx->s_r, &ctx->s_z, &ctx->s_p, &ctx->s_q,
                       &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small, &ctx->rl_blk,
-                      &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj})
+                      &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
+                      &ctx->iso})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

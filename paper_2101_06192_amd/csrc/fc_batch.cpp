@@ -45,7 +45,7 @@ struct fc_batch {
     std::vector<fc_job> jobs;
     uint64_t seed = 0;
     int32_t flags = 0;
-    DevBuf vrec, dmax;
+    DevBuf vrec, dmax, iso;
     DevBuf rl_blk, rl_base, rl_bounds, rl_inv, rl_orig, rl_adj, rl_vrec;  // degree-class relabelling
     Group grp[2];
     int ngroups = 0;
@@ -63,7 +63,7 @@ int free_batch(fc_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (DevBuf *d : {&b->vrec, &b->dmax, &b->rl_blk, &b->rl_base, &b->rl_bounds, &b->rl_inv,
+    for (DevBuf *d : {&b->vrec, &b->dmax, &b->iso, &b->rl_blk, &b->rl_base, &b->rl_bounds, &b->rl_inv,
                       &b->rl_orig, &b->rl_adj, &b->rl_vrec})
         if (d->ptr) (void)hipFree(d->ptr);
     for (Group &g : b->grp)
@@ -274,13 +274,17 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     for (size_t k = 0; k < order.size(); ++k) pos[order[k]] = k;
 
     // vertex records of every job's G* and each graph's maximum degree
-    std::vector<size_t> voff(order.size());
-    size_t vtotal = 0;
+    std::vector<size_t> voff(order.size()), ioff(order.size());
+    size_t vtotal = 0, itotal = 0;
     for (size_t k = 0; k < order.size(); ++k) {
         voff[k] = vtotal;
+        ioff[k] = itotal;
         vtotal += static_cast<size_t>(b->jobs[order[k]].graph.n);
+        itotal += (static_cast<size_t>(b->jobs[order[k]].graph.n) + 31) / 32;
     }
     if ((rc = ensure(ctx, b->vrec, sizeof(fc::VRec) * vtotal, "batch vertex records"))) return fail(rc);
+    if ((rc = ensure(ctx, b->iso, 4 * itotal, "batch isolated bitmaps"))) return fail(rc);
+    uint32_t *iso = static_cast<uint32_t *>(b->iso.ptr);
     if ((rc = ensure(ctx, b->dmax, 4 * order.size(), "batch degrees"))) return fail(rc);
     FB_HIP(hipMemsetAsync(b->dmax.ptr, 0, 4 * order.size(), b->stream), "memset degrees");
     fc::VRec *vrec = static_cast<fc::VRec *>(b->vrec.ptr);
@@ -288,7 +292,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     for (size_t k = 0; k < order.size(); ++k) {
         const fc_job &j = b->jobs[order[k]];
         FB_HIP(fc::launch_build_vrec(j.graph.row_ptr, j.graph.n, j.alpha, vrec + voff[k], dmax_d + k,
-                                     b->stream), "build_vrec");
+                                     iso + ioff[k], b->stream), "build_vrec");
     }
 
     // degree classes of each distinct graph, for the LDS-counter kernel
@@ -316,20 +320,20 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         gof[k] = static_cast<uint32_t>(f);
     }
     const bool try_lds = ctx->coop_lds_counts && !order.empty() &&
-                         n_max < (1u << fc::kRelabelIdBits) &&
-                         static_cast<size_t>(n_max) * 5u <= 8u * ctx->max_lds;
+                         n_max < (1u << fc::kRelabelIdBits);
     std::vector<unsigned int> bounds(4 * gs.size(), 0u);
     if (try_lds) {
-        if ((rc = ensure(ctx, b->rl_blk, 16 * tb, "class counts")) ||
-            (rc = ensure(ctx, b->rl_base, 16 * tb, "class offsets")) ||
+        if ((rc = ensure(ctx, b->rl_blk, 4 * fc::kRelabelClasses * tb, "class counts")) ||
+            (rc = ensure(ctx, b->rl_base, 4 * fc::kRelabelClasses * tb, "class offsets")) ||
             (rc = ensure(ctx, b->rl_bounds, 16 * gs.size(), "class bounds")))
             return fail(rc);
         uint32_t *blk = static_cast<uint32_t *>(b->rl_blk.ptr);
         uint32_t *base = static_cast<uint32_t *>(b->rl_base.ptr);
         uint32_t *bnd = static_cast<uint32_t *>(b->rl_bounds.ptr);
         for (size_t f = 0; f < gs.size(); ++f)
-            FB_HIP(fc::launch_class_bounds(gs[f].rp, gs[f].n, blk + 4 * gs[f].off_b,
-                                           base + 4 * gs[f].off_b, bnd + 4 * f, b->stream),
+            FB_HIP(fc::launch_class_bounds(gs[f].rp, gs[f].n, blk + fc::kRelabelClasses * gs[f].off_b,
+                                           base + fc::kRelabelClasses * gs[f].off_b, bnd + 4 * f,
+                                           b->stream),
                    "class bounds");
         FB_HIP(hipMemcpyAsync(bounds.data(), bnd, 16 * gs.size(), hipMemcpyDeviceToHost, b->stream),
                "copy class bounds");
@@ -343,8 +347,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     if (try_lds) {
         uint32_t words = 0;
         for (size_t f = 0; f < gs.size(); ++f) {
-            gwords[f] =
-                fc::count_layout(gs[f].n, bounds[4 * f], bounds[4 * f + 1], bounds[4 * f + 2]).words;
+            gwords[f] = fc::count_layout(bounds[4 * f + 3], bounds[4 * f], bounds[4 * f + 1],
+                                         bounds[4 * f + 2]).words;
             words = std::max(words, gwords[f]);
         }
         use_lds = 4u * static_cast<size_t>(words) + kLdsStaticBytes <= ctx->max_lds;
@@ -360,7 +364,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         uint32_t *orig = static_cast<uint32_t *>(b->rl_orig.ptr);
         unsigned long long *adj = static_cast<unsigned long long *>(b->rl_adj.ptr);
         for (const GInfo &gi : gs)
-            FB_HIP(fc::launch_relabel_graph(gi.rp, gi.ci, gi.n, gi.nnz, base + 4 * gi.off_b,
+            FB_HIP(fc::launch_relabel_graph(gi.rp, gi.ci, gi.n, gi.nnz,
+                                            base + fc::kRelabelClasses * gi.off_b,
                                             inv + gi.off_n, orig + gi.off_n, adj + gi.off_e,
                                             b->stream), "relabel");
         fc::VRec *vr = static_cast<fc::VRec *>(b->rl_vrec.ptr);
@@ -412,6 +417,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
             c.vrec = vrec + voff[k];
             c.col_idx = j.graph.col_idx;
             c.n = static_cast<uint32_t>(j.graph.n);
+            c.tree_count = j.tree_count;
+            c.iso = use_lds ? nullptr : iso + ioff[k];
             if (use_lds) {
                 const GInfo &gf = gs[gof[k]];
                 c.vrec = static_cast<const fc::VRec *>(b->rl_vrec.ptr) + voff[k];
@@ -420,6 +427,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
                 c.n0 = bounds[4 * gof[k]];
                 c.n1 = bounds[4 * gof[k] + 1];
                 c.n2 = bounds[4 * gof[k] + 2];
+                c.n3 = bounds[4 * gof[k] + 3];
             }
             bool w32;
             word_layout(c.n, dmax[k], g.word32, &c.tshift, &w32);

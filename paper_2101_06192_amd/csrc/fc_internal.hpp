@@ -22,7 +22,7 @@ struct Small {  // device-side counters of one call
     unsigned int dmax;
     unsigned int pad;
     unsigned long long phase_ticks[8];
-    unsigned int class_bounds[4];  // n0, n1, n2 of the degree-class relabelling
+    unsigned int class_bounds[4];  // n0, n1, n2, n3 of the degree-class relabelling
 };
 
 struct fc_ctx {
@@ -32,6 +32,7 @@ struct fc_ctx {
     DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists, clevels, cbits;
     DevBuf s_r64, s_r, s_z, s_p, s_q, s_d, s_pa, s_pb, s_small;  // solver workspace
     DevBuf rl_blk, rl_base, rl_inv, rl_orig, rl_vrec, rl_adj;     // degree-class relabelling
+    DevBuf iso;                                                   // isolated-vertex bitmap
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler

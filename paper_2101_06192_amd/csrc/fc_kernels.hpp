@@ -18,9 +18,11 @@ hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
 hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
                                 int64_t nnz, unsigned int *err, hipStream_t stream);
 
-// Per-vertex records of G* for one alpha; atomically maxes the degree into *dmax.
+// Per-vertex records of G* for one alpha; atomically maxes the degree into *dmax
+// and, when iso is not null, writes the bitmap of isolated vertices
+// (ceil(n / 32) words).
 hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
-                             unsigned int *dmax, hipStream_t stream);
+                             unsigned int *dmax, uint32_t *iso, hipStream_t stream);
 
 // thr(d), d = 0..d_max, as the device computes it (uint64, 2^32 for "always").
 hipError_t launch_thresholds(double alpha, int32_t d_max, unsigned long long *out,
@@ -55,15 +57,18 @@ hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
 // one (graph, alpha, stream) with a range of trees and its own outputs.
 // The LDS-counter variant reads the degree-class relabelled graph instead:
 // vrec and adj on internal ids (vrec.always_root = original id | flag << 31),
-// orig maps internal ids back, and [0, n0), [n0, n1), [n1, n2), [n2, n) are
-// the internal ids of the 4-, 8-, 16- and 32-bit counter classes.
+// orig maps internal ids back, and [0, n0), [n0, n1), [n1, n2), [n2, n3) are
+// the internal ids of the 4-, 8-, 16- and 32-bit counter classes, [n3, n) the
+// isolated vertices.
 struct CoopJob {
     const VRec *vrec;
     const int32_t *col_idx;
     const unsigned long long *adj;  // LDS variant: internal | original << 18 per CSR entry
     const uint32_t *orig;           // LDS variant: original id of each internal id
     uint32_t n;
-    uint32_t n0, n1, n2;            // LDS variant: class boundaries
+    uint32_t n0, n1, n2, n3;        // LDS variant: class boundaries
+    uint32_t tree_count;            // trees of the job (isolated vertices' totals)
+    const uint32_t *iso;            // global-counter variant: bitmap of isolated vertices, or null
     uint32_t tshift;          // bits of the target field in a tree word
     uint32_t stream_id;
     uint32_t tree_begin;
@@ -137,8 +142,9 @@ __host__ __device__ inline CountLayout count_layout(uint32_t n, uint32_t n0, uin
 constexpr uint32_t kRelabelIdBits = 18;
 
 // Degree-class relabelling (blocks of 1024 vertices): per-block class counts
-// into blk (4 per block), first internal id per block and class into base,
-// and bounds[0..2] = n0, n1, n2.
+// into blk (kRelabelClasses per block), first internal id per block and class
+// into base, and bounds[0..3] = n0, n1, n2, n3.
+constexpr uint32_t kRelabelClasses = 5;
 uint32_t relabel_blocks(uint32_t n);
 hipError_t launch_class_bounds(const int32_t *row_ptr, uint32_t n, uint32_t *blk, uint32_t *base,
                                uint32_t *bounds, hipStream_t stream);

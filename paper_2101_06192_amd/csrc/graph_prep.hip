@@ -81,7 +81,8 @@ __device__ __forceinline__ unsigned long long root_threshold(double alpha, uint3
 }
 
 __global__ void build_vrec_kernel(const int32_t *__restrict__ row_ptr, int32_t n, double alpha,
-                                  VRec *__restrict__ vrec, unsigned int *dmax) {
+                                  VRec *__restrict__ vrec, unsigned int *dmax,
+                                  uint32_t *__restrict__ iso) {
     const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
     uint32_t d = 0;
     int32_t a = 0;
@@ -92,6 +93,13 @@ __global__ void build_vrec_kernel(const int32_t *__restrict__ row_ptr, int32_t n
     uint32_t m = d;  // maximum degree: wave reduction, one atomic per wave
     for (int off = 32; off > 0; off >>= 1) m = max(m, static_cast<uint32_t>(__shfl_down(m, off, 64)));
     if ((threadIdx.x & 63u) == 0 && m) atomicMax(dmax, m);
+    if (iso) {  // 64 vertices per wave: two bitmap words (blocks are whole waves)
+        const uint64_t bits = __ballot(v < n && d == 0);
+        const int32_t w0 = static_cast<int32_t>((blockIdx.x * blockDim.x + (threadIdx.x & ~63u)) >> 5);
+        const int32_t nw = (n + 31) >> 5;
+        if ((threadIdx.x & 63u) == 0 && w0 < nw) iso[w0] = static_cast<uint32_t>(bits);
+        if ((threadIdx.x & 63u) == 32 && w0 + 1 < nw) iso[w0 + 1] = static_cast<uint32_t>(bits >> 32);
+    }
     if (v >= n) return;
     const unsigned long long t = root_threshold(alpha, d);
     VRec r;
@@ -130,9 +138,9 @@ hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, 
 }
 
 hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
-                             unsigned int *dmax, hipStream_t stream) {
+                             unsigned int *dmax, uint32_t *iso, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    build_vrec_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, n, alpha, vrec, dmax);
+    build_vrec_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, n, alpha, vrec, dmax, iso);
     return hipGetLastError();
 }
 

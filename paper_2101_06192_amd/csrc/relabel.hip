@@ -3,10 +3,12 @@
 // That sampler keeps the in-arrow count of every vertex of a tree in LDS.  A
 // count never exceeds the vertex degree, so a vertex of degree d gets a field
 // of 4 << c bits, c = class(d): 4 bits up to degree 15, 8 up to 255, 16 up to
-// 65535, else 32.  Vertices are renumbered so that each class is a contiguous
-// range of internal ids (class 0 first; original order kept inside a class),
-// which makes a field's LDS word and shift plain arithmetic on the internal
-// id.  Randomness and every output stay on original ids: the relabelled
+// 65535, else 32.  Isolated vertices form a fifth class with no field: they
+// are never a target, and in every tree they are roots after one draw.
+// Vertices are renumbered so that each class is a contiguous range of
+// internal ids (class 0 first, isolated vertices last; original order kept
+// inside a class), which makes a field's LDS word and shift plain arithmetic
+// on the internal id.  Randomness and every output stay on original ids: the relabelled
 // vertex record carries the original id, and the relabelled adjacency holds
 // (internal, original) pairs of each neighbour at the same CSR positions
 // (internal id in the low kRelabelIdBits bits, original id above), so the
@@ -18,43 +20,47 @@ namespace fc {
 namespace {
 
 constexpr int kPlaceThreads = 1024;
+constexpr uint32_t kClasses = kRelabelClasses;  // four field widths, then isolated vertices
 
 __device__ __forceinline__ uint32_t deg_class(uint32_t d) {
-    return d <= 15u ? 0u : d <= 255u ? 1u : d <= 65535u ? 2u : 3u;
+    return d == 0u ? 4u : d <= 15u ? 0u : d <= 255u ? 1u : d <= 65535u ? 2u : 3u;
 }
 
 // Per block of kPlaceThreads vertices: how many fall in each class.
 __global__ __launch_bounds__(kPlaceThreads) void class_count_kernel(
     const int32_t *__restrict__ row_ptr, uint32_t n, uint32_t *__restrict__ blk) {
-    __shared__ uint32_t s[4];
-    if (threadIdx.x < 4) s[threadIdx.x] = 0;
+    __shared__ uint32_t s[kClasses];
+    if (threadIdx.x < kClasses) s[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t v = blockIdx.x * kPlaceThreads + threadIdx.x;
-    const uint32_t c = v < n ? deg_class(static_cast<uint32_t>(row_ptr[v + 1] - row_ptr[v])) : 4u;
-    for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t c =
+        v < n ? deg_class(static_cast<uint32_t>(row_ptr[v + 1] - row_ptr[v])) : kClasses;
+    for (uint32_t k = 0; k < kClasses; ++k) {
         const uint64_t m = __ballot(c == k);
         if ((threadIdx.x & 63u) == 0 && m) atomicAdd(&s[k], static_cast<uint32_t>(__popcll(m)));
     }
     __syncthreads();
-    if (threadIdx.x < 4) blk[blockIdx.x * 4u + threadIdx.x] = s[threadIdx.x];
+    if (threadIdx.x < kClasses) blk[blockIdx.x * kClasses + threadIdx.x] = s[threadIdx.x];
 }
 
-// One block of 4 threads, thread k serial over the blocks of class k:
-// base[b][k] = first internal id of class k in block b; bounds = n0, n1, n2.
+// One block of kClasses threads, thread k serial over the blocks of class k:
+// base[b][k] = first internal id of class k in block b; bounds = n0, n1, n2,
+// n3 (the end of each field class; n3 = number of vertices that are not
+// isolated).
 __global__ void class_scan_kernel(const uint32_t *__restrict__ blk, uint32_t nb,
                                   uint32_t *__restrict__ base, uint32_t *__restrict__ bounds) {
-    __shared__ uint32_t tot[4];
+    __shared__ uint32_t tot[kClasses];
     const uint32_t k = threadIdx.x;
     uint32_t s = 0;
-    for (uint32_t b = 0; b < nb; ++b) s += blk[b * 4u + k];
+    for (uint32_t b = 0; b < nb; ++b) s += blk[b * kClasses + k];
     tot[k] = s;
     __syncthreads();
     uint32_t start = 0;
     for (uint32_t j = 0; j < k; ++j) start += tot[j];
-    if (k < 3) bounds[k] = start + tot[k];
+    if (k + 1 < kClasses) bounds[k] = start + tot[k];
     for (uint32_t b = 0; b < nb; ++b) {
-        base[b * 4u + k] = start;
-        start += blk[b * 4u + k];
+        base[b * kClasses + k] = start;
+        start += blk[b * kClasses + k];
     }
 }
 
@@ -64,19 +70,20 @@ __global__ __launch_bounds__(kPlaceThreads) void class_place_kernel(
     const int32_t *__restrict__ row_ptr, uint32_t n, const uint32_t *__restrict__ base,
     uint32_t *__restrict__ inv, uint32_t *__restrict__ orig) {
     constexpr uint32_t kWaves = kPlaceThreads / 64;
-    __shared__ uint32_t s_wave[kWaves][4];
+    __shared__ uint32_t s_wave[kWaves][kClasses];
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t v = blockIdx.x * kPlaceThreads + threadIdx.x;
-    const uint32_t c = v < n ? deg_class(static_cast<uint32_t>(row_ptr[v + 1] - row_ptr[v])) : 4u;
+    const uint32_t c =
+        v < n ? deg_class(static_cast<uint32_t>(row_ptr[v + 1] - row_ptr[v])) : kClasses;
     uint64_t mine = 0;
-    for (uint32_t k = 0; k < 4; ++k) {
+    for (uint32_t k = 0; k < kClasses; ++k) {
         const uint64_t m = __ballot(c == k);
         if (c == k) mine = m;
         if (lane == 0) s_wave[wave][k] = static_cast<uint32_t>(__popcll(m));
     }
     __syncthreads();
     if (v >= n) return;
-    uint32_t id = base[blockIdx.x * 4u + c];
+    uint32_t id = base[blockIdx.x * kClasses + c];
     for (uint32_t w = 0; w < wave; ++w) id += s_wave[w][c];
     id += static_cast<uint32_t>(__popcll(mine & ((1ull << lane) - 1ull)));
     inv[v] = id;
@@ -113,7 +120,7 @@ hipError_t launch_class_bounds(const int32_t *row_ptr, uint32_t n, uint32_t *blk
     const uint32_t nb = relabel_blocks(n);
     if (nb == 0) return hipSuccess;
     class_count_kernel<<<nb, kPlaceThreads, 0, stream>>>(row_ptr, n, blk);
-    class_scan_kernel<<<1, 4, 0, stream>>>(blk, nb, base, bounds);
+    class_scan_kernel<<<1, kClasses, 0, stream>>>(blk, nb, base, bounds);
     return hipGetLastError();
 }
 

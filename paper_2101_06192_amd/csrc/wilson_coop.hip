@@ -94,6 +94,7 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgc
 __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32_t key1,
                                          uint32_t v, uint32_t k, uint32_t t) {
     const VRec r = load_vrec(j.vrec, v);
+    if (r.always_root) return j.n;  // the arrow is u* whatever the Philox words are
     const Philox4 x = philox4x32_10(v, k, t, j.stream_id, key0, key1);
     return arrow_target(r, x.x0, x.x1, j.col_idx, j.n);
 }
@@ -462,15 +463,24 @@ void wilson_coop_kernel(CoopArgs a) {
         for (uint32_t v = tid; v < n; v += T) {
             const uint32_t tg = target_of(word[v]);
             my_digest += mix64((static_cast<unsigned long long>(v) << 32) | tg);
+            // isolated vertices (bitmap from the vertex records) are roots in every
+            // tree: their root and draw counts for all the job's trees are added at
+            // once, by the workgroup that samples its first tree
+            const bool iso = job.iso && ((job.iso[v >> 5] >> (v & 31u)) & 1u);
             if (tg == n) {
                 ++my_roots;
-                atomicAdd(&job.root_counts[v], 1u);
+                if (!iso) atomicAdd(&job.root_counts[v], 1u);
+                else if (ti == 0) atomicAdd(&job.root_counts[v], job.tree_count);
             }
             if (job.parents) job.parents[static_cast<size_t>(ti) * n + v] = static_cast<int32_t>(tg);
             if (want_k) {
                 const uint64_t kv = kk[v];
                 const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
-                if (job.visit_counts) atomicAdd(&job.visit_counts[v], static_cast<unsigned long long>(k));
+                if (job.visit_counts) {
+                    if (!iso) atomicAdd(&job.visit_counts[v], static_cast<unsigned long long>(k));
+                    else if (ti == 0)
+                        atomicAdd(&job.visit_counts[v], static_cast<unsigned long long>(job.tree_count));
+                }
                 if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + v] = k;
             }
         }

@@ -35,6 +35,8 @@
 //   levels   u32 global  peel level boundaries
 //   LDS      count fields (4/8/16/32 bits by class), then the settled bitmap
 // so redrawing a cycle vertex touches no per-vertex array besides its word.
+// Isolated vertices (internal ids [n3, n)) take no part in the rounds: only
+// the output visits them.
 #include "fc_kernels.hpp"
 
 namespace fc {
@@ -173,13 +175,15 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         const CoopJob job = a.jobs ? a.jobs[uniform(a.item_job[item])] : a.single;
         const uint32_t ti = item - job.first_item;
         const uint32_t t = job.tree_begin + ti;
-        const uint32_t n = job.n;
-        const CountLayout L = count_layout(n, job.n0, job.n1, job.n2);
+        const uint32_t n = job.n;    // also the id of u*
+        const uint32_t nl = job.n3;  // vertices that are not isolated: ids [0, nl)
+        const CountLayout L = count_layout(nl, job.n0, job.n1, job.n2);
         const Classes C{job.n0, job.n1, job.n2, L.o1, L.o2, L.o3};
         uint32_t *__restrict__ bits = s_lds + L.ob;
 
+        // targets are u* or vertices in [0, nl): isolated vertices have no in-arrows
         auto is_settled = [&](uint32_t v) -> bool {
-            return v >= n || ((bits[v >> 5] >> (v & 31u)) & 1u);
+            return v >= nl || ((bits[v >> 5] >> (v & 31u)) & 1u);
         };
         auto set_settled = [&](uint32_t v) { atomicOr(&bits[v >> 5], 1u << (v & 31u)); };
         auto count_of = [&](uint32_t v) -> uint32_t {
@@ -208,23 +212,23 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         // round 0: the first arrow of every vertex, and the first in-arrow count
         // (arrows into vertices that turn out settled are counted too; those
         // counts are never read)
-        for (uint32_t base = wave_base; base < n; base += kRD * T) {
+        for (uint32_t base = wave_base; base < nl; base += kRD * T) {
             VRec r[kRD];
             uint64_t w[kRD];
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
-                if (v < n) r[q] = load_vrec(job.vrec, v);
+                if (v < nl) r[q] = load_vrec(job.vrec, v);
             }
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
-                w[q] = v < n ? draw(job, r[q], a.key0, a.key1, 0u, t) : pack(n, n, 0u);
+                w[q] = v < nl ? draw(job, r[q], a.key0, a.key1, 0u, t) : pack(n, n, 0u);
             }
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
-                if (v < n) {
+                if (v < nl) {
                     word[v] = w[q];
                     if (f_lo(w[q]) == n) set_settled(v);
                     else count_add(f_lo(w[q]));
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
                 wave_append(listA, &s_u, n, &s_over, pack(v, f_lo(w[q]), 1u),
-                            v < n && f_lo(w[q]) != n);
+                            v < nl && f_lo(w[q]) != n);
             }
         }
         __syncthreads();
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 
         unsigned long long my_digest = 0, my_roots = 0;
         const bool want_k = job.visit_counts || job.tree_visits;
-        for (uint32_t v = tid; v < n; v += T) {
+        for (uint32_t v = tid; v < nl; v += T) {
             const uint64_t w = word[v];
             const uint32_t ov = job.orig[v];
             const uint32_t otg = f_mid(w);
@@ -481,6 +485,21 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 if (job.visit_counts)
                     atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(k));
                 if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = k;
+            }
+        }
+        // isolated vertices: a root after one draw in every tree.  Their digest
+        // terms are added per tree; their root and draw counts for all the job's
+        // trees at once, by the workgroup that samples its first tree.
+        for (uint32_t v = nl + tid; v < n; v += T) {
+            const uint32_t ov = job.orig[v];
+            my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | n);
+            ++my_roots;
+            if (job.parents) job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(n);
+            if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = 1u;
+            if (ti == 0) {
+                atomicAdd(&job.root_counts[ov], job.tree_count);
+                if (job.visit_counts)
+                    atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(job.tree_count));
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
