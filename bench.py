@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--cpu-trees", type=int, default=640,
                     help="trees the CPU oracle samples for the baseline (0 = skip)")
     ap.add_argument("--no-eps", action="store_true", help="skip the time-to-eps=0.1 leg")
-    ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop", "lds"])
+    ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop", "lds", "hyb"])
     ap.add_argument("--config", default="ba200k",
                     choices=["ba200k", "er1000", "grid1000", "rmat_batch", "rmat22", "solve"],
                     help="workload; the default is the headline configuration")
@@ -255,7 +255,7 @@ def other_config(args, fc, inputs, dev):
             g, alpha, trees, name = inputs.rmat(1 << 22, 8, 0), 1.0, 1024, "rmat_n4194304_ef8_trees1024"
         dg = fc.to_device(g, dev)
         per = {}
-        samplers = ["lane", "coop", "lds"] if args.config == "er1000" else ["coop"]
+        samplers = ["lane", "coop", "lds"] if args.config == "er1000" else ["coop", "hyb"]
         for smp in samplers:
             dt, out = _timed(lambda: fc.farness(dg, alpha=alpha, tau=trees, device=dev, as_torch=True,
                                                 sampler=smp), args.steps, args.warmup)

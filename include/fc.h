@@ -85,10 +85,13 @@ extern "C" {
 #define FC_FLAG_SAMPLER_LDS 16  /* force the workgroup-per-tree sampler with every in-arrow
                                    counter in LDS; FC_ERR_UNSUPPORTED when one tree's
                                    counters and settled bitmap do not fit */
+#define FC_FLAG_SAMPLER_HYB 32  /* force the hybrid workgroup-per-tree sampler: counters and
+                                   settled bits of the highest-degree vertices in LDS, the
+                                   rest in global memory */
 /* No sampler flag: the library picks lane or workgroup from n and the tree
- * count, and for the workgroup sampler LDS counters whenever they fit (option
- * "coop_lds_counts").  All samplers produce identical results (same trees,
- * same counts). */
+ * count, and for the workgroup sampler LDS counters whenever they fit, else
+ * the hybrid (both behind option "coop_lds_counts").  All samplers produce
+ * identical results (same trees, same counts). */
 
 typedef struct fc_ctx fc_ctx;
 
@@ -129,7 +132,8 @@ typedef struct {
     double ms_sample;        /* device time of the sampling kernel */
     double ms_total;         /* host wall time of the call */
     char sampler[16];        /* "wilson_lane", "wilson_coop", "wilson_lds" (workgroup sampler,
-                                counters in LDS), or for a batch "batch:<threads>x<wg per CU>"
+                                counters in LDS), "wilson_hyb" (hybrid), or for a batch
+                                "batch:<threads>x<wg per CU>"
                                 ("lbatch:..." with counters in LDS) */
     double phase_ms[8];      /* workgroup sampler with option "phase_timing": average
                                 milliseconds per workgroup spent in
@@ -166,6 +170,8 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "lanes_per_wave"  active lanes per wave of the lane sampler (1..64)
  *   "max_slots"       cap on trees in flight (0 = memory bound only)
  *   "phase_timing"    1: the workgroup sampler reports per-phase times in fc_stats
+ *   "hyb_hot_cap"     cap on how many (highest-degree) vertices the hybrid sampler keeps in
+ *                     LDS (default 2^31 - 1: as many as fit; 0: none, all counters global)
  *   "max_draws"       cap on the arrows one vertex may draw in one tree, below each
  *                     sampler's own limit (0, the default: no extra cap); a call that
  *                     exceeds it returns FC_ERR_OVERFLOW (exercises that error path)

@@ -179,6 +179,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     if (p->flags & FC_FLAG_SAMPLER_LANE) mode = 1;
     else if (p->flags & FC_FLAG_SAMPLER_COOP) mode = 2;
     else if (p->flags & FC_FLAG_SAMPLER_LDS) mode = 3;
+    else if (p->flags & FC_FLAG_SAMPLER_HYB) mode = 4;
     else mode = ctx->force_sampler;
     const bool use_coop = mode == 0 ? tree_count < 16u * ctx->cu_count * 64u / 4u || g.n >= 65536
                                     : mode >= 2;
@@ -193,8 +194,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::LaneArgs a{};
     fc::CoopArgs c{};
     bool lds_bits = false, in_bits = false, word32 = false;
-    bool use_lds = false;
-    uint32_t lds_words = 0, lds_threads = 1024;
+    bool use_lds = false, use_hyb = false;
+    uint32_t lds_words = 0, lds_threads = 1024, hot = 0;
     uint32_t tshift = 32;
     unsigned int dmax = 0;
     if (use_coop) {
@@ -208,14 +209,12 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             if ((rc = ensure(ctx, ctx->rl_blk, 4u * fc::kRelabelClasses * nb, "class counts")) ||
                 (rc = ensure(ctx, ctx->rl_base, 4u * fc::kRelabelClasses * nb, "class offsets")))
                 return rc;
-            FC_HIP(ctx, fc::launch_class_bounds(g.row_ptr, static_cast<uint32_t>(g.n),
+            FC_HIP(ctx, fc::launch_class_bounds(g.row_ptr, static_cast<uint32_t>(g.n), false,
                                                 static_cast<uint32_t *>(ctx->rl_blk.ptr),
                                                 static_cast<uint32_t *>(ctx->rl_base.ptr),
                                                 sm->class_bounds, ctx->stream),
                    "class bounds");
         }
-        // 32-bit tree words when target and in-arrow count both fit (the count of
-        // a vertex never exceeds its degree)
         unsigned int cb[4] = {0, 0, 0, 0};
         FC_HIP(ctx, hipMemcpyAsync(&dmax, &sm->dmax, sizeof(dmax), hipMemcpyDeviceToHost, ctx->stream),
                "copy dmax");
@@ -233,6 +232,122 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         if (mode == 3 && !use_lds)
             return set_err(ctx, FC_ERR_UNSUPPORTED,
                            "the in-arrow counters of one tree do not fit in LDS");
+        // hybrid variant: the widest-class (highest-degree) prefix of the ids in LDS.
+        // Automatically only where the global-counter variant cannot keep its
+        // settled bitmap in LDS either (beyond that size the hybrid wins).
+        const bool coop_bits_fit = fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) + 1024u <= ctx->max_lds;
+        if (!use_lds && (mode == 4 || (mode == 0 && ctx->coop_lds_counts && !coop_bits_fit)) &&
+            g.n >= 1) {
+            if ((rc = ensure(ctx, ctx->rl_blk, 4u * fc::kRelabelClasses * nb, "class counts")) ||
+                (rc = ensure(ctx, ctx->rl_base, 4u * fc::kRelabelClasses * nb, "class offsets")))
+                return rc;
+            FC_HIP(ctx, fc::launch_class_bounds(g.row_ptr, static_cast<uint32_t>(g.n), true,
+                                                static_cast<uint32_t *>(ctx->rl_blk.ptr),
+                                                static_cast<uint32_t *>(ctx->rl_base.ptr),
+                                                sm->class_bounds, ctx->stream),
+                   "class bounds");
+            FC_HIP(ctx, hipMemcpyAsync(cb, sm->class_bounds, sizeof(cb), hipMemcpyDeviceToHost,
+                                       ctx->stream), "copy class bounds");
+            FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "class bounds");
+            // largest prefix whose fields and settled bits fit
+            uint32_t lo = 0, hi = cb[3];
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo + 1) / 2;
+                if (4u * static_cast<size_t>(fc::hot_layout(mid, cb[0], cb[1], cb[2]).words) +
+                        kLdsStaticBytes <= ctx->max_lds)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            lo = std::min<uint32_t>(lo, ctx->hyb_hot_cap);
+            if (lo > 0 || cb[3] == 0 || mode == 4) {
+                use_hyb = true;
+                hot = lo;
+                lds_words = fc::hot_layout(hot, cb[0], cb[1], cb[2]).words;
+            }
+        }
+        if (mode == 4 && !use_hyb)
+            return set_err(ctx, FC_ERR_UNSUPPORTED, "no vertex of the graph fits the hybrid sampler");
+        if (use_hyb) {
+            kname = "wilson_hyb";
+            const size_t n = static_cast<size_t>(g.n);
+            const size_t nwords = (n + 31u) / 32u;
+            if ((rc = ensure(ctx, ctx->rl_inv, 4u * n, "relabel inverse")) ||
+                (rc = ensure(ctx, ctx->rl_orig, 4u * n, "relabel ids")) ||
+                (rc = ensure(ctx, ctx->rl_vrec, sizeof(fc::VRec) * n, "relabelled records")) ||
+                (rc = ensure(ctx, ctx->rl_adj, 8u * static_cast<size_t>(g.nnz), "relabelled adjacency")))
+                return rc;
+            FC_HIP(ctx, fc::launch_relabel_graph(g.row_ptr, g.col_idx, static_cast<uint32_t>(g.n),
+                                                 g.nnz, static_cast<const uint32_t *>(ctx->rl_base.ptr),
+                                                 32u, static_cast<uint32_t *>(ctx->rl_inv.ptr),
+                                                 static_cast<uint32_t *>(ctx->rl_orig.ptr),
+                                                 static_cast<unsigned long long *>(ctx->rl_adj.ptr),
+                                                 ctx->stream),
+                   "relabel");
+            FC_HIP(ctx, fc::launch_relabel_vrec(vrec, static_cast<const uint32_t *>(ctx->rl_inv.ptr),
+                                                static_cast<uint32_t>(g.n),
+                                                static_cast<fc::VRec *>(ctx->rl_vrec.ptr), ctx->stream),
+                   "relabel records");
+            const size_t per_slot = (8u + 4u + 8u + 24u + 4u) * n + 8u + 4u * nwords;
+            slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+            slots = std::min<size_t>(slots, tree_count);
+            lds_threads = lds_threads_for(ctx, tree_count, lds_words);
+            const int fit = fc::hyb_max_active(lds_threads, lds_words);
+            uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
+            per_cu = fit > 0 ? std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit)) : 1u;
+            slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
+            if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
+            if ((rc = ensure(ctx, ctx->cword, 8u * n * slots, "tree words")) ||
+                (rc = ensure(ctx, ctx->corigt, 4u * n * slots, "target ids")) ||
+                (rc = ensure(ctx, ctx->ckk, 8u * n * slots, "draw counts")) ||
+                (rc = ensure(ctx, ctx->clists, 24u * n * slots, "lists")) ||
+                (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")) ||
+                (rc = ensure(ctx, ctx->cbits, 4u * nwords * slots, "settled bitmap")))
+                return rc;
+            FC_HIP(ctx, hipMemsetAsync(ctx->ckk.ptr, 0, 8u * n * slots, ctx->stream),
+                   "memset draw counts");
+            c.word = ctx->cword.ptr;
+            c.origt = static_cast<uint32_t *>(ctx->corigt.ptr);
+            c.kk = static_cast<uint64_t *>(ctx->ckk.ptr);
+            c.lists = static_cast<uint64_t *>(ctx->clists.ptr);
+            c.levels = static_cast<uint32_t *>(ctx->clevels.ptr);
+            c.bits = static_cast<uint32_t *>(ctx->cbits.ptr);
+            c.n_max = static_cast<uint32_t>(g.n);
+            c.slots = static_cast<uint32_t>(slots);
+            c.item_count = tree_count;
+            c.key0 = static_cast<uint32_t>(p->seed);
+            c.key1 = static_cast<uint32_t>(p->seed >> 32);
+            c.max_rounds = 0x40000000u;
+            c.k_limit = ctx->max_draws ? ctx->max_draws : 0x7FFFFFFFu;
+            c.queue = &sm->queue;
+            c.totals = &sm->totals;
+            c.jobs = nullptr;
+            c.item_job = nullptr;
+            fc::CoopJob &j = c.single;
+            j.vrec = static_cast<const fc::VRec *>(ctx->rl_vrec.ptr);
+            j.col_idx = g.col_idx;
+            j.adj = static_cast<const unsigned long long *>(ctx->rl_adj.ptr);
+            j.orig = static_cast<const uint32_t *>(ctx->rl_orig.ptr);
+            j.n = static_cast<uint32_t>(g.n);
+            j.n0 = cb[0];
+            j.n1 = cb[1];
+            j.n2 = cb[2];
+            j.n3 = cb[3];
+            j.hot = hot;
+            j.tree_count = tree_count;
+            j.tshift = 32;
+            j.stream_id = p->stream_id;
+            j.tree_begin = tree_begin;
+            j.first_item = 0;
+            j.step_cap = step_cap;
+            j.root_counts = root_counts;
+            j.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
+            j.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
+            j.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
+            j.parents = parents;
+            j.tree_visits = tree_visits;
+            c.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
+        }
         if (use_lds) {
             kname = "wilson_lds";
             const size_t n = static_cast<size_t>(g.n);
@@ -243,6 +358,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                 return rc;
             FC_HIP(ctx, fc::launch_relabel_graph(g.row_ptr, g.col_idx, static_cast<uint32_t>(g.n),
                                                  g.nnz, static_cast<const uint32_t *>(ctx->rl_base.ptr),
+                                                 fc::kRelabelIdBits,
                                                  static_cast<uint32_t *>(ctx->rl_inv.ptr),
                                                  static_cast<uint32_t *>(ctx->rl_orig.ptr),
                                                  static_cast<unsigned long long *>(ctx->rl_adj.ptr),
@@ -307,7 +423,9 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             c.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
         }
     }
-    if (use_coop && !use_lds) {
+    if (use_coop && !use_lds && !use_hyb) {
+        // 32-bit tree words when target and in-arrow count both fit (the count of
+        // a vertex never exceeds its degree)
         word_layout(static_cast<uint32_t>(g.n), dmax, ctx->coop_word32, &tshift, &word32);
         const size_t wbytes = word32 ? 4u : 8u;
         const size_t nwords = (static_cast<size_t>(g.n) + 31u) / 32u;
@@ -408,7 +526,10 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     }
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
-    if (use_lds) {
+    if (use_hyb) {
+        FC_HIP(ctx, fc::launch_wilson_hyb(c, lds_threads, lds_words, ctx->stream),
+               "wilson_hyb launch");
+    } else if (use_lds) {
         FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, ctx->stream),
                "wilson_lds launch");
     } else if (use_coop) {
@@ -439,7 +560,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         stats->digest_sum = tot.digest_sum;
         stats->ms_sample = ms;
         for (int i = 0; i < 8; ++i) stats->phase_ms[i] = 0.0;
-        if ((use_coop || use_lds) && ctx->phase_timing) {
+        if (use_coop && ctx->phase_timing) {
             unsigned long long ticks[8];
             FC_HIP(ctx, hipMemcpy(ticks, sm->phase_ticks, sizeof(ticks), hipMemcpyDeviceToHost),
                    "copy phase ticks");
@@ -532,7 +653,8 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     // dynamic LDS: allow the workgroup kernels up to the device limit once;
     // each launch passes what it uses
     if (fc::coop_set_lds_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess ||
-        fc::lds_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess) {
+        fc::lds_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess ||
+        fc::hyb_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess) {
         (void)hipGetLastError();
         fc_destroy(ctx);
         return FC_ERR_HIP;
@@ -551,6 +673,7 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
         if (fs && !std::strcmp(fs, "lane")) ctx->force_sampler = 1;
         if (fs && !std::strcmp(fs, "coop")) ctx->force_sampler = 2;
         if (fs && !std::strcmp(fs, "lds")) ctx->force_sampler = 3;
+        if (fs && !std::strcmp(fs, "hyb")) ctx->force_sampler = 4;
     }
     *out = ctx;
     return FC_OK;
@@ -566,7 +689,7 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->cbits, &ctx->s_r64, &ctx->s_r, &ctx->s_z, &ctx->s_p, &ctx->s_q,
                       &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small, &ctx->rl_blk,
                       &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
-                      &ctx->iso})
+                      &ctx->iso, &ctx->corigt})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -607,6 +730,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "lds_wg_per_cu") {
         if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
         ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
+    } else if (k == "hyb_hot_cap") {
+        if (value < 0 || value > 0x7FFFFFFF) return set_err(ctx, FC_ERR_ARG, "hyb_hot_cap");
+        ctx->hyb_hot_cap = static_cast<uint32_t>(value);
     } else if (k == "max_draws") {
         if (value < 0 || value > 0x7FFFFFFF) return set_err(ctx, FC_ERR_ARG, "max_draws");
         ctx->max_draws = static_cast<uint32_t>(value);

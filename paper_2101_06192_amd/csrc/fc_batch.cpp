@@ -331,7 +331,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         uint32_t *base = static_cast<uint32_t *>(b->rl_base.ptr);
         uint32_t *bnd = static_cast<uint32_t *>(b->rl_bounds.ptr);
         for (size_t f = 0; f < gs.size(); ++f)
-            FB_HIP(fc::launch_class_bounds(gs[f].rp, gs[f].n, blk + fc::kRelabelClasses * gs[f].off_b,
+            FB_HIP(fc::launch_class_bounds(gs[f].rp, gs[f].n, false,
+                                           blk + fc::kRelabelClasses * gs[f].off_b,
                                            base + fc::kRelabelClasses * gs[f].off_b, bnd + 4 * f,
                                            b->stream),
                    "class bounds");
@@ -365,7 +366,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         unsigned long long *adj = static_cast<unsigned long long *>(b->rl_adj.ptr);
         for (const GInfo &gi : gs)
             FB_HIP(fc::launch_relabel_graph(gi.rp, gi.ci, gi.n, gi.nnz,
-                                            base + fc::kRelabelClasses * gi.off_b,
+                                            base + fc::kRelabelClasses * gi.off_b, fc::kRelabelIdBits,
                                             inv + gi.off_n, orig + gi.off_n, adj + gi.off_e,
                                             b->stream), "relabel");
         fc::VRec *vr = static_cast<fc::VRec *>(b->rl_vrec.ptr);

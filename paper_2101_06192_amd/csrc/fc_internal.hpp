@@ -33,6 +33,7 @@ struct fc_ctx {
     DevBuf s_r64, s_r, s_z, s_p, s_q, s_d, s_pa, s_pb, s_small;  // solver workspace
     DevBuf rl_blk, rl_base, rl_inv, rl_orig, rl_vrec, rl_adj;     // degree-class relabelling
     DevBuf iso;                                                   // isolated-vertex bitmap
+    DevBuf corigt;                                                // hybrid: target ids per slot
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
@@ -41,12 +42,13 @@ struct fc_ctx {
     size_t max_lds = 65536;       // dynamic LDS a workgroup may use
     uint32_t coop_threads = 512;  // threads per workgroup in the workgroup sampler
     uint32_t coop_wg_per_cu = 3;  // resident workgroups per CU in the workgroup sampler
-    uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop, 3 lds (environment override)
+    uint32_t force_sampler = 0;   // 0 auto, 1 lane, 2 coop, 3 lds, 4 hyb (environment override)
     bool coop_lds_bits = true;    // settled bitmap in LDS when it fits
     bool coop_word32 = true;      // 32-bit tree words when target and count fit
     bool coop_in_bits = true;     // in-arrow bitmap in LDS when both bitmaps fit
     bool phase_timing = false;    // per-phase wall-clock ticks of the workgroup sampler
     uint32_t max_draws = 0;       // per-vertex draw limit in one tree (0: each sampler's own)
+    uint32_t hyb_hot_cap = 0x7FFFFFFF;  // hybrid sampler: cap on the LDS-resident id prefix
     bool coop_lds_counts = true;  // in-arrow counters in LDS when the tree's fields fit
     uint32_t lds_threads = 0;     // threads per workgroup of the LDS-counter sampler (0: by n)
     uint32_t lds_wg_per_cu = 0;   // its resident workgroups per CU (0: as many as fit)

@@ -68,6 +68,7 @@ struct CoopJob {
     uint32_t n;
     uint32_t n0, n1, n2, n3;        // LDS variant: class boundaries
     uint32_t tree_count;            // trees of the job (isolated vertices' totals)
+    uint32_t hot;                   // hybrid variant: ids [0, hot) keep their counter in LDS
     const uint32_t *iso;            // global-counter variant: bitmap of isolated vertices, or null
     uint32_t tshift;          // bits of the target field in a tree word
     uint32_t stream_id;
@@ -89,6 +90,7 @@ struct CoopArgs {
     uint64_t *lists;          // slots * 3 n_max: (vertex, target) pairs: two unsettled lists, peel order
     uint32_t *levels;         // slots * (n_max + 2): peel level boundaries
     uint32_t *bits;           // slots * ceil(n_max/32): settled bitmap when it is not kept in LDS
+    uint32_t *origt;          // hybrid variant: slots * n_max original target ids
     uint32_t n_max;           // largest n of any job (per-slot stride)
     uint32_t slots;           // workgroups (trees in flight)
     uint32_t item_count;      // trees over all jobs
@@ -122,6 +124,26 @@ hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_w
 hipError_t lds_set_limit(size_t bytes);  // as coop_set_lds_limit, for the LDS-counter kernel
 int lds_max_active(uint32_t threads, uint32_t lds_words);
 
+// Hybrid variant (ids widest class first: 32-bit fields end at e3, 16-bit at
+// e2, 8-bit at e1, then 4-bit): LDS fields and settled bits of ids [0, hot).
+hipError_t launch_wilson_hyb(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
+                             hipStream_t stream);
+hipError_t hyb_set_limit(size_t bytes);
+int hyb_max_active(uint32_t threads, uint32_t lds_words);
+struct HotLayout {
+    uint32_t o2, o1, o0, ob, words;
+};
+__host__ __device__ inline HotLayout hot_layout(uint32_t hot, uint32_t e3, uint32_t e2, uint32_t e1) {
+    const uint32_t h3 = hot < e3 ? hot : e3, h2 = hot < e2 ? hot : e2, h1 = hot < e1 ? hot : e1;
+    HotLayout L;
+    L.o2 = h3;
+    L.o1 = L.o2 + ((h2 - h3 + 1u) >> 1);
+    L.o0 = L.o1 + ((h1 - h2 + 3u) >> 2);
+    L.ob = L.o0 + ((hot - h1 + 7u) >> 3);
+    L.words = L.ob + ((hot + 31u) >> 5);
+    return L;
+}
+
 // LDS word offsets of one tree's counter classes and settled bitmap.
 struct CountLayout {
     uint32_t o1, o2, o3, ob, words;
@@ -146,13 +168,16 @@ constexpr uint32_t kRelabelIdBits = 18;
 // into base, and bounds[0..3] = n0, n1, n2, n3.
 constexpr uint32_t kRelabelClasses = 5;
 uint32_t relabel_blocks(uint32_t n);
-hipError_t launch_class_bounds(const int32_t *row_ptr, uint32_t n, uint32_t *blk, uint32_t *base,
-                               uint32_t *bounds, hipStream_t stream);
+// widest_first orders the classes 32-, 16-, 8-, 4-bit (hybrid sampler) instead
+// of 4-, 8-, 16-, 32-bit; isolated vertices come last either way.
+hipError_t launch_class_bounds(const int32_t *row_ptr, uint32_t n, bool widest_first, uint32_t *blk,
+                               uint32_t *base, uint32_t *bounds, hipStream_t stream);
 // inv/orig permutations and relabelled adjacency of one graph (base from
 // launch_class_bounds).
 hipError_t launch_relabel_graph(const int32_t *row_ptr, const int32_t *col_idx, uint32_t n,
-                                int64_t nnz, const uint32_t *base, uint32_t *inv, uint32_t *orig,
-                                unsigned long long *adj, hipStream_t stream);
+                                int64_t nnz, const uint32_t *base, uint32_t orig_shift,
+                                uint32_t *inv, uint32_t *orig, unsigned long long *adj,
+                                hipStream_t stream);
 // Relabelled records of one G* (from the original-id records vrec).
 hipError_t launch_relabel_vrec(const VRec *vrec, const uint32_t *inv, uint32_t n, VRec *vrec_r,
                                hipStream_t stream);

@@ -11,8 +11,9 @@
 // on the internal id.  Randomness and every output stay on original ids: the relabelled
 // vertex record carries the original id, and the relabelled adjacency holds
 // (internal, original) pairs of each neighbour at the same CSR positions
-// (internal id in the low kRelabelIdBits bits, original id above), so the
-// neighbour chosen by a draw is the one the original CSR gives.
+// (internal id in the low bits, original id shifted by 18 for the LDS sampler
+// or 32 for the hybrid one), so the neighbour chosen by a draw is the one the
+// original CSR gives.
 #include "fc_kernels.hpp"
 
 namespace fc {
@@ -43,21 +44,29 @@ __global__ __launch_bounds__(kPlaceThreads) void class_count_kernel(
     if (threadIdx.x < kClasses) blk[blockIdx.x * kClasses + threadIdx.x] = s[threadIdx.x];
 }
 
+// Rank of class c in the id order: narrowest field first (LDS sampler) or
+// widest first (hybrid sampler, whose LDS holds a prefix of the ids: the
+// highest-degree vertices, which receive most arrows); isolated vertices last.
+__device__ __forceinline__ uint32_t class_rank(uint32_t c, bool widest_first) {
+    return c == 4u || !widest_first ? c : 3u - c;
+}
+
 // One block of kClasses threads, thread k serial over the blocks of class k:
-// base[b][k] = first internal id of class k in block b; bounds = n0, n1, n2,
-// n3 (the end of each field class; n3 = number of vertices that are not
+// base[b][k] = first internal id of class k in block b; bounds[r] = end of the
+// class of rank r, r < 4 (bounds[3] = number of vertices that are not
 // isolated).
-__global__ void class_scan_kernel(const uint32_t *__restrict__ blk, uint32_t nb,
+__global__ void class_scan_kernel(const uint32_t *__restrict__ blk, uint32_t nb, int widest_first,
                                   uint32_t *__restrict__ base, uint32_t *__restrict__ bounds) {
     __shared__ uint32_t tot[kClasses];
     const uint32_t k = threadIdx.x;
     uint32_t s = 0;
     for (uint32_t b = 0; b < nb; ++b) s += blk[b * kClasses + k];
-    tot[k] = s;
+    tot[class_rank(k, widest_first)] = s;
     __syncthreads();
+    const uint32_t r = class_rank(k, widest_first);
     uint32_t start = 0;
-    for (uint32_t j = 0; j < k; ++j) start += tot[j];
-    if (k + 1 < kClasses) bounds[k] = start + tot[k];
+    for (uint32_t j = 0; j < r; ++j) start += tot[j];
+    if (r + 1 < kClasses) bounds[r] = start + tot[r];
     for (uint32_t b = 0; b < nb; ++b) {
         base[b * kClasses + k] = start;
         start += blk[b * kClasses + k];
@@ -101,13 +110,13 @@ __global__ void relabel_vrec_kernel(const VRec *__restrict__ vrec, const uint32_
 }
 
 __global__ void relabel_adj_kernel(const int32_t *__restrict__ col_idx, int64_t nnz,
-                                   const uint32_t *__restrict__ inv,
+                                   const uint32_t *__restrict__ inv, uint32_t orig_shift,
                                    unsigned long long *__restrict__ adj) {
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < nnz;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const uint32_t u = static_cast<uint32_t>(col_idx[e]);
         adj[e] = static_cast<unsigned long long>(inv[u]) |
-                 (static_cast<unsigned long long>(u) << kRelabelIdBits);
+                 (static_cast<unsigned long long>(u) << orig_shift);
     }
 }
 
@@ -115,12 +124,12 @@ __global__ void relabel_adj_kernel(const int32_t *__restrict__ col_idx, int64_t 
 
 uint32_t relabel_blocks(uint32_t n) { return (n + kPlaceThreads - 1) / kPlaceThreads; }
 
-hipError_t launch_class_bounds(const int32_t *row_ptr, uint32_t n, uint32_t *blk, uint32_t *base,
-                               uint32_t *bounds, hipStream_t stream) {
+hipError_t launch_class_bounds(const int32_t *row_ptr, uint32_t n, bool widest_first, uint32_t *blk,
+                               uint32_t *base, uint32_t *bounds, hipStream_t stream) {
     const uint32_t nb = relabel_blocks(n);
     if (nb == 0) return hipSuccess;
     class_count_kernel<<<nb, kPlaceThreads, 0, stream>>>(row_ptr, n, blk);
-    class_scan_kernel<<<1, kClasses, 0, stream>>>(blk, nb, base, bounds);
+    class_scan_kernel<<<1, kClasses, 0, stream>>>(blk, nb, widest_first ? 1 : 0, base, bounds);
     return hipGetLastError();
 }
 
@@ -132,16 +141,17 @@ hipError_t launch_relabel_vrec(const VRec *vrec, const uint32_t *inv, uint32_t n
 }
 
 hipError_t launch_relabel_graph(const int32_t *row_ptr, const int32_t *col_idx, uint32_t n,
-                                int64_t nnz, const uint32_t *base, uint32_t *inv, uint32_t *orig,
-                                unsigned long long *adj, hipStream_t stream) {
+                                int64_t nnz, const uint32_t *base, uint32_t orig_shift,
+                                uint32_t *inv, uint32_t *orig, unsigned long long *adj,
+                                hipStream_t stream) {
     const uint32_t nb = relabel_blocks(n);
     if (nb == 0) return hipSuccess;
     class_place_kernel<<<nb, kPlaceThreads, 0, stream>>>(row_ptr, n, base, inv, orig);
     if (nnz > 0) {
         int64_t blocks = (nnz + 255) / 256;
         if (blocks > 16384) blocks = 16384;
-        relabel_adj_kernel<<<static_cast<unsigned int>(blocks), 256, 0, stream>>>(col_idx, nnz, inv,
-                                                                                  adj);
+        relabel_adj_kernel<<<static_cast<unsigned int>(blocks), 256, 0, stream>>>(
+            col_idx, nnz, inv, orig_shift, adj);
     }
     return hipGetLastError();
 }

@@ -22,7 +22,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-SAMPLERS = ["lane", "coop", "lds"]
+SAMPLERS = ["lane", "coop", "lds", "hyb"]
 
 
 def _compare(fc, g, alpha, seed, t0, count, stream=0, per_tree=True, sampler="lane"):
@@ -181,7 +181,7 @@ def test_ba200k_tree_subset_bit_exact(gpu_lib, sampler):
     _compare(gpu_lib, g, 1.0, 0, 4000, 16, per_tree=False, sampler=sampler)
 
 
-@pytest.mark.parametrize("sampler", ["lane", "coop"])
+@pytest.mark.parametrize("sampler", ["lane", "coop", "hyb"])
 @pytest.mark.parametrize("alpha", [0.5, 1.0, 2.0])
 def test_grid_tree_subset_bit_exact(gpu_lib, alpha, sampler):
     """1000 x 1000 grid with 12% of edges removed: 16 trees per alpha."""
@@ -261,6 +261,21 @@ def test_lds_counter_classes_and_size_limit(gpu_lib):
     assert np.array_equal(got["tree_digests"], oracle.sample(over, 1.0, 2, 0, 8).digests)
 
 
+@pytest.mark.parametrize("cap", [0, 1, 100, 5000])
+def test_hybrid_hot_prefix_sizes_bit_exact(gpu_lib, cap):
+    """Hybrid sampler with at most `cap` vertices in LDS (0: every counter and
+    settled bit global; the rest: a split between LDS and global memory that
+    falls inside different degree classes)."""
+    fc = gpu_lib
+    fc.set_option("hyb_hot_cap", cap)
+    try:
+        _compare(fc, inputs.barabasi_albert(20_000, 3, 7), 1.5, 77, 9, 24, sampler="hyb")
+        _compare(fc, inputs.rmat(1 << 14, 8, 12), 1.0, 5, 0, 16, sampler="hyb")
+        _compare(fc, inputs.grid_removed(120, 90, 0.12, 3), 2.0, 78, 0, 12, sampler="hyb")
+    finally:
+        fc.set_option("hyb_hot_cap", 0x7FFFFFFF)
+
+
 def test_auto_choice_prefers_lds_counters(gpu_lib):
     """Without a sampler flag a tree that fits uses LDS counters; the option
     turns that off."""
@@ -308,7 +323,8 @@ def test_set_option_rejects_bad_values(gpu_lib):
     for key, val in (("coop_threads", 100), ("coop_threads", 1024), ("coop_wg_per_cu", 0),
                      ("lanes_per_wave", 65), ("nonsense", 1), ("coop_lds_bits", 2),
                      ("coop_lds_counts", 2), ("lds_threads", 1088), ("lds_threads", 96),
-                     ("lds_wg_per_cu", -1), ("lds_wg_per_cu", 65), ("max_draws", -1),
+                     ("lds_wg_per_cu", -1), ("lds_wg_per_cu", 65), ("hyb_hot_cap", -1),
+                     ("max_draws", -1),
                      ("max_draws", 1 << 31)):
         with pytest.raises(fc.FCError) as e:
             fc.set_option(key, val)
