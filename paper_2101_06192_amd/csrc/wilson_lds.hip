@@ -83,6 +83,38 @@ __device__ __forceinline__ void wave_append(uint64_t *__restrict__ list, uint32_
     }
 }
 
+// The same for R items per lane at once, with a single LDS atomic per wave:
+// item q of every lane goes after items 0..q-1 of all the wave's lanes.
+template <int R>
+__device__ __forceinline__ void wave_append_many(uint64_t *__restrict__ list, uint32_t *tail,
+                                                 uint32_t cap, uint32_t *overflow,
+                                                 const uint64_t (&item)[R], const bool (&pred)[R]) {
+    uint64_t mask[R];
+    uint32_t total = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        mask[q] = __ballot(pred[q]);
+        total += static_cast<uint32_t>(__popcll(mask[q]));
+    }
+    if (total == 0) return;
+    const uint32_t lane = __lane_id();
+    uint32_t base = 0;
+    if (lane == 0) {
+        base = atomicAdd(tail, total);
+        if (base + total > cap) atomicOr(overflow, 1u);
+    }
+    base = __shfl(base, 0, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (pred[q]) {
+            const uint32_t at = base + static_cast<uint32_t>(__popcll(mask[q] & below));
+            if (at < cap) list[at] = item[q];
+        }
+        base += static_cast<uint32_t>(__popcll(mask[q]));
+    }
+}
+
 // Order this wave's LDS accesses before and after (single-wave phases).
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -129,7 +161,7 @@ __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32
 
 // Items per lane per pass iteration (independent loads in flight per lane):
 // streaming passes, and passes that also draw arrows (more registers each).
-constexpr int kR = 4;
+constexpr int kR = 8;
 constexpr int kRD = 2;
 
 __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
@@ -262,8 +294,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 __syncthreads();
             }
             counted = false;
-            if (tid == 0) s_p = 0;
-            // level 0 of the peel: no in-arrows
+            // level 0 of the peel: no in-arrows (s_p is 0 here: reset at the
+            // tree's start and in the split phase, both before a barrier)
             for (uint32_t base = wave_base; base < ucount; base += kR * T) {
                 uint64_t it[kR];
                 bool leaf[kR];
@@ -277,8 +309,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     const uint32_t i = base + q * T + lane;
                     leaf[q] = i < ucount && count_of(f_lo(it[q])) == 0u;
                 }
-#pragma unroll
-                for (int q = 0; q < kR; ++q) wave_append(peel, &s_p, n, &s_over, it[q], leaf[q]);
+                wave_append_many<kR>(peel, &s_p, n, &s_over, it, leaf);
             }
             __syncthreads();
             mark(kPhLevel0);
@@ -302,8 +333,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 #pragma unroll
                     for (int q = 0; q < kR; ++q) nx[q] = push[q] ? word[tg[q]] : 0ull;
 #pragma unroll
-                    for (int q = 0; q < kR; ++q)
-                        wave_append(peel, &s_p, n, &s_over, pack(tg[q], f_lo(nx[q]), 0u), push[q]);
+                    for (int q = 0; q < kR; ++q) nx[q] = pack(tg[q], f_lo(nx[q]), 0u);
+                    wave_append_many<kR>(peel, &s_p, n, &s_over, nx, push);
                 }
                 __syncthreads();
                 ++nlev;
@@ -383,9 +414,16 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             __syncthreads();
             for (int32_t Lv = static_cast<int32_t>(tail0) - 1; Lv >= 0; --Lv) {
                 const uint32_t a0 = uniform(lvl[Lv]), a1 = uniform(lvl[Lv + 1]);
-                for (uint32_t i = a0 + tid; i < a1; i += T) {
-                    const uint64_t p = peel[i];
-                    if (is_settled(f_mid(p))) set_settled(f_lo(p));
+                for (uint32_t base = a0 + tid; base < a1; base += kR * T) {
+                    uint64_t p[kR];
+#pragma unroll
+                    for (int q = 0; q < kR; ++q) {
+                        const uint32_t i = base + q * T;
+                        p[q] = i < a1 ? peel[i] : pack(n, n, 0u);
+                    }
+#pragma unroll
+                    for (int q = 0; q < kR; ++q)
+                        if (f_lo(p[q]) < n && is_settled(f_mid(p[q]))) set_settled(f_lo(p[q]));
                 }
                 __syncthreads();
             }
@@ -396,6 +434,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             if (tid == 0) {
                 s_u = 0;
                 s_cycles = 0;
+                s_p = 0;  // for the next round's peel (last read before the sweep)
             }
             __syncthreads();
             uint64_t *__restrict__ cyc = peel;
@@ -414,11 +453,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     pop[q] = live && count_of(v) != 0u;
                     keep[q] = live && !pop[q];
                 }
-#pragma unroll
-                for (int q = 0; q < kR; ++q) {
-                    wave_append(Unext, &s_u, n, &s_over, it[q], keep[q]);
-                    wave_append(cyc, &s_cycles, n, &s_over, it[q], pop[q]);
-                }
+                wave_append_many<kR>(Unext, &s_u, n, &s_over, it, keep);
+                wave_append_many<kR>(cyc, &s_cycles, n, &s_over, it, pop);
             }
             __syncthreads();
             mark(kPhSplit);
@@ -470,21 +506,35 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 
         unsigned long long my_digest = 0, my_roots = 0;
         const bool want_k = job.visit_counts || job.tree_visits;
-        for (uint32_t v = tid; v < nl; v += T) {
-            const uint64_t w = word[v];
-            const uint32_t ov = job.orig[v];
-            const uint32_t otg = f_mid(w);
-            my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | otg);
-            if (f_lo(w) == n) {
-                ++my_roots;
-                atomicAdd(&job.root_counts[ov], 1u);
+        constexpr int kO = 4;
+        for (uint32_t base = tid; base < nl; base += kO * T) {
+            uint64_t ws[kO];
+            uint32_t ovs[kO];
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                ws[q] = v < nl ? word[v] : 0ull;
+                ovs[q] = v < nl ? job.orig[v] : 0u;
             }
-            if (job.parents) job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(otg);
-            if (want_k) {
-                const uint32_t k = f_k(w);
-                if (job.visit_counts)
-                    atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(k));
-                if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = k;
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                if (base + q * T >= nl) continue;
+                const uint64_t w = ws[q];
+                const uint32_t ov = ovs[q];
+                const uint32_t otg = f_mid(w);
+                my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | otg);
+                if (f_lo(w) == n) {
+                    ++my_roots;
+                    atomicAdd(&job.root_counts[ov], 1u);
+                }
+                if (job.parents)
+                    job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(otg);
+                if (want_k) {
+                    const uint32_t k = f_k(w);
+                    if (job.visit_counts)
+                        atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(k));
+                    if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = k;
+                }
             }
         }
         // isolated vertices: a root after one draw in every tree.  Their digest
