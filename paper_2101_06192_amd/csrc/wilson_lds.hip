@@ -89,13 +89,9 @@ template <int R>
 __device__ __forceinline__ void wave_append_many(uint64_t *__restrict__ list, uint32_t *tail,
                                                  uint32_t cap, uint32_t *overflow,
                                                  const uint64_t (&item)[R], const bool (&pred)[R]) {
-    uint64_t mask[R];
     uint32_t total = 0;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        mask[q] = __ballot(pred[q]);
-        total += static_cast<uint32_t>(__popcll(mask[q]));
-    }
+    for (int q = 0; q < R; ++q) total += static_cast<uint32_t>(__popcll(__ballot(pred[q])));
     if (total == 0) return;
     const uint32_t lane = __lane_id();
     uint32_t base = 0;
@@ -107,11 +103,12 @@ __device__ __forceinline__ void wave_append_many(uint64_t *__restrict__ list, ui
     const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
+        const uint64_t mask = __ballot(pred[q]);  // recomputed: fewer live scalar registers
         if (pred[q]) {
-            const uint32_t at = base + static_cast<uint32_t>(__popcll(mask[q] & below));
+            const uint32_t at = base + static_cast<uint32_t>(__popcll(mask & below));
             if (at < cap) list[at] = item[q];
         }
-        base += static_cast<uint32_t>(__popcll(mask[q]));
+        base += static_cast<uint32_t>(__popcll(mask));
     }
 }
 
@@ -163,6 +160,7 @@ __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32
 // streaming passes, and passes that also draw arrows (more registers each).
 constexpr int kR = 8;
 constexpr int kRD = 2;
+constexpr int kRC = 2;
 
 __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_lds[];
@@ -266,12 +264,14 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     else count_add(f_lo(w[q]));
                 }
             }
+            bool live[kRD];
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
-                wave_append(listA, &s_u, n, &s_over, pack(v, f_lo(w[q]), 1u),
-                            v < nl && f_lo(w[q]) != n);
+                live[q] = v < nl && f_lo(w[q]) != n;
+                w[q] = pack(v, f_lo(w[q]), 1u);
             }
+            wave_append_many<kRD>(listA, &s_u, n, &s_over, w, live);
         }
         __syncthreads();
         mark(kPhDraw0);
@@ -460,12 +460,12 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             mark(kPhSplit);
             // pop every cycle: each cycle vertex draws its next arrow
             const uint32_t ccount = min(uniform(s_cycles), n);
-            for (uint32_t base = wave_base; base < ccount; base += kRD * T) {
-                uint32_t v[kRD], k[kRD];
-                VRec r[kRD];
-                uint64_t w[kRD];
+            for (uint32_t base = wave_base; base < ccount; base += kRC * T) {
+                uint32_t v[kRC], k[kRC];
+                VRec r[kRC];
+                uint64_t w[kRC];
 #pragma unroll
-                for (int q = 0; q < kRD; ++q) {
+                for (int q = 0; q < kRC; ++q) {
                     const uint32_t i = base + q * T + lane;
                     const uint64_t e = i < ccount ? cyc[i] : pack(n, n, 0u);
                     v[q] = f_lo(e);
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     if (v[q] < n) r[q] = load_vrec(job.vrec, v[q]);
                 }
 #pragma unroll
-                for (int q = 0; q < kRD; ++q) {
+                for (int q = 0; q < kRC; ++q) {
                     if (v[q] < n && k[q] >= min(kKMax, a.k_limit)) {  // count past the limit
                         err |= kErrVisitOverflow;
                         v[q] = n;
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     w[q] = v[q] < n ? draw(job, r[q], a.key0, a.key1, k[q], t) : pack(n, n, 0u);
                 }
 #pragma unroll
-                for (int q = 0; q < kRD; ++q) {
+                for (int q = 0; q < kRC; ++q) {
                     if (v[q] < n) {
                         (void)count_dec(v[q]);  // the cycle's arrow into v is gone
                         word[v[q]] = w[q];
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < kRD; ++q)
+                for (int q = 0; q < kRC; ++q)
                     wave_append(Unext, &s_u, n, &s_over, pack(v[q], f_lo(w[q]), f_k(w[q])),
                                 v[q] < n && f_lo(w[q]) != n);
             }
