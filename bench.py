@@ -38,8 +38,12 @@ CSRC = os.path.join(ROOT, "paper_2101_06192_amd", "csrc")
 
 
 def _kernel_hash(sampler: str) -> str:
-    with open(os.path.join(CSRC, f"{sampler}.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sampling kernel's source and the device header it includes."""
+    h = hashlib.sha256()
+    for name in (f"{sampler}.hip", "fc_device.hpp", "fc_kernels.hpp"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _traffic(sampler: str):

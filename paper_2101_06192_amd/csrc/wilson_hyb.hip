@@ -20,6 +20,7 @@
 //   bits      global      settled bitmap of the ids >= hot
 //   LDS                   fields of the ids < hot, then their settled bitmap
 #include "fc_kernels.hpp"
+#include "fc_wave.hpp"
 
 namespace fc {
 
@@ -29,29 +30,6 @@ __device__ __forceinline__ uint32_t lo32(uint64_t w) { return static_cast<uint32
 __device__ __forceinline__ uint32_t hi32(uint64_t w) { return static_cast<uint32_t>(w >> 32); }
 __device__ __forceinline__ uint64_t pair(uint32_t v, uint32_t tg) {
     return static_cast<uint64_t>(v) | (static_cast<uint64_t>(tg) << 32);
-}
-__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Wave-aggregated append with a capacity check (entries past `cap` are dropped
-// and reported through *overflow).  Every lane of the wave must reach it.
-__device__ __forceinline__ void wave_append(uint64_t *__restrict__ list, uint32_t *tail,
-                                            uint32_t cap, uint32_t *overflow, uint64_t item,
-                                            bool pred) {
-    const uint64_t mask = __ballot(pred);
-    if (mask == 0) return;
-    const uint32_t lane = __lane_id();
-    const uint32_t leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-    uint32_t base = 0;
-    if (lane == leader) {
-        const uint32_t cnt = static_cast<uint32_t>(__popcll(mask));
-        base = atomicAdd(tail, cnt);
-        if (base + cnt > cap) atomicOr(overflow, 1u);
-    }
-    base = __shfl(base, leader, 64);
-    if (pred) {
-        const uint32_t at = base + static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
-        if (at < cap) list[at] = item;
-    }
 }
 
 // Per-tree global arrays belong to one workgroup for the whole launch:
@@ -63,12 +41,11 @@ __device__ __forceinline__ void wg_or(uint32_t *p, uint32_t v) {
     (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-constexpr int kR = 2;
+// Items per lane per pass iteration: streaming passes, wide peel levels (each
+// item may add a global atomic or load), passes that draw arrows.
+constexpr int kR = 8;
+constexpr int kRP = 4;
+constexpr int kRD = 2;
 constexpr uint64_t kCntOne = 1ull << 32;
 
 enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedraw, kPhOutput,
@@ -213,28 +190,27 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
         __syncthreads();
 
         // round 0: the first arrow of every vertex that is not isolated
-        for (uint32_t base = wave_base; base < nl; base += kR * T) {
-            uint64_t w[kR];
+        for (uint32_t base = wave_base; base < nl; base += kRD * T) {
+            uint64_t w[kRD];
+            bool live[kRD];
 #pragma unroll
-            for (int q = 0; q < kR; ++q) {
+            for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
                 w[q] = pair(n, n);
                 if (v < nl) w[q] = draw(job, load_vrec(job.vrec, v), a.key0, a.key1, 0u, t);
             }
 #pragma unroll
-            for (int q = 0; q < kR; ++q) {
+            for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
                 if (v < nl) {
                     word[v] = lo32(w[q]);
                     origt[v] = hi32(w[q]);
                     if (lo32(w[q]) == n) set_settled(v);
                 }
+                live[q] = v < nl && lo32(w[q]) != n;
+                w[q] = pair(v, lo32(w[q]));
             }
-#pragma unroll
-            for (int q = 0; q < kR; ++q) {
-                const uint32_t v = base + q * T + lane;
-                wave_append(listA, &s_u, n, &s_over, pair(v, lo32(w[q])), v < nl && lo32(w[q]) != n);
-            }
+            wave_append_many<kRD>(listA, &s_u, n, &s_over, w, live);
         }
         __syncthreads();
         mark(kPhDraw0);
@@ -277,8 +253,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                     const uint32_t i = base + q * T + lane;
                     leaf[q] = i < ucount && count_of(lo32(it[q])) == 0u;
                 }
-#pragma unroll
-                for (int q = 0; q < kR; ++q) wave_append(peel, &s_p, n, &s_over, it[q], leaf[q]);
+                wave_append_many<kR>(peel, &s_p, n, &s_over, it, leaf);
             }
             __syncthreads();
             mark(kPhLevel0);
@@ -286,21 +261,22 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             if (tid == 0) lvl[0] = 0;
             while (hi - lo > 64u) {
                 if (tid == 0) lvl[nlev + 1] = hi;
-                for (uint32_t base = lo + wave_base; base < hi; base += kR * T) {
-                    uint32_t tg[kR];
-                    uint64_t nx[kR];
+                for (uint32_t base = lo + wave_base; base < hi; base += kRP * T) {
+                    uint32_t tg[kRP];
+                    uint64_t nx[kRP];
+                    bool push[kRP];
 #pragma unroll
-                    for (int q = 0; q < kR; ++q) {
+                    for (int q = 0; q < kRP; ++q) {
                         const uint32_t i = base + q * T + lane;
                         tg[q] = i < hi ? hi32(peel[i]) : n;
                         nx[q] = 0ull;
                     }
 #pragma unroll
-                    for (int q = 0; q < kR; ++q)
+                    for (int q = 0; q < kRP; ++q) {
                         if (!is_settled(tg[q])) nx[q] = count_dec(tg[q]);
-#pragma unroll
-                    for (int q = 0; q < kR; ++q)
-                        wave_append(peel, &s_p, n, &s_over, nx[q], nx[q] != 0ull);
+                        push[q] = nx[q] != 0ull;
+                    }
+                    wave_append_many<kRP>(peel, &s_p, n, &s_over, nx, push);
                 }
                 __syncthreads();
                 ++nlev;
@@ -374,9 +350,16 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             __syncthreads();
             for (int32_t L = static_cast<int32_t>(tail0) - 1; L >= 0; --L) {
                 const uint32_t a0 = uniform(lvl[L]), a1 = uniform(lvl[L + 1]);
-                for (uint32_t i = a0 + tid; i < a1; i += T) {
-                    const uint64_t p = peel[i];
-                    if (is_settled(hi32(p))) set_settled(lo32(p));
+                for (uint32_t base = a0 + tid; base < a1; base += kR * T) {
+                    uint64_t p[kR];
+#pragma unroll
+                    for (int q = 0; q < kR; ++q) {
+                        const uint32_t i = base + q * T;
+                        p[q] = i < a1 ? peel[i] : pair(n, n);
+                    }
+#pragma unroll
+                    for (int q = 0; q < kR; ++q)
+                        if (lo32(p[q]) < n && is_settled(hi32(p[q]))) set_settled(lo32(p[q]));
                 }
                 __syncthreads();
             }
@@ -404,20 +387,17 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                     pop[q] = live && count_of(v) != 0u;
                     keep[q] = live && !pop[q];
                 }
-#pragma unroll
-                for (int q = 0; q < kR; ++q) {
-                    wave_append(Unext, &s_u, n, &s_over, it[q], keep[q]);
-                    wave_append(cyc, &s_cycles, n, &s_over, it[q], pop[q]);
-                }
+                wave_append_many<kR>(Unext, &s_u, n, &s_over, it, keep);
+                wave_append_many<kR>(cyc, &s_cycles, n, &s_over, it, pop);
             }
             __syncthreads();
             // pop every cycle: each cycle vertex draws its next arrow
             const uint32_t ccount = min(uniform(s_cycles), n);
-            for (uint32_t base = wave_base; base < ccount; base += kR * T) {
-                uint32_t v[kR], k[kR];
-                uint64_t w[kR];
+            for (uint32_t base = wave_base; base < ccount; base += kRD * T) {
+                uint32_t v[kRD], k[kRD];
+                uint64_t w[kRD];
 #pragma unroll
-                for (int q = 0; q < kR; ++q) {
+                for (int q = 0; q < kRD; ++q) {
                     const uint32_t i = base + q * T + lane;
                     v[q] = i < ccount ? lo32(cyc[i]) : n;
                     k[q] = 1u;
@@ -427,11 +407,11 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < kR; ++q)
+                for (int q = 0; q < kRD; ++q)
                     w[q] = v[q] < n ? draw(job, load_vrec(job.vrec, v[q]), a.key0, a.key1, k[q], t)
                                     : pair(n, n);
 #pragma unroll
-                for (int q = 0; q < kR; ++q) {
+                for (int q = 0; q < kRD; ++q) {
                     if (v[q] < n) {
                         if (k[q] + 1u > a.k_limit) err |= kErrVisitOverflow;
                         kk[v[q]] = (static_cast<uint64_t>(epoch) << 32) | (k[q] + 1u);
@@ -444,10 +424,13 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                         if (lo32(w[q]) == n) set_settled(v[q]);
                     }
                 }
+                bool live[kRD];
 #pragma unroll
-                for (int q = 0; q < kR; ++q)
-                    wave_append(Unext, &s_u, n, &s_over, pair(v[q], lo32(w[q])),
-                                v[q] < n && lo32(w[q]) != n);
+                for (int q = 0; q < kRD; ++q) {
+                    live[q] = v[q] < n && lo32(w[q]) != n;
+                    w[q] = pair(v[q], lo32(w[q]));
+                }
+                wave_append_many<kRD>(Unext, &s_u, n, &s_over, w, live);
             }
             __syncthreads();
             mark(kPhRedraw);
@@ -462,22 +445,35 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
 
         unsigned long long my_digest = 0, my_roots = 0;
         const bool want_k = job.visit_counts || job.tree_visits;
-        for (uint32_t v = tid; v < nl; v += T) {
-            const uint32_t tg = lo32(word[v]);
-            const uint32_t ov = job.orig[v];
-            const uint32_t otg = origt[v];
-            my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | otg);
-            if (tg == n) {
-                ++my_roots;
-                atomicAdd(&job.root_counts[ov], 1u);
+        constexpr int kO = 4;
+        for (uint32_t base = tid; base < nl; base += kO * T) {
+            uint32_t tgs[kO], ovs[kO], otgs[kO];
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                tgs[q] = v < nl ? lo32(word[v]) : 0u;
+                ovs[q] = v < nl ? job.orig[v] : 0u;
+                otgs[q] = v < nl ? origt[v] : 0u;
             }
-            if (job.parents) job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(otg);
-            if (want_k) {
-                const uint64_t kv = kk[v];
-                const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
-                if (job.visit_counts)
-                    atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(k));
-                if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = k;
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                if (v >= nl) continue;
+                const uint32_t tg = tgs[q], ov = ovs[q], otg = otgs[q];
+                my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | otg);
+                if (tg == n) {
+                    ++my_roots;
+                    atomicAdd(&job.root_counts[ov], 1u);
+                }
+                if (job.parents)
+                    job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(otg);
+                if (want_k) {
+                    const uint64_t kv = kk[v];
+                    const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
+                    if (job.visit_counts)
+                        atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(k));
+                    if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = k;
+                }
             }
         }
         // isolated vertices: per-tree digest terms; totals once per job

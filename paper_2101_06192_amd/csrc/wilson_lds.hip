@@ -38,6 +38,7 @@
 // Isolated vertices (internal ids [n3, n)) take no part in the rounds: only
 // the output visits them.
 #include "fc_kernels.hpp"
+#include "fc_wave.hpp"
 
 namespace fc {
 
@@ -57,65 +58,6 @@ __device__ __forceinline__ uint32_t f_k(uint64_t w) { return static_cast<uint32_
 __device__ __forceinline__ uint64_t pack(uint32_t lo, uint32_t mid, uint32_t k) {
     return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(mid) << kIdBits) |
            (static_cast<uint64_t>(k) << kKShift);
-}
-__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Wave-aggregated append with a capacity check: one LDS atomic per wave;
-// entries past `cap` are dropped and reported through *overflow.  Every
-// lane of the wave must reach it.
-__device__ __forceinline__ void wave_append(uint64_t *__restrict__ list, uint32_t *tail,
-                                            uint32_t cap, uint32_t *overflow, uint64_t item,
-                                            bool pred) {
-    const uint64_t mask = __ballot(pred);
-    if (mask == 0) return;
-    const uint32_t lane = __lane_id();
-    const uint32_t leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-    uint32_t base = 0;
-    if (lane == leader) {
-        const uint32_t cnt = static_cast<uint32_t>(__popcll(mask));
-        base = atomicAdd(tail, cnt);
-        if (base + cnt > cap) atomicOr(overflow, 1u);
-    }
-    base = __shfl(base, leader, 64);
-    if (pred) {
-        const uint32_t at = base + static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
-        if (at < cap) list[at] = item;
-    }
-}
-
-// The same for R items per lane at once, with a single LDS atomic per wave:
-// item q of every lane goes after items 0..q-1 of all the wave's lanes.
-template <int R>
-__device__ __forceinline__ void wave_append_many(uint64_t *__restrict__ list, uint32_t *tail,
-                                                 uint32_t cap, uint32_t *overflow,
-                                                 const uint64_t (&item)[R], const bool (&pred)[R]) {
-    uint32_t total = 0;
-#pragma unroll
-    for (int q = 0; q < R; ++q) total += static_cast<uint32_t>(__popcll(__ballot(pred[q])));
-    if (total == 0) return;
-    const uint32_t lane = __lane_id();
-    uint32_t base = 0;
-    if (lane == 0) {
-        base = atomicAdd(tail, total);
-        if (base + total > cap) atomicOr(overflow, 1u);
-    }
-    base = __shfl(base, 0, 64);
-    const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const uint64_t mask = __ballot(pred[q]);  // recomputed: fewer live scalar registers
-        if (pred[q]) {
-            const uint32_t at = base + static_cast<uint32_t>(__popcll(mask & below));
-            if (at < cap) list[at] = item[q];
-        }
-        base += static_cast<uint32_t>(__popcll(mask));
-    }
-}
-
-// Order this wave's LDS accesses before and after (single-wave phases).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
 }
 
 // Per-phase clock sums: first arrows, in-arrow count + peel level 0, wide peel
@@ -159,6 +101,7 @@ __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32
 // Items per lane per pass iteration (independent loads in flight per lane):
 // streaming passes, and passes that also draw arrows (more registers each).
 constexpr int kR = 8;
+constexpr int kRP = 4;  // wide peel levels (each item may add a random load)
 constexpr int kRD = 2;
 constexpr int kRC = 2;
 
@@ -287,9 +230,16 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 break;
             }
             if (!counted) {
-                for (uint32_t i = tid; i < ucount; i += T) {
-                    const uint32_t tg = f_mid(U[i]);
-                    if (!is_settled(tg)) count_add(tg);
+                for (uint32_t base = tid; base < ucount; base += kR * T) {
+                    uint32_t tg[kR];
+#pragma unroll
+                    for (int q = 0; q < kR; ++q) {
+                        const uint32_t i = base + q * T;
+                        tg[q] = i < ucount ? f_mid(U[i]) : n;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kR; ++q)
+                        if (!is_settled(tg[q])) count_add(tg[q]);
                 }
                 __syncthreads();
             }
@@ -317,24 +267,24 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             if (tid == 0) lvl[0] = 0;
             while (hi - lo > 64u) {
                 if (tid == 0) lvl[nlev + 1] = hi;
-                for (uint32_t base = lo + wave_base; base < hi; base += kR * T) {
-                    uint32_t tg[kR];
-                    bool push[kR];
-                    uint64_t nx[kR];
+                for (uint32_t base = lo + wave_base; base < hi; base += kRP * T) {
+                    uint32_t tg[kRP];
+                    bool push[kRP];
+                    uint64_t nx[kRP];
 #pragma unroll
-                    for (int q = 0; q < kR; ++q) {
+                    for (int q = 0; q < kRP; ++q) {
                         const uint32_t i = base + q * T + lane;
                         tg[q] = i < hi ? f_mid(peel[i]) : n;
                         push[q] = false;
                     }
 #pragma unroll
-                    for (int q = 0; q < kR; ++q)
+                    for (int q = 0; q < kRP; ++q)
                         if (!is_settled(tg[q])) push[q] = count_dec(tg[q]) == 1u;
 #pragma unroll
-                    for (int q = 0; q < kR; ++q) nx[q] = push[q] ? word[tg[q]] : 0ull;
+                    for (int q = 0; q < kRP; ++q) nx[q] = push[q] ? word[tg[q]] : 0ull;
 #pragma unroll
-                    for (int q = 0; q < kR; ++q) nx[q] = pack(tg[q], f_lo(nx[q]), 0u);
-                    wave_append_many<kR>(peel, &s_p, n, &s_over, nx, push);
+                    for (int q = 0; q < kRP; ++q) nx[q] = pack(tg[q], f_lo(nx[q]), 0u);
+                    wave_append_many<kRP>(peel, &s_p, n, &s_over, nx, push);
                 }
                 __syncthreads();
                 ++nlev;
