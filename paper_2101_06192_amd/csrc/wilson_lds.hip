@@ -185,13 +185,21 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         // round 0: the first arrow of every vertex, and the first in-arrow count
         // (arrows into vertices that turn out settled are counted too; those
         // counts are never read)
+        // (records are loaded one iteration ahead, so each iteration waits for
+        // one global load, the neighbour gather, instead of two in a row)
+        VRec r[kRD] = {};
+#pragma unroll
+        for (int q = 0; q < kRD; ++q) {
+            const uint32_t v = wave_base + q * T + lane;
+            if (v < nl) r[q] = load_vrec(job.vrec, v);
+        }
         for (uint32_t base = wave_base; base < nl; base += kRD * T) {
-            VRec r[kRD];
+            VRec rn[kRD] = {};
             uint64_t w[kRD];
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
-                const uint32_t v = base + q * T + lane;
-                if (v < nl) r[q] = load_vrec(job.vrec, v);
+                const uint32_t v = base + (kRD + q) * T + lane;
+                if (v < nl) rn[q] = load_vrec(job.vrec, v);
             }
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
@@ -215,6 +223,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 w[q] = pack(v, f_lo(w[q]), 1u);
             }
             wave_append_many<kRD>(listA, &s_u, n, &s_over, w, live);
+#pragma unroll
+            for (int q = 0; q < kRD; ++q) r[q] = rn[q];
         }
         __syncthreads();
         mark(kPhDraw0);
@@ -267,14 +277,22 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             if (tid == 0) lvl[0] = 0;
             while (hi - lo > 64u) {
                 if (tid == 0) lvl[nlev + 1] = hi;
+                // (the level's entries are loaded one iteration ahead; entries
+                // appended meanwhile lie beyond hi)
+                uint32_t tg[kRP];
+#pragma unroll
+                for (int q = 0; q < kRP; ++q) {
+                    const uint32_t i = lo + wave_base + q * T + lane;
+                    tg[q] = i < hi ? f_mid(peel[i]) : n;
+                }
                 for (uint32_t base = lo + wave_base; base < hi; base += kRP * T) {
-                    uint32_t tg[kRP];
+                    uint32_t tgn[kRP];
                     bool push[kRP];
                     uint64_t nx[kRP];
 #pragma unroll
                     for (int q = 0; q < kRP; ++q) {
-                        const uint32_t i = base + q * T + lane;
-                        tg[q] = i < hi ? f_mid(peel[i]) : n;
+                        const uint32_t i = base + (kRP + q) * T + lane;
+                        tgn[q] = i < hi ? f_mid(peel[i]) : n;
                         push[q] = false;
                     }
 #pragma unroll
@@ -285,6 +303,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 #pragma unroll
                     for (int q = 0; q < kRP; ++q) nx[q] = pack(tg[q], f_lo(nx[q]), 0u);
                     wave_append_many<kRP>(peel, &s_p, n, &s_over, nx, push);
+#pragma unroll
+                    for (int q = 0; q < kRP; ++q) tg[q] = tgn[q];
                 }
                 __syncthreads();
                 ++nlev;
