@@ -68,7 +68,7 @@ class fc_stats(ctypes.Structure):
                 ("walk_steps", ctypes.c_uint64), ("roots", ctypes.c_uint64),
                 ("digest_sum", ctypes.c_uint64), ("ms_sample", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("sampler", ctypes.c_char * 16),
-                ("phase_ms", ctypes.c_double * 8)]
+                ("phase_ms", ctypes.c_double * 8), ("ms_predraw", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -22,7 +22,7 @@
 
 static_assert(sizeof(fc_graph) == 40, "fc_graph layout");
 static_assert(sizeof(fc_params) == 56, "fc_params layout");
-static_assert(sizeof(fc_stats) == 128, "fc_stats layout");
+static_assert(sizeof(fc_stats) == 136, "fc_stats layout");
 static_assert(sizeof(fc_job) == 80, "fc_job layout");
 
 namespace fc_host {
@@ -378,11 +378,18 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             else per_cu = 1;
             slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
             if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
-            if ((rc = ensure(ctx, ctx->cword, 8u * n * slots, "tree words")) ||
+            // first arrows of all trees drawn ahead by one vertex-major kernel when
+            // every tree's words fit the budget (the trees then work in place)
+            const size_t pre_bytes = 8u * n * static_cast<size_t>(tree_count);
+            const bool predraw = ctx->lds_predraw_mib != 0 && cb[3] > 0 &&
+                                 pre_bytes <= (static_cast<size_t>(ctx->lds_predraw_mib) << 20);
+            if ((!predraw && (rc = ensure(ctx, ctx->cword, 8u * n * slots, "tree words"))) ||
+                (predraw && (rc = ensure(ctx, ctx->cpre, pre_bytes, "pre-drawn tree words"))) ||
                 (rc = ensure(ctx, ctx->clists, 24u * n * slots, "lists")) ||
                 (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")))
                 return rc;
-            c.word = ctx->cword.ptr;
+            c.word = predraw ? nullptr : ctx->cword.ptr;
+            c.pre = predraw ? static_cast<uint64_t *>(ctx->cpre.ptr) : nullptr;
             c.kk = nullptr;  // draw counts travel in the tree words
             c.lists = static_cast<uint64_t *>(ctx->clists.ptr);
             c.levels = static_cast<uint32_t *>(ctx->clevels.ptr);
@@ -530,6 +537,10 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         FC_HIP(ctx, fc::launch_wilson_hyb(c, lds_threads, lds_words, ctx->stream),
                "wilson_hyb launch");
     } else if (use_lds) {
+        if (c.pre) {
+            FC_HIP(ctx, fc::launch_lds_predraw(c, ctx->stream), "lds_predraw launch");
+            FC_HIP(ctx, hipEventRecord(ctx->evm, ctx->stream), "event");
+        }
         FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, ctx->stream),
                "wilson_lds launch");
     } else if (use_coop) {
@@ -559,6 +570,12 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         stats->roots = tot.roots;
         stats->digest_sum = tot.digest_sum;
         stats->ms_sample = ms;
+        stats->ms_predraw = 0.0;
+        if (use_lds && c.pre) {
+            float pm = 0.f;
+            (void)hipEventElapsedTime(&pm, ctx->ev0, ctx->evm);
+            stats->ms_predraw = pm;
+        }
         for (int i = 0; i < 8; ++i) stats->phase_ms[i] = 0.0;
         if (use_coop && ctx->phase_timing) {
             unsigned long long ticks[8];
@@ -627,6 +644,7 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     ctx->device = hip_device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        hipEventCreate(&ctx->evm) != hipSuccess ||
         ensure(ctx, ctx->small, sizeof(Small), "counters") != FC_OK) {
         fc_destroy(ctx);
         return FC_ERR_HIP;
@@ -689,10 +707,11 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->cbits, &ctx->s_r64, &ctx->s_r, &ctx->s_z, &ctx->s_p, &ctx->s_q,
                       &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small, &ctx->rl_blk,
                       &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
-                      &ctx->iso, &ctx->corigt})
+                      &ctx->iso, &ctx->corigt, &ctx->cpre})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->evm) (void)hipEventDestroy(ctx->evm);
     delete ctx;
     return FC_OK;
 }
@@ -730,6 +749,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "lds_wg_per_cu") {
         if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
         ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
+    } else if (k == "lds_predraw_mib") {
+        if (value < 0 || value > (int64_t(1) << 22)) return set_err(ctx, FC_ERR_ARG, "lds_predraw_mib");
+        ctx->lds_predraw_mib = static_cast<uint32_t>(value);
     } else if (k == "hyb_hot_cap") {
         if (value < 0 || value > 0x7FFFFFFF) return set_err(ctx, FC_ERR_ARG, "hyb_hot_cap");
         ctx->hyb_hot_cap = static_cast<uint32_t>(value);

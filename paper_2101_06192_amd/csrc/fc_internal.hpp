@@ -34,7 +34,8 @@ struct fc_ctx {
     DevBuf rl_blk, rl_base, rl_inv, rl_orig, rl_vrec, rl_adj;     // degree-class relabelling
     DevBuf iso;                                                   // isolated-vertex bitmap
     DevBuf corigt;                                                // hybrid: target ids per slot
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevBuf cpre;                                                  // LDS: pre-drawn tree words
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
     uint32_t max_slots = 0;       // 0 = as many trees in flight as memory allows
@@ -52,6 +53,7 @@ struct fc_ctx {
     bool coop_lds_counts = true;  // in-arrow counters in LDS when the tree's fields fit
     uint32_t lds_threads = 0;     // threads per workgroup of the LDS-counter sampler (0: by n)
     uint32_t lds_wg_per_cu = 0;   // its resident workgroups per CU (0: as many as fit)
+    uint32_t lds_predraw_mib = 16384;  // budget of its pre-drawn first arrows (0: off)
     double wall_khz = 100000.0;   // device wall clock rate
 };
 

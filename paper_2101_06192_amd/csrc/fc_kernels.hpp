@@ -91,6 +91,9 @@ struct CoopArgs {
     uint32_t *levels;         // slots * (n_max + 2): peel level boundaries
     uint32_t *bits;           // slots * ceil(n_max/32): settled bitmap when it is not kept in LDS
     uint32_t *origt;          // hybrid variant: slots * n_max original target ids
+    uint64_t *pre;            // LDS variant, single job: item_count * n_max tree words whose
+                              // first arrows are drawn already (launch_lds_predraw), used in
+                              // place of the slot's word array; or null
     uint32_t n_max;           // largest n of any job (per-slot stride)
     uint32_t slots;           // workgroups (trees in flight)
     uint32_t item_count;      // trees over all jobs
@@ -122,6 +125,11 @@ size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
                              hipStream_t stream);
 hipError_t lds_set_limit(size_t bytes);  // as coop_set_lds_limit, for the LDS-counter kernel
+// First arrow of every non-isolated vertex in every tree of a single-job LDS
+// launch (a.single, items [0, a.item_count)): a.pre[item * a.n_max + v] = the
+// tree word the LDS kernel's first round would write.  Vertex-major, so the
+// relabelled records and adjacency are read once per vertex tile for many trees.
+hipError_t launch_lds_predraw(const CoopArgs &a, hipStream_t stream);
 int lds_max_active(uint32_t threads, uint32_t lds_words);
 
 // Hybrid variant (ids widest class first: 32-bit fields end at e3, 16-bit at

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     const uint32_t lane = tid & 63u;
     const size_t slot = blockIdx.x;
     const size_t stride = a.n_max;
-    uint64_t *__restrict__ word = static_cast<uint64_t *>(a.word) + slot * stride;
+    uint64_t *const slot_word = a.word ? static_cast<uint64_t *>(a.word) + slot * stride : nullptr;
     uint64_t *__restrict__ listA = a.lists + slot * (3ull * stride);
     uint64_t *__restrict__ listB = listA + stride;
     uint64_t *__restrict__ peel = listB + stride;
@@ -150,6 +150,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         const uint32_t t = job.tree_begin + ti;
         const uint32_t n = job.n;    // also the id of u*
         const uint32_t nl = job.n3;  // vertices that are not isolated: ids [0, nl)
+        // the tree's words: its own pre-drawn array, or the slot's
+        uint64_t *__restrict__ word = a.pre ? a.pre + static_cast<size_t>(item) * stride : slot_word;
         const CountLayout L = count_layout(nl, job.n0, job.n1, job.n2);
         const Classes C{job.n0, job.n1, job.n2, L.o1, L.o2, L.o3};
         uint32_t *__restrict__ bits = s_lds + L.ob;
@@ -185,6 +187,28 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         // round 0: the first arrow of every vertex, and the first in-arrow count
         // (arrows into vertices that turn out settled are counted too; those
         // counts are never read)
+        if (a.pre) {  // arrows drawn already: stream them
+            for (uint32_t base = wave_base; base < nl; base += kR * T) {
+                uint64_t w[kR];
+                bool live[kR];
+#pragma unroll
+                for (int q = 0; q < kR; ++q) {
+                    const uint32_t v = base + q * T + lane;
+                    w[q] = v < nl ? word[v] : pack(n, n, 0u);
+                }
+#pragma unroll
+                for (int q = 0; q < kR; ++q) {
+                    const uint32_t v = base + q * T + lane;
+                    live[q] = v < nl && f_lo(w[q]) != n;
+                    if (v < nl) {
+                        if (live[q]) count_add(f_lo(w[q]));
+                        else set_settled(v);
+                    }
+                    w[q] = pack(v, f_lo(w[q]), 1u);
+                }
+                wave_append_many<kR>(listA, &s_u, n, &s_over, w, live);
+            }
+        } else {
         // (records are loaded one iteration ahead, so each iteration waits for
         // one global load, the neighbour gather, instead of two in a row)
         VRec r[kRD] = {};
@@ -225,6 +249,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             wave_append_many<kRD>(listA, &s_u, n, &s_over, w, live);
 #pragma unroll
             for (int q = 0; q < kRD; ++q) r[q] = rn[q];
+        }
         }
         __syncthreads();
         mark(kPhDraw0);
@@ -545,7 +570,41 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     if (err) atomicOr(&a.totals->error, err);
 }
 
+// Trees per workgroup of the pre-draw kernel (each thread owns one vertex and
+// draws its first arrow in that many trees).
+constexpr uint32_t kPreTrees = 16;
+constexpr uint32_t kPreThreads = 256;
+
+__global__ __launch_bounds__(kPreThreads) void lds_predraw_kernel(CoopArgs a, uint32_t groups) {
+    const CoopJob &job = a.single;
+    const uint32_t v = blockIdx.x * kPreThreads + threadIdx.x;
+    if (v >= job.n3) return;
+    const VRec r = load_vrec(job.vrec, v);
+    for (uint32_t g = blockIdx.y; g < groups; g += gridDim.y) {
+        const uint32_t i0 = g * kPreTrees;
+#pragma unroll
+        for (uint32_t q = 0; q < kPreTrees; ++q) {
+            const uint32_t item = i0 + q;
+            if (item < a.item_count)
+                a.pre[static_cast<size_t>(item) * a.n_max + v] =
+                    draw(job, r, a.key0, a.key1, 0u, job.tree_begin + item);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_lds_predraw(const CoopArgs &a, hipStream_t stream) {
+    if (!a.pre || a.single.n3 == 0 || a.item_count == 0) return hipSuccess;
+    // vertex tiles a multiple of 8 wide: block b of every tree group then runs on
+    // XCD b mod 8, whose L2 keeps that tile's records and adjacency rows
+    uint32_t tiles = (a.single.n3 + kPreThreads - 1) / kPreThreads;
+    tiles = (tiles + 7u) & ~7u;
+    const uint32_t groups = (a.item_count + kPreTrees - 1) / kPreTrees;
+    const dim3 grid(tiles, groups < 65535u ? groups : 65535u);
+    lds_predraw_kernel<<<grid, kPreThreads, 0, stream>>>(a, groups);
+    return hipGetLastError();
+}
 
 hipError_t lds_set_limit(size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_lds_kernel),

@@ -94,5 +94,5 @@ def test_struct_layouts():
     assert fc.fc_graph.nnz.offset == 8 and fc.fc_graph.mem.offset == 32
     assert ctypes.sizeof(fc.fc_params) == 56
     assert fc.fc_params.seed.offset == 32 and fc.fc_params.flags.offset == 52
-    assert ctypes.sizeof(fc.fc_stats) == 128
+    assert ctypes.sizeof(fc.fc_stats) == 136 and fc.fc_stats.ms_predraw.offset == 128
     assert ctypes.sizeof(fc.fc_job) == 80 and fc.fc_job.root_counts.offset == 64

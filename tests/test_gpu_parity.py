@@ -243,6 +243,30 @@ def test_lds_launch_shapes_bit_exact(gpu_lib, threads, wg):
         fc.set_option("lds_wg_per_cu", 0)
 
 
+@pytest.mark.parametrize("mib", [0, 1, 16384], ids=["off", "over_budget", "default"])
+def test_lds_first_arrows_drawn_ahead_or_in_place(gpu_lib, mib):
+    """The LDS sampler's first arrows, drawn by the vertex-major pre-draw
+    kernel (the default when every tree's words fit the budget) or by each
+    tree's workgroup (budget 0, or too small: 40 trees of 20000 vertices need
+    6.1 MiB, more than 1 MiB), give the oracle's trees."""
+    fc = gpu_lib
+    fc.set_option("lds_predraw_mib", mib)
+
+    def drawn_ahead(n, trees):
+        return mib > 0 and 8 * n * trees <= mib << 20
+
+    try:
+        g = inputs.barabasi_albert(20_000, 3, 7)
+        got, _ = _compare(fc, g, 1.5, 77, 9, 40, sampler="lds")
+        assert (got["stats"]["ms_predraw"] > 0.0) == drawn_ahead(g.n, 40)
+        # isolated vertices and a tree range not starting at 0
+        g2 = inputs.rmat(3000, 8, 5)
+        got, _ = _compare(fc, g2, 0.3, 5, 1000, 33, stream=7, sampler="lds")
+        assert (got["stats"]["ms_predraw"] > 0.0) == drawn_ahead(g2.n, 33)
+    finally:
+        fc.set_option("lds_predraw_mib", 16384)
+
+
 def test_lds_counter_classes_and_size_limit(gpu_lib):
     """A star whose centre has degree 70000 needs a 32-bit field (the widest
     class); BA(250000, 3) needs 161.8 KB of fields and bitmap, just inside
