@@ -228,6 +228,16 @@ def main():
                      "random_access_ceiling": ceiling},
         "cpu_baseline": cpu,
     }
+    if ceiling:
+        # the line model of sequential Wilson walks: 3 random lines per walk step
+        # plus one line per 8 vertices for the start scan, against the measured
+        # rate of independent random loads over 4 GiB
+        lines = 3.0 * walk_steps + n * trees / 8.0
+        rate = lines / (ms_kernel / 1000.0)
+        line["roofline"]["random_gather_model"] = {
+            "lines_per_launch": lines, "lines_per_s": rate,
+            "ceiling_loads_per_s": ceiling["random_loads_per_s"],
+            "frac": rate / ceiling["random_loads_per_s"]}
     if args.phase_timing:
         if sampler == "wilson_lds":
             names = ["first_arrows", "count_and_level0", "peel_wide", "peel_tail", "sweep",
