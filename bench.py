@@ -240,8 +240,8 @@ def main():
             "frac": rate / ceiling["random_loads_per_s"]}
     if args.phase_timing:
         if sampler == "wilson_lds":
-            names = ["first_arrows", "count_and_level0", "peel_wide", "peel_tail", "sweep",
-                     "split", "cycles", "output"]
+            names = ["first_arrows", "count_and_level0", "peel_wide", "peel_tail",
+                     "sweep_and_split", "cycle_scan", "cycles", "output"]
         else:
             names = ["first_arrows", "in_arrows", "peel_level0", "peel_levels", "sweep", "redraw",
                      "output"]

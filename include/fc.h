@@ -141,8 +141,9 @@ typedef struct {
                                   level 0, peel levels, reverse sweep, redraw, output;
                                 wilson_lds: first arrows, in-arrow counting with peel
                                   level 0, wide peel levels, single-wave peel levels,
-                                  reverse sweep, split of the unsettled list, cycle
-                                  popping, output;
+                                  reverse sweep (which also lists the vertices left
+                                  hanging off cycles), scan for the cycle vertices,
+                                  cycle popping, output;
                                 else zeros */
     double ms_predraw;       /* part of ms_sample spent drawing every tree's first arrows
                                 ahead of the LDS-counter sampler (option "lds_predraw_mib"),

@@ -46,6 +46,14 @@ __device__ __forceinline__ void wave_append_many(uint64_t *__restrict__ list, ui
     }
 }
 
+// Adds the sum over the wave of each lane's `count` to an LDS counter with one
+// atomic.  Every lane of the wave must reach the call.
+__device__ __forceinline__ void wave_count(uint32_t *counter, uint32_t count) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
+    if (__lane_id() == 0 && count != 0u) atomicAdd(counter, count);
+}
+
 __device__ __forceinline__ void wave_append(uint64_t *__restrict__ list, uint32_t *tail,
                                             uint32_t cap, uint32_t *overflow, uint64_t item,
                                             bool pred) {

@@ -10,15 +10,17 @@
 //
 // Per round r, with U the unsettled vertices as (v, target) pairs:
 //   count    cnt[t] += 1 for every arrow of U into an unsettled target t
-//            (merged into the draw pass in round 0)
+//            (merged into the first-arrow pass in round 0)
 //   level 0  v with cnt[v] == 0 starts the peel list
 //   peel     a peeled x decrements cnt[target(x)]; the one that drops it to 0
 //            appends (target, its own target) to the list (a global load of
 //            the target's tree word); levels of at most 64 vertices (the long
 //            tail) are peeled by one wave without workgroup barriers
-//   sweep    peel levels in reverse: x is settled when its target is
-//   redraw   what is left with cnt[v] == 1 lies on a cycle: v draws its next
-//            arrow (cnt[v] back to 0); vertices hanging off a cycle keep theirs
+//   sweep    peel levels in reverse: x is settled when its target is, else it
+//            hangs off a cycle, keeps its arrow and joins the next U
+//   cycles   unsettled vertices with cnt[v] != 0 (found by scanning the
+//            settled bitmap and the fields) were never peeled: they lie on a
+//            cycle and draw their next arrow (cnt[v] back to 0)
 // A count is exact for every unsettled vertex: after the peel, peeled
 // vertices are at 0 and cycle vertices at 1 (one arrow from the cycle, a
 // functional graph's leftover after Kahn peeling is a union of cycles), so
@@ -30,11 +32,12 @@
 // leaves room to carry each vertex's draw count k_v with its arrow:
 //   word[v]  u64 global  internal target | original target << 18 | k_v << 36
 //                        (u* = n in both numberings)
-//   lists    u64 global  v | internal target << 18 | k_v << 36: two unsettled
-//                        lists and the peel order (k unused there)
+//   lists    u64 global  v | internal target << 18: two unsettled lists and
+//                        the peel order (reused for the cycle list)
 //   levels   u32 global  peel level boundaries
 //   LDS      count fields (4/8/16/32 bits by class), then the settled bitmap
-// so redrawing a cycle vertex touches no per-vertex array besides its word.
+// so redrawing a cycle vertex touches no per-vertex array besides its word
+// (whose k_v it reads, except in round 0, where every k_v is 1).
 // Isolated vertices (internal ids [n3, n)) take no part in the rounds: only
 // the output visits them.
 #include "fc_kernels.hpp"
@@ -61,8 +64,8 @@ __device__ __forceinline__ uint64_t pack(uint32_t lo, uint32_t mid, uint32_t k) 
 }
 
 // Per-phase clock sums: first arrows, in-arrow count + peel level 0, wide peel
-// levels, narrow (single-wave) peel levels, reverse sweep, split of the
-// unsettled list, cycle popping, output.
+// levels, narrow (single-wave) peel levels, reverse sweep (with the next
+// unsettled list), cycle scan, cycle popping, output.
 enum Phase : int { kPhDraw0 = 0, kPhLevel0, kPhPeel, kPhTail, kPhSweep, kPhSplit, kPhCycles,
                    kPhOutput, kPhCount };
 
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                         if (live[q]) count_add(f_lo(w[q]));
                         else set_settled(v);
                     }
-                    w[q] = pack(v, f_lo(w[q]), 1u);
+                    w[q] = pack(v, f_lo(w[q]), 0u);
                 }
                 wave_append_many<kR>(listA, &s_u, n, &s_over, w, live);
             }
@@ -230,21 +233,17 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 const uint32_t v = base + q * T + lane;
                 w[q] = v < nl ? draw(job, r[q], a.key0, a.key1, 0u, t) : pack(n, n, 0u);
             }
-#pragma unroll
-            for (int q = 0; q < kRD; ++q) {
-                const uint32_t v = base + q * T + lane;
-                if (v < nl) {
-                    word[v] = w[q];
-                    if (f_lo(w[q]) == n) set_settled(v);
-                    else count_add(f_lo(w[q]));
-                }
-            }
             bool live[kRD];
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
                 live[q] = v < nl && f_lo(w[q]) != n;
-                w[q] = pack(v, f_lo(w[q]), 1u);
+                if (v < nl) {
+                    word[v] = w[q];
+                    if (live[q]) count_add(f_lo(w[q]));
+                    else set_settled(v);
+                }
+                w[q] = pack(v, f_lo(w[q]), 0u);
             }
             wave_append_many<kRD>(listA, &s_u, n, &s_over, w, live);
 #pragma unroll
@@ -257,14 +256,14 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
         uint64_t *U = listA, *Unext = listB;
         unsigned long long draws = n;
         uint32_t rounds = 0;
-        bool counted = true;
 
         while (ucount > 0) {
             if (++rounds > a.max_rounds || draws > job.step_cap || s_over) {
                 err |= kErrStepCap;
                 break;
             }
-            if (!counted) {
+            const bool first = rounds == 1;
+            if (!first) {
                 for (uint32_t base = tid; base < ucount; base += kR * T) {
                     uint32_t tg[kR];
 #pragma unroll
@@ -278,21 +277,20 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 }
                 __syncthreads();
             }
-            counted = false;
             // level 0 of the peel: no in-arrows (s_p is 0 here: reset at the
-            // tree's start and in the split phase, both before a barrier)
+            // tree's start and before the sweep, both followed by a barrier)
             for (uint32_t base = wave_base; base < ucount; base += kR * T) {
                 uint64_t it[kR];
                 bool leaf[kR];
 #pragma unroll
                 for (int q = 0; q < kR; ++q) {
                     const uint32_t i = base + q * T + lane;
-                    it[q] = i < ucount ? U[i] : 0ull;
+                    it[q] = i < ucount ? U[i] : pack(n, n, 0u);
                 }
 #pragma unroll
                 for (int q = 0; q < kR; ++q) {
-                    const uint32_t i = base + q * T + lane;
-                    leaf[q] = i < ucount && count_of(f_lo(it[q])) == 0u;
+                    const uint32_t v = f_lo(it[q]);
+                    leaf[q] = v < nl && count_of(v) == 0u;
                 }
                 wave_append_many<kR>(peel, &s_p, n, &s_over, it, leaf);
             }
@@ -388,8 +386,19 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 ucount = 0;
                 break;
             }
-            // reverse sweep; the narrow tail levels first, by wave 0 alone (level
-            // boundaries fetched 63 at a time), then the wide ones
+            // every wave has read s_p and s_nlev: reset the list tails (the next
+            // unsettled list, the cycle list, the next round's peel)
+            __syncthreads();
+            if (tid == 0) {
+                s_u = 0;
+                s_cycles = 0;
+                s_p = 0;
+            }
+            __syncthreads();
+            // reverse sweep: a peeled vertex is settled when its target is; the
+            // others hang off a cycle, keep their arrow and go to the next
+            // unsettled list.  The narrow tail levels first, by wave 0 alone
+            // (level boundaries fetched 63 at a time), then the wide ones.
             if (wave_base == 0 && nlev > tail0) {
                 for (int32_t top = static_cast<int32_t>(nlev) - 1; top >= static_cast<int32_t>(tail0);
                      top -= 63) {
@@ -398,10 +407,14 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     const int32_t levels = min(63, top - static_cast<int32_t>(tail0) + 1);
                     for (int32_t j = 0; j < levels; ++j) {
                         const uint32_t a1 = __shfl(bnd, j, 64), a0 = __shfl(bnd, j + 1, 64);
+                        uint64_t p = pack(n, n, 0u);
+                        bool hang = false;
                         if (lane < a1 - a0) {
-                            const uint64_t p = peel[a0 + lane];
+                            p = peel[a0 + lane];
                             if (is_settled(f_mid(p))) set_settled(f_lo(p));
+                            else hang = true;
                         }
+                        wave_append(Unext, &s_u, n, &s_over, p, hang);
                         wave_sync();
                     }
                 }
@@ -409,51 +422,57 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             __syncthreads();
             for (int32_t Lv = static_cast<int32_t>(tail0) - 1; Lv >= 0; --Lv) {
                 const uint32_t a0 = uniform(lvl[Lv]), a1 = uniform(lvl[Lv + 1]);
-                for (uint32_t base = a0 + tid; base < a1; base += kR * T) {
+                for (uint32_t base = a0 + wave_base; base < a1; base += kR * T) {
                     uint64_t p[kR];
+                    bool hang[kR];
 #pragma unroll
                     for (int q = 0; q < kR; ++q) {
-                        const uint32_t i = base + q * T;
+                        const uint32_t i = base + q * T + lane;
                         p[q] = i < a1 ? peel[i] : pack(n, n, 0u);
                     }
 #pragma unroll
-                    for (int q = 0; q < kR; ++q)
-                        if (f_lo(p[q]) < n && is_settled(f_mid(p[q]))) set_settled(f_lo(p[q]));
+                    for (int q = 0; q < kR; ++q) {
+                        hang[q] = false;
+                        if (f_lo(p[q]) < n) {
+                            if (is_settled(f_mid(p[q]))) set_settled(f_lo(p[q]));
+                            else hang[q] = true;
+                        }
+                    }
+                    wave_append_many<kR>(Unext, &s_u, n, &s_over, p, hang);
                 }
                 __syncthreads();
             }
             mark(kPhSweep);
-            // split the unsettled vertices: hanging ones keep their arrow (next
-            // list), cycle vertices (count 1) go to a cycle list in the dead peel
-            // buffer
-            if (tid == 0) {
-                s_u = 0;
-                s_cycles = 0;
-                s_p = 0;  // for the next round's peel (last read before the sweep)
-            }
-            __syncthreads();
+            // the cycle vertices: unsettled and never peeled, i.e. an in-arrow
+            // count left (1: the arrow of the cycle predecessor), found by a scan
+            // of the settled bitmap and the fields, in id order, into the dead
+            // peel buffer
             uint64_t *__restrict__ cyc = peel;
-            for (uint32_t base = wave_base; base < ucount; base += kR * T) {
-                uint64_t it[kR];
-                bool keep[kR], pop[kR];
-#pragma unroll
-                for (int q = 0; q < kR; ++q) {
-                    const uint32_t i = base + q * T + lane;
-                    it[q] = i < ucount ? U[i] : pack(n, n, 0u);
+            const uint32_t nbw = (nl + 31u) >> 5;
+            for (uint32_t wb = wave_base; wb < nbw; wb += T) {
+                const uint32_t wi = wb + lane;
+                uint32_t m = 0;
+                if (wi < nbw) {
+                    m = ~bits[wi];
+                    if (wi == nbw - 1u && (nl & 31u)) m &= (1u << (nl & 31u)) - 1u;
                 }
+                while (__ballot(m != 0u)) {
+                    uint64_t e[kR];
+                    bool pop[kR];
 #pragma unroll
-                for (int q = 0; q < kR; ++q) {
-                    const uint32_t v = f_lo(it[q]);
-                    const bool live = !is_settled(v);
-                    pop[q] = live && count_of(v) != 0u;
-                    keep[q] = live && !pop[q];
+                    for (int q = 0; q < kR; ++q) {
+                        const uint32_t v = m != 0u ? (wi << 5) + static_cast<uint32_t>(__builtin_ctz(m)) : 0u;
+                        pop[q] = m != 0u && count_of(v) != 0u;
+                        e[q] = pack(v, 0u, 0u);
+                        m &= m - 1u;
+                    }
+                    wave_append_many<kR>(cyc, &s_cycles, n, &s_over, e, pop);
                 }
-                wave_append_many<kR>(Unext, &s_u, n, &s_over, it, keep);
-                wave_append_many<kR>(cyc, &s_cycles, n, &s_over, it, pop);
             }
             __syncthreads();
             mark(kPhSplit);
-            // pop every cycle: each cycle vertex draws its next arrow
+            // pop every cycle: each cycle vertex draws its next arrow (in round 0
+            // every vertex has drawn once; later the count is in its word)
             const uint32_t ccount = min(uniform(s_cycles), n);
             for (uint32_t base = wave_base; base < ccount; base += kRC * T) {
                 uint32_t v[kRC], k[kRC];
@@ -462,10 +481,12 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < kRC; ++q) {
                     const uint32_t i = base + q * T + lane;
-                    const uint64_t e = i < ccount ? cyc[i] : pack(n, n, 0u);
-                    v[q] = f_lo(e);
-                    k[q] = f_k(e);
-                    if (v[q] < n) r[q] = load_vrec(job.vrec, v[q]);
+                    v[q] = i < ccount ? f_lo(cyc[i]) : n;
+                    k[q] = 1u;
+                    if (v[q] < n) {
+                        r[q] = load_vrec(job.vrec, v[q]);
+                        if (!first) k[q] = f_k(word[v[q]]);
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < kRC; ++q) {
@@ -475,18 +496,18 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     }
                     w[q] = v[q] < n ? draw(job, r[q], a.key0, a.key1, k[q], t) : pack(n, n, 0u);
                 }
+                bool live[kRC];
 #pragma unroll
                 for (int q = 0; q < kRC; ++q) {
+                    live[q] = v[q] < n && f_lo(w[q]) != n;
                     if (v[q] < n) {
                         (void)count_dec(v[q]);  // the cycle's arrow into v is gone
                         word[v[q]] = w[q];
-                        if (f_lo(w[q]) == n) set_settled(v[q]);
+                        if (!live[q]) set_settled(v[q]);
                     }
+                    w[q] = pack(v[q], f_lo(w[q]), 0u);
                 }
-#pragma unroll
-                for (int q = 0; q < kRC; ++q)
-                    wave_append(Unext, &s_u, n, &s_over, pack(v[q], f_lo(w[q]), f_k(w[q])),
-                                v[q] < n && f_lo(w[q]) != n);
+                wave_append_many<kRC>(Unext, &s_u, n, &s_over, w, live);
             }
             __syncthreads();
             mark(kPhCycles);
