@@ -379,9 +379,10 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
             if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
             // first arrows of all trees drawn ahead by one vertex-major kernel when
-            // every tree's words fit the budget (the trees then work in place)
+            // every tree's words fit the budget (the trees then work in place);
+            // below 16384 vertices a tree's own first pass is too short to gain
             const size_t pre_bytes = 8u * n * static_cast<size_t>(tree_count);
-            const bool predraw = ctx->lds_predraw_mib != 0 && cb[3] > 0 &&
+            const bool predraw = ctx->lds_predraw_mib != 0 && cb[3] >= kPredrawMinVertices &&
                                  pre_bytes <= (static_cast<size_t>(ctx->lds_predraw_mib) << 20);
             if ((!predraw && (rc = ensure(ctx, ctx->cword, 8u * n * slots, "tree words"))) ||
                 (predraw && (rc = ensure(ctx, ctx->cpre, pre_bytes, "pre-drawn tree words"))) ||

@@ -69,6 +69,8 @@ namespace fc_host {
 
 // static LDS of the LDS-counter kernel (item, tails, totals, phase clocks) with margin
 constexpr size_t kLdsStaticBytes = 1024;
+// fewest non-isolated vertices for which the LDS sampler draws first arrows ahead
+constexpr uint32_t kPredrawMinVertices = 16384;
 
 int set_err(fc_ctx *ctx, int code, const std::string &msg);
 int hip_fail(fc_ctx *ctx, hipError_t e, const char *what);

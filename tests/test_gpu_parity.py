@@ -247,22 +247,28 @@ def test_lds_launch_shapes_bit_exact(gpu_lib, threads, wg):
 def test_lds_first_arrows_drawn_ahead_or_in_place(gpu_lib, mib):
     """The LDS sampler's first arrows, drawn by the vertex-major pre-draw
     kernel (the default when every tree's words fit the budget) or by each
-    tree's workgroup (budget 0, or too small: 40 trees of 20000 vertices need
-    6.1 MiB, more than 1 MiB), give the oracle's trees."""
+    tree's workgroup (budget 0, a budget too small: 40 trees of 20000 vertices
+    need 6.1 MiB, more than 1 MiB, or fewer than 16384 non-isolated vertices),
+    give the oracle's trees."""
     fc = gpu_lib
     fc.set_option("lds_predraw_mib", mib)
 
-    def drawn_ahead(n, trees):
-        return mib > 0 and 8 * n * trees <= mib << 20
+    def drawn_ahead(g, trees):
+        non_isolated = int((np.diff(g.row_ptr) > 0).sum())
+        return mib > 0 and non_isolated >= 16384 and 8 * g.n * trees <= mib << 20
 
     try:
         g = inputs.barabasi_albert(20_000, 3, 7)
         got, _ = _compare(fc, g, 1.5, 77, 9, 40, sampler="lds")
-        assert (got["stats"]["ms_predraw"] > 0.0) == drawn_ahead(g.n, 40)
+        assert (got["stats"]["ms_predraw"] > 0.0) == drawn_ahead(g, 40)
         # isolated vertices and a tree range not starting at 0
-        g2 = inputs.rmat(3000, 8, 5)
-        got, _ = _compare(fc, g2, 0.3, 5, 1000, 33, stream=7, sampler="lds")
-        assert (got["stats"]["ms_predraw"] > 0.0) == drawn_ahead(g2.n, 33)
+        g2 = inputs.rmat(40_000, 8, 5)
+        got, _ = _compare(fc, g2, 0.3, 5, 1000, 6, stream=7, sampler="lds")
+        assert (got["stats"]["ms_predraw"] > 0.0) == drawn_ahead(g2, 6)
+        # too small to draw ahead
+        g3 = inputs.rmat(3000, 8, 5)
+        got, _ = _compare(fc, g3, 0.3, 5, 1000, 33, stream=7, sampler="lds")
+        assert got["stats"]["ms_predraw"] == 0.0
     finally:
         fc.set_option("lds_predraw_mib", 16384)
 
