@@ -107,6 +107,9 @@ constexpr int kR = 8;
 constexpr int kRP = 4;  // wide peel levels (each item may add a random load)
 constexpr int kRD = 2;
 constexpr int kRC = 2;
+// Registers per lane that hold a batch of narrow peel levels for the sweep
+// (up to 64 kTailRegs entries).
+constexpr int kTailRegs = 6;
 
 __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_lds[];
@@ -405,12 +408,35 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     const int32_t li = top + 1 - static_cast<int32_t>(lane);  // lane j: lvl[top + 1 - j]
                     const uint32_t bnd = li >= static_cast<int32_t>(tail0) ? lvl[li] : 0u;
                     const int32_t levels = min(63, top - static_cast<int32_t>(tail0) + 1);
+                    // the batch's entries [A, B): in registers when they fit (entry
+                    // A + 64 s + lane in buf[s]), so each level waits for no load
+                    const uint32_t B = __shfl(bnd, 0, 64), A = __shfl(bnd, levels, 64);
+                    const bool inreg = B - A <= 64u * kTailRegs;
+                    uint64_t buf[kTailRegs];
+#pragma unroll
+                    for (int q = 0; q < kTailRegs; ++q) {
+                        const uint32_t i = A + 64u * q + lane;
+                        buf[q] = inreg && i < B ? peel[i] : pack(n, n, 0u);
+                    }
                     for (int32_t j = 0; j < levels; ++j) {
                         const uint32_t a1 = __shfl(bnd, j, 64), a0 = __shfl(bnd, j + 1, 64);
                         uint64_t p = pack(n, n, 0u);
-                        bool hang = false;
-                        if (lane < a1 - a0) {
+                        bool own = false;
+                        if (inreg) {  // a level has at most 64 entries: one per lane at most
+#pragma unroll
+                            for (int q = 0; q < kTailRegs; ++q) {
+                                const uint32_t i = A + 64u * q + lane;
+                                if (i >= a0 && i < a1) {
+                                    p = buf[q];
+                                    own = true;
+                                }
+                            }
+                        } else if (lane < a1 - a0) {
                             p = peel[a0 + lane];
+                            own = true;
+                        }
+                        bool hang = false;
+                        if (own) {
                             if (is_settled(f_mid(p))) set_settled(f_lo(p));
                             else hang = true;
                         }
