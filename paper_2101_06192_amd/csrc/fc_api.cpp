@@ -271,7 +271,6 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         if (use_hyb) {
             kname = "wilson_hyb";
             const size_t n = static_cast<size_t>(g.n);
-            const size_t nwords = (n + 31u) / 32u;
             if ((rc = ensure(ctx, ctx->rl_inv, 4u * n, "relabel inverse")) ||
                 (rc = ensure(ctx, ctx->rl_orig, 4u * n, "relabel ids")) ||
                 (rc = ensure(ctx, ctx->rl_vrec, sizeof(fc::VRec) * n, "relabelled records")) ||
@@ -288,7 +287,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                                                 static_cast<uint32_t>(g.n),
                                                 static_cast<fc::VRec *>(ctx->rl_vrec.ptr), ctx->stream),
                    "relabel records");
-            const size_t per_slot = (8u + 4u + 8u + 24u + 4u) * n + 8u + 4u * nwords;
+            const size_t per_slot = (8u + 4u + 8u + 24u + 4u) * n + 8u;
             slots = std::max<size_t>(1, ctx->state_budget / per_slot);
             slots = std::min<size_t>(slots, tree_count);
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
@@ -301,8 +300,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                 (rc = ensure(ctx, ctx->corigt, 4u * n * slots, "target ids")) ||
                 (rc = ensure(ctx, ctx->ckk, 8u * n * slots, "draw counts")) ||
                 (rc = ensure(ctx, ctx->clists, 24u * n * slots, "lists")) ||
-                (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")) ||
-                (rc = ensure(ctx, ctx->cbits, 4u * nwords * slots, "settled bitmap")))
+                (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")))
                 return rc;
             FC_HIP(ctx, hipMemsetAsync(ctx->ckk.ptr, 0, 8u * n * slots, ctx->stream),
                    "memset draw counts");
@@ -311,7 +309,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             c.kk = static_cast<uint64_t *>(ctx->ckk.ptr);
             c.lists = static_cast<uint64_t *>(ctx->clists.ptr);
             c.levels = static_cast<uint32_t *>(ctx->clevels.ptr);
-            c.bits = static_cast<uint32_t *>(ctx->cbits.ptr);
+            c.bits = nullptr;  // settled flags live in the tree words
             c.n_max = static_cast<uint32_t>(g.n);
             c.slots = static_cast<uint32_t>(slots);
             c.item_count = tree_count;

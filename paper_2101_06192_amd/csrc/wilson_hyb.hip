@@ -11,13 +11,13 @@
 // Isolated vertices (ids [n3, n)) take no part in the rounds.
 //
 // Memory per tree (slot), n vertices:
-//   word[v]   u64 global  internal target | in-arrow count << 32 (count used
+//   word[v]   u64 global  internal target | settled << 31 | in-arrow count << 32
+//                         (settled flag and count used for ids >= hot only;
 //                         for ids >= hot only)
 //   origt[v]  u32 global  original id of the target (outputs)
 //   kk[v]     u64 global  (epoch << 32) | k_v for redrawn vertices
 //   lists     u64 global  (v, internal target) pairs: two unsettled lists and
 //                         the peel order; peel level boundaries (u32)
-//   bits      global      settled bitmap of the ids >= hot
 //   LDS                   fields of the ids < hot, then their settled bitmap
 #include "fc_kernels.hpp"
 #include "fc_wave.hpp"
@@ -37,9 +37,6 @@ __device__ __forceinline__ uint64_t pair(uint32_t v, uint32_t tg) {
 __device__ __forceinline__ uint64_t wg_add(uint64_t *p, uint64_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void wg_or(uint32_t *p, uint32_t v) {
-    (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
 // Items per lane per pass iteration: streaming passes, wide peel levels (each
 // item may add a global atomic or load), passes that draw arrows.
@@ -47,6 +44,9 @@ constexpr int kR = 8;
 constexpr int kRP = 4;
 constexpr int kRD = 2;
 constexpr uint64_t kCntOne = 1ull << 32;
+// settled flag of an id >= hot: bit 31 of its tree word (targets are < 2^31)
+constexpr uint32_t kSettled = 1u << 31;
+__device__ __forceinline__ uint32_t tgt_of(uint64_t w) { return lo32(w) & ~kSettled; }
 
 enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedraw, kPhOutput,
                    kPhCount };
@@ -99,7 +99,6 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
     const uint32_t lane = tid & 63u;
     const size_t slot = blockIdx.x;
     const size_t stride = a.n_max;
-    const size_t bstride = (stride + 31u) >> 5;
     uint64_t *__restrict__ word = static_cast<uint64_t *>(a.word) + slot * stride;
     uint32_t *__restrict__ origt = a.origt + slot * stride;
     uint64_t *__restrict__ kk = a.kk + slot * stride;
@@ -107,7 +106,6 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
     uint64_t *__restrict__ listB = listA + stride;
     uint64_t *__restrict__ peel = listB + stride;
     uint32_t *__restrict__ lvl = a.levels + slot * (stride + 2);
-    uint32_t *__restrict__ gbits = a.bits + slot * bstride;
     unsigned int err = 0;
     uint32_t epoch = 0;
 
@@ -142,40 +140,59 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                            uniform(H.o1), uniform(H.o0)};
         uint32_t *__restrict__ hbits = s_lds + H.ob;
 
+        // Settled state: an LDS bit for ids < hot, bit 31 of the tree word for
+        // the others.  Counts of settled vertices are never read, so a count
+        // may change after its vertex settles: the count pass adds to ids >= hot
+        // without checking, and a peel decrement learns from the word it gets
+        // back whether the vertex had settled (the count field wraps harmlessly
+        // above the flag).
+        auto hot_settled = [&](uint32_t v) -> bool { return (hbits[v >> 5] >> (v & 31u)) & 1u; };
         auto is_settled = [&](uint32_t v) -> bool {
             if (v >= nl) return true;
-            if (v < hot) return (hbits[v >> 5] >> (v & 31u)) & 1u;
-            return (gbits[v >> 5] >> (v & 31u)) & 1u;
+            if (v < hot) return hot_settled(v);
+            return (lo32(word[v]) & kSettled) != 0u;
         };
-        auto set_settled = [&](uint32_t v) {
-            if (v < hot) atomicOr(&hbits[v >> 5], 1u << (v & 31u));
-            else wg_or(&gbits[v >> 5], 1u << (v & 31u));
+        // x (peeled, so its count is 0) settles; tx is its target
+        auto settle = [&](uint32_t x, uint32_t tx) {
+            if (x < hot) atomicOr(&hbits[x >> 5], 1u << (x & 31u));
+            else word[x] = tx | kSettled;
         };
-        auto count_add = [&](uint32_t v) {
-            if (v < hot) {
-                const Field f = hot_field(C, v);
-                atomicAdd(&s_lds[f.w], 1u << f.sh);
-            } else {
-                (void)wg_add(&word[v], kCntOne);
+        // an in-arrow into t from an unsettled vertex
+        auto count_arrow = [&](uint32_t t) {
+            if (t < hot) {
+                if (!hot_settled(t)) {
+                    const Field f = hot_field(C, t);
+                    atomicAdd(&s_lds[f.w], 1u << f.sh);
+                }
+            } else if (t < nl) {
+                (void)wg_add(&word[t], kCntOne);
             }
         };
-        auto count_of = [&](uint32_t v) -> uint32_t {
+        // one in-arrow of t removed: when t is unsettled and that was its last,
+        // returns the peel entry (t, target of t), else 0 (no entry is 0: t is
+        // never its own target)
+        auto peel_dec = [&](uint32_t t) -> uint64_t {
+            if (t < hot) {
+                if (hot_settled(t)) return 0ull;
+                const Field f = hot_field(C, t);
+                const uint32_t old = (atomicAdd(&s_lds[f.w], 0u - (1u << f.sh)) >> f.sh) & f.mask;
+                return old == 1u ? pair(t, tgt_of(word[t])) : 0ull;
+            }
+            if (t >= nl) return 0ull;
+            const uint64_t old = wg_add(&word[t], 0ull - kCntOne);
+            return (lo32(old) & kSettled) == 0u && hi32(old) == 1u ? pair(t, tgt_of(old)) : 0ull;
+        };
+        // whether unsettled v still has an in-arrow (a cycle vertex after the peel)
+        // and whether it is settled, from one look at its state
+        auto live_count = [&](uint32_t v, bool &live) -> uint32_t {
             if (v < hot) {
+                live = !hot_settled(v);
                 const Field f = hot_field(C, v);
                 return (s_lds[f.w] >> f.sh) & f.mask;
             }
-            return hi32(word[v]);
-        };
-        // one in-arrow of v removed; if it was the last, returns the peel entry
-        // (v, target of v), else 0 (no entry is 0: v is never its own target)
-        auto count_dec = [&](uint32_t v) -> uint64_t {
-            if (v < hot) {
-                const Field f = hot_field(C, v);
-                const uint32_t old = (atomicAdd(&s_lds[f.w], 0u - (1u << f.sh)) >> f.sh) & f.mask;
-                return old == 1u ? pair(v, lo32(word[v])) : 0ull;
-            }
-            const uint64_t old = wg_add(&word[v], 0ull - kCntOne);
-            return hi32(old) == 1u ? pair(v, lo32(old)) : 0ull;
+            const uint64_t w = word[v];
+            live = (lo32(w) & kSettled) == 0u;
+            return hi32(w);
         };
 
         ++epoch;
@@ -186,7 +203,6 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             s_roots = 0;
         }
         for (uint32_t i = tid; i < H.words; i += T) s_lds[i] = 0u;
-        for (uint32_t i = (hot >> 5) + tid; i < ((nl + 31u) >> 5); i += T) gbits[i] = 0u;
         __syncthreads();
 
         // round 0: the first arrow of every vertex that is not isolated
@@ -203,9 +219,10 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
                 if (v < nl) {
-                    word[v] = lo32(w[q]);
+                    const bool root = lo32(w[q]) == n;
+                    word[v] = lo32(w[q]) | (root ? kSettled : 0u);
                     origt[v] = hi32(w[q]);
-                    if (lo32(w[q]) == n) set_settled(v);
+                    if (root && v < hot) atomicOr(&hbits[v >> 5], 1u << (v & 31u));
                 }
                 live[q] = v < nl && lo32(w[q]) != n;
                 w[q] = pair(v, lo32(w[q]));
@@ -234,7 +251,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                 }
 #pragma unroll
                 for (int q = 0; q < kR; ++q)
-                    if (!is_settled(tg[q])) count_add(tg[q]);
+                    count_arrow(tg[q]);
             }
             if (tid == 0) s_p = 0;
             __syncthreads();
@@ -251,7 +268,8 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < kR; ++q) {
                     const uint32_t i = base + q * T + lane;
-                    leaf[q] = i < ucount && count_of(lo32(it[q])) == 0u;
+                    bool live = false;
+                    leaf[q] = i < ucount && live_count(lo32(it[q]), live) == 0u;
                 }
                 wave_append_many<kR>(peel, &s_p, n, &s_over, it, leaf);
             }
@@ -273,7 +291,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                     }
 #pragma unroll
                     for (int q = 0; q < kRP; ++q) {
-                        if (!is_settled(tg[q])) nx[q] = count_dec(tg[q]);
+                        nx[q] = peel_dec(tg[q]);
                         push[q] = nx[q] != 0ull;
                     }
                     wave_append_many<kRP>(peel, &s_p, n, &s_over, nx, push);
@@ -294,7 +312,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                         if (lane == 0) lvl[nl2 + 1] = pos;
                         const uint32_t tg = hi32(it);
                         uint64_t nx = 0ull;
-                        if (lane < cnt && !is_settled(tg)) nx = count_dec(tg);
+                        if (lane < cnt) nx = peel_dec(tg);
                         const bool push = nx != 0ull;
                         const uint64_t mask = __ballot(push);
                         const uint32_t m = static_cast<uint32_t>(__popcll(mask));
@@ -341,7 +359,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                         const uint32_t a1 = __shfl(bnd, j, 64), a0 = __shfl(bnd, j + 1, 64);
                         if (lane < a1 - a0) {
                             const uint64_t p = peel[a0 + lane];
-                            if (is_settled(hi32(p))) set_settled(lo32(p));
+                            if (is_settled(hi32(p))) settle(lo32(p), hi32(p));
                         }
                         wave_sync();
                     }
@@ -359,7 +377,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                     }
 #pragma unroll
                     for (int q = 0; q < kR; ++q)
-                        if (lo32(p[q]) < n && is_settled(hi32(p[q]))) set_settled(lo32(p[q]));
+                        if (lo32(p[q]) < n && is_settled(hi32(p[q]))) settle(lo32(p[q]), hi32(p[q]));
                 }
                 __syncthreads();
             }
@@ -383,8 +401,9 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < kR; ++q) {
                     const uint32_t v = lo32(it[q]);
-                    const bool live = !is_settled(v);
-                    pop[q] = live && count_of(v) != 0u;
+                    bool live = false;
+                    const uint32_t c = v < nl ? live_count(v, live) : 0u;
+                    pop[q] = live && c != 0u;
                     keep[q] = live && !pop[q];
                 }
                 wave_append_many<kR>(Unext, &s_u, n, &s_over, it, keep);
@@ -419,9 +438,11 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                             const Field f = hot_field(C, v[q]);
                             atomicAdd(&s_lds[f.w], 0u - (1u << f.sh));
                         }
-                        word[v[q]] = lo32(w[q]);  // (a global counter goes back to 0 with it)
+                        const bool root = lo32(w[q]) == n;
+                        // (a global counter goes back to 0 with it)
+                        word[v[q]] = lo32(w[q]) | (root ? kSettled : 0u);
                         origt[v[q]] = hi32(w[q]);
-                        if (lo32(w[q]) == n) set_settled(v[q]);
+                        if (root && v[q] < hot) atomicOr(&hbits[v[q] >> 5], 1u << (v[q] & 31u));
                     }
                 }
                 bool live[kRD];
@@ -451,7 +472,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
 #pragma unroll
             for (int q = 0; q < kO; ++q) {
                 const uint32_t v = base + q * T;
-                tgs[q] = v < nl ? lo32(word[v]) : 0u;
+                tgs[q] = v < nl ? tgt_of(word[v]) : 0u;
                 ovs[q] = v < nl ? job.orig[v] : 0u;
                 otgs[q] = v < nl ? origt[v] : 0u;
             }
