@@ -380,10 +380,13 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             // every tree's words fit the budget (the trees then work in place);
             // below 16384 vertices a tree's own first pass is too short to gain
             const size_t pre_bytes = 8u * n * static_cast<size_t>(tree_count);
-            const bool predraw = ctx->lds_predraw_mib != 0 && cb[3] >= kPredrawMinVertices &&
-                                 pre_bytes <= (static_cast<size_t>(ctx->lds_predraw_mib) << 20);
+            bool predraw = ctx->lds_predraw_mib != 0 && cb[3] >= kPredrawMinVertices &&
+                           pre_bytes <= (static_cast<size_t>(ctx->lds_predraw_mib) << 20);
+            if (predraw && ensure(ctx, ctx->cpre, pre_bytes, "pre-drawn tree words") != FC_OK) {
+                predraw = false;  // not enough device memory: each tree draws its own
+                ctx->last_error.clear();
+            }
             if ((!predraw && (rc = ensure(ctx, ctx->cword, 8u * n * slots, "tree words"))) ||
-                (predraw && (rc = ensure(ctx, ctx->cpre, pre_bytes, "pre-drawn tree words"))) ||
                 (rc = ensure(ctx, ctx->clists, 24u * n * slots, "lists")) ||
                 (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")))
                 return rc;
