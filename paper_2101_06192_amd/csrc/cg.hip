@@ -40,21 +40,25 @@ __device__ __forceinline__ void row_range(uint32_t kk, uint32_t *first_group, ui
     (void)kk;
 }
 
-// sum over the neighbours u of v of X[u][col], four independent gathers in flight.
+// sum over the neighbours u of v of X[u][col], eight independent gathers in
+// flight (fixed association: deterministic).
 template <typename T>
 __device__ __forceinline__ T neighbour_sum(const int32_t *__restrict__ col_idx, int32_t b, int32_t e,
                                            const T *__restrict__ X, uint32_t k, uint32_t col) {
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    constexpr int U = 8;
+    T s[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) s[i] = T(0);
     int32_t q = b;
-    for (; q + 4 <= e; q += 4) {
-        const int32_t u0 = col_idx[q], u1 = col_idx[q + 1], u2 = col_idx[q + 2], u3 = col_idx[q + 3];
-        s0 += X[static_cast<size_t>(u0) * k + col];
-        s1 += X[static_cast<size_t>(u1) * k + col];
-        s2 += X[static_cast<size_t>(u2) * k + col];
-        s3 += X[static_cast<size_t>(u3) * k + col];
+    for (; q + U <= e; q += U) {
+        int32_t u[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) u[i] = col_idx[q + i];
+#pragma unroll
+        for (int i = 0; i < U; ++i) s[i] += X[static_cast<size_t>(u[i]) * k + col];
     }
-    for (; q < e; ++q) s0 += X[static_cast<size_t>(col_idx[q]) * k + col];
-    return (s0 + s1) + (s2 + s3);
+    for (int i = 0; q < e; ++q, ++i) s[i] += X[static_cast<size_t>(col_idx[q]) * k + col];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // Block-level per-column reduction of `acc` into partial[blockIdx.x * k + col].
@@ -133,14 +137,34 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const int32_t *__res
     if (partial_bb) block_column_sum(bb, ln, k, partial_bb, lds);
 }
 
-// out[j] = sum over blocks of partial[b * k + j], in block order (deterministic).
-__global__ void reduce_kernel(const double *__restrict__ partial, uint32_t blocks, uint32_t k,
-                              double *__restrict__ out) {
-    const uint32_t j = threadIdx.x;
-    if (j >= k) return;
-    double s = 0.0;
-    for (uint32_t b = 0; b < blocks; ++b) s += partial[static_cast<size_t>(b) * k + j];
-    out[j] = s;
+// out[j] = sum over blocks of partial[b * k + j] in a fixed order (deterministic):
+// thread (g, j) of kReduceGroups groups sums blocks b = g (mod kReduceGroups) in
+// four interleaved accumulators, then group sums are added in group order.
+constexpr int kReduceGroups = 16;
+__global__ __launch_bounds__(64 * kReduceGroups) void reduce_kernel(const double *__restrict__ partial,
+                                                                   uint32_t blocks, uint32_t k,
+                                                                   double *__restrict__ out) {
+    __shared__ double s_sum[kReduceGroups][64];
+    const uint32_t j = threadIdx.x & 63u, g = threadIdx.x >> 6;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (j < k) {
+        constexpr uint32_t G = kReduceGroups;
+        uint32_t b = g;
+        for (; b + 3u * G < blocks; b += 4u * G) {
+            a0 += partial[static_cast<size_t>(b) * k + j];
+            a1 += partial[static_cast<size_t>(b + G) * k + j];
+            a2 += partial[static_cast<size_t>(b + 2u * G) * k + j];
+            a3 += partial[static_cast<size_t>(b + 3u * G) * k + j];
+        }
+        for (; b < blocks; b += G) a0 += partial[static_cast<size_t>(b) * k + j];
+    }
+    s_sum[g][j] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (g == 0 && j < k) {
+        double t = 0.0;
+        for (uint32_t q = 0; q < kReduceGroups; ++q) t += s_sum[q][j];
+        out[j] = t;
+    }
 }
 
 // Inner CG start on the scaled residual: r = R64 / scale_j (as T), d = 0,
@@ -312,20 +336,20 @@ hipError_t cg_inner(const CgWork &w, uint32_t max_iters, uint32_t poll, uint32_t
     // start: r = R64 / scale, z = Minv r, p = z, d = 0; rz = r.z; rr = |r|^2
     start_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, n, k, w.alpha, w.R64, w.scale, r, z,
                                                      p, d, w.partial_a, w.partial_b);
-    reduce_kernel<<<1, 64, 0, stream>>>(w.partial_a, blocks, k, rzn);
-    reduce_kernel<<<1, 64, 0, stream>>>(w.partial_b, blocks, k, rr);
+    reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, k, rzn);
+    reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_b, blocks, k, rr);
     scalars_kernel<<<1, 64, 0, stream>>>(0, k, S, w.any);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     uint32_t it = 0;
     while (it < max_iters) {
         apply_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.col_idx, n, k, w.alpha, p, q,
                                                          w.partial_a);
-        reduce_kernel<<<1, 64, 0, stream>>>(w.partial_a, blocks, k, pq);
+        reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, k, pq);
         scalars_kernel<<<1, 64, 0, stream>>>(1, k, S, nullptr);
         update_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, n, k, w.alpha, step, p, q, d, r,
                                                           z, w.partial_a, w.partial_b);
-        reduce_kernel<<<1, 64, 0, stream>>>(w.partial_a, blocks, k, rzn);
-        reduce_kernel<<<1, 64, 0, stream>>>(w.partial_b, blocks, k, rr);
+        reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, k, rzn);
+        reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_b, blocks, k, rr);
         scalars_kernel<<<1, 64, 0, stream>>>(2, k, S, w.any);
         direction_kernel<T><<<blocks, kThreads, 0, stream>>>(n, k, beta, z, p);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -351,8 +375,8 @@ hipError_t cg_residual(const CgWork &w, bool with_b, hipStream_t stream) {
     residual_kernel<<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.col_idx, w.n, w.k, w.alpha, w.B,
                                                      w.X, w.R64, w.partial_a,
                                                      with_b ? w.partial_b : nullptr);
-    reduce_kernel<<<1, 64, 0, stream>>>(w.partial_a, blocks, w.k, w.res_rr);
-    if (with_b) reduce_kernel<<<1, 64, 0, stream>>>(w.partial_b, blocks, w.k, w.res_bb);
+    reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, w.k, w.res_rr);
+    if (with_b) reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_b, blocks, w.k, w.res_bb);
     return hipGetLastError();
 }
 
