@@ -7,6 +7,9 @@ benchmark times, on outputs the oracle can recompute one by one.
 - R-MAT 2^22, 1024 trees: per-tree digests of three trees against the
   oracle, and the estimate of Omega_vv against CG on sampled vertices
   within the Hoeffding radius.
+- 1000 x 1000 grid with 12% of the edges removed, 1024 trees at alpha = 1
+  and 2: per-tree digests and walk steps of sampled trees against the oracle.
+(BA(200000, 5) with 4096 trees is in test_gpu_parity.py.)
 """
 import sys
 
@@ -68,3 +71,19 @@ def test_rmat22_digests_and_estimate(gpu_lib):
     om = oracle.omega_diag_cg(g, 1.0, vs, rtol=1e-9)
     # Hoeffding radius at delta = 1e-6 over the sampled vertices, 1024 trees
     assert np.abs(R[vs] / 1024 - om).max() < np.sqrt(np.log(2 * len(vs) / 1e-6) / (2 * 1024))
+
+
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_grid_full_size_sampled(gpu_lib, alpha):
+    fc = gpu_lib
+    g = inputs.grid_removed(1000, 1000, 0.12, 0)
+    dg = fc.to_device(g)
+    got = fc.sample(dg, alpha=alpha, seed=0, tree_begin=0, tree_count=1024, want_digests=True,
+                    want_steps=True, trusted=True)
+    _say(f"grid alpha={alpha}: sampler={got['stats']['sampler']} ms={got['stats']['ms_sample']:.1f}")
+    assert got["stats"]["sampler"] == "wilson_coop"
+    for t in (0, 1023):
+        ref = oracle.sample(g, alpha, 0, t, 1)
+        assert got["tree_digests"][t] == ref.digests[0], t
+        assert got["tree_steps"][t] == ref.steps[0], t
+    assert int(got["root_counts"].astype(np.int64).sum()) == got["stats"]["roots"]

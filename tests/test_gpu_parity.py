@@ -380,6 +380,8 @@ def test_ba200k_full_run_sampled(gpu_lib):
     got = fc.sample(dg, alpha=1.0, seed=0, tree_begin=0, tree_count=4096, want_digests=True,
                     want_steps=True, trusted=True)
     _say(f"full run sampler={got['stats']['sampler']} ms={got['stats']['ms_sample']:.1f}")
+    # the benchmark's launch: LDS counters, first arrows drawn ahead
+    assert got["stats"]["sampler"] == "wilson_lds" and got["stats"]["ms_predraw"] > 0.0
     for t in (0, 1, 777, 2048, 4095):
         ref = oracle.sample(g, 1.0, 0, t, 1)
         assert got["tree_digests"][t] == ref.digests[0], t
