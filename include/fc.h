@@ -88,10 +88,12 @@ extern "C" {
 #define FC_FLAG_SAMPLER_HYB 32  /* force the hybrid workgroup-per-tree sampler: counters and
                                    settled bits of the highest-degree vertices in LDS, the
                                    rest in global memory */
-/* No sampler flag: the library picks lane or workgroup from n and the tree
- * count, and for the workgroup sampler LDS counters whenever they fit, else
- * the hybrid (both behind option "coop_lds_counts").  All samplers produce
- * identical results (same trees, same counts). */
+/* No sampler flag: a workgroup-per-tree sampler, with LDS counters whenever
+ * one tree's counters and settled bitmap fit; else with global counters when
+ * the settled bitmap alone fits in LDS; else the hybrid (option
+ * "coop_lds_counts" = 0: global counters throughout).  The lane sampler runs
+ * only on request.  All samplers produce identical results (same trees, same
+ * counts). */
 
 typedef struct fc_ctx fc_ctx;
 

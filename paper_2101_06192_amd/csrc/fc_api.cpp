@@ -181,8 +181,9 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     else if (p->flags & FC_FLAG_SAMPLER_LDS) mode = 3;
     else if (p->flags & FC_FLAG_SAMPLER_HYB) mode = 4;
     else mode = ctx->force_sampler;
-    const bool use_coop = mode == 0 ? tree_count < 16u * ctx->cu_count * 64u / 4u || g.n >= 65536
-                                    : mode >= 2;
+    // automatically always a workgroup sampler: measured, the LDS-counter one beats
+    // the lane-per-tree walk even with 2^18 trees of a 1000-vertex graph
+    const bool use_coop = mode == 0 || mode >= 2;
     // expected steps per tree are at most n + 2 alpha m; a valid run never
     // comes near 256 times that, so exceeding it marks a fault, not bad luck
     const double cap = 256.0 * (static_cast<double>(g.n) + p->alpha * static_cast<double>(g.nnz)) +
