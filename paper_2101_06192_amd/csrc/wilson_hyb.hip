@@ -205,15 +205,28 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
         for (uint32_t i = tid; i < H.words; i += T) s_lds[i] = 0u;
         __syncthreads();
 
-        // round 0: the first arrow of every vertex that is not isolated
+        // round 0: the first arrow of every vertex that is not isolated (records
+        // loaded one iteration ahead: one dependent global load per iteration)
+        VRec r[kRD] = {};
+#pragma unroll
+        for (int q = 0; q < kRD; ++q) {
+            const uint32_t v = wave_base + q * T + lane;
+            if (v < nl) r[q] = load_vrec(job.vrec, v);
+        }
         for (uint32_t base = wave_base; base < nl; base += kRD * T) {
             uint64_t w[kRD];
             bool live[kRD];
+            VRec rn[kRD] = {};
+#pragma unroll
+            for (int q = 0; q < kRD; ++q) {
+                const uint32_t v = base + (kRD + q) * T + lane;
+                if (v < nl) rn[q] = load_vrec(job.vrec, v);
+            }
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
                 w[q] = pair(n, n);
-                if (v < nl) w[q] = draw(job, load_vrec(job.vrec, v), a.key0, a.key1, 0u, t);
+                if (v < nl) w[q] = draw(job, r[q], a.key0, a.key1, 0u, t);
             }
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
@@ -228,6 +241,8 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                 w[q] = pair(v, lo32(w[q]));
             }
             wave_append_many<kRD>(listA, &s_u, n, &s_over, w, live);
+#pragma unroll
+            for (int q = 0; q < kRD; ++q) r[q] = rn[q];
         }
         __syncthreads();
         mark(kPhDraw0);
@@ -279,15 +294,22 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             if (tid == 0) lvl[0] = 0;
             while (hi - lo > 64u) {
                 if (tid == 0) lvl[nlev + 1] = hi;
+                // (entries loaded one iteration ahead; those appended meanwhile
+                // lie beyond hi)
+                uint32_t tg[kRP];
+#pragma unroll
+                for (int q = 0; q < kRP; ++q) {
+                    const uint32_t i = lo + wave_base + q * T + lane;
+                    tg[q] = i < hi ? hi32(peel[i]) : n;
+                }
                 for (uint32_t base = lo + wave_base; base < hi; base += kRP * T) {
-                    uint32_t tg[kRP];
+                    uint32_t tgn[kRP];
                     uint64_t nx[kRP];
                     bool push[kRP];
 #pragma unroll
                     for (int q = 0; q < kRP; ++q) {
-                        const uint32_t i = base + q * T + lane;
-                        tg[q] = i < hi ? hi32(peel[i]) : n;
-                        nx[q] = 0ull;
+                        const uint32_t i = base + (kRP + q) * T + lane;
+                        tgn[q] = i < hi ? hi32(peel[i]) : n;
                     }
 #pragma unroll
                     for (int q = 0; q < kRP; ++q) {
@@ -295,6 +317,8 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                         push[q] = nx[q] != 0ull;
                     }
                     wave_append_many<kRP>(peel, &s_p, n, &s_over, nx, push);
+#pragma unroll
+                    for (int q = 0; q < kRP; ++q) tg[q] = tgn[q];
                 }
                 __syncthreads();
                 ++nlev;
