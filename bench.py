@@ -334,13 +334,22 @@ def other_config(args, fc, inputs, dev):
                 fc.sample(j["graph"], alpha=j["alpha"], seed=0, tree_count=512,
                           stream_id=j["stream_id"], device=dev, as_torch=True, trusted=True)
         dt_single, _ = _timed(per_job, 1, 0)
+        # the Wilson model's bytes (as for the single-graph line) over the batch kernel's time
+        vertex_trees = 512 * len(alphas) * int(sum(g.n for g in gs))
+        alg = (BYTES_STEP * st["walk_steps"] + (BYTES_RETRACE + BYTES_SCAN) * vertex_trees
+               + BYTES_ROOT * st["roots"])
+        ach = alg / (st["ms_sample"] / 1000.0) / 1e9
         res.update({"value": ntrees / dt, "unit": "trees/s",
                     "config": {"workload": "rmat_batch_256graphs_alpha0.1_1_10_trees512",
                                "graphs": len(gs), "sum_n": int(sum(g.n for g in gs)),
                                "sum_m": int(sum(g.m for g in gs)), "jobs": len(jobs), "trees": ntrees},
                     "batched": {"ms_per_run": 1000 * dt, "kernel_ms": st["ms_sample"],
                                 "launch_shape": st["sampler"], "walk_steps_per_s": st["walk_steps"] / dt,
-                                "create_s": create_s},
+                                "create_s": create_s,
+                                "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                             "algorithmic_bytes_per_launch": alg,
+                                             "kernel": "wilson_lds_kernel (launch groups)"}},
                     "per_job_launches": {"ms_total": 1000 * dt_single, "trees_per_s": ntrees / dt_single},
                     "generation_s": gen_s})
         b.close()
@@ -356,8 +365,17 @@ def other_config(args, fc, inputs, dev):
             dt, out = _timed(lambda: fc.solve(dg, 1.0, B, rtol=1e-9, precision=prec, device=dev,
                                               trusted=True, as_torch=True), args.steps, args.warmup)
             sols[prec] = out["X"]
+            # bytes of the inner iterations alone (gathered neighbour rows + 12 streamed
+            # n x k arrays per iteration: apply, update, direction) over the whole leg,
+            # residuals and refinement included in the time: a lower bound on the rate
+            es = 8 if prec == "fp64" else 4
+            alg = out["iters"] * (2 * g.m * k * es + 12 * g.n * k * es)
+            ach = alg / dt / 1e9
             legs[prec] = {"ms": 1000 * dt, "inner_iters": out["iters"],
-                          "max_relres": float(out["relres"].max())}
+                          "max_relres": float(out["relres"].max()),
+                          "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                       "algorithmic_bytes": alg}}
         diff = (sols["fp32_refined"] - sols["fp64"]).abs().amax(dim=0)
         scale = sols["fp64"].abs().amax(dim=0)
         legs["fp32_refined"]["max_abs_err_vs_fp64_per_column_max"] = float(diff.max())
