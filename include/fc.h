@@ -148,7 +148,7 @@ typedef struct {
                                   cycle popping, output;
                                 else zeros */
     double ms_predraw;       /* part of ms_sample spent drawing every tree's first arrows
-                                ahead of the LDS-counter sampler (option "lds_predraw_mib"),
+                                ahead of the LDS-counter sampler (option "predraw_mib"),
                                 else 0 */
 } fc_stats;
 
@@ -178,12 +178,12 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "phase_timing"    1: the workgroup sampler reports per-phase times in fc_stats
  *   "hyb_hot_cap"     cap on how many (highest-degree) vertices the hybrid sampler keeps in
  *                     LDS (default 2^31 - 1: as many as fit; 0: none, all counters global)
- *   "lds_predraw_mib" the LDS-counter sampler draws every tree's first arrows in one
+ *   "predraw_mib"     the LDS-counter sampler draws every tree's first arrows in one
  *                     vertex-major kernel beforehand (each vertex's record and adjacency
  *                     row read once for many trees) when the graph has at least 16384
  *                     non-isolated vertices and the words of all the call's trees
  *                     (8 n bytes each) fit in this many MiB; 0: never (each tree draws
- *                     its own); default 16384
+ *                     its own); default 32768
  *   "max_draws"       cap on the arrows one vertex may draw in one tree, below each
  *                     sampler's own limit (0, the default: no extra cap); a call that
  *                     exceeds it returns FC_ERR_OVERFLOW (exercises that error path)

@@ -381,8 +381,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             // every tree's words fit the budget (the trees then work in place);
             // below 16384 vertices a tree's own first pass is too short to gain
             const size_t pre_bytes = 8u * n * static_cast<size_t>(tree_count);
-            bool predraw = ctx->lds_predraw_mib != 0 && cb[3] >= kPredrawMinVertices &&
-                           pre_bytes <= (static_cast<size_t>(ctx->lds_predraw_mib) << 20);
+            bool predraw = ctx->predraw_mib != 0 && cb[3] >= kPredrawMinVertices &&
+                           pre_bytes <= (static_cast<size_t>(ctx->predraw_mib) << 20);
             if (predraw && ensure(ctx, ctx->cpre, pre_bytes, "pre-drawn tree words") != FC_OK) {
                 predraw = false;  // not enough device memory: each tree draws its own
                 ctx->last_error.clear();
@@ -752,9 +752,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "lds_wg_per_cu") {
         if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
         ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
-    } else if (k == "lds_predraw_mib") {
-        if (value < 0 || value > (int64_t(1) << 22)) return set_err(ctx, FC_ERR_ARG, "lds_predraw_mib");
-        ctx->lds_predraw_mib = static_cast<uint32_t>(value);
+    } else if (k == "predraw_mib") {
+        if (value < 0 || value > (int64_t(1) << 22)) return set_err(ctx, FC_ERR_ARG, "predraw_mib");
+        ctx->predraw_mib = static_cast<uint32_t>(value);
     } else if (k == "hyb_hot_cap") {
         if (value < 0 || value > 0x7FFFFFFF) return set_err(ctx, FC_ERR_ARG, "hyb_hot_cap");
         ctx->hyb_hot_cap = static_cast<uint32_t>(value);

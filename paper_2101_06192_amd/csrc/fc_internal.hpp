@@ -53,7 +53,7 @@ struct fc_ctx {
     bool coop_lds_counts = true;  // in-arrow counters in LDS when the tree's fields fit
     uint32_t lds_threads = 0;     // threads per workgroup of the LDS-counter sampler (0: by n)
     uint32_t lds_wg_per_cu = 0;   // its resident workgroups per CU (0: as many as fit)
-    uint32_t lds_predraw_mib = 16384;  // budget of its pre-drawn first arrows (0: off)
+    uint32_t predraw_mib = 32768;  // budget of pre-drawn first arrows (0: off)
     double wall_khz = 100000.0;   // device wall clock rate
 };
 

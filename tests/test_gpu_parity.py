@@ -243,7 +243,7 @@ def test_lds_launch_shapes_bit_exact(gpu_lib, threads, wg):
         fc.set_option("lds_wg_per_cu", 0)
 
 
-@pytest.mark.parametrize("mib", [0, 1, 16384], ids=["off", "over_budget", "default"])
+@pytest.mark.parametrize("mib", [0, 1, 32768], ids=["off", "over_budget", "default"])
 def test_lds_first_arrows_drawn_ahead_or_in_place(gpu_lib, mib):
     """The LDS sampler's first arrows, drawn by the vertex-major pre-draw
     kernel (the default when every tree's words fit the budget) or by each
@@ -251,7 +251,7 @@ def test_lds_first_arrows_drawn_ahead_or_in_place(gpu_lib, mib):
     need 6.1 MiB, more than 1 MiB, or fewer than 16384 non-isolated vertices),
     give the oracle's trees."""
     fc = gpu_lib
-    fc.set_option("lds_predraw_mib", mib)
+    fc.set_option("predraw_mib", mib)
 
     def drawn_ahead(g, trees):
         non_isolated = int((np.diff(g.row_ptr) > 0).sum())
@@ -270,7 +270,7 @@ def test_lds_first_arrows_drawn_ahead_or_in_place(gpu_lib, mib):
         got, _ = _compare(fc, g3, 0.3, 5, 1000, 33, stream=7, sampler="lds")
         assert got["stats"]["ms_predraw"] == 0.0
     finally:
-        fc.set_option("lds_predraw_mib", 16384)
+        fc.set_option("predraw_mib", 32768)
 
 
 def test_lds_counter_classes_and_size_limit(gpu_lib):
