@@ -140,6 +140,20 @@ def test_tree_ranges_streams_and_device_graph(gpu_lib):
 
 
 @pytest.mark.parametrize("sampler", SAMPLERS)
+def test_counter_words_at_their_limits(gpu_lib, sampler):
+    """The last tree ids of the 32-bit range, the largest stream id and a
+    64-bit seed with every bit set: the Philox counter and key words at their
+    extremes (BA(20000, 3): the LDS sampler also draws the first arrows
+    ahead here).  A range past 2^32 is rejected."""
+    fc = gpu_lib
+    g = inputs.barabasi_albert(20_000, 3, 3)
+    _compare(fc, g, 1.0, (1 << 64) - 1, (1 << 32) - 6, 6, stream=(1 << 32) - 1, sampler=sampler)
+    with pytest.raises(fc.FCError) as e:
+        fc.sample(g, alpha=1.0, tree_begin=(1 << 32) - 2, tree_count=3, sampler=sampler)
+    assert e.value.code == fc.FC_ERR_ARG
+
+
+@pytest.mark.parametrize("sampler", SAMPLERS)
 def test_root_test_boundary(gpu_lib, sampler):
     """alpha chosen so that thr(1) equals x0 of vertex 0's first arrow in tree
     0 (seed 0): both sides must take the strict comparison."""
