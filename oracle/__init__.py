@@ -64,6 +64,13 @@ def _load():
         lib.orc_sample.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_double, ctypes.c_uint64,
                                    ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, i32p,
                                    u32p, u64p, i32p, u32p, u64p, u64p, u32p]
+        lib.orc_sample_w.restype = ctypes.c_int
+        lib.orc_sample_w.argtypes = [ctypes.c_int32, i32p, i32p, f64p, ctypes.c_double,
+                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint32, i32p, u32p, u64p, i32p, u32p, u64p, u64p,
+                                     u32p]
+        lib.orc_root_threshold_w.restype = ctypes.c_uint64
+        lib.orc_root_threshold_w.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.orc_estimate.restype = None
         lib.orc_estimate.argtypes = [ctypes.c_int32, u32p, ctypes.c_uint32, ctypes.c_int,
                                      f64p, f64p, f64p]
@@ -88,6 +95,16 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     lib.orc_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
                           _ptr(out, ctypes.c_uint32))
     return out
+
+
+def _weights(g):
+    """The graph's edge weights as float64 aligned with col_idx, or None."""
+    w = getattr(g, "weights", None)
+    return None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+
+
+def root_threshold_w(alpha: float, W: float) -> int:
+    return int(_load().orc_root_threshold_w(float(alpha), float(W)))
 
 
 def root_threshold(alpha: float, d: int) -> int:
@@ -117,7 +134,8 @@ class SampleResult:
 
 def sample(g, alpha: float, seed: int, t_begin: int, count: int, stream: int = 0,
            order=None, per_tree: bool = False) -> SampleResult:
-    """Run the oracle sampler on trees [t_begin, t_begin + count)."""
+    """Run the oracle sampler on trees [t_begin, t_begin + count) (with the
+    graph's edge weights when it has them)."""
     lib = _load()
     n = int(g.n)
     R = np.zeros(n, np.uint32)
@@ -132,12 +150,16 @@ def sample(g, alpha: float, seed: int, t_begin: int, count: int, stream: int = 0
     if ci.size == 0:
         ci = np.zeros(1, np.int32)
     ordr = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
-    rc = lib.orc_sample(n, _ptr(rp, ctypes.c_int32), _ptr(ci, ctypes.c_int32), float(alpha),
-                        int(seed), int(stream), int(t_begin), int(count),
-                        _ptr(ordr, ctypes.c_int32), _ptr(R, ctypes.c_uint32),
-                        _ptr(visits, ctypes.c_uint64), _ptr(parents, ctypes.c_int32),
-                        _ptr(tvis, ctypes.c_uint32), _ptr(digests, ctypes.c_uint64),
-                        _ptr(steps, ctypes.c_uint64), _ptr(roots, ctypes.c_uint32))
+    w = _weights(g)
+    if w is not None and w.size == 0:
+        w = np.zeros(1, np.float64)
+    rc = lib.orc_sample_w(n, _ptr(rp, ctypes.c_int32), _ptr(ci, ctypes.c_int32),
+                          _ptr(w, ctypes.c_double), float(alpha), int(seed), int(stream),
+                          int(t_begin), int(count), _ptr(ordr, ctypes.c_int32),
+                          _ptr(R, ctypes.c_uint32), _ptr(visits, ctypes.c_uint64),
+                          _ptr(parents, ctypes.c_int32), _ptr(tvis, ctypes.c_uint32),
+                          _ptr(digests, ctypes.c_uint64), _ptr(steps, ctypes.c_uint64),
+                          _ptr(roots, ctypes.c_uint32))
     if rc != 0:
         raise ValueError(f"orc_sample failed ({rc})")
     return SampleResult(R, visits, parents, tvis, digests, steps, roots)
@@ -161,14 +183,17 @@ def estimate(R: np.ndarray, tau_: int, literal: bool = False):
 # binary64 definitions (numpy)
 # --------------------------------------------------------------------------
 def laplacian(g) -> np.ndarray:
-    """L = diag(deg) - A (Section 2, unit weights)."""
+    """L = diag(deg) - A (Section 2; weighted degree and adjacency when the
+    graph has edge weights)."""
     n = g.n
     L = np.zeros((n, n), np.float64)
     rp, ci = g.row_ptr, g.col_idx
+    w = _weights(g)
     for v in range(n):
         for j in range(rp[v], rp[v + 1]):
-            L[v, ci[j]] -= 1.0
-        L[v, v] += rp[v + 1] - rp[v]
+            wj = 1.0 if w is None else float(w[j])
+            L[v, ci[j]] -= wj
+            L[v, v] += wj
     return L
 
 
@@ -227,12 +252,13 @@ def effective_resistance(Lpinv: np.ndarray, u: int, v: int) -> float:
 
 
 def _operator(g, alpha: float):
-    """alpha L + I as a scipy sparse matrix (unit weights)."""
+    """alpha L + I as a scipy sparse matrix (with the edge weights, if any)."""
     import scipy.sparse as sp
     n = g.n
-    deg = np.diff(g.row_ptr).astype(np.float64)
-    A = sp.csr_matrix((np.ones(g.col_idx.size), g.col_idx.astype(np.int64),
-                       g.row_ptr.astype(np.int64)), shape=(n, n))
+    w = _weights(g)
+    vals = np.ones(g.col_idx.size) if w is None else w
+    A = sp.csr_matrix((vals, g.col_idx.astype(np.int64), g.row_ptr.astype(np.int64)), shape=(n, n))
+    deg = np.asarray(A.sum(axis=1)).ravel()
     return (sp.diags(1.0 + alpha * deg) - alpha * A).tocsr()
 
 
@@ -284,15 +310,17 @@ def omega_diag_cg(g, alpha: float, vertices, rtol: float = 1e-9) -> np.ndarray:
 # exact / brute-force tools for tiny graphs
 # --------------------------------------------------------------------------
 def augmented_edges(g):
-    """Edge list of G*: (u, v, is_star_edge); u* has id n."""
+    """Edge list of G*: (u, v, is_star_edge, w) with w the G-edge weight (1 for
+    unweighted graphs and for the star edges); u* has id n."""
     out = []
+    wts = _weights(g)
     for v in range(g.n):
         for j in range(g.row_ptr[v], g.row_ptr[v + 1]):
             w = int(g.col_idx[j])
             if v < w:
-                out.append((v, w, False))
+                out.append((v, w, False, 1.0 if wts is None else float(wts[j])))
     for v in range(g.n):
-        out.append((v, g.n, True))
+        out.append((v, g.n, True, 1.0))
     return out
 
 
@@ -312,7 +340,7 @@ def spanning_trees(g):
             return x
         ok = True
         for e in sub:
-            a, b, _ = E[e]
+            a, b = E[e][0], E[e][1]
             ra, rb = find(a), find(b)
             if ra == rb:
                 ok = False
@@ -322,7 +350,7 @@ def spanning_trees(g):
             continue
         adj = {x: [] for x in range(n + 1)}
         for e in sub:
-            a, b, _ = E[e]
+            a, b = E[e][0], E[e][1]
             adj[a].append(b)
             adj[b].append(a)
         par = [-1] * n
@@ -335,7 +363,11 @@ def spanning_trees(g):
                     seen.add(y)
                     par[y] = x
                     stack.append(y)
-        trees.append((tuple(par), sum(1 for e in sub if not E[e][2])))
+        wprod = Fraction(1)
+        for e in sub:
+            if not E[e][2]:
+                wprod *= Fraction(E[e][3])
+        trees.append((tuple(par), sum(1 for e in sub if not E[e][2]), wprod))
     return trees
 
 
@@ -344,10 +376,13 @@ def exact_omega_diag(g, alpha: Fraction):
     n = g.n
     alpha = Fraction(alpha)
     A = [[Fraction(0)] * n for _ in range(n)]
+    wts = _weights(g)
     for v in range(n):
         for j in range(g.row_ptr[v], g.row_ptr[v + 1]):
-            A[v][int(g.col_idx[j])] -= alpha
-        A[v][v] += alpha * (int(g.row_ptr[v + 1]) - int(g.row_ptr[v])) + 1
+            w = Fraction(1) if wts is None else Fraction(float(wts[j]))
+            A[v][int(g.col_idx[j])] -= alpha * w
+            A[v][v] += alpha * w
+        A[v][v] += 1
     M = [row[:] + [Fraction(int(i == j)) for j in range(n)] for i, row in enumerate(A)]
     for c in range(n):
         p = next(r for r in range(c, n) if M[r][c] != 0)

@@ -15,7 +15,12 @@
  *     weight 1; the edges of G get weight alpha.  u* is the id n here and is
  *     never stored.
  *   - A random walk on G* leaves v to u* with probability 1/(1 + alpha d_v)
- *     and otherwise to a uniform neighbour (unit weights).
+ *     and otherwise to a uniform neighbour (unit weights).  With edge weights
+ *     w (Section 2 allows non-negative weights), G's edges weigh alpha w and
+ *     the walk leaves v to u* with probability 1/(1 + alpha W_v), W_v the
+ *     weighted degree, and to neighbour u with probability alpha w_vu / (1 +
+ *     alpha W_v) (a random walk on a weighted graph moves along an edge with
+ *     probability proportional to its weight).
  *   - tau uniform spanning trees of G* rooted at u* are sampled; R[v] counts
  *     the trees that contain the edge {u*, v}; R[v]/tau estimates Omega_vv,
  *     Omega = (alpha L + I)^{-1}.
@@ -29,6 +34,11 @@
  *   - step to u* iff x0 < thr(d_v), thr(d) = floor(2^32 * fl(1 / fl(fl(alpha d) + 1)))
  *     in IEEE binary64 round-to-nearest with no fused multiply-add, thr(0) = 2^32;
  *     otherwise to col_idx[row_ptr[v] + floor(x1 * d_v / 2^32)].
+ *   - With weights: W_v = the binary64 sum of v's row weights in CSR order,
+ *     thr as above with W_v for d_v (thr = 2^32 when W_v = 0); otherwise u =
+ *     fl(x1 W_v) 2^-32 and the step goes to the first neighbour in CSR order
+ *     whose running binary64 weight sum exceeds u.  With unit weights this is
+ *     exactly the unweighted rule (the sums are exact integers).
  *   Wilson's cycle-popping argument (Wilson 1996, the paper's reference for
  *   the sampler) makes the tree and every k_v independent of the order in
  *   which walks are started; the tests check that property on this code.
@@ -106,17 +116,41 @@ uint32_t orc_tau(int64_t m, int64_t n, double eps, double delta, double kappa) {
     return (uint32_t)c;
 }
 
-/* One random step of the walk on G* from v, using arrow j of v in tree t. */
+/* Root threshold of a vertex of weighted degree W (W = 0: always u*). */
+uint64_t orc_root_threshold_w(double alpha, double W) {
+    if (W == 0.0) return (uint64_t)1 << 32;
+    double aw = alpha * W;
+    double den = aw + 1.0;
+    double p = 1.0 / den;
+    return (uint64_t)(p * 4294967296.0);
+}
+
+/* One random step of the walk on G* from v, using arrow j of v in tree t
+ * (weights == NULL: unit weights). */
 static int32_t orc_successor(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
-                             double alpha, const uint32_t key[2], uint32_t stream,
-                             uint32_t t, int32_t v, uint32_t j) {
+                             const double *weights, double alpha, const uint32_t key[2],
+                             uint32_t stream, uint32_t t, int32_t v, uint32_t j) {
     uint32_t ctr[4] = {(uint32_t)v, j, t, stream};
     uint32_t x[4];
     orc_philox4x32_10(ctr, key, x);
-    int64_t d = (int64_t)row_ptr[v + 1] - row_ptr[v];
-    if ((uint64_t)x[0] < orc_root_threshold(alpha, d)) return n; /* to u* */
-    uint64_t idx = ((uint64_t)x[1] * (uint64_t)d) >> 32;
-    return col_idx[row_ptr[v] + (int64_t)idx];
+    if (!weights) {
+        int64_t d = (int64_t)row_ptr[v + 1] - row_ptr[v];
+        if ((uint64_t)x[0] < orc_root_threshold(alpha, d)) return n; /* to u* */
+        uint64_t idx = ((uint64_t)x[1] * (uint64_t)d) >> 32;
+        return col_idx[row_ptr[v] + (int64_t)idx];
+    }
+    double W = 0.0;
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) W += weights[e];
+    if ((uint64_t)x[0] < orc_root_threshold_w(alpha, W)) return n;   /* to u* */
+    /* the neighbour whose weight interval [sum before it, sum through it)
+     * contains u, a point of [0, W) */
+    double u = ((double)x[1] * W) * (1.0 / 4294967296.0);
+    double s = 0.0;
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        s += weights[e];
+        if (u < s) return col_idx[e];
+    }
+    return -1; /* unreachable: u < W */
 }
 
 /* Stable ascending-degree order of V (Algorithm 3: "reordering of V according
@@ -161,10 +195,11 @@ static void orc_push(orc_vec *a, int32_t x) {
  *   roots        : uint32[count] or NULL: number of v with parent u*
  * Returns 0, or -1 on invalid arguments / allocation failure.
  */
-int orc_sample(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, double alpha,
-               uint64_t seed, uint32_t stream, uint32_t t_begin, uint32_t count,
-               const int32_t *order, uint32_t *R, uint64_t *visits, int32_t *parents,
-               uint32_t *tree_visits, uint64_t *digests, uint64_t *steps, uint32_t *roots) {
+int orc_sample_w(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                 const double *weights, double alpha, uint64_t seed, uint32_t stream,
+                 uint32_t t_begin, uint32_t count, const int32_t *order, uint32_t *R,
+                 uint64_t *visits, int32_t *parents, uint32_t *tree_visits, uint64_t *digests,
+                 uint64_t *steps, uint32_t *roots) {
     if (n < 0 || !(alpha > 0.0) || !R) return -1;
     if (n == 0 || count == 0) return 0;
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -198,7 +233,8 @@ int orc_sample(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, double
             orc_push(&P, s);
             int32_t u = s;
             for (;;) {
-                int32_t w = orc_successor(n, row_ptr, col_idx, alpha, key, stream, t, u, k[u]);
+                int32_t w = orc_successor(n, row_ptr, col_idx, weights, alpha, key, stream, t, u,
+                                          k[u]);
                 k[u] += 1;
                 orc_push(&P, w);
                 if (in_tree[w]) break;
@@ -244,6 +280,15 @@ int orc_sample(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, double
     free(P.data); free(LE.data);
     free(ord); free(in_tree); free(parent); free(k); free(pos);
     return 0;
+}
+
+/* Unit weights (the paper's unweighted graphs). */
+int orc_sample(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, double alpha,
+               uint64_t seed, uint32_t stream, uint32_t t_begin, uint32_t count,
+               const int32_t *order, uint32_t *R, uint64_t *visits, int32_t *parents,
+               uint32_t *tree_visits, uint64_t *digests, uint64_t *steps, uint32_t *roots) {
+    return orc_sample_w(n, row_ptr, col_idx, NULL, alpha, seed, stream, t_begin, count, order, R,
+                        visits, parents, tree_visits, digests, steps, roots);
 }
 
 /*

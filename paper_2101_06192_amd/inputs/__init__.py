@@ -72,6 +72,7 @@ class CSRGraph:
     row_ptr: np.ndarray  # int32[n+1]
     col_idx: np.ndarray  # int32[2m]
     name: str = ""
+    weights: np.ndarray | None = None  # float64[2m] aligned with col_idx (symmetric), or None
 
     @property
     def m(self) -> int:
@@ -177,6 +178,41 @@ def gaussian(count: int, seed: int = 0) -> np.ndarray:
     out = np.empty(count, np.float64)
     lib.gg_normals(count, seed, _pf64(out))
     return out
+
+
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 (Steele, Lea and Flood 2014) on a uint64 array (wrapping)."""
+    z = x + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def with_weights(g: CSRGraph, seed: int = 0, lo: float = 0.1, hi: float = 10.0) -> CSRGraph:
+    """The graph with a seeded edge weight on every edge, log-uniform in
+    [lo, hi): a function of the unordered pair {u, v} and the seed only, so both
+    stored directions carry the same value."""
+    with np.errstate(over="ignore"):
+        deg = np.diff(g.row_ptr).astype(np.int64)
+        v = np.repeat(np.arange(g.n, dtype=np.uint64), deg)
+        u = g.col_idx.astype(np.uint64)
+        a, b = np.minimum(u, v), np.maximum(u, v)
+        key = (a << np.uint64(32)) | b
+        h = _splitmix64(key ^ _splitmix64(np.full(key.shape, seed, np.uint64)))
+    unif = (h >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    w = lo * np.power(hi / lo, unif)
+    return CSRGraph(g.n, g.row_ptr, g.col_idx, (g.name + "_w") if g.name else "", w)
+
+
+def from_weighted_edge_list(n: int, edges, name: str = "") -> CSRGraph:
+    """Small hand-written weighted graphs (tests): edges (u, v, w)."""
+    g = from_edge_list(n, [(a, b) for a, b, _ in edges], name)
+    wt = {(min(a, b), max(a, b)): float(w) for a, b, w in edges}
+    deg = np.diff(g.row_ptr)
+    v = np.repeat(np.arange(n), deg)
+    w = np.array([wt[(min(int(x), int(y)), max(int(x), int(y)))] for x, y in zip(v, g.col_idx)],
+                 np.float64)
+    return CSRGraph(g.n, g.row_ptr, g.col_idx, name, w)
 
 
 def from_edge_list(n: int, edges, name: str = "") -> CSRGraph:

@@ -48,9 +48,9 @@ def _is_spanning_tree(g, parent):
 
 def _chi2_tree_test(g, alpha, n_trees, seed):
     trees = oracle.spanning_trees(g)
-    weights = np.array([alpha ** k for _, k in trees], np.float64)
+    weights = np.array([alpha ** k for _, k, _ in trees], np.float64)
     probs = weights / weights.sum()
-    index = {t: i for i, (t, _) in enumerate(trees)}
+    index = {t: i for i, (t, _, _) in enumerate(trees)}
     res = oracle.sample(g, alpha, seed, 0, n_trees, per_tree=True)
     counts = np.zeros(len(trees), np.int64)
     for row in res.parents:
@@ -87,9 +87,9 @@ def test_root_frequency_equals_exact_omega():
     alpha = Fraction(1, 2)
     exact = oracle.exact_omega_diag(g, alpha)
     trees = oracle.spanning_trees(g)
-    W = sum(alpha ** k for _, k in trees)
+    W = sum(alpha ** k for _, k, _ in trees)
     for v in range(g.n):
-        frac = sum(alpha ** k for t, k in trees if t[v] == g.n) / W
+        frac = sum(alpha ** k for t, k, _ in trees if t[v] == g.n) / W
         assert frac == exact[v]
     n_trees = 200000
     res = oracle.sample(g, float(alpha), 3, 0, n_trees)
