@@ -19,9 +19,11 @@
  *   - Return FC_OK (0) or a negative FC_ERR_* code; fc_last_error() gives a
  *     message for the context's last failure.  Nothing is written to the
  *     outputs of a failing call unless stated.
- *   - Graphs are simple, undirected and unweighted (Section 2: finite,
- *     simple, undirected), in CSR with both directions stored, rows sorted
- *     strictly ascending, no self-loops.  Input that violates this is
+ *   - Graphs are simple and undirected (Section 2: finite, simple,
+ *     undirected), in CSR with both directions stored, rows sorted strictly
+ *     ascending, no self-loops; unweighted, or with non-negative edge weights
+ *     (Section 2 defines L for weighted graphs: L = D - A with A holding the
+ *     weights and D the weighted degrees).  Input that violates this is
  *     rejected with FC_ERR_GRAPH (checked on the device for every call,
  *     unless params.flags has FC_FLAG_TRUSTED_GRAPH).  The graph is never
  *     modified.
@@ -43,6 +45,17 @@
  *     thr(d) = floor(2^32 * (1 / ((alpha * d) + 1))) evaluated in IEEE
  *     binary64 with each operation rounded separately; otherwise it goes to
  *     col_idx[row_ptr[v] + floor(x1 * d_v / 2^32)].
+ *   - Weighted graphs (fc_graph.weights): W_v is the binary64 sum of v's row
+ *     weights, added one by one in CSR order starting from 0, and
+ *     S_v(i) the same running sum through entry i of the row.  The step goes
+ *     to u* iff W_v = 0 or x0 < thr_w(W_v), thr_w(W) = floor(2^32 * (1 /
+ *     ((alpha * W) + 1))) (binary64, each operation rounded); otherwise it
+ *     goes to the first entry i of the row with u < S_v(i), where
+ *     u = (x1 * W_v) * 2^-32 (binary64).  A walk on a weighted graph leaves v
+ *     along an edge with probability proportional to its weight (Section 4.1
+ *     weighs G's edges by alpha and u*'s by 1), and this picks entry i with
+ *     probability w_i / W_v up to binary64 rounding.  With unit weights and
+ *     degrees below 2^21 (x1 * d is then exact) it is the unweighted rule.
  *   By Wilson's cycle-popping theorem the sampled tree and the number of
  *   steps taken out of every vertex do not depend on the order in which
  *   walks are started, which lets the device schedule walks freely.
@@ -99,13 +112,20 @@ typedef struct fc_ctx fc_ctx;
 
 /* A graph G = (V, E) with V = {0, ..., n-1}: n >= 0 vertices and nnz = 2|E|
  * stored directed entries. row_ptr: int32[n+1], row_ptr[0] = 0,
- * row_ptr[n] = nnz; col_idx: int32[nnz]. n < 2^31 - 1, nnz < 2^31. */
+ * row_ptr[n] = nnz; col_idx: int32[nnz]. n < 2^31 - 1, nnz < 2^31.
+ * weights: NULL (every edge weighs 1), or double[nnz] in the same memory as
+ * row_ptr and col_idx: weights[e] is the weight of the edge {v, col_idx[e]}
+ * of row v, equal (bit for bit) to the weight stored with the reverse entry,
+ * and either 0 or in [2^-64, 2^64] (so that every sum, product and quotient
+ * of the randomness contract stays finite and normal; a zero-weight edge is
+ * never walked and is absent from L).  Violations are FC_ERR_GRAPH. */
 typedef struct {
     int32_t n;
     int64_t nnz;
     const int32_t *row_ptr;
     const int32_t *col_idx;
-    int32_t mem; /* FC_MEM_HOST or FC_MEM_DEVICE */
+    const double *weights; /* NULL or double[nnz] */
+    int32_t mem;           /* FC_MEM_HOST or FC_MEM_DEVICE */
 } fc_graph;
 
 /* Parameters of Algorithm 1 (ApproxDiagForestMatrix(G, alpha, eps, delta)).

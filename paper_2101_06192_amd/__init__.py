@@ -52,7 +52,7 @@ class FCError(RuntimeError):
 class fc_graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
-                ("mem", ctypes.c_int32)]
+                ("weights", ctypes.c_void_p), ("mem", ctypes.c_int32)]
 
 
 class fc_params(ctypes.Structure):
@@ -193,10 +193,11 @@ def context(device="cuda:0") -> Context:
 
 @dataclass
 class DeviceGraph:
-    """CSR held in device memory (torch int32 tensors)."""
+    """CSR held in device memory (torch int32 tensors; weights: float64 or None)."""
     n: int
     row_ptr: "object"
     col_idx: "object"
+    weights: "object" = None
 
     @property
     def nnz(self) -> int:
@@ -211,18 +212,30 @@ def to_device(g, device="cuda:0") -> DeviceGraph:
     import torch
     rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int32)).to(device)
     ci = torch.from_numpy(np.ascontiguousarray(g.col_idx, dtype=np.int32)).to(device)
-    return DeviceGraph(int(g.n), rp, ci)
+    w = getattr(g, "weights", None)
+    if w is not None:
+        w = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).to(device)
+    return DeviceGraph(int(g.n), rp, ci, w)
 
 
 def _graph_struct(g) -> fc_graph:
     if isinstance(g, DeviceGraph):
+        w = g.weights
+        wp = w.data_ptr() if w is not None and g.nnz else 0
         return fc_graph(g.n, g.nnz, ctypes.c_void_p(g.row_ptr.data_ptr()),
-                        ctypes.c_void_p(g.col_idx.data_ptr() if g.nnz else 0), FC_MEM_DEVICE)
+                        ctypes.c_void_p(g.col_idx.data_ptr() if g.nnz else 0), ctypes.c_void_p(wp),
+                        FC_MEM_DEVICE)
     rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    w = getattr(g, "weights", None)
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        if w.size != ci.size:
+            raise ValueError("weights must have one entry per CSR entry")
     s = fc_graph(int(g.n), int(ci.size), ctypes.c_void_p(rp.ctypes.data),
-                 ctypes.c_void_p(ci.ctypes.data if ci.size else 0), FC_MEM_HOST)
-    s._keep = (rp, ci)
+                 ctypes.c_void_p(ci.ctypes.data if ci.size else 0),
+                 ctypes.c_void_p(w.ctypes.data if w is not None and w.size else 0), FC_MEM_HOST)
+    s._keep = (rp, ci, w)
     return s
 
 

@@ -40,10 +40,12 @@ __device__ __forceinline__ void row_range(uint32_t kk, uint32_t *first_group, ui
     (void)kk;
 }
 
-// sum over the neighbours u of v of X[u][col], eight independent gathers in
+// sum over the neighbours u of v of X[u][col] (kWeighted: of w_vu X[u][col],
+// the off-diagonal of the weighted Laplacian), eight independent gathers in
 // flight (fixed association: deterministic).
-template <typename T>
-__device__ __forceinline__ T neighbour_sum(const int32_t *__restrict__ col_idx, int32_t b, int32_t e,
+template <typename T, bool kWeighted>
+__device__ __forceinline__ T neighbour_sum(const int32_t *__restrict__ col_idx,
+                                           const double *__restrict__ wt, int32_t b, int32_t e,
                                            const T *__restrict__ X, uint32_t k, uint32_t col) {
     constexpr int U = 8;
     T s[U];
@@ -54,11 +56,28 @@ __device__ __forceinline__ T neighbour_sum(const int32_t *__restrict__ col_idx, 
         int32_t u[U];
 #pragma unroll
         for (int i = 0; i < U; ++i) u[i] = col_idx[q + i];
+        if (kWeighted) {
+            T c[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) s[i] += X[static_cast<size_t>(u[i]) * k + col];
+            for (int i = 0; i < U; ++i) c[i] = static_cast<T>(wt[q + i]);
+#pragma unroll
+            for (int i = 0; i < U; ++i) s[i] += c[i] * X[static_cast<size_t>(u[i]) * k + col];
+        } else {
+#pragma unroll
+            for (int i = 0; i < U; ++i) s[i] += X[static_cast<size_t>(u[i]) * k + col];
+        }
     }
-    for (int i = 0; q < e; ++q, ++i) s[i] += X[static_cast<size_t>(col_idx[q]) * k + col];
+    for (int i = 0; q < e; ++q, ++i) {
+        const T xu = X[static_cast<size_t>(col_idx[q]) * k + col];
+        s[i] += kWeighted ? static_cast<T>(wt[q]) * xu : xu;
+    }
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// Diagonal of L at v: the degree, or the weighted degree wdeg[v] when given.
+__device__ __forceinline__ double degree_of(const int32_t *__restrict__ row_ptr,
+                                            const double *__restrict__ wdeg, uint32_t v) {
+    return wdeg ? wdeg[v] : static_cast<double>(row_ptr[v + 1] - row_ptr[v]);
 }
 
 // Block-level per-column reduction of `acc` into partial[blockIdx.x * k + col].
@@ -77,9 +96,11 @@ __device__ __forceinline__ void block_column_sum(A acc, const Lane &ln, uint32_t
 }
 
 // Y = A X with A = alpha L + I; optional partial dots sum_v X[v][j] Y[v][j].
-template <typename T>
+template <typename T, bool kWeighted>
 __global__ __launch_bounds__(kThreads) void apply_kernel(const int32_t *__restrict__ row_ptr,
                                                          const int32_t *__restrict__ col_idx,
+                                                         const double *__restrict__ wt,
+                                                         const double *__restrict__ wdeg,
                                                          uint32_t n, uint32_t k, double alpha,
                                                          const T *__restrict__ X, T *__restrict__ Y,
                                                          double *__restrict__ partial) {
@@ -94,9 +115,9 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(const int32_t *__restri
         const uint32_t v = g * rows_per_group + ln.rsub;
         if (v < n && ln.valid) {
             const int32_t b = row_ptr[v], e = row_ptr[v + 1];
-            const T s = neighbour_sum<T>(col_idx, b, e, X, k, ln.col);
+            const T s = neighbour_sum<T, kWeighted>(col_idx, wt, b, e, X, k, ln.col);
             const T x = X[static_cast<size_t>(v) * k + ln.col];
-            const T d = static_cast<T>(e - b);
+            const T d = kWeighted ? static_cast<T>(wdeg[v]) : static_cast<T>(e - b);
             const T y = (T(1) + a * d) * x - a * s;
             Y[static_cast<size_t>(v) * k + ln.col] = y;
             acc += static_cast<double>(x) * static_cast<double>(y);
@@ -106,8 +127,11 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(const int32_t *__restri
 }
 
 // R = B - A X in binary64; partial sums of R_j . R_j (and of B_j . B_j).
+template <bool kWeighted>
 __global__ __launch_bounds__(kThreads) void residual_kernel(const int32_t *__restrict__ row_ptr,
                                                             const int32_t *__restrict__ col_idx,
+                                                            const double *__restrict__ wt,
+                                                            const double *__restrict__ wdeg,
                                                             uint32_t n, uint32_t k, double alpha,
                                                             const double *__restrict__ B,
                                                             const double *__restrict__ X,
@@ -124,9 +148,10 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const int32_t *__res
         const uint32_t v = g * rows_per_group + ln.rsub;
         if (v < n && ln.valid) {
             const int32_t b = row_ptr[v], e = row_ptr[v + 1];
-            const double s = neighbour_sum<double>(col_idx, b, e, X, k, ln.col);
+            const double s = neighbour_sum<double, kWeighted>(col_idx, wt, b, e, X, k, ln.col);
             const size_t i = static_cast<size_t>(v) * k + ln.col;
-            const double ax = (1.0 + alpha * static_cast<double>(e - b)) * X[i] - alpha * s;
+            const double dv = kWeighted ? wdeg[v] : static_cast<double>(e - b);
+            const double ax = (1.0 + alpha * dv) * X[i] - alpha * s;
             const double r = B[i] - ax;
             R[i] = r;
             rr += r * r;
@@ -171,6 +196,7 @@ __global__ __launch_bounds__(64 * kReduceGroups) void reduce_kernel(const double
 // z = Minv r, p = z; partial sums of r.z.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void start_kernel(const int32_t *__restrict__ row_ptr,
+                                                         const double *__restrict__ wdeg,
                                                          uint32_t n, uint32_t k, double alpha,
                                                          const double *__restrict__ R64,
                                                          const double *__restrict__ scale,
@@ -190,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void start_kernel(const int32_t *__restri
             const size_t i = static_cast<size_t>(v) * k + ln.col;
             const double sc = scale[ln.col];
             const T rv = static_cast<T>(sc > 0.0 ? R64[i] / sc : 0.0);
-            const T minv = static_cast<T>(1.0 / (1.0 + alpha * static_cast<double>(row_ptr[v + 1] - row_ptr[v])));
+            const T minv = static_cast<T>(1.0 / (1.0 + alpha * degree_of(row_ptr, wdeg, v)));
             const T zv = minv * rv;
             r[i] = rv;
             z[i] = zv;
@@ -207,6 +233,7 @@ __global__ __launch_bounds__(kThreads) void start_kernel(const int32_t *__restri
 // d += a_j p; r -= a_j q; z = Minv r; partial sums of r.z and r.r.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void update_kernel(const int32_t *__restrict__ row_ptr,
+                                                          const double *__restrict__ wdeg,
                                                           uint32_t n, uint32_t k, double alpha,
                                                           const double *__restrict__ step,
                                                           const T *__restrict__ p,
@@ -227,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void update_kernel(const int32_t *__restr
             const size_t i = static_cast<size_t>(v) * k + ln.col;
             d[i] = d[i] + a * p[i];
             const T rv = r[i] - a * q[i];
-            const T minv = static_cast<T>(1.0 / (1.0 + alpha * static_cast<double>(row_ptr[v + 1] - row_ptr[v])));
+            const T minv = static_cast<T>(1.0 / (1.0 + alpha * degree_of(row_ptr, wdeg, v)));
             const T zv = minv * rv;
             r[i] = rv;
             z[i] = zv;
@@ -334,20 +361,26 @@ hipError_t cg_inner(const CgWork &w, uint32_t max_iters, uint32_t poll, uint32_t
     (void)rz;
     hipError_t e;
     // start: r = R64 / scale, z = Minv r, p = z, d = 0; rz = r.z; rr = |r|^2
-    start_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, n, k, w.alpha, w.R64, w.scale, r, z,
-                                                     p, d, w.partial_a, w.partial_b);
+    start_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.wdeg, n, k, w.alpha, w.R64,
+                                                     w.scale, r, z, p, d, w.partial_a, w.partial_b);
     reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, k, rzn);
     reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_b, blocks, k, rr);
     scalars_kernel<<<1, 64, 0, stream>>>(0, k, S, w.any);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     uint32_t it = 0;
     while (it < max_iters) {
-        apply_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.col_idx, n, k, w.alpha, p, q,
-                                                         w.partial_a);
+        if (w.weights)
+            apply_kernel<T, true><<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.col_idx, w.weights,
+                                                                   w.wdeg, n, k, w.alpha, p, q,
+                                                                   w.partial_a);
+        else
+            apply_kernel<T, false><<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.col_idx, nullptr,
+                                                                    nullptr, n, k, w.alpha, p, q,
+                                                                    w.partial_a);
         reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, k, pq);
         scalars_kernel<<<1, 64, 0, stream>>>(1, k, S, nullptr);
-        update_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, n, k, w.alpha, step, p, q, d, r,
-                                                          z, w.partial_a, w.partial_b);
+        update_kernel<T><<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.wdeg, n, k, w.alpha, step, p,
+                                                          q, d, r, z, w.partial_a, w.partial_b);
         reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, k, rzn);
         reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_b, blocks, k, rr);
         scalars_kernel<<<1, 64, 0, stream>>>(2, k, S, w.any);
@@ -372,9 +405,14 @@ template hipError_t cg_inner<double>(const CgWork &, uint32_t, uint32_t, uint32_
 
 hipError_t cg_residual(const CgWork &w, bool with_b, hipStream_t stream) {
     const unsigned int blocks = grid_for(w.n, w.k, w.max_blocks);
-    residual_kernel<<<blocks, kThreads, 0, stream>>>(w.row_ptr, w.col_idx, w.n, w.k, w.alpha, w.B,
-                                                     w.X, w.R64, w.partial_a,
-                                                     with_b ? w.partial_b : nullptr);
+    if (w.weights)
+        residual_kernel<true><<<blocks, kThreads, 0, stream>>>(
+            w.row_ptr, w.col_idx, w.weights, w.wdeg, w.n, w.k, w.alpha, w.B, w.X, w.R64,
+            w.partial_a, with_b ? w.partial_b : nullptr);
+    else
+        residual_kernel<false><<<blocks, kThreads, 0, stream>>>(
+            w.row_ptr, w.col_idx, nullptr, nullptr, w.n, w.k, w.alpha, w.B, w.X, w.R64,
+            w.partial_a, with_b ? w.partial_b : nullptr);
     reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_a, blocks, w.k, w.res_rr);
     if (with_b) reduce_kernel<<<1, 64 * kReduceGroups, 0, stream>>>(w.partial_b, blocks, w.k, w.res_bb);
     return hipGetLastError();

@@ -20,10 +20,10 @@
 
 #pragma STDC FP_CONTRACT OFF
 
-static_assert(sizeof(fc_graph) == 40, "fc_graph layout");
+static_assert(sizeof(fc_graph) == 48, "fc_graph layout");
 static_assert(sizeof(fc_params) == 56, "fc_params layout");
 static_assert(sizeof(fc_stats) == 136, "fc_stats layout");
-static_assert(sizeof(fc_job) == 80, "fc_job layout");
+static_assert(sizeof(fc_job) == 88, "fc_job layout");
 
 namespace fc_host {
 
@@ -98,9 +98,19 @@ int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out) 
                                        hipMemcpyHostToDevice, ctx->stream), "copy col_idx");
         v.row_ptr = static_cast<const int32_t *>(ctx->row_ptr.ptr);
         v.col_idx = static_cast<const int32_t *>(ctx->col_idx.ptr);
+        if (g->weights && g->nnz) {
+            if ((rc = ensure(ctx, ctx->weights, sizeof(double) * static_cast<size_t>(g->nnz),
+                             "weights")))
+                return rc;
+            FC_HIP(ctx, hipMemcpyAsync(ctx->weights.ptr, g->weights,
+                                       sizeof(double) * static_cast<size_t>(g->nnz),
+                                       hipMemcpyHostToDevice, ctx->stream), "copy weights");
+            v.weights = static_cast<const double *>(ctx->weights.ptr);
+        }
     } else {
         v.row_ptr = g->row_ptr;
         v.col_idx = g->col_idx;
+        v.weights = g->nnz ? g->weights : nullptr;
     }
     if (!trusted) {
         Small *sm = static_cast<Small *>(ctx->small.ptr);
@@ -112,8 +122,8 @@ int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out) 
                                    ctx->stream), "copy error word");
         FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "validate_rows");
         if (err) return set_err(ctx, FC_ERR_GRAPH, "row_ptr is not monotone from 0 to nnz");
-        FC_HIP(ctx, fc::launch_validate_cols(v.row_ptr, v.col_idx, v.n, v.nnz, &sm->graph_err,
-                                             ctx->stream),
+        FC_HIP(ctx, fc::launch_validate_cols(v.row_ptr, v.col_idx, v.weights, v.n, v.nnz,
+                                             &sm->graph_err, ctx->stream),
                "validate_cols launch");
         FC_HIP(ctx, hipMemcpyAsync(&err, &sm->graph_err, sizeof(err), hipMemcpyDeviceToHost,
                                    ctx->stream), "copy error word");
@@ -124,10 +134,24 @@ int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out) 
             if (err & fc::kErrGraphSelfLoop) m += " self-loop;";
             if (err & fc::kErrGraphOrder) m += " row not strictly ascending;";
             if (err & fc::kErrGraphAsymmetric) m += " missing reverse edge;";
+            if (err & fc::kErrGraphWeight) m += " weight not 0 or in [2^-64, 2^64];";
+            if (err & fc::kErrGraphWeightAsym) m += " weight differs from its reverse entry's;";
             return set_err(ctx, FC_ERR_GRAPH, m);
         }
     }
     *out = v;
+    return FC_OK;
+}
+
+int row_wsum(fc_ctx *ctx, const GraphView &g, DevBuf &buf, const double **S) {
+    *S = nullptr;
+    if (!g.weights || g.nnz == 0) return FC_OK;
+    int rc = ensure(ctx, buf, sizeof(double) * static_cast<size_t>(g.nnz), "row weight sums");
+    if (rc) return rc;
+    FC_HIP(ctx, fc::launch_row_wsum(g.row_ptr, g.weights, g.n, static_cast<double *>(buf.ptr),
+                                    ctx->stream),
+           "row weight sums");
+    *S = static_cast<const double *>(buf.ptr);
     return FC_OK;
 }
 
@@ -168,9 +192,19 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::VRec *vrec = static_cast<fc::VRec *>(ctx->vrec.ptr);
     if ((rc = ensure(ctx, ctx->iso, 4u * ((static_cast<size_t>(g.n) + 31u) / 32u), "isolated bitmap")))
         return rc;
-    FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, g.n, p->alpha, vrec, &sm->dmax,
-                                      static_cast<uint32_t *>(ctx->iso.ptr), ctx->stream),
+    const double *wsum = nullptr;
+    if ((rc = row_wsum(ctx, g, ctx->wsum, &wsum))) return rc;
+    const bool weighted = wsum != nullptr;
+    FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, wsum, g.n, p->alpha, vrec, &sm->dmax,
+                                      static_cast<uint32_t *>(ctx->iso.ptr), &sm->wtotal,
+                                      ctx->stream),
            "build_vrec");
+    double vol = static_cast<double>(g.nnz);  // sum of the (weighted) degrees
+    if (weighted) {
+        FC_HIP(ctx, hipMemcpyAsync(&vol, &sm->wtotal, sizeof(vol), hipMemcpyDeviceToHost,
+                                   ctx->stream), "copy weighted volume");
+        FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "weighted volume");
+    }
 
     // which sampler: the lane sampler needs many trees to fill the GPU; the
     // workgroup sampler parallelises inside each tree
@@ -184,10 +218,10 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     // automatically always a workgroup sampler: measured, the LDS-counter one beats
     // the lane-per-tree walk even with 2^18 trees of a 1000-vertex graph
     const bool use_coop = mode == 0 || mode >= 2;
-    // expected steps per tree are at most n + 2 alpha m; a valid run never
-    // comes near 256 times that, so exceeding it marks a fault, not bad luck
-    const double cap = 256.0 * (static_cast<double>(g.n) + p->alpha * static_cast<double>(g.nnz)) +
-                       1048576.0;
+    // expected steps per tree are at most n + alpha vol (n + 2 alpha m without
+    // weights); a valid run never comes near 256 times that, so exceeding it
+    // marks a fault, not bad luck
+    const double cap = 256.0 * (static_cast<double>(g.n) + p->alpha * vol) + 1048576.0;
     const unsigned long long step_cap =
         cap > 4.0e18 ? 4000000000000000000ull : static_cast<unsigned long long>(cap);
     size_t slots = 0;
@@ -292,7 +326,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             slots = std::max<size_t>(1, ctx->state_budget / per_slot);
             slots = std::min<size_t>(slots, tree_count);
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
-            const int fit = fc::hyb_max_active(lds_threads, lds_words);
+            const int fit = fc::hyb_max_active(lds_threads, lds_words, weighted);
             uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
             per_cu = fit > 0 ? std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit)) : 1u;
             slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
@@ -325,6 +359,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             fc::CoopJob &j = c.single;
             j.vrec = static_cast<const fc::VRec *>(ctx->rl_vrec.ptr);
             j.col_idx = g.col_idx;
+            j.wsum = wsum;
             j.adj = static_cast<const unsigned long long *>(ctx->rl_adj.ptr);
             j.orig = static_cast<const uint32_t *>(ctx->rl_orig.ptr);
             j.n = static_cast<uint32_t>(g.n);
@@ -372,7 +407,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             slots = std::min<size_t>(slots, tree_count);
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
             uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
-            const int fit = fc::lds_max_active(lds_threads, lds_words);
+            const int fit = fc::lds_max_active(lds_threads, lds_words, weighted);
             if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
             else per_cu = 1;
             slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
@@ -411,6 +446,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             fc::CoopJob &j = c.single;
             j.vrec = static_cast<const fc::VRec *>(ctx->rl_vrec.ptr);
             j.col_idx = g.col_idx;
+            j.wsum = wsum;
             j.adj = static_cast<const unsigned long long *>(ctx->rl_adj.ptr);
             j.orig = static_cast<const uint32_t *>(ctx->rl_orig.ptr);
             j.n = static_cast<uint32_t>(g.n);
@@ -452,7 +488,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
 
         uint32_t per_cu = ctx->coop_wg_per_cu;
         const int fit = fc::coop_max_active(ctx->coop_threads, lds_bits, in_bits, word32,
-                                            static_cast<uint32_t>(g.n));
+                                            static_cast<uint32_t>(g.n), weighted);
         if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
         slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
         if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
@@ -489,6 +525,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         fc::CoopJob &j = c.single;
         j.vrec = vrec;
         j.col_idx = g.col_idx;
+        j.wsum = wsum;
         j.iso = static_cast<const uint32_t *>(ctx->iso.ptr);
         j.tree_count = tree_count;
         j.n = static_cast<uint32_t>(g.n);
@@ -514,6 +551,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         FC_HIP(ctx, hipMemsetAsync(ctx->state.ptr, 0, per_slot * slots, ctx->stream), "memset state");
         a.vrec = vrec;
         a.col_idx = g.col_idx;
+        a.wsum = wsum;
         a.state = static_cast<uint64_t *>(ctx->state.ptr);
         a.n = static_cast<uint32_t>(g.n);
         a.slots = static_cast<uint32_t>(slots);
@@ -544,10 +582,11 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             FC_HIP(ctx, fc::launch_lds_predraw(c, ctx->stream), "lds_predraw launch");
             FC_HIP(ctx, hipEventRecord(ctx->evm, ctx->stream), "event");
         }
-        FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, ctx->stream),
+        FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, weighted, ctx->stream),
                "wilson_lds launch");
     } else if (use_coop) {
-        FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, ctx->stream),
+        FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, weighted,
+                                           ctx->stream),
                "wilson_coop launch");
     } else
         FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
@@ -710,7 +749,7 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->cbits, &ctx->s_r64, &ctx->s_r, &ctx->s_z, &ctx->s_p, &ctx->s_q,
                       &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small, &ctx->rl_blk,
                       &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
-                      &ctx->iso, &ctx->corigt, &ctx->cpre})
+                      &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->s_wdeg})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <utility>
 #include <vector>
 
 #include "fc_internal.hpp"
@@ -35,6 +36,7 @@ struct Group {
     uint32_t n_max = 0, item_count = 0, slots = 0, threads = 512, wg_per_cu = 4;
     size_t ntab = 0, kk_words = 0;
     bool use_lds = false, lds_bits = false, in_bits = false, word32 = true;
+    bool weighted = false;   // some job's graph carries edge weights
     uint32_t lds_words = 0;  // dynamic LDS of the LDS-counter kernel (largest graph)
 };
 
@@ -45,7 +47,8 @@ struct fc_batch {
     std::vector<fc_job> jobs;
     uint64_t seed = 0;
     int32_t flags = 0;
-    DevBuf vrec, dmax, iso;
+    DevBuf vrec, dmax, iso, wsum, wtot;  // running row weight sums of the weighted graphs and
+                                         // each job's weighted volume
     DevBuf rl_blk, rl_base, rl_bounds, rl_inv, rl_orig, rl_adj, rl_vrec;  // degree-class relabelling
     Group grp[2];
     int ngroups = 0;
@@ -63,7 +66,7 @@ int free_batch(fc_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (DevBuf *d : {&b->vrec, &b->dmax, &b->iso, &b->rl_blk, &b->rl_base, &b->rl_bounds, &b->rl_inv,
+    for (DevBuf *d : {&b->vrec, &b->dmax, &b->iso, &b->wsum, &b->wtot, &b->rl_blk, &b->rl_base, &b->rl_bounds, &b->rl_inv,
                       &b->rl_orig, &b->rl_adj, &b->rl_vrec})
         if (d->ptr) (void)hipFree(d->ptr);
     for (Group &g : b->grp)
@@ -84,10 +87,10 @@ hipError_t enqueue_group(const Group &g, const fc::CoopArgs &a, uint32_t threads
     hipError_t e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.small.ptr),
                                        sizeof(Small) / 8, 0ull, stream);
     if (e != hipSuccess) return e;
-    if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, stream);
+    if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, g.weighted, stream);
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.kk.ptr), g.kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
-    return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, stream);
+    return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, g.weighted, stream);
 }
 
 // Size a group's scratch for `slots` workgroups and point its arguments at it.
@@ -115,8 +118,9 @@ int size_scratch(fc_ctx *ctx, Group &g, uint32_t slots) {
 
 uint32_t slots_for(const fc_ctx *ctx, const Group &g, uint32_t threads, uint32_t wg_per_cu) {
     const size_t n = g.n_max;
-    const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words)
-                              : fc::coop_max_active(threads, g.lds_bits, g.in_bits, g.word32, g.n_max);
+    const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words, g.weighted)
+                              : fc::coop_max_active(threads, g.lds_bits, g.in_bits, g.word32,
+                                                    g.n_max, g.weighted);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
     const size_t per_slot = g.use_lds ? (8 + 24 + 4) * n + 8
                                       : ((g.word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
@@ -254,10 +258,11 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
 
     // validate each distinct graph once
     if (!(flags & FC_FLAG_TRUSTED_GRAPH)) {
-        std::vector<const int32_t *> seen;
+        std::vector<std::pair<const int32_t *, const double *>> seen;
         for (const fc_job &j : b->jobs) {
-            if (std::find(seen.begin(), seen.end(), j.graph.row_ptr) != seen.end()) continue;
-            seen.push_back(j.graph.row_ptr);
+            const std::pair<const int32_t *, const double *> key(j.graph.row_ptr, j.graph.weights);
+            if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+            seen.push_back(key);
             GraphView gv;
             if ((rc = prepare_graph(ctx, &j.graph, false, &gv))) return fail(rc);
         }
@@ -287,17 +292,15 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     uint32_t *iso = static_cast<uint32_t *>(b->iso.ptr);
     if ((rc = ensure(ctx, b->dmax, 4 * order.size(), "batch degrees"))) return fail(rc);
     FB_HIP(hipMemsetAsync(b->dmax.ptr, 0, 4 * order.size(), b->stream), "memset degrees");
+    if ((rc = ensure(ctx, b->wtot, 8 * order.size(), "batch weighted volumes"))) return fail(rc);
+    FB_HIP(hipMemsetAsync(b->wtot.ptr, 0, 8 * order.size(), b->stream), "memset volumes");
+    double *wtot_d = static_cast<double *>(b->wtot.ptr);
     fc::VRec *vrec = static_cast<fc::VRec *>(b->vrec.ptr);
     unsigned int *dmax_d = static_cast<unsigned int *>(b->dmax.ptr);
-    for (size_t k = 0; k < order.size(); ++k) {
-        const fc_job &j = b->jobs[order[k]];
-        FB_HIP(fc::launch_build_vrec(j.graph.row_ptr, j.graph.n, j.alpha, vrec + voff[k], dmax_d + k,
-                                     iso + ioff[k], b->stream), "build_vrec");
-    }
-
     // degree classes of each distinct graph, for the LDS-counter kernel
     struct GInfo {
         const int32_t *rp, *ci;
+        const double *w;
         uint32_t n;
         int64_t nnz;
         size_t off_n, off_e, off_b;
@@ -308,16 +311,38 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     for (size_t k = 0; k < order.size(); ++k) {
         const fc_graph &gr = b->jobs[order[k]].graph;
         size_t f = 0;
+        const double *w = gr.nnz ? gr.weights : nullptr;
         while (f < gs.size() && !(gs[f].rp == gr.row_ptr && gs[f].ci == gr.col_idx &&
-                                  gs[f].n == static_cast<uint32_t>(gr.n)))
+                                  gs[f].w == w && gs[f].n == static_cast<uint32_t>(gr.n)))
             ++f;
         if (f == gs.size()) {
-            gs.push_back({gr.row_ptr, gr.col_idx, static_cast<uint32_t>(gr.n), gr.nnz, tn, te, tb});
+            gs.push_back({gr.row_ptr, gr.col_idx, w, static_cast<uint32_t>(gr.n), gr.nnz, tn, te, tb});
             tn += static_cast<size_t>(gr.n);
             te += static_cast<size_t>(gr.nnz);
             tb += fc::relabel_blocks(static_cast<uint32_t>(gr.n));
         }
         gof[k] = static_cast<uint32_t>(f);
+    }
+    // running row weight sums of each distinct weighted graph (same offsets as
+    // its CSR entries), then the records with weighted root thresholds
+    bool any_weighted = false;
+    for (const GInfo &gi : gs) any_weighted = any_weighted || gi.w;
+    if (any_weighted && (rc = ensure(ctx, b->wsum, 8 * std::max<size_t>(te, 1), "batch weight sums")))
+        return fail(rc);
+    double *wsum = static_cast<double *>(b->wsum.ptr);
+    for (const GInfo &gi : gs)
+        if (gi.w)
+            FB_HIP(fc::launch_row_wsum(gi.rp, gi.w, static_cast<int32_t>(gi.n), wsum + gi.off_e,
+                                       b->stream), "row weight sums");
+    auto wsum_of = [&](size_t k) -> const double * {
+        const GInfo &gi = gs[gof[k]];
+        return gi.w ? wsum + gi.off_e : nullptr;
+    };
+    for (size_t k = 0; k < order.size(); ++k) {
+        const fc_job &j = b->jobs[order[k]];
+        FB_HIP(fc::launch_build_vrec(j.graph.row_ptr, wsum_of(k), j.graph.n, j.alpha, vrec + voff[k],
+                                     dmax_d + k, iso + ioff[k], wtot_d + k, b->stream),
+               "build_vrec");
     }
     const bool try_lds = ctx->coop_lds_counts && !order.empty() &&
                          n_max < (1u << fc::kRelabelIdBits);
@@ -342,6 +367,9 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     std::vector<unsigned int> dmax(order.size());
     FB_HIP(hipMemcpyAsync(dmax.data(), dmax_d, 4 * order.size(), hipMemcpyDeviceToHost, b->stream),
            "copy degrees");
+    std::vector<double> wvol(order.size());
+    FB_HIP(hipMemcpyAsync(wvol.data(), wtot_d, 8 * order.size(), hipMemcpyDeviceToHost, b->stream),
+           "copy weighted volumes");
     FB_HIP(hipStreamSynchronize(b->stream), "batch preparation");
     std::vector<uint32_t> gwords(gs.size(), 0);
     bool use_lds = false;
@@ -395,6 +423,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
             const size_t k = pos[j];
             g.n_max = std::max<uint32_t>(g.n_max, static_cast<uint32_t>(b->jobs[j].graph.n));
             g.item_count += b->jobs[j].tree_count;
+            g.weighted = g.weighted || wsum_of(k) != nullptr;
             if (use_lds) g.lds_words = std::max(g.lds_words, gwords[gof[k]]);
             uint32_t ts;
             bool w32;
@@ -417,6 +446,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
             std::memset(&c, 0, sizeof(c));
             c.vrec = vrec + voff[k];
             c.col_idx = j.graph.col_idx;
+            c.wsum = wsum_of(k);
             c.n = static_cast<uint32_t>(j.graph.n);
             c.tree_count = j.tree_count;
             c.iso = use_lds ? nullptr : iso + ioff[k];
@@ -435,8 +465,8 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
             c.stream_id = j.stream_id;
             c.tree_begin = j.tree_begin;
             c.first_item = first;
-            const double cap = 256.0 * (static_cast<double>(j.graph.n) +
-                                        j.alpha * static_cast<double>(j.graph.nnz)) + 1048576.0;
+            const double vol = c.wsum ? wvol[k] : static_cast<double>(j.graph.nnz);
+            const double cap = 256.0 * (static_cast<double>(j.graph.n) + j.alpha * vol) + 1048576.0;
             c.step_cap = cap > 4.0e18 ? 4000000000000000000ull : static_cast<unsigned long long>(cap);
             c.root_counts = j.root_counts;
             c.tree_digests = reinterpret_cast<unsigned long long *>(j.tree_digests);

@@ -63,12 +63,43 @@ __device__ __forceinline__ VRec load_vrec(const VRec *__restrict__ vrec, uint32_
     return {static_cast<int32_t>(q.x), q.y, q.z, q.w};
 }
 
+
+// Weighted step (Section 2's non-negative edge weights; a walk leaves v along
+// an edge with probability proportional to its weight): the 0-based entry of
+// v's row taken for Philox word x1, given the row's running weight sums
+// S[0..deg) (binary64, added in CSR order from 0, so S[deg - 1] = W_v): the
+// first entry with u < S[i], u = (x1 * W_v) * 2^-32.  Needs W_v > 0 (a vertex
+// with W_v = 0 always steps to u*); with W_v in [2^-64, 2^95] u < W_v holds,
+// so the entry exists.  S is non-decreasing, so a binary search finds it.
+__device__ __forceinline__ uint32_t weighted_entry(const double *__restrict__ S, uint32_t deg,
+                                                   uint32_t x1) {
+    const double W = S[deg - 1];
+    const double u = (static_cast<double>(x1) * W) * 0x1p-32;
+    uint32_t lo = 0, hi = deg - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (u < S[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Entry of v's row taken by a step that does not go to u*: uniform
+// (floor(x1 * d / 2^32)) or, with running sums S of the graph, weighted.
+template <bool kWeighted>
+__device__ __forceinline__ uint32_t neighbour_entry(const VRec &r, uint32_t x1,
+                                                    const double *__restrict__ S) {
+    if (kWeighted && S) return weighted_entry(S + r.start, r.deg, x1);
+    return __umulhi(x1, r.deg);
+}
+
 // One arrow of v: returns the successor (n = u*) given Philox words x0, x1.
+template <bool kWeighted>
 __device__ __forceinline__ uint32_t arrow_target(const VRec &r, uint32_t x0, uint32_t x1,
                                                  const int32_t *__restrict__ col_idx,
-                                                 uint32_t n) {
+                                                 const double *__restrict__ S, uint32_t n) {
     if (r.always_root || x0 < r.thr) return n;
-    const uint32_t idx = __umulhi(x1, r.deg);
+    const uint32_t idx = neighbour_entry<kWeighted>(r, x1, S);
     return static_cast<uint32_t>(col_idx[r.start + static_cast<int32_t>(idx)]);
 }
 
@@ -112,6 +143,8 @@ constexpr uint32_t kErrGraphSelfLoop = 8u;
 constexpr uint32_t kErrGraphOrder = 16u;
 constexpr uint32_t kErrGraphAsymmetric = 32u;
 constexpr uint32_t kErrStepCap = 64u;
+constexpr uint32_t kErrGraphWeight = 128u;     // weight not 0 or in [2^-64, 2^64]
+constexpr uint32_t kErrGraphWeightAsym = 256u; // weight differs from its reverse entry's
 
 // Device-side totals shared by a launch.
 struct Totals {

@@ -23,6 +23,7 @@ struct Small {  // device-side counters of one call
     unsigned int pad;
     unsigned long long phase_ticks[8];
     unsigned int class_bounds[4];  // n0, n1, n2, n3 of the degree-class relabelling
+    double wtotal;                 // sum of the weighted degrees (weighted graphs)
 };
 
 struct fc_ctx {
@@ -30,11 +31,12 @@ struct fc_ctx {
     hipStream_t stream = nullptr;
     std::string last_error;
     DevBuf state, vrec, row_ptr, col_idx, small, rtmp, thr, cword, ckk, clists, clevels, cbits;
-    DevBuf s_r64, s_r, s_z, s_p, s_q, s_d, s_pa, s_pb, s_small;  // solver workspace
+    DevBuf s_r64, s_r, s_z, s_p, s_q, s_d, s_pa, s_pb, s_small, s_wdeg;  // solver workspace
     DevBuf rl_blk, rl_base, rl_inv, rl_orig, rl_vrec, rl_adj;     // degree-class relabelling
     DevBuf iso;                                                   // isolated-vertex bitmap
     DevBuf corigt;                                                // hybrid: target ids per slot
     DevBuf cpre;                                                  // LDS: pre-drawn tree words
+    DevBuf weights, wsum;  // staged edge weights (host graphs), running row weight sums
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
@@ -85,11 +87,14 @@ struct GraphView {
     int64_t nnz = 0;
     const int32_t *row_ptr = nullptr;
     const int32_t *col_idx = nullptr;
+    const double *weights = nullptr;  // device edge weights, or null (unit weights)
 };
 
 int check_graph_args(fc_ctx *ctx, const fc_graph *g);
-// Stage (if on the host) and validate the CSR on the device.
+// Stage (if on the host) and validate the CSR (and weights) on the device.
 int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out);
+// Running row weight sums of a weighted graph into `buf` (null for an unweighted one).
+int row_wsum(fc_ctx *ctx, const GraphView &g, DevBuf &buf, const double **S);
 double now_ms();
 int begin(fc_ctx *ctx);
 // Threads per workgroup of the LDS-counter sampler for `trees` trees whose

@@ -15,14 +15,28 @@ namespace fc {
 // nothing, checks columns, self-loops, ordering and symmetry.
 hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
                                 unsigned int *err, hipStream_t stream);
-hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
-                                int64_t nnz, unsigned int *err, hipStream_t stream);
+// With weights (not null) it also checks every weight's range and that it
+// equals the weight of the reverse entry.
+hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx,
+                                const double *weights, int32_t n, int64_t nnz, unsigned int *err,
+                                hipStream_t stream);
+
+// Running weight sums of every row: S[e] = binary64 sum of weights[row_ptr[v] .. e],
+// added one by one in CSR order from 0 (one thread per row).
+hipError_t launch_row_wsum(const int32_t *row_ptr, const double *weights, int32_t n, double *S,
+                           hipStream_t stream);
+// Weighted degrees: W[v] = the last running sum of row v (0 for an empty row).
+hipError_t launch_row_wdeg(const int32_t *row_ptr, const double *weights, int32_t n, double *W,
+                           hipStream_t stream);
 
 // Per-vertex records of G* for one alpha; atomically maxes the degree into *dmax
 // and, when iso is not null, writes the bitmap of isolated vertices
-// (ceil(n / 32) words).
-hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
-                             unsigned int *dmax, uint32_t *iso, hipStream_t stream);
+// (ceil(n / 32) words).  With running sums S (not null) the root threshold is
+// that of the weighted degree W_v = S[row_ptr[v + 1] - 1] (0 for an empty row),
+// and the W_v are added into *wtotal (when not null; any order).
+hipError_t launch_build_vrec(const int32_t *row_ptr, const double *S, int32_t n, double alpha,
+                             VRec *vrec, unsigned int *dmax, uint32_t *iso, double *wtotal,
+                             hipStream_t stream);
 
 // thr(d), d = 0..d_max, as the device computes it (uint64, 2^32 for "always").
 hipError_t launch_thresholds(double alpha, int32_t d_max, unsigned long long *out,
@@ -32,6 +46,7 @@ hipError_t launch_thresholds(double alpha, int32_t d_max, unsigned long long *ou
 struct LaneArgs {
     const VRec *vrec;
     const int32_t *col_idx;
+    const double *wsum;       // running weight sums per CSR entry (weighted graph), or null
     uint64_t *state;          // slots * n words
     uint32_t n;
     uint32_t slots;
@@ -63,6 +78,7 @@ hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream);
 struct CoopJob {
     const VRec *vrec;
     const int32_t *col_idx;
+    const double *wsum;             // running weight sums per CSR entry (weighted graph), or null
     const unsigned long long *adj;  // LDS variant: internal | original << 18 per CSR entry
     const uint32_t *orig;           // LDS variant: original id of each internal id
     uint32_t n;
@@ -109,35 +125,40 @@ struct CoopArgs {
 };
 // lds_bits: settled bitmap in LDS; in_bits (needs lds_bits): second LDS bitmap of
 // vertices with in-arrows.
+// weighted: some job carries running weight sums (the weighted instantiation
+// checks each job's pointer).
 hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
-                              bool word32, hipStream_t stream);
+                              bool word32, bool weighted, hipStream_t stream);
 // Allow up to `bytes` of dynamic LDS per workgroup for every variant (set once
 // per device to the device limit; launches pass what they need).
 hipError_t coop_set_lds_limit(size_t bytes);
 // Workgroups of the chosen variant that fit on one CU at once (0 if unknown).
-int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max);
+int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max,
+                    bool weighted);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 
 // LDS-counter variant (n < 2^kRelabelIdBits): the per-tree arrays are word
 // (u64: internal target | original target << 18 | draw count << 36), lists
 // and levels as above (no kk); the settled bitmap and all in-arrow counters
 // live in LDS.
+// weighted: some job carries running weight sums (the weighted instantiation
+// checks each job's pointer).
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
-                             hipStream_t stream);
+                             bool weighted, hipStream_t stream);
 hipError_t lds_set_limit(size_t bytes);  // as coop_set_lds_limit, for the LDS-counter kernel
 // First arrow of every non-isolated vertex in every tree of a single-job LDS
 // launch (a.single, items [0, a.item_count)): a.pre[item * a.n_max + v] = the
 // tree word the LDS kernel's first round would write.  Vertex-major, so the
 // relabelled records and adjacency are read once per vertex tile for many trees.
 hipError_t launch_lds_predraw(const CoopArgs &a, hipStream_t stream);
-int lds_max_active(uint32_t threads, uint32_t lds_words);
+int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted);
 
 // Hybrid variant (ids widest class first: 32-bit fields end at e3, 16-bit at
 // e2, 8-bit at e1, then 4-bit): LDS fields and settled bits of ids [0, hot).
 hipError_t launch_wilson_hyb(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
                              hipStream_t stream);
 hipError_t hyb_set_limit(size_t bytes);
-int hyb_max_active(uint32_t threads, uint32_t lds_words);
+int hyb_max_active(uint32_t threads, uint32_t lds_words, bool weighted);
 struct HotLayout {
     uint32_t o2, o1, o0, ob, words;
 };
@@ -212,6 +233,8 @@ hipError_t launch_estimate(const uint32_t *R, int32_t n, uint32_t tau, int liter
 struct CgWork {
     const int32_t *row_ptr;
     const int32_t *col_idx;
+    const double *weights;  // edge weights (weighted Laplacian), or null
+    const double *wdeg;     // weighted degrees (with weights), or null
     uint32_t n, k;
     double alpha;
     uint32_t max_blocks;

@@ -1,5 +1,6 @@
 // fc_solve: block CG on (alpha L + I) X = B in binary64, or binary32 CG
 // inside binary64 iterative refinement (residual and update in binary64).
+// L is the Laplacian of the graph, weighted when the graph carries weights.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -51,6 +52,15 @@ extern "C" int fc_solve(fc_ctx *ctx, const fc_graph *g, double alpha, const doub
     fc::CgWork w{};
     w.row_ptr = gv.row_ptr;
     w.col_idx = gv.col_idx;
+    if (gv.weights) {  // weighted Laplacian: the weights and the weighted degrees
+        if ((rc = ensure(ctx, ctx->s_wdeg, 8 * static_cast<size_t>(n), "weighted degrees")))
+            return fail(rc);
+        FC_HIP(ctx, fc::launch_row_wdeg(gv.row_ptr, gv.weights, gv.n,
+                                        static_cast<double *>(ctx->s_wdeg.ptr), ctx->stream),
+               "weighted degrees");
+        w.weights = gv.weights;
+        w.wdeg = static_cast<const double *>(ctx->s_wdeg.ptr);
+    }
     w.n = n;
     w.k = k;
     w.alpha = alpha;

@@ -32,7 +32,8 @@ __global__ void validate_rows_kernel(const int32_t *__restrict__ row_ptr, int32_
 constexpr int64_t kColChunk = 16;
 
 __global__ void validate_cols_kernel(const int32_t *__restrict__ row_ptr,
-                                     const int32_t *__restrict__ col_idx, int32_t n, int64_t nnz,
+                                     const int32_t *__restrict__ col_idx,
+                                     const double *__restrict__ weights, int32_t n, int64_t nnz,
                                      unsigned int *err) {
     const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * kColChunk;
     if (e0 >= nnz) return;
@@ -65,24 +66,66 @@ __global__ void validate_cols_kernel(const int32_t *__restrict__ row_ptr,
             if (col_idx[mid] < v) a = mid + 1;
             else b = mid;
         }
-        if (a >= row_ptr[u + 1] || col_idx[a] != v) e |= kErrGraphAsymmetric;
+        if (a >= row_ptr[u + 1] || col_idx[a] != v) {
+            e |= kErrGraphAsymmetric;
+            continue;
+        }
+        if (weights) {  // 0 or in [2^-64, 2^64] (NaN fails both), equal to the reverse entry's
+            const double w = weights[j];
+            if (!(w == 0.0 || (w >= 0x1p-64 && w <= 0x1p64))) e |= kErrGraphWeight;
+            if (!(weights[a] == w)) e |= kErrGraphWeightAsym;
+        }
     }
     if (e) atomicOr(err, e);
 }
 
 // thr(d) = floor(2^32 * (1 / ((alpha * d) + 1))), each operation rounded to
 // binary64 (IEEE division; no contraction in this file).
-__device__ __forceinline__ unsigned long long root_threshold(double alpha, uint32_t d) {
-    if (d == 0) return 1ull << 32;
-    const double ad = alpha * static_cast<double>(d);
-    const double den = ad + 1.0;
+// The weighted threshold is the same expression in the weighted degree W
+// (an integer d is exact in binary64, so W = d gives thr(d)).
+__device__ __forceinline__ unsigned long long root_threshold_w(double alpha, double W) {
+    if (W == 0.0) return 1ull << 32;
+    const double aw = alpha * W;
+    const double den = aw + 1.0;
     const double p = 1.0 / den;
     return static_cast<unsigned long long>(p * 4294967296.0);
 }
+__device__ __forceinline__ unsigned long long root_threshold(double alpha, uint32_t d) {
+    return root_threshold_w(alpha, static_cast<double>(d));
+}
 
-__global__ void build_vrec_kernel(const int32_t *__restrict__ row_ptr, int32_t n, double alpha,
+// One thread per row; the sum is sequential by definition (its rounding is
+// part of the randomness contract), so rows are not split.
+__global__ void row_wsum_kernel(const int32_t *__restrict__ row_ptr,
+                                const double *__restrict__ weights, int32_t n,
+                                double *__restrict__ S) {
+    const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (v >= n) return;
+    const int32_t b = row_ptr[v], e = row_ptr[v + 1];
+    double s = 0.0;
+#pragma unroll 8
+    for (int32_t q = b; q < e; ++q) {
+        s += weights[q];
+        S[q] = s;
+    }
+}
+
+__global__ void row_wdeg_kernel(const int32_t *__restrict__ row_ptr,
+                                const double *__restrict__ weights, int32_t n,
+                                double *__restrict__ W) {
+    const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (v >= n) return;
+    const int32_t b = row_ptr[v], e = row_ptr[v + 1];
+    double s = 0.0;
+#pragma unroll 8
+    for (int32_t q = b; q < e; ++q) s += weights[q];
+    W[v] = s;
+}
+
+__global__ void build_vrec_kernel(const int32_t *__restrict__ row_ptr,
+                                  const double *__restrict__ S, int32_t n, double alpha,
                                   VRec *__restrict__ vrec, unsigned int *dmax,
-                                  uint32_t *__restrict__ iso) {
+                                  uint32_t *__restrict__ iso, double *wtotal) {
     const int32_t v = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
     uint32_t d = 0;
     int32_t a = 0;
@@ -100,8 +143,14 @@ __global__ void build_vrec_kernel(const int32_t *__restrict__ row_ptr, int32_t n
         if ((threadIdx.x & 63u) == 0 && w0 < nw) iso[w0] = static_cast<uint32_t>(bits);
         if ((threadIdx.x & 63u) == 32 && w0 + 1 < nw) iso[w0 + 1] = static_cast<uint32_t>(bits >> 32);
     }
+    const double W = S && d ? S[a + static_cast<int32_t>(d) - 1] : 0.0;
+    if (S && wtotal) {  // sum of the weighted degrees (bounds the expected walk length)
+        double sw = W;
+        for (int off = 32; off > 0; off >>= 1) sw += __shfl_down(sw, off, 64);
+        if ((threadIdx.x & 63u) == 0 && sw > 0.0) atomicAdd(wtotal, sw);
+    }
     if (v >= n) return;
-    const unsigned long long t = root_threshold(alpha, d);
+    const unsigned long long t = S ? root_threshold_w(alpha, W) : root_threshold(alpha, d);
     VRec r;
     r.start = a;
     r.deg = d;
@@ -129,18 +178,35 @@ hipError_t launch_validate_rows(const int32_t *row_ptr, int32_t n, int64_t nnz,
     return hipGetLastError();
 }
 
-hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
-                                int64_t nnz, unsigned int *err, hipStream_t stream) {
+hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx,
+                                const double *weights, int32_t n, int64_t nnz, unsigned int *err,
+                                hipStream_t stream) {
     if (n == 0 || nnz == 0) return hipSuccess;
     validate_cols_kernel<<<blocks_for((nnz + kColChunk - 1) / kColChunk, 256), 256, 0, stream>>>(
-        row_ptr, col_idx, n, nnz, err);
+        row_ptr, col_idx, weights, n, nnz, err);
     return hipGetLastError();
 }
 
-hipError_t launch_build_vrec(const int32_t *row_ptr, int32_t n, double alpha, VRec *vrec,
-                             unsigned int *dmax, uint32_t *iso, hipStream_t stream) {
+hipError_t launch_row_wsum(const int32_t *row_ptr, const double *weights, int32_t n, double *S,
+                           hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    build_vrec_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, n, alpha, vrec, dmax, iso);
+    row_wsum_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, weights, n, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_wdeg(const int32_t *row_ptr, const double *weights, int32_t n, double *W,
+                           hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    row_wdeg_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, weights, n, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_vrec(const int32_t *row_ptr, const double *S, int32_t n, double alpha,
+                             VRec *vrec, unsigned int *dmax, uint32_t *iso, double *wtotal,
+                             hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    build_vrec_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, S, n, alpha, vrec, dmax,
+                                                              iso, wtotal);
     return hipGetLastError();
 }
 

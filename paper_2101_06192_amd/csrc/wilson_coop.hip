@@ -90,13 +90,15 @@ enum Phase : int { kPhDraw0 = 0, kPhIndeg, kPhLevel0, kPhPeel, kPhSweep, kPhRedr
 // so that what depends on it lives in scalar registers.
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// One arrow of v in tree t with draw index k.
+// One arrow of v in tree t with draw index k (kWeighted: the job may carry
+// running weight sums).
+template <bool kWeighted>
 __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32_t key1,
                                          uint32_t v, uint32_t k, uint32_t t) {
     const VRec r = load_vrec(j.vrec, v);
     if (r.always_root) return j.n;  // the arrow is u* whatever the Philox words are
     const Philox4 x = philox4x32_10(v, k, t, j.stream_id, key0, key1);
-    return arrow_target(r, x.x0, x.x1, j.col_idx, j.n);
+    return arrow_target<kWeighted>(r, x.x0, x.x1, j.col_idx, j.wsum, j.n);
 }
 
 // Work items are trees; a single-graph launch has one implicit job, a batch
@@ -105,7 +107,7 @@ __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32
 // still have in-arrows in the current round -- set while counting, cleared
 // when the vertex is peeled -- so peel level 0 and cycle detection read LDS
 // instead of the global tree words.
-template <bool kLdsBits, typename W, bool kInBits>
+template <bool kLdsBits, typename W, bool kInBits, bool kWeighted>
 // At most 512 threads, and registers for six waves per SIMD (24 per CU):
 // the phases are latency bound, so resident waves matter more than unrolling.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6)))
@@ -193,7 +195,7 @@ void wilson_coop_kernel(CoopArgs a) {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const uint32_t v = base + q * T + lane;
-                tg[q] = v < n ? draw(job, a.key0, a.key1, v, 0u, t) : n;
+                tg[q] = v < n ? draw<kWeighted>(job, a.key0, a.key1, v, 0u, t) : n;
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
@@ -431,7 +433,7 @@ void wilson_coop_kernel(CoopArgs a) {
                 }
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    tg[q] = v[q] < n ? draw(job, a.key0, a.key1, v[q], k[q], t) : n;
+                    tg[q] = v[q] < n ? draw<kWeighted>(job, a.key0, a.key1, v[q], k[q], t) : n;
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     if (v[q] < n) {
@@ -511,24 +513,31 @@ void wilson_coop_kernel(CoopArgs a) {
 
 size_t coop_lds_bytes(uint32_t n) { return 4u * ((static_cast<size_t>(n) + 31u) >> 5); }
 
-template <bool kLds, typename W, bool kIn>
+template <bool kLds, typename W, bool kIn, bool kWt>
 hipError_t launch_one(const CoopArgs &a, uint32_t threads, hipStream_t stream) {
     const size_t lds = kLds ? (kIn ? 2 : 1) * coop_lds_bytes(a.n_max) : 0;
-    wilson_coop_kernel<kLds, W, kIn><<<a.slots, threads, lds, stream>>>(a);
+    wilson_coop_kernel<kLds, W, kIn, kWt><<<a.slots, threads, lds, stream>>>(a);
     return hipGetLastError();
 }
 
-template <typename W>
+template <typename W, bool kWt>
 const void *kernel_of(bool lds_bits, bool in_bits) {
-    if (!lds_bits) return reinterpret_cast<const void *>(&wilson_coop_kernel<false, W, false>);
-    return in_bits ? reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, true>)
-                   : reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, false>);
+    if (!lds_bits) return reinterpret_cast<const void *>(&wilson_coop_kernel<false, W, false, kWt>);
+    return in_bits ? reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, true, kWt>)
+                   : reinterpret_cast<const void *>(&wilson_coop_kernel<true, W, false, kWt>);
 }
 
-int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max) {
+template <bool kWt>
+const void *kernel_of(bool lds_bits, bool in_bits, bool word32) {
+    return word32 ? kernel_of<uint32_t, kWt>(lds_bits, in_bits)
+                  : kernel_of<unsigned long long, kWt>(lds_bits, in_bits);
+}
+
+int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max,
+                    bool weighted) {
     const size_t lds = lds_bits ? (in_bits ? 2 : 1) * coop_lds_bytes(n_max) : 0;
-    const void *f = word32 ? kernel_of<uint32_t>(lds_bits, in_bits)
-                           : kernel_of<unsigned long long>(lds_bits, in_bits);
+    const void *f = weighted ? kernel_of<true>(lds_bits, in_bits, word32)
+                             : kernel_of<false>(lds_bits, in_bits, word32);
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, static_cast<int>(threads), lds) !=
         hipSuccess)
@@ -538,28 +547,34 @@ int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, 
 
 hipError_t coop_set_lds_limit(size_t bytes) {
     const int lim = static_cast<int>(bytes);
-    const void *fs[] = {kernel_of<uint32_t>(false, false), kernel_of<uint32_t>(true, false),
-                        kernel_of<uint32_t>(true, true), kernel_of<unsigned long long>(false, false),
-                        kernel_of<unsigned long long>(true, false),
-                        kernel_of<unsigned long long>(true, true)};
-    for (const void *f : fs) {
+    for (int m = 0; m < 12; ++m) {
+        const bool lds_bits = (m % 3) != 0, in_bits = (m % 3) == 2, word32 = (m / 3) % 2 == 0;
+        const void *f = m < 6 ? kernel_of<false>(lds_bits, in_bits, word32)
+                              : kernel_of<true>(lds_bits, in_bits, word32);
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
-                              bool word32, hipStream_t stream) {
-    if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
+template <bool kWt>
+hipError_t launch_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
+                       bool word32, hipStream_t stream) {
     if (lds_bits && in_bits)
-        return word32 ? launch_one<true, uint32_t, true>(a, threads, stream)
-                      : launch_one<true, unsigned long long, true>(a, threads, stream);
+        return word32 ? launch_one<true, uint32_t, true, kWt>(a, threads, stream)
+                      : launch_one<true, unsigned long long, true, kWt>(a, threads, stream);
     if (lds_bits)
-        return word32 ? launch_one<true, uint32_t, false>(a, threads, stream)
-                      : launch_one<true, unsigned long long, false>(a, threads, stream);
-    return word32 ? launch_one<false, uint32_t, false>(a, threads, stream)
-                  : launch_one<false, unsigned long long, false>(a, threads, stream);
+        return word32 ? launch_one<true, uint32_t, false, kWt>(a, threads, stream)
+                      : launch_one<true, unsigned long long, false, kWt>(a, threads, stream);
+    return word32 ? launch_one<false, uint32_t, false, kWt>(a, threads, stream)
+                  : launch_one<false, unsigned long long, false, kWt>(a, threads, stream);
+}
+
+hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
+                              bool word32, bool weighted, hipStream_t stream) {
+    if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
+    return weighted ? launch_coop<true>(a, threads, lds_bits, in_bits, word32, stream)
+                    : launch_coop<false>(a, threads, lds_bits, in_bits, word32, stream);
 }
 
 }  // namespace fc

@@ -75,17 +75,20 @@ __device__ __forceinline__ Field hot_field(const HotClasses c, uint32_t x) {
 }
 
 // Arrow number k of the vertex with (relabelled) record r in tree t:
-// internal | original target (u* = n in both).
+// internal | original target (u* = n in both).  kWeighted: the job carries
+// running weight sums (weighted step).
+template <bool kWeighted>
 __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32_t key0,
                                          uint32_t key1, uint32_t k, uint32_t t) {
     if (r.always_root >> 31) return pair(j.n, j.n);
     const uint32_t orig = r.always_root & 0x7FFFFFFFu;
     const Philox4 x = philox4x32_10(orig, k, t, j.stream_id, key0, key1);
     if (x.x0 < r.thr) return pair(j.n, j.n);
-    const uint32_t idx = __umulhi(x.x1, r.deg);
+    const uint32_t idx = neighbour_entry<kWeighted>(r, x.x1, j.wsum);
     return j.adj[r.start + static_cast<int32_t>(idx)];
 }
 
+template <bool kWeighted>
 __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_lds[];
     __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev;
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
                 w[q] = pair(n, n);
-                if (v < nl) w[q] = draw(job, r[q], a.key0, a.key1, 0u, t);
+                if (v < nl) w[q] = draw<kWeighted>(job, r[q], a.key0, a.key1, 0u, t);
             }
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
@@ -451,7 +454,8 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
                 }
 #pragma unroll
                 for (int q = 0; q < kRD; ++q)
-                    w[q] = v[q] < n ? draw(job, load_vrec(job.vrec, v[q]), a.key0, a.key1, k[q], t)
+                    w[q] = v[q] < n ? draw<kWeighted>(job, load_vrec(job.vrec, v[q]), a.key0,
+                                                      a.key1, k[q], t)
                                     : pair(n, n);
 #pragma unroll
                 for (int q = 0; q < kRD; ++q) {
@@ -560,15 +564,21 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
 }  // namespace
 
 hipError_t hyb_set_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_hyb_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_hyb_kernel<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_hyb_kernel<true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
-int hyb_max_active(uint32_t threads, uint32_t lds_words) {
+int hyb_max_active(uint32_t threads, uint32_t lds_words, bool weighted) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &blocks, reinterpret_cast<const void *>(&wilson_hyb_kernel), static_cast<int>(threads),
-            4u * static_cast<size_t>(lds_words)) != hipSuccess)
+    const void *f = weighted ? reinterpret_cast<const void *>(&wilson_hyb_kernel<true>)
+                             : reinterpret_cast<const void *>(&wilson_hyb_kernel<false>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, static_cast<int>(threads),
+                                                     4u * static_cast<size_t>(lds_words)) !=
+        hipSuccess)
         return 0;
     return blocks;
 }
@@ -576,7 +586,9 @@ int hyb_max_active(uint32_t threads, uint32_t lds_words) {
 hipError_t launch_wilson_hyb(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
                              hipStream_t stream) {
     if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
-    wilson_hyb_kernel<<<a.slots, threads, 4u * static_cast<size_t>(lds_words), stream>>>(a);
+    const size_t lds = 4u * static_cast<size_t>(lds_words);
+    if (a.single.wsum) wilson_hyb_kernel<true><<<a.slots, threads, lds, stream>>>(a);
+    else wilson_hyb_kernel<false><<<a.slots, threads, lds, stream>>>(a);
     return hipGetLastError();
 }
 

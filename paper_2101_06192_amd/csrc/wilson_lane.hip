@@ -22,6 +22,7 @@ namespace {
 
 enum : uint32_t { kScan = 0, kWalk = 1, kRetrace = 2 };
 
+template <bool kWeighted>
 __global__ __launch_bounds__(64) void wilson_lane_kernel(LaneArgs a) {
     const uint32_t lane = threadIdx.x;
     if (lane >= a.lanes_per_wave) return;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(64) void wilson_lane_kernel(LaneArgs a) {
                 const uint32_t k = sw::visits(w, ep);
                 const VRec r = load_vrec(vrec, cur);
                 const Philox4 x = philox4x32_10(cur, k, t, a.stream_id, a.key0, a.key1);
-                const uint32_t nxt = arrow_target(r, x.x0, x.x1, col, n);
+                const uint32_t nxt = arrow_target<kWeighted>(r, x.x0, x.x1, col, a.wsum, n);
                 if (k + 1 > a.k_limit) err |= kErrVisitOverflow;
                 st[cur] = sw::pack(nxt, k + 1, ep);
                 if (++steps > a.step_cap) {  // never reached by a valid walk; keeps the kernel finite
@@ -129,7 +130,8 @@ hipError_t launch_wilson_lane(const LaneArgs &a, hipStream_t stream) {
     if (a.n == 0 || a.tree_count == 0 || a.slots == 0) return hipSuccess;
     const uint32_t lpw = a.lanes_per_wave;
     const uint32_t blocks = (a.slots + lpw - 1) / lpw;
-    wilson_lane_kernel<<<blocks, 64, 0, stream>>>(a);
+    if (a.wsum) wilson_lane_kernel<true><<<blocks, 64, 0, stream>>>(a);
+    else wilson_lane_kernel<false><<<blocks, 64, 0, stream>>>(a);
     return hipGetLastError();
 }
 

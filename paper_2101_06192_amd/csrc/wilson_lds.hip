@@ -91,13 +91,15 @@ __device__ __forceinline__ Field field_of(const Classes &c, uint32_t x) {
 
 // Arrow number k (0-based) of the vertex with record r in tree t: its tree
 // word with draw count k + 1 (internal | original target; u* = n in both).
+// kWeighted: the job may carry running weight sums (weighted step).
+template <bool kWeighted>
 __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32_t key0,
                                          uint32_t key1, uint32_t k, uint32_t t) {
     const uint32_t orig = r.always_root & 0x7FFFFFFFu;
     const Philox4 x = philox4x32_10(orig, k, t, j.stream_id, key0, key1);
     const uint64_t kbits = static_cast<uint64_t>(k + 1u) << kKShift;
     if ((r.always_root >> 31) || x.x0 < r.thr) return pack(j.n, j.n, 0u) | kbits;
-    const uint32_t idx = __umulhi(x.x1, r.deg);
+    const uint32_t idx = neighbour_entry<kWeighted>(r, x.x1, j.wsum);
     return j.adj[r.start + static_cast<int32_t>(idx)] | kbits;
 }
 
@@ -111,6 +113,7 @@ constexpr int kRC = 2;
 // (up to 64 kTailRegs entries).
 constexpr int kTailRegs = 6;
 
+template <bool kWeighted>
 __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_lds[];
     __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev;
@@ -234,7 +237,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 #pragma unroll
             for (int q = 0; q < kRD; ++q) {
                 const uint32_t v = base + q * T + lane;
-                w[q] = v < nl ? draw(job, r[q], a.key0, a.key1, 0u, t) : pack(n, n, 0u);
+                w[q] = v < nl ? draw<kWeighted>(job, r[q], a.key0, a.key1, 0u, t)
+                              : pack(n, n, 0u);
             }
             bool live[kRD];
 #pragma unroll
@@ -520,7 +524,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                         err |= kErrVisitOverflow;
                         v[q] = n;
                     }
-                    w[q] = v[q] < n ? draw(job, r[q], a.key0, a.key1, k[q], t) : pack(n, n, 0u);
+                    w[q] = v[q] < n ? draw<kWeighted>(job, r[q], a.key0, a.key1, k[q], t)
+                                    : pack(n, n, 0u);
                 }
                 bool live[kRC];
 #pragma unroll
@@ -622,6 +627,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 constexpr uint32_t kPreTrees = 16;
 constexpr uint32_t kPreThreads = 256;
 
+template <bool kWeighted>
 __global__ __launch_bounds__(kPreThreads) void lds_predraw_kernel(CoopArgs a, uint32_t groups) {
     const CoopJob &job = a.single;
     const uint32_t v = blockIdx.x * kPreThreads + threadIdx.x;
@@ -634,7 +640,7 @@ __global__ __launch_bounds__(kPreThreads) void lds_predraw_kernel(CoopArgs a, ui
             const uint32_t item = i0 + q;
             if (item < a.item_count)
                 a.pre[static_cast<size_t>(item) * a.n_max + v] =
-                    draw(job, r, a.key0, a.key1, 0u, job.tree_begin + item);
+                    draw<kWeighted>(job, r, a.key0, a.key1, 0u, job.tree_begin + item);
         }
     }
 }
@@ -649,28 +655,37 @@ hipError_t launch_lds_predraw(const CoopArgs &a, hipStream_t stream) {
     tiles = (tiles + 7u) & ~7u;
     const uint32_t groups = (a.item_count + kPreTrees - 1) / kPreTrees;
     const dim3 grid(tiles, groups < 65535u ? groups : 65535u);
-    lds_predraw_kernel<<<grid, kPreThreads, 0, stream>>>(a, groups);
+    if (a.single.wsum) lds_predraw_kernel<true><<<grid, kPreThreads, 0, stream>>>(a, groups);
+    else lds_predraw_kernel<false><<<grid, kPreThreads, 0, stream>>>(a, groups);
     return hipGetLastError();
 }
 
 hipError_t lds_set_limit(size_t bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_lds_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_lds_kernel<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(bytes));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_lds_kernel<true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
-int lds_max_active(uint32_t threads, uint32_t lds_words) {
+int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &blocks, reinterpret_cast<const void *>(&wilson_lds_kernel), static_cast<int>(threads),
-            4u * static_cast<size_t>(lds_words)) != hipSuccess)
+    const void *f = weighted ? reinterpret_cast<const void *>(&wilson_lds_kernel<true>)
+                             : reinterpret_cast<const void *>(&wilson_lds_kernel<false>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, static_cast<int>(threads),
+                                                     4u * static_cast<size_t>(lds_words)) !=
+        hipSuccess)
         return 0;
     return blocks;
 }
 
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
-                             hipStream_t stream) {
+                             bool weighted, hipStream_t stream) {
     if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
-    wilson_lds_kernel<<<a.slots, threads, 4u * static_cast<size_t>(lds_words), stream>>>(a);
+    const size_t lds = 4u * static_cast<size_t>(lds_words);
+    if (weighted) wilson_lds_kernel<true><<<a.slots, threads, lds, stream>>>(a);
+    else wilson_lds_kernel<false><<<a.slots, threads, lds, stream>>>(a);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@ error strings) behaves as documented.  No compute call is made here."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -71,7 +72,7 @@ def test_null_context_arguments():
     assert L.fc_set_stream(None, None) == fc.FC_ERR_ARG
     assert L.fc_set_option(None, b"coop_threads", 256) == fc.FC_ERR_ARG
     st = fc.fc_stats()
-    gs = fc.fc_graph(1, 0, ctypes.c_void_p(1), None, 0)
+    gs = fc.fc_graph(1, 0, ctypes.c_void_p(1), None, None, 0)
     ps = fc.fc_params(1.0, 0.1, 0.1, 0.0, 0, 1, 0, 0, 0)
     assert L.fc_sample(None, ctypes.byref(gs), ctypes.byref(ps), 0, 1, None, None, None,
                        None, None, None, ctypes.byref(st)) == fc.FC_ERR_ARG
@@ -90,9 +91,34 @@ def test_create_without_gpu_fails_cleanly():
 
 def test_struct_layouts():
     # field offsets must agree with the C declarations in include/fc.h
-    assert ctypes.sizeof(fc.fc_graph) == 40
-    assert fc.fc_graph.nnz.offset == 8 and fc.fc_graph.mem.offset == 32
+    assert ctypes.sizeof(fc.fc_graph) == 48
+    assert fc.fc_graph.nnz.offset == 8 and fc.fc_graph.weights.offset == 32
+    assert fc.fc_graph.mem.offset == 40
     assert ctypes.sizeof(fc.fc_params) == 56
     assert fc.fc_params.seed.offset == 32 and fc.fc_params.flags.offset == 52
     assert ctypes.sizeof(fc.fc_stats) == 136 and fc.fc_stats.ms_predraw.offset == 128
-    assert ctypes.sizeof(fc.fc_job) == 80 and fc.fc_job.root_counts.offset == 64
+    assert ctypes.sizeof(fc.fc_job) == 88 and fc.fc_job.root_counts.offset == 72
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    # every ctypes field offset and struct size against offsetof / sizeof from
+    # a C program compiled against include/fc.h
+    structs = [fc.fc_graph, fc.fc_params, fc.fc_stats, fc.fc_job]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "fc.h"', 'int main(void) {']
+    for st in structs:
+        name = st.__name__
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, (name, f)
