@@ -32,6 +32,9 @@ WORKLOAD = {"workload": "ba_n200000_m5_alpha1_trees4096", "graph": "barabasi_alb
 #   start scan  : read the state word of each start candidate        =  8 B
 #   root        : read-modify-write of R[v] (4 + 4)                  =  8 B
 BYTES_STEP, BYTES_RETRACE, BYTES_SCAN, BYTES_ROOT = 28, 16, 8, 8
+# weighted graphs: a walk step also reads the weighted degree of v and the
+# running weight sum of the entry it takes (8 + 8)                  = 44 B
+BYTES_STEP_W = 44
 HBM_PEAK_GBS = 8000.0
 
 CSRC = os.path.join(ROOT, "paper_2101_06192_amd", "csrc")
@@ -46,10 +49,10 @@ def _kernel_hash(sampler: str) -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(sampler: str):
+def _traffic(sampler: str, workload: str = "ba200k"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{sampler}_ba200k_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{sampler}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -107,7 +110,8 @@ def main():
     ap.add_argument("--no-eps", action="store_true", help="skip the time-to-eps=0.1 leg")
     ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop", "lds", "hyb"])
     ap.add_argument("--config", default="ba200k",
-                    choices=["ba200k", "er1000", "grid1000", "rmat_batch", "rmat22", "solve"],
+                    choices=["ba200k", "ba200k_w", "er1000", "grid1000", "rmat_batch", "rmat22",
+                             "solve"],
                     help="workload; the default is the headline configuration")
     ap.add_argument("--phase-timing", action="store_true",
                     help="report per-phase times of the workgroup sampler (adds clock reads)")
@@ -239,14 +243,19 @@ def main():
             "ceiling_loads_per_s": ceiling["random_loads_per_s"],
             "frac": rate / ceiling["random_loads_per_s"]}
     if args.phase_timing:
-        if sampler == "wilson_lds":
-            names = ["first_arrows", "count_and_level0", "peel_wide", "peel_tail",
-                     "sweep_and_split", "cycle_scan", "cycles", "output"]
-        else:
-            names = ["first_arrows", "in_arrows", "peel_level0", "peel_levels", "sweep", "redraw",
-                     "output"]
-        line["phase_ms_per_workgroup"] = dict(zip(names, stats[-1]["phase_ms"]))
+        line["phase_ms_per_workgroup"] = _phases(stats[-1])
     print(json.dumps(line), flush=True)
+
+
+def _phases(st):
+    """Per-phase wall time per workgroup of a workgroup sampler's call."""
+    if st["sampler"] == "wilson_lds":
+        names = ["first_arrows", "count_and_level0", "peel_wide", "peel_tail",
+                 "sweep_and_split", "cycle_scan", "cycles", "output"]
+    else:
+        names = ["first_arrows", "in_arrows", "peel_level0", "peel_levels", "sweep", "redraw",
+                 "output"]
+    return dict(zip(names, st["phase_ms"]))
 
 
 def _timed(fn, steps, warmup):
@@ -295,6 +304,50 @@ def other_config(args, fc, inputs, dev):
             import torch
             torch.cuda.synchronize()
             res["time_to_eps0.1_diag"] = {"tau": o["tau"], "ms": 1000 * (time.perf_counter() - te)}
+    elif args.config == "ba200k_w":
+        # the headline graph with seeded log-uniform edge weights in [0.1, 10)
+        g = inputs.with_weights(inputs.barabasi_albert(200_000, 5, 0), 0)
+        dg = fc.to_device(g, dev)
+        trees, alpha = 4096, 1.0
+        stats = []
+
+        def step():
+            out = fc.farness(dg, alpha=alpha, tau=trees, device=dev, as_torch=True,
+                             sampler=args.sampler)
+            stats.append(out["stats"])
+            return out
+        dt, out = _timed(step, args.steps, args.warmup)
+        st = out["stats"]
+        timed = stats[args.warmup:]
+        ms_kernel = float(np.mean([s["ms_sample"] for s in timed]))
+        ms_pre = float(np.mean([s.get("ms_predraw", 0.0) for s in timed]))
+        alg = (BYTES_STEP_W * st["walk_steps"] + (BYTES_RETRACE + BYTES_SCAN) * g.n * trees
+               + BYTES_ROOT * st["roots"])
+        ach = alg / (ms_kernel / 1000.0) / 1e9
+        eps_leg = None
+        if not args.no_eps:
+            import torch
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            o = fc.diag_estimate(dg, alpha=alpha, eps=0.1, delta=0.1, device=dev, as_torch=True,
+                                 sampler=args.sampler)
+            torch.cuda.synchronize()
+            eps_leg = {"tau": o["tau"], "ms": 1000 * (time.perf_counter() - te)}
+        res.update({"value": trees / dt, "unit": "trees/s", "ms_per_step": 1000 * dt,
+                    "config": {"workload": "ba_n200000_m5_logw0.1_10_alpha1_trees4096", "n": g.n,
+                               "m": g.m, "alpha": alpha, "trees": trees},
+                    "sampler": st["sampler"], "walk_steps_per_tree": st["walk_steps"] / trees,
+                    "walk_steps_per_s": st["walk_steps"] / dt,
+                    "time_to_eps0.1_diag": eps_leg,
+                    "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                 "traffic": _traffic(st["sampler"], "ba200k_w"),
+                                 "kernel_ms": ms_kernel,
+                                 "kernels_ms": {"lds_predraw_kernel": ms_pre,
+                                                f"{st['sampler']}_kernel": ms_kernel - ms_pre},
+                                 "algorithmic_bytes_per_launch": alg}})
+        if args.phase_timing:
+            res["phase_ms_per_workgroup"] = _phases(st)
     elif args.config == "grid1000":
         g = inputs.grid_removed(1000, 1000, 0.12, 0)
         dg = fc.to_device(g, dev)

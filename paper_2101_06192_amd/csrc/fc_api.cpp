@@ -143,15 +143,23 @@ int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out) 
     return FC_OK;
 }
 
-int row_wsum(fc_ctx *ctx, const GraphView &g, DevBuf &buf, const double **S) {
+int weight_tables(fc_ctx *ctx, const GraphView &g, DevBuf &sbuf, DevBuf &tbuf, const double **S,
+                  const uint32_t **T) {
     *S = nullptr;
+    *T = nullptr;
     if (!g.weights || g.nnz == 0) return FC_OK;
-    int rc = ensure(ctx, buf, sizeof(double) * static_cast<size_t>(g.nnz), "row weight sums");
-    if (rc) return rc;
-    FC_HIP(ctx, fc::launch_row_wsum(g.row_ptr, g.weights, g.n, static_cast<double *>(buf.ptr),
-                                    ctx->stream),
-           "row weight sums");
-    *S = static_cast<const double *>(buf.ptr);
+    const size_t nnz = static_cast<size_t>(g.nnz);
+    int rc;
+    if ((rc = ensure(ctx, sbuf, sizeof(double) * nnz, "row weight sums")) ||
+        (rc = ensure(ctx, tbuf, sizeof(uint32_t) * (nnz + fc::kWeightedScan), "step thresholds")))
+        return rc;
+    double *s = static_cast<double *>(sbuf.ptr);
+    uint32_t *t = static_cast<uint32_t *>(tbuf.ptr);
+    FC_HIP(ctx, fc::launch_row_wsum(g.row_ptr, g.weights, g.n, s, ctx->stream), "row weight sums");
+    FC_HIP(ctx, fc::launch_step_thresholds(g.row_ptr, s, g.n, g.nnz, t, ctx->stream),
+           "step thresholds");
+    *S = s;
+    *T = t;
     return FC_OK;
 }
 
@@ -193,7 +201,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     if ((rc = ensure(ctx, ctx->iso, 4u * ((static_cast<size_t>(g.n) + 31u) / 32u), "isolated bitmap")))
         return rc;
     const double *wsum = nullptr;
-    if ((rc = row_wsum(ctx, g, ctx->wsum, &wsum))) return rc;
+    const uint32_t *wthr = nullptr;
+    if ((rc = weight_tables(ctx, g, ctx->wsum, ctx->wthr, &wsum, &wthr))) return rc;
     const bool weighted = wsum != nullptr;
     FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, wsum, g.n, p->alpha, vrec, &sm->dmax,
                                       static_cast<uint32_t *>(ctx->iso.ptr), &sm->wtotal,
@@ -360,6 +369,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             j.vrec = static_cast<const fc::VRec *>(ctx->rl_vrec.ptr);
             j.col_idx = g.col_idx;
             j.wsum = wsum;
+            j.wthr = wthr;
             j.adj = static_cast<const unsigned long long *>(ctx->rl_adj.ptr);
             j.orig = static_cast<const uint32_t *>(ctx->rl_orig.ptr);
             j.n = static_cast<uint32_t>(g.n);
@@ -447,6 +457,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             j.vrec = static_cast<const fc::VRec *>(ctx->rl_vrec.ptr);
             j.col_idx = g.col_idx;
             j.wsum = wsum;
+            j.wthr = wthr;
             j.adj = static_cast<const unsigned long long *>(ctx->rl_adj.ptr);
             j.orig = static_cast<const uint32_t *>(ctx->rl_orig.ptr);
             j.n = static_cast<uint32_t>(g.n);
@@ -526,6 +537,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         j.vrec = vrec;
         j.col_idx = g.col_idx;
         j.wsum = wsum;
+        j.wthr = wthr;
         j.iso = static_cast<const uint32_t *>(ctx->iso.ptr);
         j.tree_count = tree_count;
         j.n = static_cast<uint32_t>(g.n);
@@ -552,6 +564,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         a.vrec = vrec;
         a.col_idx = g.col_idx;
         a.wsum = wsum;
+        a.wthr = wthr;
         a.state = static_cast<uint64_t *>(ctx->state.ptr);
         a.n = static_cast<uint32_t>(g.n);
         a.slots = static_cast<uint32_t>(slots);
@@ -749,7 +762,8 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->cbits, &ctx->s_r64, &ctx->s_r, &ctx->s_z, &ctx->s_p, &ctx->s_q,
                       &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small, &ctx->rl_blk,
                       &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
-                      &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->s_wdeg})
+                      &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->wthr,
+                      &ctx->s_wdeg})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

@@ -47,8 +47,8 @@ struct fc_batch {
     std::vector<fc_job> jobs;
     uint64_t seed = 0;
     int32_t flags = 0;
-    DevBuf vrec, dmax, iso, wsum, wtot;  // running row weight sums of the weighted graphs and
-                                         // each job's weighted volume
+    DevBuf vrec, dmax, iso, wsum, wthr, wtot;  // weighted graphs' running row sums and step
+                                               // thresholds, each job's weighted volume
     DevBuf rl_blk, rl_base, rl_bounds, rl_inv, rl_orig, rl_adj, rl_vrec;  // degree-class relabelling
     Group grp[2];
     int ngroups = 0;
@@ -66,7 +66,7 @@ int free_batch(fc_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (DevBuf *d : {&b->vrec, &b->dmax, &b->iso, &b->wsum, &b->wtot, &b->rl_blk, &b->rl_base, &b->rl_bounds, &b->rl_inv,
+    for (DevBuf *d : {&b->vrec, &b->dmax, &b->iso, &b->wsum, &b->wthr, &b->wtot, &b->rl_blk, &b->rl_base, &b->rl_bounds, &b->rl_inv,
                       &b->rl_orig, &b->rl_adj, &b->rl_vrec})
         if (d->ptr) (void)hipFree(d->ptr);
     for (Group &g : b->grp)
@@ -327,16 +327,27 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
     // its CSR entries), then the records with weighted root thresholds
     bool any_weighted = false;
     for (const GInfo &gi : gs) any_weighted = any_weighted || gi.w;
-    if (any_weighted && (rc = ensure(ctx, b->wsum, 8 * std::max<size_t>(te, 1), "batch weight sums")))
+    if (any_weighted &&
+        ((rc = ensure(ctx, b->wsum, 8 * std::max<size_t>(te, 1), "batch weight sums")) ||
+         (rc = ensure(ctx, b->wthr, 4 * (te + fc::kWeightedScan), "batch step thresholds"))))
         return fail(rc);
     double *wsum = static_cast<double *>(b->wsum.ptr);
+    uint32_t *wthr = static_cast<uint32_t *>(b->wthr.ptr);
     for (const GInfo &gi : gs)
-        if (gi.w)
+        if (gi.w) {
             FB_HIP(fc::launch_row_wsum(gi.rp, gi.w, static_cast<int32_t>(gi.n), wsum + gi.off_e,
                                        b->stream), "row weight sums");
+            FB_HIP(fc::launch_step_thresholds(gi.rp, wsum + gi.off_e, static_cast<int32_t>(gi.n),
+                                              gi.nnz, wthr + gi.off_e, b->stream),
+                   "step thresholds");
+        }
     auto wsum_of = [&](size_t k) -> const double * {
         const GInfo &gi = gs[gof[k]];
         return gi.w ? wsum + gi.off_e : nullptr;
+    };
+    auto wthr_of = [&](size_t k) -> const uint32_t * {
+        const GInfo &gi = gs[gof[k]];
+        return gi.w ? wthr + gi.off_e : nullptr;
     };
     for (size_t k = 0; k < order.size(); ++k) {
         const fc_job &j = b->jobs[order[k]];
@@ -447,6 +458,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
             c.vrec = vrec + voff[k];
             c.col_idx = j.graph.col_idx;
             c.wsum = wsum_of(k);
+            c.wthr = wthr_of(k);
             c.n = static_cast<uint32_t>(j.graph.n);
             c.tree_count = j.tree_count;
             c.iso = use_lds ? nullptr : iso + ioff[k];

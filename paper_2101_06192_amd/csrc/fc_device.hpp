@@ -65,14 +65,21 @@ __device__ __forceinline__ VRec load_vrec(const VRec *__restrict__ vrec, uint32_
 
 
 // Weighted step (Section 2's non-negative edge weights; a walk leaves v along
-// an edge with probability proportional to its weight): the 0-based entry of
-// v's row taken for Philox word x1, given the row's running weight sums
-// S[0..deg) (binary64, added in CSR order from 0, so S[deg - 1] = W_v): the
-// first entry with u < S[i], u = (x1 * W_v) * 2^-32.  Needs W_v > 0 (a vertex
-// with W_v = 0 always steps to u*); with W_v in [2^-64, 2^95] u < W_v holds,
-// so the entry exists.  S is non-decreasing, so a binary search finds it.
-__device__ __forceinline__ uint32_t weighted_entry(const double *__restrict__ S, uint32_t deg,
-                                                   uint32_t x1) {
+// an edge with probability proportional to its weight).  With S[0..deg) the
+// row's running weight sums (binary64, added in CSR order from 0, so
+// S[deg - 1] = W_v > 0) the step takes the first entry i with u < S[i],
+// u = (x1 * W_v) * 2^-32.  With W_v in [2^-64, 2^95], u < W_v for every x1,
+// so the entry exists.
+//
+// u(x) is non-decreasing in the integer x (a product by a positive constant
+// and rounding are both monotone), so {x : u(x) < S[i]} is a prefix [0, T_i)
+// of the integers, T_i in [0, 2^32], non-decreasing in i.  The tables hold
+// T_i clamped to [1, 2^32 - 1] (launch_step_thresholds), which decides
+// "x1 < T_i" exactly for every x1 in [1, 2^32 - 2]; the two extreme words
+// (probability 2^-31) take the binary64 search over S instead.  Either way
+// the entry is the contract's, bit for bit.
+__device__ __forceinline__ uint32_t weighted_entry_exact(const double *__restrict__ S,
+                                                         uint32_t deg, uint32_t x1) {
     const double W = S[deg - 1];
     const double u = (static_cast<double>(x1) * W) * 0x1p-32;
     uint32_t lo = 0, hi = deg - 1;
@@ -84,12 +91,61 @@ __device__ __forceinline__ uint32_t weighted_entry(const double *__restrict__ S,
     return lo;
 }
 
+// T is scanned in chunks of kWeightedScan entries with unconditional loads:
+// every threshold table carries kWeightedScan entries of padding after its
+// last row, so a chunk that runs past the row (or the table) stays in bounds;
+// entries past the row are masked out of the count.
+constexpr uint32_t kWeightedScan = 8;
+
+// First i in [base, m) of the chunk t = T[base .. base + kWeightedScan) with
+// x1 < T[i], or m: the entries of the chunk below m that are <= x1, counted
+// (T is non-decreasing).
+__device__ __forceinline__ uint32_t weighted_chunk_count(const uint32_t (&t)[kWeightedScan],
+                                                         uint32_t base, uint32_t m, uint32_t x1) {
+    uint32_t c = base;
+#pragma unroll
+    for (uint32_t i = 0; i < kWeightedScan; ++i) c += (base + i < m && t[i] <= x1) ? 1u : 0u;
+    return c;
+}
+
+__device__ __forceinline__ void load_chunk(const uint32_t *__restrict__ T,
+                                           uint32_t (&t)[kWeightedScan]) {
+#pragma unroll
+    for (uint32_t i = 0; i < kWeightedScan; ++i) t[i] = T[i];
+}
+
+// Chunk of the answer in a row of m > kWeightedScan candidates: the first
+// chunk whose last entry exceeds x1 (binary search over chunk ends), or the
+// last chunk.
+__device__ __forceinline__ uint32_t weighted_chunk(const uint32_t *__restrict__ T, uint32_t m,
+                                                   uint32_t x1) {
+    uint32_t lo = 0, hi = (m - 1) / kWeightedScan;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (x1 < T[mid * kWeightedScan + kWeightedScan - 1]) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo * kWeightedScan;
+}
+
+__device__ __forceinline__ uint32_t weighted_entry(const double *__restrict__ S,
+                                                   const uint32_t *__restrict__ T, uint32_t deg,
+                                                   uint32_t x1) {
+    if (x1 - 1u >= 0xFFFFFFFEu) return weighted_entry_exact(S, deg, x1);  // x1 = 0 or 2^32 - 1
+    const uint32_t m = deg - 1;  // the last entry is taken when every T_i <= x1 (i < m)
+    const uint32_t base = m > kWeightedScan ? weighted_chunk(T, m, x1) : 0u;
+    uint32_t t[kWeightedScan];
+    load_chunk(T + base, t);
+    return weighted_chunk_count(t, base, m, x1);
+}
+
 // Entry of v's row taken by a step that does not go to u*: uniform
-// (floor(x1 * d / 2^32)) or, with running sums S of the graph, weighted.
+// (floor(x1 * d / 2^32)) or, with the weight tables of the graph, weighted.
 template <bool kWeighted>
 __device__ __forceinline__ uint32_t neighbour_entry(const VRec &r, uint32_t x1,
-                                                    const double *__restrict__ S) {
-    if (kWeighted && S) return weighted_entry(S + r.start, r.deg, x1);
+                                                    const double *__restrict__ S,
+                                                    const uint32_t *__restrict__ T) {
+    if (kWeighted && S) return weighted_entry(S + r.start, T + r.start, r.deg, x1);
     return __umulhi(x1, r.deg);
 }
 
@@ -97,9 +153,10 @@ __device__ __forceinline__ uint32_t neighbour_entry(const VRec &r, uint32_t x1,
 template <bool kWeighted>
 __device__ __forceinline__ uint32_t arrow_target(const VRec &r, uint32_t x0, uint32_t x1,
                                                  const int32_t *__restrict__ col_idx,
-                                                 const double *__restrict__ S, uint32_t n) {
+                                                 const double *__restrict__ S,
+                                                 const uint32_t *__restrict__ T, uint32_t n) {
     if (r.always_root || x0 < r.thr) return n;
-    const uint32_t idx = neighbour_entry<kWeighted>(r, x1, S);
+    const uint32_t idx = neighbour_entry<kWeighted>(r, x1, S, T);
     return static_cast<uint32_t>(col_idx[r.start + static_cast<int32_t>(idx)]);
 }
 

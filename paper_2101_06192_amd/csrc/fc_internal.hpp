@@ -36,7 +36,8 @@ struct fc_ctx {
     DevBuf iso;                                                   // isolated-vertex bitmap
     DevBuf corigt;                                                // hybrid: target ids per slot
     DevBuf cpre;                                                  // LDS: pre-drawn tree words
-    DevBuf weights, wsum;  // staged edge weights (host graphs), running row weight sums
+    DevBuf weights, wsum, wthr;  // staged edge weights (host graphs), running row weight sums,
+                                 // step thresholds
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
@@ -93,8 +94,10 @@ struct GraphView {
 int check_graph_args(fc_ctx *ctx, const fc_graph *g);
 // Stage (if on the host) and validate the CSR (and weights) on the device.
 int prepare_graph(fc_ctx *ctx, const fc_graph *g, bool trusted, GraphView *out);
-// Running row weight sums of a weighted graph into `buf` (null for an unweighted one).
-int row_wsum(fc_ctx *ctx, const GraphView &g, DevBuf &buf, const double **S);
+// Running row weight sums and step thresholds of a weighted graph into the two
+// buffers (both null for an unweighted graph).
+int weight_tables(fc_ctx *ctx, const GraphView &g, DevBuf &sbuf, DevBuf &tbuf, const double **S,
+                  const uint32_t **T);
 double now_ms();
 int begin(fc_ctx *ctx);
 // Threads per workgroup of the LDS-counter sampler for `trees` trees whose

@@ -25,6 +25,12 @@ hipError_t launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx,
 // added one by one in CSR order from 0 (one thread per row).
 hipError_t launch_row_wsum(const int32_t *row_ptr, const double *weights, int32_t n, double *S,
                            hipStream_t stream);
+// Step thresholds of a weighted graph from its running sums S: T[e] = the
+// smallest x in [0, 2^32] with (x * W_v) * 2^-32 >= S[e] (W_v the last running
+// sum of e's row), clamped to [1, 2^32 - 1] (one thread per kColChunk entries).
+// T has room for nnz + kWeightedScan entries (the padding is never counted).
+hipError_t launch_step_thresholds(const int32_t *row_ptr, const double *S, int32_t n,
+                                  int64_t nnz, uint32_t *T, hipStream_t stream);
 // Weighted degrees: W[v] = the last running sum of row v (0 for an empty row).
 hipError_t launch_row_wdeg(const int32_t *row_ptr, const double *weights, int32_t n, double *W,
                            hipStream_t stream);
@@ -47,6 +53,7 @@ struct LaneArgs {
     const VRec *vrec;
     const int32_t *col_idx;
     const double *wsum;       // running weight sums per CSR entry (weighted graph), or null
+    const uint32_t *wthr;     // step thresholds per CSR entry (with wsum)
     uint64_t *state;          // slots * n words
     uint32_t n;
     uint32_t slots;
@@ -79,6 +86,7 @@ struct CoopJob {
     const VRec *vrec;
     const int32_t *col_idx;
     const double *wsum;             // running weight sums per CSR entry (weighted graph), or null
+    const uint32_t *wthr;           // step thresholds per CSR entry (with wsum)
     const unsigned long long *adj;  // LDS variant: internal | original << 18 per CSR entry
     const uint32_t *orig;           // LDS variant: original id of each internal id
     uint32_t n;

@@ -110,6 +110,38 @@ __global__ void row_wsum_kernel(const int32_t *__restrict__ row_ptr,
     }
 }
 
+// Step thresholds: entry-parallel like the column check (kColChunk entries
+// per thread, the row of the first found by binary search over row_ptr).
+__global__ void step_thr_kernel(const int32_t *__restrict__ row_ptr, const double *__restrict__ S,
+                                int32_t n, int64_t nnz, uint32_t *__restrict__ T) {
+    const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * kColChunk;
+    if (e0 >= nnz) return;
+    const int64_t e1 = e0 + kColChunk < nnz ? e0 + kColChunk : nnz;
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (row_ptr[mid] <= e0) lo = mid;
+        else hi = mid - 1;
+    }
+    int32_t v = lo;
+    int64_t row_end = row_ptr[v + 1];
+    for (int64_t j = e0; j < e1; ++j) {
+        while (j >= row_end) {
+            ++v;
+            row_end = row_ptr[v + 1];
+        }
+        const double W = S[row_end - 1], s = S[j];
+        // smallest x in [0, 2^32] with (x * W) * 2^-32 >= s (x = 2^32 gives W >= s)
+        uint64_t a = 0, b = 1ull << 32;
+        while (a < b) {
+            const uint64_t mid = (a + b) >> 1;
+            if ((static_cast<double>(mid) * W) * 0x1p-32 >= s) b = mid;
+            else a = mid + 1;
+        }
+        T[j] = static_cast<uint32_t>(a < 1 ? 1 : a > 0xFFFFFFFFull ? 0xFFFFFFFFull : a);
+    }
+}
+
 __global__ void row_wdeg_kernel(const int32_t *__restrict__ row_ptr,
                                 const double *__restrict__ weights, int32_t n,
                                 double *__restrict__ W) {
@@ -191,6 +223,14 @@ hipError_t launch_row_wsum(const int32_t *row_ptr, const double *weights, int32_
                            hipStream_t stream) {
     if (n == 0) return hipSuccess;
     row_wsum_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(row_ptr, weights, n, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_thresholds(const int32_t *row_ptr, const double *S, int32_t n,
+                                  int64_t nnz, uint32_t *T, hipStream_t stream) {
+    if (n == 0 || nnz == 0) return hipSuccess;
+    step_thr_kernel<<<blocks_for((nnz + kColChunk - 1) / kColChunk, 256), 256, 0, stream>>>(
+        row_ptr, S, n, nnz, T);
     return hipGetLastError();
 }
 

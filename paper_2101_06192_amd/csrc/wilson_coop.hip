@@ -98,7 +98,7 @@ __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32
     const VRec r = load_vrec(j.vrec, v);
     if (r.always_root) return j.n;  // the arrow is u* whatever the Philox words are
     const Philox4 x = philox4x32_10(v, k, t, j.stream_id, key0, key1);
-    return arrow_target<kWeighted>(r, x.x0, x.x1, j.col_idx, j.wsum, j.n);
+    return arrow_target<kWeighted>(r, x.x0, x.x1, j.col_idx, j.wsum, j.wthr, j.n);
 }
 
 // Work items are trees; a single-graph launch has one implicit job, a batch

@@ -84,7 +84,7 @@ __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32
     const uint32_t orig = r.always_root & 0x7FFFFFFFu;
     const Philox4 x = philox4x32_10(orig, k, t, j.stream_id, key0, key1);
     if (x.x0 < r.thr) return pair(j.n, j.n);
-    const uint32_t idx = neighbour_entry<kWeighted>(r, x.x1, j.wsum);
+    const uint32_t idx = neighbour_entry<kWeighted>(r, x.x1, j.wsum, j.wthr);
     return j.adj[r.start + static_cast<int32_t>(idx)];
 }
 

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64) void wilson_lane_kernel(LaneArgs a) {
                 const uint32_t k = sw::visits(w, ep);
                 const VRec r = load_vrec(vrec, cur);
                 const Philox4 x = philox4x32_10(cur, k, t, a.stream_id, a.key0, a.key1);
-                const uint32_t nxt = arrow_target<kWeighted>(r, x.x0, x.x1, col, a.wsum, n);
+                const uint32_t nxt = arrow_target<kWeighted>(r, x.x0, x.x1, col, a.wsum, a.wthr, n);
                 if (k + 1 > a.k_limit) err |= kErrVisitOverflow;
                 st[cur] = sw::pack(nxt, k + 1, ep);
                 if (++steps > a.step_cap) {  // never reached by a valid walk; keeps the kernel finite

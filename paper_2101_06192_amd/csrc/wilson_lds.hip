@@ -99,7 +99,7 @@ __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32
     const Philox4 x = philox4x32_10(orig, k, t, j.stream_id, key0, key1);
     const uint64_t kbits = static_cast<uint64_t>(k + 1u) << kKShift;
     if ((r.always_root >> 31) || x.x0 < r.thr) return pack(j.n, j.n, 0u) | kbits;
-    const uint32_t idx = neighbour_entry<kWeighted>(r, x.x1, j.wsum);
+    const uint32_t idx = neighbour_entry<kWeighted>(r, x.x1, j.wsum, j.wthr);
     return j.adj[r.start + static_cast<int32_t>(idx)] | kbits;
 }
 
@@ -627,12 +627,31 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
 constexpr uint32_t kPreTrees = 16;
 constexpr uint32_t kPreThreads = 256;
 
+// First arrow of a weighted graph's vertex in tree t, given the first chunk
+// of its row's step thresholds (loaded once for all of the vertex's trees):
+// the same word as draw<true>(j, r, key0, key1, 0, t).
+__device__ __forceinline__ uint64_t draw_first_w(const CoopJob &j, const VRec &r,
+                                                 const uint32_t (&t0)[kWeightedScan],
+                                                 uint32_t key0, uint32_t key1, uint32_t t) {
+    const uint32_t orig = r.always_root & 0x7FFFFFFFu;
+    const Philox4 x = philox4x32_10(orig, 0u, t, j.stream_id, key0, key1);
+    const uint64_t kbits = 1ull << kKShift;
+    if ((r.always_root >> 31) || x.x0 < r.thr) return pack(j.n, j.n, 0u) | kbits;
+    const uint32_t m = r.deg - 1;
+    const uint32_t idx = (x.x1 - 1u >= 0xFFFFFFFEu || m > kWeightedScan)
+                             ? weighted_entry(j.wsum + r.start, j.wthr + r.start, r.deg, x.x1)
+                             : weighted_chunk_count(t0, 0u, m, x.x1);
+    return j.adj[r.start + static_cast<int32_t>(idx)] | kbits;
+}
+
 template <bool kWeighted>
 __global__ __launch_bounds__(kPreThreads) void lds_predraw_kernel(CoopArgs a, uint32_t groups) {
     const CoopJob &job = a.single;
     const uint32_t v = blockIdx.x * kPreThreads + threadIdx.x;
     if (v >= job.n3) return;
     const VRec r = load_vrec(job.vrec, v);
+    uint32_t t0[kWeightedScan];
+    if (kWeighted) load_chunk(job.wthr + r.start, t0);  // padded table: in bounds
     for (uint32_t g = blockIdx.y; g < groups; g += gridDim.y) {
         const uint32_t i0 = g * kPreTrees;
 #pragma unroll
@@ -640,7 +659,8 @@ __global__ __launch_bounds__(kPreThreads) void lds_predraw_kernel(CoopArgs a, ui
             const uint32_t item = i0 + q;
             if (item < a.item_count)
                 a.pre[static_cast<size_t>(item) * a.n_max + v] =
-                    draw<kWeighted>(job, r, a.key0, a.key1, 0u, job.tree_begin + item);
+                    kWeighted ? draw_first_w(job, r, t0, a.key0, a.key1, job.tree_begin + item)
+                              : draw<false>(job, r, a.key0, a.key1, 0u, job.tree_begin + item);
         }
     }
 }
