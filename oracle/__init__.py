@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import ctypes
 import itertools
+import math
 import os
 from fractions import Fraction
 
@@ -71,6 +72,9 @@ def _load():
                                      u32p]
         lib.orc_root_threshold_w.restype = ctypes.c_uint64
         lib.orc_root_threshold_w.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_kendall_counts.restype = None
+        lib.orc_kendall_counts.argtypes = [ctypes.c_int64, f64p, f64p,
+                                           np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")]
         lib.orc_estimate.restype = None
         lib.orc_estimate.argtypes = [ctypes.c_int32, u32p, ctypes.c_uint32, ctypes.c_int,
                                      f64p, f64p, f64p]
@@ -394,3 +398,48 @@ def exact_omega_diag(g, alpha: Fraction):
                 f = M[r][c]
                 M[r] = [x - f * y for x, y in zip(M[r], M[c])]
     return [M[v][n + v] for v in range(n)]
+
+
+# --------------------------------------------------------------------------
+# Ranking output (Section 6, "Vertex Ranking"; footnote on the accuracy
+# paragraph: the top vertices of the forest closeness ranking are those with
+# the lowest Omega_vv).
+# --------------------------------------------------------------------------
+def ranking(score, descending: bool = False):
+    """Vertices sorted by score (ascending, or descending), ties by vertex id
+    ascending; returns (order, rank) with order[rank[v]] = v.  -0 and +0 tie;
+    NaN is not a score."""
+    s = np.asarray(score, dtype=np.float64)
+    if np.isnan(s).any():
+        raise ValueError("NaN score")
+    key = -s if descending else s
+    order = np.lexsort((np.arange(s.size), key)).astype(np.int32)
+    rank = np.empty_like(order)
+    rank[order] = np.arange(s.size, dtype=np.int32)
+    return order, rank
+
+
+def kendall_counts(a, b):
+    """Pair counts over i < j: (concordant, discordant, tied in a, tied in b,
+    tied in both); the two 'tied in' counts include the pairs tied in both."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    assert a.shape == b.shape
+    out = np.zeros(5, np.int64)
+    L = _load()
+    L.orc_kendall_counts(a.size, _ptr(a, ctypes.c_double), _ptr(b, ctypes.c_double), out)
+    return tuple(int(x) for x in out)
+
+
+def kendall_tau_b(a, b) -> float:
+    """Kendall's tau-b: (n_c - n_d) / sqrt((n_0 - n_a)(n_0 - n_b)) with n_0 the
+    number of pairs and n_a, n_b the pairs tied in a and in b; NaN when either
+    vector is constant.  Evaluated in binary64 from the exact integer counts:
+    the product of the two differences, its square root, one division."""
+    nc, nd, ta, tb, _ = kendall_counts(a, b)
+    n = len(a)
+    n0 = n * (n - 1) // 2
+    d1, d2 = n0 - ta, n0 - tb
+    if d1 == 0 or d2 == 0:
+        return float("nan")
+    return float(nc - nd) / math.sqrt(float(d1) * float(d2))

@@ -37,8 +37,9 @@
  *   - With weights: W_v = the binary64 sum of v's row weights in CSR order,
  *     thr as above with W_v for d_v (thr = 2^32 when W_v = 0); otherwise u =
  *     fl(x1 W_v) 2^-32 and the step goes to the first neighbour in CSR order
- *     whose running binary64 weight sum exceeds u.  With unit weights this is
- *     exactly the unweighted rule (the sums are exact integers).
+ *     whose running binary64 weight sum exceeds u.  With unit weights and
+ *     degrees below 2^21 this is exactly the unweighted rule (the sums are
+ *     exact integers and so is x1 * d).
  *   Wilson's cycle-popping argument (Wilson 1996, the paper's reference for
  *   the sampler) makes the tree and every k_v independent of the order in
  *   which walks are started; the tests check that property on this code.
@@ -315,4 +316,33 @@ void orc_estimate(int32_t n, const uint32_t *R, uint32_t tau, int literal, doubl
         if (farness) farness[v] = fv;
         if (closeness) closeness[v] = (double)n / fv;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kendall's rank correlation of two score vectors (Section 6, "Vertex       */
+/* Ranking": the ranking of the estimate against the ground truth).  Over    */
+/* all pairs i < j: concordant when a and b order the pair the same way,     */
+/* discordant when oppositely, and otherwise tied in a, in b or in both.     */
+/* Plain O(n^2) loop over the pairs; comparisons only, no differences.       */
+/* counts = {concordant, discordant, tied in a (both included), tied in b    */
+/* (both included), tied in both}.                                           */
+/* ------------------------------------------------------------------------ */
+void orc_kendall_counts(int64_t n, const double *a, const double *b, int64_t counts[5]) {
+    int64_t nc = 0, nd = 0, ta = 0, tb = 0, tab = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            int sa = (a[i] < a[j]) ? 1 : (a[i] > a[j]) ? -1 : 0;
+            int sb = (b[i] < b[j]) ? 1 : (b[i] > b[j]) ? -1 : 0;
+            if (sa == 0) ta += 1;
+            if (sb == 0) tb += 1;
+            if (sa == 0 && sb == 0) tab += 1;
+            if (sa * sb > 0) nc += 1;
+            if (sa * sb < 0) nd += 1;
+        }
+    }
+    counts[0] = nc;
+    counts[1] = nd;
+    counts[2] = ta;
+    counts[3] = tb;
+    counts[4] = tab;
 }
