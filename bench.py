@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop", "lds", "hyb"])
     ap.add_argument("--config", default="ba200k",
                     choices=["ba200k", "ba200k_w", "er1000", "grid1000", "rmat_batch", "rmat22",
-                             "solve"],
+                             "solve", "rank"],
                     help="workload; the default is the headline configuration")
     ap.add_argument("--phase-timing", action="store_true",
                     help="report per-phase times of the workgroup sampler (adds clock reads)")
@@ -348,6 +348,50 @@ def other_config(args, fc, inputs, dev):
                                  "algorithmic_bytes_per_launch": alg}})
         if args.phase_timing:
             res["phase_ms_per_workgroup"] = _phases(st)
+    elif args.config == "rank":
+        # ranking output: the headline graph's closeness ranking and Kendall's tau-b
+        # at n = 200000; the KT of eps-estimates against a CG ground truth of every
+        # Omega_vv on BA(20000, 5)
+        import torch
+        g = inputs.barabasi_albert(200_000, 5, 0)
+        dg = fc.to_device(g, dev)
+        est = fc.farness(dg, alpha=1.0, eps=0.1, delta=0.1, device=dev, as_torch=True)
+        clo, diag = est["closeness"], est["diag"]
+        dt_rank, _ = _timed(lambda: fc.rank(clo, descending=True, device=dev, as_torch=True),
+                            args.steps, args.warmup)
+        other = fc.farness(dg, alpha=1.0, eps=0.1, delta=0.1, seed=1, device=dev, as_torch=True)
+        dt_kt, kt = _timed(lambda: fc.kendall_tau(diag, other["diag"], device=dev), args.steps,
+                           args.warmup)
+        n = g.n
+        pairs = n * (n - 1) // 2
+        gs = inputs.barabasi_albert(20_000, 5, 0)
+        dgs = fc.to_device(gs, dev)
+        t0 = time.perf_counter()
+        truth = torch.empty(gs.n, dtype=torch.float64, device=dev)
+        for c0 in range(0, gs.n, 64):
+            k = min(64, gs.n - c0)
+            B = torch.zeros(gs.n, k, dtype=torch.float64, device=dev)
+            B[torch.arange(c0, c0 + k, device=dev), torch.arange(k, device=dev)] = 1.0
+            X = fc.solve(dgs, 1.0, B, rtol=1e-9, precision="fp32_refined", device=dev,
+                         trusted=True, as_torch=True)["X"]
+            truth[c0:c0 + k] = X[torch.arange(c0, c0 + k, device=dev), torch.arange(k, device=dev)]
+        torch.cuda.synchronize()
+        truth_s = time.perf_counter() - t0
+        quality = {}
+        for eps in (0.1, 0.3):
+            e = fc.diag_estimate(dgs, alpha=1.0, eps=eps, delta=0.1, device=dev, as_torch=True)
+            r = fc.kendall_tau(e["diag"], truth, device=dev)
+            quality[str(eps)] = {"tau": e["tau"], "kendall_tau_b": r["tau_b"],
+                                 "max_abs_err": float((e["diag"] - truth).abs().max())}
+        res.update({"metric": "ranking: fc_rank and fc_kendall_tau time at n = 200000; KT vs CG",
+                    "value": 1000 * dt_kt, "unit": "ms (fc_kendall_tau, n = 200000)",
+                    "higher_is_better": False,
+                    "config": {"workload": "ba_n200000_m5_alpha1_eps0.1_rank_kendall", "n": n,
+                               "kt_graph": "ba_n20000_m5_alpha1"},
+                    "rank_ms": 1000 * dt_rank,
+                    "kendall_ms": 1000 * dt_kt, "kendall_pairs_per_s": pairs / dt_kt,
+                    "kendall_two_estimates_tau_b": kt["tau_b"],
+                    "ground_truth_s": truth_s, "kt_vs_cg": quality})
     elif args.config == "grid1000":
         g = inputs.grid_removed(1000, 1000, 0.12, 0)
         dg = fc.to_device(g, dev)

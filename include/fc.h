@@ -324,6 +324,37 @@ FC_API int fc_solve(fc_ctx *ctx, const fc_graph *g, double alpha, const double *
                     int32_t nrhs, double rtol, int32_t precision, int32_t max_iters, int32_t flags,
                     int32_t *iters_out, double *relres_out);
 
+/* ---------------------------------------------------------------------- */
+/* Ranking output (Section 6, "Vertex Ranking", and the footnote of its   */
+/* accuracy paragraph: the top vertices of the forest closeness ranking   */
+/* have the lowest Omega_vv, since farness grows with Omega_vv by Eq.     */
+/* "eq-fdistu-tr").  Both calls work on device arrays and synchronise.    */
+/* ---------------------------------------------------------------------- */
+
+/* Vertices sorted by score: ascending (descending = 0) or descending, equal
+ * scores by vertex id ascending; -0 and +0 are equal, +-inf are ordinary.
+ *   score: device double[n] (n >= 0), no NaN (else FC_ERR_ARG, nothing written).
+ *   order: device int32[n] or NULL: order[i] = the vertex at position i.
+ *   rank:  device int32[n] or NULL: rank[v] = the position of v.
+ * The top k of the forest closeness ranking are order[0..k) for score = the
+ * estimated diagonal (ascending) or the closeness (descending). */
+FC_API int fc_rank(fc_ctx *ctx, const double *score, int32_t n, int32_t descending,
+                   int32_t *order, int32_t *rank);
+
+/* Kendall's rank correlation tau-b of two score vectors (the KT the paper
+ * reports for the ranking of the estimate against the ground truth).  Over all
+ * pairs i < j: n_c concordant, n_d discordant, n_a tied in a, n_b tied in b
+ * (pairs tied in both count in n_a and n_b, and n_ab of them);
+ * tau_b = (n_c - n_d) / sqrt((n0 - n_a)(n0 - n_b)), n0 = n(n-1)/2, evaluated in
+ * binary64 from the exact integer counts (NaN when a or b is constant, n < 2).
+ *   a, b:   device double[n], 0 <= n <= 65535 * 256 (else FC_ERR_UNSUPPORTED),
+ *           no NaN (FC_ERR_ARG).
+ *   tau_b:  host double, or NULL.
+ *   counts: host int64[5] = {n_c, n_d, n_a, n_b, n_ab}, or NULL.
+ * The device compares all n(n-1)/2 pairs (tiled through LDS). */
+FC_API int fc_kendall_tau(fc_ctx *ctx, const double *a, const double *b, int32_t n,
+                          double *tau_b, int64_t *counts);
+
 /* Measurement utility (not part of the method): rate of independent random
  * 4-byte accesses -- loads (atomics = 0) or atomic adds (atomics = 1) -- over
  * a device footprint of footprint_bytes (rounded down to a power of two,

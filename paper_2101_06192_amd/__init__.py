@@ -120,6 +120,9 @@ def lib() -> ctypes.CDLL:
             "fc_batch_destroy": (ctypes.c_int, [vp]),
             "fc_probe_random_access": (ctypes.c_int, [vp, ctypes.c_uint64, i32,
                                                       ctypes.POINTER(ctypes.c_double)]),
+            "fc_rank": (ctypes.c_int, [vp, vp, i32, i32, vp, vp]),
+            "fc_kendall_tau": (ctypes.c_int, [vp, vp, vp, i32, ctypes.POINTER(f64),
+                                              ctypes.POINTER(i64)]),
             "fc_error_string": (ctypes.c_char_p, [ctypes.c_int]),
             "fc_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -456,6 +459,37 @@ def solve(g, alpha: float, B, X0=None, rtol: float = 1e-9, precision: str = "fp3
                              FC_FLAG_TRUSTED_GRAPH if trusted else 0, ctypes.byref(it),
                              ctypes.c_void_p(rel.ctypes.data)))
     return {"X": X if as_torch else X.cpu().numpy(), "iters": int(it.value), "relres": rel[:k]}
+
+
+def rank(score, descending: bool = False, device="cuda:0", as_torch: bool = False) -> dict:
+    """Vertices sorted by score, ties by id (fc_rank): {"order", "rank"}."""
+    import torch
+    ctx = context(device)
+    s = torch.as_tensor(score, dtype=torch.float64).to(ctx.device).reshape(-1).contiguous()
+    n = int(s.numel())
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=ctx.device)
+    rk = torch.empty(max(n, 1), dtype=torch.int32, device=ctx.device)
+    ctx.check(lib().fc_rank(ctx.handle, ctypes.c_void_p(s.data_ptr() if n else 0), n,
+                            int(bool(descending)), _ptr(order), _ptr(rk)))
+    return {"order": _out(order[:n], as_torch), "rank": _out(rk[:n], as_torch)}
+
+
+def kendall_tau(a, b, device="cuda:0") -> dict:
+    """Kendall's tau-b of two score vectors with its exact pair counts
+    (fc_kendall_tau): {"tau_b", "counts": (n_c, n_d, n_a, n_b, n_ab)}."""
+    import torch
+    ctx = context(device)
+    ta = torch.as_tensor(a, dtype=torch.float64).to(ctx.device).reshape(-1).contiguous()
+    tb = torch.as_tensor(b, dtype=torch.float64).to(ctx.device).reshape(-1).contiguous()
+    if ta.numel() != tb.numel():
+        raise ValueError("a and b must have the same length")
+    n = int(ta.numel())
+    tau_b = ctypes.c_double(0.0)
+    counts = (ctypes.c_int64 * 5)()
+    ctx.check(lib().fc_kendall_tau(ctx.handle, ctypes.c_void_p(ta.data_ptr() if n else 0),
+                                   ctypes.c_void_p(tb.data_ptr() if n else 0), n,
+                                   ctypes.byref(tau_b), counts))
+    return {"tau_b": float(tau_b.value), "counts": tuple(int(x) for x in counts)}
 
 
 def probe_random_access(footprint_bytes: int, atomics: bool = False, device="cuda:0") -> float:

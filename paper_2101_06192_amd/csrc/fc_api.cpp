@@ -763,7 +763,8 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->s_d, &ctx->s_pa, &ctx->s_pb, &ctx->s_small, &ctx->rl_blk,
                       &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
                       &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->wthr,
-                      &ctx->s_wdeg})
+                      &ctx->s_wdeg, &ctx->rk_key0, &ctx->rk_key1, &ctx->rk_val0, &ctx->rk_val1,
+                      &ctx->rk_hist, &ctx->rk_thist, &ctx->rk_ra, &ctx->rk_rb})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
