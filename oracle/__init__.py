@@ -443,3 +443,45 @@ def kendall_tau_b(a, b) -> float:
     if d1 == 0 or d2 == 0:
         return float("nan")
     return float(nc - nd) / math.sqrt(float(d1) * float(d2))
+
+
+# --------------------------------------------------------------------------
+# Group forest closeness (Section 5): f(S) = tr((L*_{-S})^{-1}), L* the
+# Laplacian of G* with the rows and columns of S removed; the greedy
+# maximiser of the group forest closeness 1/f(S) (Algorithm 2).
+# --------------------------------------------------------------------------
+def group_farness(g, alpha: float, S) -> float:
+    """tr((L*_{-S})^{-1}) by a dense inverse (Section 5's definition)."""
+    Ls = augmented_laplacian(g, alpha)
+    keep = np.setdiff1d(np.arange(g.n + 1), np.asarray(list(S), dtype=np.int64))
+    return float(np.trace(np.linalg.inv(Ls[np.ix_(keep, keep)])))
+
+
+def greedy_group(g, alpha: float, k: int):
+    """Algorithm 2, step by step: P = pinv(L*); the first vertex minimises
+    n P[v, v] + tr(P); M = inverse of L* without that vertex; then, while
+    |S| < k, the vertex v of V \\ S maximising |M e_v|^2 / (e_v^T M e_v) joins S
+    and M <- (M - M e_v e_v^T M / (e_v^T M e_v)) without row and column v.
+    Ties go to the smallest vertex id.  Returns (S in order of choice,
+    [f(S) after each choice])."""
+    n = g.n
+    Ls = augmented_laplacian(g, alpha)
+    P = np.linalg.pinv(Ls)
+    score = n * np.diag(P)[:n] + np.trace(P)
+    v = int(np.flatnonzero(score == score.min())[0])
+    idx = [x for x in range(n + 1) if x != v]          # row/column i of M is vertex idx[i]
+    M = np.linalg.inv(Ls[np.ix_(idx, idx)])
+    S = [v]
+    f = [float(np.trace(M))]
+    while len(S) < k:
+        cand = [i for i, x in enumerate(idx) if x < n]   # V \ S (u* is not a candidate)
+        gain = np.array([(M[:, i] @ M[:, i]) / M[i, i] for i in cand])
+        best = cand[int(np.flatnonzero(gain == gain.max())[0])]
+        col = M[:, best].copy()
+        M = M - np.outer(col, col) / col[best]
+        keep = [i for i in range(len(idx)) if i != best]
+        M = M[np.ix_(keep, keep)]
+        S.append(idx[best])
+        idx = [idx[i] for i in keep]
+        f.append(float(np.trace(M)))
+    return S, f
