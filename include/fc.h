@@ -355,6 +355,28 @@ FC_API int fc_rank(fc_ctx *ctx, const double *score, int32_t n, int32_t descendi
 FC_API int fc_kendall_tau(fc_ctx *ctx, const double *a, const double *b, int32_t n,
                           double *tau_b, int64_t *counts);
 
+/* ---------------------------------------------------------------------- */
+/* Group forest closeness (Section 5): the forest farness of a vertex set */
+/* S is f(S) = tr((L*_{-S})^{-1}), L* the Laplacian of G* with the rows   */
+/* and columns of S removed; its closeness is 1/f(S).                     */
+/* ---------------------------------------------------------------------- */
+
+/* The greedy maximiser of group forest closeness (Algorithm 2): the first
+ * vertex has the lowest Omega_vv (the highest forest closeness); then, k - 1
+ * times, the vertex v of V \ S maximising |M e_v|^2 / M_vv, M = (L*_{-S})^{-1},
+ * joins S, and M is downdated by the rank-1 formula (ties: the smallest id).
+ * Dense binary64 on the device: one inverse of alpha L + I (blocked
+ * Gauss-Jordan with fp64 matrix cores), a change of ground to the first vertex
+ * in place of Algorithm 2's pseudo-inverse and second inverse, then one pass
+ * over M per step.  Needs 8 N^2 bytes of device memory, N = n rounded up to 64.
+ *   g:      the graph (weights allowed); 1 <= k <= n <= 65535 (FC_ERR_UNSUPPORTED
+ *           beyond 65535).
+ *   flags:  FC_FLAG_TRUSTED_GRAPH or 0.
+ *   group:  host int32[k]: the vertices in the order chosen.
+ *   farness: host double[k] or NULL: f(S) after each choice. */
+FC_API int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, int32_t k,
+                              int32_t flags, int32_t *group, double *farness);
+
 /* Measurement utility (not part of the method): rate of independent random
  * 4-byte accesses -- loads (atomics = 0) or atomic adds (atomics = 1) -- over
  * a device footprint of footprint_bytes (rounded down to a power of two,

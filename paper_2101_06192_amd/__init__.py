@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
             "fc_rank": (ctypes.c_int, [vp, vp, i32, i32, vp, vp]),
             "fc_kendall_tau": (ctypes.c_int, [vp, vp, vp, i32, ctypes.POINTER(f64),
                                               ctypes.POINTER(i64)]),
+            "fc_group_closeness": (ctypes.c_int, [vp, gp, f64, i32, i32, ctypes.POINTER(i32),
+                                                  ctypes.POINTER(f64)]),
             "fc_error_string": (ctypes.c_char_p, [ctypes.c_int]),
             "fc_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -490,6 +492,17 @@ def kendall_tau(a, b, device="cuda:0") -> dict:
                                    ctypes.c_void_p(tb.data_ptr() if n else 0), n,
                                    ctypes.byref(tau_b), counts))
     return {"tau_b": float(tau_b.value), "counts": tuple(int(x) for x in counts)}
+
+
+def group_closeness(g, alpha: float, k: int, device="cuda:0", trusted: bool = False) -> dict:
+    """Greedy group forest closeness (fc_group_closeness): {"group", "farness"}."""
+    ctx = context(device)
+    gs = _graph_struct(g)
+    grp = (ctypes.c_int32 * max(int(k), 1))()
+    far = (ctypes.c_double * max(int(k), 1))()
+    ctx.check(lib().fc_group_closeness(ctx.handle, ctypes.byref(gs), float(alpha), int(k),
+                                       FC_FLAG_TRUSTED_GRAPH if trusted else 0, grp, far))
+    return {"group": [int(x) for x in grp[:k]], "farness": [float(x) for x in far[:k]]}
 
 
 def probe_random_access(footprint_bytes: int, atomics: bool = False, device="cuda:0") -> float:

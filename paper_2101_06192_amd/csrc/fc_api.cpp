@@ -764,7 +764,8 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
                       &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->wthr,
                       &ctx->s_wdeg, &ctx->rk_key0, &ctx->rk_key1, &ctx->rk_val0, &ctx->rk_val1,
-                      &ctx->rk_hist, &ctx->rk_thist, &ctx->rk_ra, &ctx->rk_rb})
+                      &ctx->rk_hist, &ctx->rk_thist, &ctx->rk_ra, &ctx->rk_rb, &ctx->g_mat,
+                      &ctx->g_vec, &ctx->g_part, &ctx->g_taken})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

@@ -1,0 +1,84 @@
+// fc_group_closeness: the greedy group forest closeness maximiser of
+// Algorithm 2 (Section 5) on dense device matrices.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fc_internal.hpp"
+
+using namespace fc_host;
+
+extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, int32_t k,
+                                  int32_t flags, int32_t *group, double *farness) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    if (!valid_alpha(alpha)) return set_err(ctx, FC_ERR_ARG, "alpha must be finite and > 0");
+    if (!group) return set_err(ctx, FC_ERR_ARG, "group is NULL");
+    GraphView gv;
+    if ((rc = prepare_graph(ctx, g, flags & FC_FLAG_TRUSTED_GRAPH, &gv))) return rc;
+    if (gv.n < 1 || k < 1 || k > gv.n) return set_err(ctx, FC_ERR_ARG, "need 1 <= k <= n");
+    if (gv.n > 65535) return set_err(ctx, FC_ERR_UNSUPPORTED, "dense group closeness needs n <= 65535");
+    const uint32_t n = static_cast<uint32_t>(gv.n);
+    const uint32_t N = fc::group_dim(n);
+    const size_t chunks = fc::group_chunks(n);
+    if ((rc = ensure(ctx, ctx->g_mat, sizeof(double) * N * static_cast<size_t>(N), "dense matrix")) ||
+        (rc = ensure(ctx, ctx->g_vec, sizeof(double) * (4 * static_cast<size_t>(n) + 64 * 64 + 16),
+                     "group vectors")) ||
+        (rc = ensure(ctx, ctx->g_part, sizeof(double) * chunks * N, "column sums")) ||
+        (rc = ensure(ctx, ctx->g_taken, n, "group flags")))
+        return rc;
+    double *A = static_cast<double *>(ctx->g_mat.ptr);
+    double *vec = static_cast<double *>(ctx->g_vec.ptr);
+    double *cv = vec, *rv = vec + n, *diag = vec + 2 * n, *gain = vec + 3 * n;
+    double *Dinv = vec + 4 * static_cast<size_t>(n);
+    double *scal = Dinv + 64 * 64;  // [0] trace, [1] pivot
+    unsigned long long *sel = reinterpret_cast<unsigned long long *>(scal + 4);
+    double *part = static_cast<double *>(ctx->g_part.ptr);
+    uint8_t *taken = static_cast<uint8_t *>(ctx->g_taken.ptr);
+
+    // Omega = (alpha L + I)^{-1}; the first vertex minimises Omega_vv (Algorithm 2
+    // takes the minimiser of n P[v, v] + tr(P), P = pinv(L*), whose V-block is Omega
+    // minus a constant)
+    FC_HIP(ctx, fc::launch_group_build(gv.row_ptr, gv.col_idx, gv.weights, n, alpha, A, ctx->stream),
+           "dense build");
+    FC_HIP(ctx, fc::launch_group_invert(A, N, Dinv, ctx->stream), "dense inverse");
+    FC_HIP(ctx, hipMemsetAsync(sel, 0xFF, 2 * sizeof(unsigned long long), ctx->stream), "memset");
+    FC_HIP(ctx, fc::launch_group_first(A, n, N, diag, sel, ctx->stream), "first vertex");
+    unsigned long long hsel[2];
+    FC_HIP(ctx, hipMemcpyAsync(hsel, sel, sizeof(hsel), hipMemcpyDeviceToHost, ctx->stream), "copy");
+    FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "first vertex");
+    if (hsel[1] >= n) return set_err(ctx, FC_ERR_HIP, "no first vertex (non-finite inverse)");
+    const uint32_t v0 = static_cast<uint32_t>(hsel[1]);
+    // M = inverse of L* without v0 (slot v0 now stands for u*)
+    FC_HIP(ctx, fc::launch_group_reground(A, n, N, v0, cv, ctx->stream), "change of ground");
+    FC_HIP(ctx, hipMemsetAsync(taken, 0, n, ctx->stream), "memset flags");
+    FC_HIP(ctx, hipMemsetAsync(taken + v0, 1, 1, ctx->stream), "flag");
+    FC_HIP(ctx, fc::launch_group_trace(A, n, N, n, scal, scal + 1, ctx->stream), "trace");
+    FC_HIP(ctx, fc::launch_group_colsq(A, n, N, n, cv, rv, scal + 1, part, ctx->stream), "column sums");
+    double tr = 0.0;
+    FC_HIP(ctx, hipMemcpyAsync(&tr, scal, sizeof(tr), hipMemcpyDeviceToHost, ctx->stream), "copy");
+    FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "trace");
+    group[0] = static_cast<int32_t>(v0);
+    if (farness) farness[0] = tr;
+    for (int32_t s = 1; s < k; ++s) {
+        const unsigned long long init[2] = {0ull, ~0ull};
+        FC_HIP(ctx, hipMemcpyAsync(sel, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream), "copy");
+        FC_HIP(ctx, fc::launch_group_argmax(A, n, N, part, taken, gain, sel, ctx->stream), "argmax");
+        FC_HIP(ctx, hipMemcpyAsync(hsel, sel, sizeof(hsel), hipMemcpyDeviceToHost, ctx->stream), "copy");
+        FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "argmax");
+        if (hsel[1] >= n) return set_err(ctx, FC_ERR_HIP, "no candidate vertex (non-finite gains)");
+        const uint32_t v = static_cast<uint32_t>(hsel[1]);
+        group[s] = static_cast<int32_t>(v);
+        FC_HIP(ctx, hipMemsetAsync(taken + v, 1, 1, ctx->stream), "flag");
+        FC_HIP(ctx, fc::launch_group_trace(A, n, N, v, scal, scal + 1, ctx->stream), "pivot");
+        FC_HIP(ctx, fc::launch_group_colsq(A, n, N, v, cv, rv, scal + 1, part, ctx->stream),
+               "downdate");
+        if (farness) {
+            FC_HIP(ctx, fc::launch_group_trace(A, n, N, n, scal, scal + 1, ctx->stream), "trace");
+            FC_HIP(ctx, hipMemcpyAsync(&farness[s], scal, sizeof(double), hipMemcpyDeviceToHost,
+                                       ctx->stream), "copy");
+        }
+    }
+    FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "group closeness");
+    return FC_OK;
+}

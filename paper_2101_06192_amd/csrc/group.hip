@@ -1,0 +1,397 @@
+// Group forest closeness (Section 5): the greedy of Algorithm 2 on dense
+// matrices in HBM.
+//
+// f(S) = tr((L*_{-S})^{-1}); Algorithm 2 keeps M = (L*_{-S})^{-1} and, per
+// step, adds the vertex v maximising |M e_v|^2 / M_vv and downdates
+// M <- M - M e_v e_v^T M / M_vv (row and column v become zero).
+//
+// Layout: one N x N row-major binary64 matrix, N = n rounded up to 64; the
+// padding is an identity block, never read by the greedy.  It first holds
+// alpha L + I, inverted in place by blocked Gauss-Jordan (64 x 64 pivot
+// blocks; the rank-64 trailing update on fp64 MFMA), i.e. Omega; then, in
+// place, the inverse of L* grounded at the first vertex v0, with slot v0
+// standing for u*.
+#include "fc_kernels.hpp"
+
+namespace fc {
+
+namespace {
+
+constexpr uint32_t kT = 64;        // tile edge
+constexpr uint32_t kPad = kT + 1;  // LDS row stride (doubles): rows fall on different banks
+constexpr uint32_t kThreads = 256;
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 operand layout (wave64): lane l holds A[l % 16][l / 16]
+// of the 16 x 4 left operand, B[l / 16][l % 16] of the 4 x 16 right operand,
+// and D[l / 16 + 4 r][l % 16] in item r of the 16 x 16 result.
+__device__ __forceinline__ uint32_t d_row(uint32_t lane, uint32_t r) { return (lane >> 4) + 4u * r; }
+__device__ __forceinline__ uint32_t d_col(uint32_t lane) { return lane & 15u; }
+
+// acc += X * Y over one wave's 32 x 32 quadrant (qr, qc) of a 64 x 64 tile,
+// X and Y 64 x 64 in LDS (row stride kPad).
+__device__ __forceinline__ void tile_mma(const double *X, const double *Y, uint32_t qr,
+                                         uint32_t qc, uint32_t lane, double4_t (&acc)[2][2]) {
+    const uint32_t li = lane & 15u, lk = lane >> 4;
+#pragma unroll 4
+    for (uint32_t k0 = 0; k0 < kT; k0 += 4) {
+        double a[2], b[2];
+#pragma unroll
+        for (uint32_t s = 0; s < 2; ++s) {
+            a[s] = X[(qr + 16u * s + li) * kPad + k0 + lk];
+            b[s] = Y[(k0 + lk) * kPad + qc + 16u * s + li];
+        }
+#pragma unroll
+        for (uint32_t s = 0; s < 2; ++s)
+#pragma unroll
+            for (uint32_t t = 0; t < 2; ++t)
+                acc[s][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[t], acc[s][t], 0, 0, 0);
+    }
+}
+
+// Stage the 64 x 64 tile at (r0, c0) of a row-major N x N matrix into LDS,
+// optionally negated.
+__device__ __forceinline__ void stage(const double *__restrict__ A, uint32_t N, uint32_t r0,
+                                      uint32_t c0, double *S, bool negate) {
+    for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads) {
+        const uint32_t r = e / kT, c = e % kT;
+        const double x = A[static_cast<size_t>(r0 + r) * N + c0 + c];
+        S[r * kPad + c] = negate ? -x : x;
+    }
+}
+
+// The wave's quadrant and the global element of (s, t, item r) of it.
+struct Quad {
+    uint32_t qr, qc, lane;
+};
+__device__ __forceinline__ Quad quad() {
+    const uint32_t w = threadIdx.x >> 6;
+    return {32u * (w >> 1), 32u * (w & 1u), threadIdx.x & 63u};
+}
+
+// Pivot block inverse: D = A[p0.., p0..] (64 x 64, SPD) inverted in LDS by
+// Gauss-Jordan without pivoting, written to Dinv (64 x 64, row-major).
+__global__ __launch_bounds__(kThreads) void gj_pivot_kernel(const double *__restrict__ A, uint32_t N,
+                                                            uint32_t p0, double *__restrict__ Dinv) {
+    __shared__ double D[kT * kPad];
+    __shared__ double colp[kT];
+    stage(A, N, p0, p0, D, false);
+    __syncthreads();
+    for (uint32_t p = 0; p < kT; ++p) {
+        const double piv = D[p * kPad + p];
+        __syncthreads();
+        if (threadIdx.x < kT) {  // row p divided by the pivot (its own entry becomes 1 / piv)
+            const uint32_t j = threadIdx.x;
+            colp[j] = D[j * kPad + p];  // the multipliers, read before any row changes them
+            D[p * kPad + j] = (j == p ? 1.0 : D[p * kPad + j]) / piv;
+        }
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads) {
+            const uint32_t i = e / kT, j = e % kT;
+            if (i == p) continue;
+            // column p of row i becomes -f / piv; the others subtract f * row p
+            D[i * kPad + j] = (j == p ? 0.0 : D[i * kPad + j]) - colp[i] * D[p * kPad + j];
+        }
+        __syncthreads();
+    }
+    for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads)
+        Dinv[e] = D[(e / kT) * kPad + e % kT];
+}
+
+// Row panel: A[p-rows, j-tile] <- Dinv A[p-rows, j-tile] (j-tile != p);
+// column panel: A[i-tile, p-cols] <- -A[i-tile, p-cols] Dinv (i-tile != p).
+__global__ __launch_bounds__(kThreads) void gj_panel_kernel(double *__restrict__ A, uint32_t N,
+                                                            uint32_t pt,
+                                                            const double *__restrict__ Dinv,
+                                                            uint32_t column) {
+    const uint32_t t = blockIdx.x;
+    if (t == pt) return;
+    __shared__ double X[kT * kPad], Y[kT * kPad];
+    const uint32_t p0 = pt * kT, t0 = t * kT;
+    if (!column) {
+        for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads)
+            X[(e / kT) * kPad + e % kT] = Dinv[e];
+        stage(A, N, p0, t0, Y, false);
+    } else {
+        stage(A, N, t0, p0, X, true);
+        for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads)
+            Y[(e / kT) * kPad + e % kT] = Dinv[e];
+    }
+    __syncthreads();
+    const Quad q = quad();
+    double4_t acc[2][2] = {};
+    tile_mma(X, Y, q.qr, q.qc, q.lane, acc);
+    const uint32_t r0 = column ? t0 : p0, c0 = column ? p0 : t0;
+#pragma unroll
+    for (uint32_t s = 0; s < 2; ++s)
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
+                const uint32_t row = q.qr + 16u * s + d_row(q.lane, r);
+                const uint32_t col = q.qc + 16u * u + d_col(q.lane);
+                A[static_cast<size_t>(r0 + row) * N + c0 + col] = acc[s][u][r];
+            }
+}
+
+// Trailing update: A[i, j] -= A[i, p] A[p, j] for tiles i, j != p (A[i, p]
+// still the old column panel, A[p, j] the new row panel).
+__global__ __launch_bounds__(kThreads) void gj_update_kernel(double *__restrict__ A, uint32_t N,
+                                                             uint32_t pt) {
+    const uint32_t ti = blockIdx.y, tj = blockIdx.x;
+    if (ti == pt || tj == pt) return;
+    __shared__ double X[kT * kPad], Y[kT * kPad];
+    const uint32_t p0 = pt * kT, i0 = ti * kT, j0 = tj * kT;
+    stage(A, N, i0, p0, X, true);  // -A[i, p]
+    stage(A, N, p0, j0, Y, false);
+    __syncthreads();
+    const Quad q = quad();
+    double4_t acc[2][2];
+#pragma unroll
+    for (uint32_t s = 0; s < 2; ++s)
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                acc[s][u][r] = A[static_cast<size_t>(i0 + q.qr + 16u * s + d_row(q.lane, r)) * N + j0 +
+                                 q.qc + 16u * u + d_col(q.lane)];
+    tile_mma(X, Y, q.qr, q.qc, q.lane, acc);
+#pragma unroll
+    for (uint32_t s = 0; s < 2; ++s)
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                A[static_cast<size_t>(i0 + q.qr + 16u * s + d_row(q.lane, r)) * N + j0 + q.qc +
+                  16u * u + d_col(q.lane)] = acc[s][u][r];
+}
+
+__global__ __launch_bounds__(kThreads) void gj_put_kernel(double *__restrict__ A, uint32_t N,
+                                                          uint32_t pt,
+                                                          const double *__restrict__ Dinv) {
+    const uint32_t p0 = pt * kT;
+    for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads)
+        A[static_cast<size_t>(p0 + e / kT) * N + p0 + e % kT] = Dinv[e];
+}
+
+// alpha L + I of the first n rows (weighted when w is not null), identity on
+// the padding, zeros elsewhere; one thread per row, after the matrix was zeroed.
+__global__ __launch_bounds__(kThreads) void dense_build_kernel(const int32_t *__restrict__ row_ptr,
+                                                               const int32_t *__restrict__ col_idx,
+                                                               const double *__restrict__ w,
+                                                               uint32_t n, uint32_t N, double alpha,
+                                                               double *__restrict__ A) {
+    const uint32_t v = blockIdx.x * kThreads + threadIdx.x;
+    if (v >= N) return;
+    double *row = A + static_cast<size_t>(v) * N;
+    if (v >= n) {
+        row[v] = 1.0;
+        return;
+    }
+    double deg = 0.0;
+    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        const double we = w ? w[e] : 1.0;
+        row[col_idx[e]] = -(alpha * we);
+        deg += we;
+    }
+    row[v] = alpha * deg + 1.0;
+}
+
+// Diagonal (n entries) into out, for the argmin of the first vertex.
+__global__ __launch_bounds__(kThreads) void diag_kernel(const double *__restrict__ A, uint32_t n,
+                                                        uint32_t N, double *__restrict__ out) {
+    const uint32_t v = blockIdx.x * kThreads + threadIdx.x;
+    if (v < n) out[v] = A[static_cast<size_t>(v) * N + v];
+}
+
+// First vertex: the smallest id of minimal diagonal (Omega_vv >= 0, so the
+// binary64 bits order as uint64).  sel[0] = min bits, then sel[1] = min id.
+__global__ __launch_bounds__(kThreads) void argmin_bits_kernel(const double *__restrict__ x, uint32_t n,
+                                                               unsigned long long *sel) {
+    const uint32_t v = blockIdx.x * kThreads + threadIdx.x;
+    if (v < n) atomicMin(&sel[0], static_cast<unsigned long long>(__double_as_longlong(x[v])));
+}
+__global__ __launch_bounds__(kThreads) void argmin_id_kernel(const double *__restrict__ x, uint32_t n,
+                                                             unsigned long long *sel) {
+    const uint32_t v = blockIdx.x * kThreads + threadIdx.x;
+    if (v < n && static_cast<unsigned long long>(__double_as_longlong(x[v])) == sel[0])
+        atomicMin(&sel[1], static_cast<unsigned long long>(v));
+}
+
+// Change of ground from u* to v0: with c = column v0 of Omega and Omega(u*, .)
+// = 0 (slot v0 stands for u*), M[i][j] = O(i, j) - c^(i) - c^(j) + c[v0],
+// O(i, j) = Omega[i][j] off row and column v0 and 0 on them, c^ = c with
+// c^[v0] = 0 (identity of grounded inverses of one Laplacian:
+// G_r(i, j) = P(i, j) - P(i, r) - P(r, j) + P(r, r) for any pseudo-inverse P).
+__global__ __launch_bounds__(kThreads) void reground_kernel(double *__restrict__ A, uint32_t n,
+                                                            uint32_t N, uint32_t v0,
+                                                            const double *__restrict__ c) {
+    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t i = blockIdx.y;
+    if (j >= n) return;
+    const double cvv = c[v0];
+    const double ci = i == v0 ? 0.0 : c[i], cj = j == v0 ? 0.0 : c[j];
+    double *p = A + static_cast<size_t>(i) * N + j;
+    const double o = (i == v0 || j == v0) ? 0.0 : *p;
+    *p = (o - ci - cj) + cvv;
+}
+
+__global__ __launch_bounds__(kThreads) void copy_col_kernel(const double *__restrict__ A, uint32_t n,
+                                                            uint32_t N, uint32_t v,
+                                                            double *__restrict__ col,
+                                                            double *__restrict__ row) {
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    col[i] = A[static_cast<size_t>(i) * N + v];
+    if (row) row[i] = A[static_cast<size_t>(v) * N + i];
+}
+
+// Column sums of squares over row chunks of kChunk rows (part[chunk * N + j]),
+// optionally after the downdate M[i][j] -= cv[i] rv[j] / piv of vertex v,
+// whose row and column become zero.
+constexpr uint32_t kChunk = 64;
+__global__ __launch_bounds__(kThreads) void colsq_kernel(double *__restrict__ A, uint32_t n, uint32_t N,
+                                                         uint32_t v, const double *__restrict__ cv,
+                                                         const double *__restrict__ rv,
+                                                         const double *__restrict__ pivp,
+                                                         double *__restrict__ part) {
+    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t c = blockIdx.y;
+    if (j >= n) return;
+    const uint32_t i0 = c * kChunk, i1 = min(n, i0 + kChunk);
+    double s = 0.0;
+    if (cv) {
+        const double piv = *pivp;
+        const double f = rv[j] / piv;
+        for (uint32_t i = i0; i < i1; ++i) {
+            double *p = A + static_cast<size_t>(i) * N + j;
+            const double x = (i == v || j == v) ? 0.0 : *p - cv[i] * f;
+            *p = x;
+            s += x * x;
+        }
+    } else {
+        for (uint32_t i = i0; i < i1; ++i) {
+            const double x = A[static_cast<size_t>(i) * N + j];
+            s += x * x;
+        }
+    }
+    part[static_cast<size_t>(c) * N + j] = s;
+}
+
+// gain[j] = |M e_j|^2 / M_jj for candidates (not taken, not the u* slot),
+// else -1; the chunk sums added in chunk order.
+__global__ __launch_bounds__(kThreads) void gain_kernel(const double *__restrict__ A, uint32_t n,
+                                                        uint32_t N, uint32_t chunks,
+                                                        const double *__restrict__ part,
+                                                        const uint8_t *__restrict__ taken,
+                                                        double *__restrict__ gain,
+                                                        unsigned long long *sel) {
+    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= n) return;
+    double g = -1.0;
+    if (!taken[j]) {
+        double s = 0.0;
+        for (uint32_t c = 0; c < chunks; ++c) s += part[static_cast<size_t>(c) * N + j];
+        g = s / A[static_cast<size_t>(j) * N + j];
+        atomicMax(&sel[0], static_cast<unsigned long long>(__double_as_longlong(g)));
+    }
+    gain[j] = g;
+}
+__global__ __launch_bounds__(kThreads) void argmax_id_kernel(const double *__restrict__ gain, uint32_t n,
+                                                             unsigned long long *sel) {
+    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
+    if (j < n && gain[j] >= 0.0 &&
+        static_cast<unsigned long long>(__double_as_longlong(gain[j])) == sel[0])
+        atomicMin(&sel[1], static_cast<unsigned long long>(j));
+}
+
+// tr(M) over the first n slots (one block, fixed order), into *out; also
+// stores M[v][v] into *piv when v < n.
+__global__ __launch_bounds__(kThreads) void trace_kernel(const double *__restrict__ A, uint32_t n,
+                                                         uint32_t N, uint32_t v,
+                                                         double *__restrict__ out,
+                                                         double *__restrict__ piv) {
+    __shared__ double s[kThreads];
+    double t = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += kThreads) t += A[static_cast<size_t>(i) * N + i];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (uint32_t h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out = s[0];
+        if (v < n) *piv = A[static_cast<size_t>(v) * N + v];
+    }
+}
+
+inline unsigned int blocks_for(uint32_t items) { return (items + kThreads - 1) / kThreads; }
+
+}  // namespace
+
+uint32_t group_dim(uint32_t n) { return (n + kT - 1) / kT * kT; }
+uint32_t group_chunks(uint32_t n) { return (n + kChunk - 1) / kChunk; }
+
+hipError_t launch_group_build(const int32_t *row_ptr, const int32_t *col_idx, const double *w,
+                              uint32_t n, double alpha, double *A, hipStream_t stream) {
+    const uint32_t N = group_dim(n);
+    hipError_t e = hipMemsetAsync(A, 0, sizeof(double) * N * N, stream);
+    if (e != hipSuccess) return e;
+    dense_build_kernel<<<blocks_for(N), kThreads, 0, stream>>>(row_ptr, col_idx, w, n, N, alpha, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_invert(double *A, uint32_t N, double *Dinv, hipStream_t stream) {
+    const uint32_t nt = N / kT;
+    for (uint32_t pt = 0; pt < nt; ++pt) {
+        gj_pivot_kernel<<<1, kThreads, 0, stream>>>(A, N, pt * kT, Dinv);
+        gj_panel_kernel<<<nt, kThreads, 0, stream>>>(A, N, pt, Dinv, 0u);
+        gj_update_kernel<<<dim3(nt, nt), kThreads, 0, stream>>>(A, N, pt);
+        gj_panel_kernel<<<nt, kThreads, 0, stream>>>(A, N, pt, Dinv, 1u);
+        gj_put_kernel<<<1, kThreads, 0, stream>>>(A, N, pt, Dinv);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_group_first(const double *A, uint32_t n, uint32_t N, double *diag,
+                              unsigned long long *sel, hipStream_t stream) {
+    diag_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, diag);
+    argmin_bits_kernel<<<blocks_for(n), kThreads, 0, stream>>>(diag, n, sel);
+    argmin_id_kernel<<<blocks_for(n), kThreads, 0, stream>>>(diag, n, sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_reground(double *A, uint32_t n, uint32_t N, uint32_t v0, double *c,
+                                 hipStream_t stream) {
+    copy_col_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, v0, c, nullptr);
+    reground_kernel<<<dim3(blocks_for(n), n), kThreads, 0, stream>>>(A, n, N, v0, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_trace(const double *A, uint32_t n, uint32_t N, uint32_t v, double *out,
+                              double *piv, hipStream_t stream) {
+    trace_kernel<<<1, kThreads, 0, stream>>>(A, n, N, v, out, piv);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_colsq(double *A, uint32_t n, uint32_t N, uint32_t v, double *cv, double *rv,
+                              const double *piv, double *part, hipStream_t stream) {
+    const bool down = v < n;
+    if (down) copy_col_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, v, cv, rv);
+    colsq_kernel<<<dim3(blocks_for(n), group_chunks(n)), kThreads, 0, stream>>>(
+        A, n, N, v, down ? cv : nullptr, down ? rv : nullptr, piv, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_argmax(const double *A, uint32_t n, uint32_t N, const double *part,
+                               const uint8_t *taken, double *gain, unsigned long long *sel,
+                               hipStream_t stream) {
+    gain_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, group_chunks(n), part, taken, gain,
+                                                        sel);
+    argmax_id_kernel<<<blocks_for(n), kThreads, 0, stream>>>(gain, n, sel);
+    return hipGetLastError();
+}
+
+}  // namespace fc

@@ -1,0 +1,127 @@
+"""GPU parity of group forest closeness (Section 5, Algorithm 2) against the
+oracle, through the C-ABI.
+
+The greedy is binary64 linear algebra on both sides, with different
+summation orders (blocked Gauss-Jordan and a change of ground on the device;
+pinv, inverse and numpy downdates in the oracle), so f(S) is compared within a
+relative tolerance derived from the conditioning (1e-9 here: the matrices are
+(alpha L + I)-like, condition number below 1 + 2 alpha d_max), and the chosen
+vertices are compared exactly on graphs whose gains are far from ties; where
+ties are possible each choice is checked to attain the maximal gain instead.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_06192_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _check_farness(g, alpha, got):
+    for i in range(len(got["group"])):
+        ref = oracle.group_farness(g, alpha, got["group"][:i + 1])
+        assert abs(got["farness"][i] - ref) <= RTOL * ref, (i, got["farness"][i], ref)
+
+
+@pytest.mark.parametrize("name,alpha,k", [("ba600", 1.0, 8), ("er900", 0.5, 10),
+                                          ("ba500w", 2.0, 6), ("grid_rm", 1.5, 7),
+                                          ("ba64", 1.0, 5)])
+def test_greedy_matches_oracle(gpu_lib, name, alpha, k):
+    g = {"ba600": lambda: inputs.barabasi_albert(600, 3, 1),
+         "er900": lambda: inputs.erdos_renyi(900, 0.006, 2),
+         "ba500w": lambda: inputs.with_weights(inputs.barabasi_albert(500, 2, 3), 4),
+         "grid_rm": lambda: inputs.grid_removed(25, 31, 0.12, 5),
+         "ba64": lambda: inputs.barabasi_albert(64, 2, 6)}[name]()
+    _say(f"group {name} n={g.n} alpha={alpha} k={k}")
+    got = gpu_lib.group_closeness(g, alpha, k)
+    S, f = oracle.greedy_group(g, alpha, k)
+    assert got["group"] == S
+    for a, b in zip(got["farness"], f):
+        assert abs(a - b) <= RTOL * b
+    _check_farness(g, alpha, got)
+
+
+def test_every_choice_attains_the_maximal_gain(gpu_lib):
+    """A symmetric graph (ties everywhere): each choice must maximise the gain
+    f(S) - f(S + v) computed by direct inversion, up to the tolerance."""
+    g = inputs.grid_removed(8, 9, 0.0, 0)
+    alpha, k = 1.0, 6
+    got = gpu_lib.group_closeness(g, alpha, k)
+    S = got["group"]
+    assert len(set(S)) == k
+    d = np.diag(oracle.forest_matrix(g, alpha))
+    assert d[S[0]] <= d.min() * (1 + RTOL)
+    for i in range(1, k):
+        base = oracle.group_farness(g, alpha, S[:i])
+        gains = [base - oracle.group_farness(g, alpha, S[:i] + [v]) for v in range(g.n)
+                 if v not in S[:i]]
+        chosen = base - oracle.group_farness(g, alpha, S[:i + 1])
+        assert chosen >= max(gains) - RTOL * base
+    _check_farness(g, alpha, got)
+
+
+def test_vertex_cover_closed_form_on_petersen(gpu_lib):
+    """Petersen graph (3-regular): the farness of the greedy set is the
+    oracle's, and no set of size k beats a vertex cover's closed form."""
+    edges = ([(i, (i + 1) % 5) for i in range(5)] + [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+             + [(i, 5 + i) for i in range(5)])
+    g = inputs.from_edge_list(10, edges, "petersen")
+    n = 10
+    for k in range(1, 9):
+        got = gpu_lib.group_closeness(g, 1.0, k)
+        _check_farness(g, 1.0, got)
+        t = (n - k) / 4 + (1 + (n - k) / 16) / (n - (n - k) / 4)
+        assert got["farness"][-1] >= t * (1 - RTOL)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_tiny_graphs(gpu_lib, n):
+    """Paths of 1-3 vertices (symmetric: ties between the ends), every k: the
+    same f(S) trajectory as the oracle, and a valid set."""
+    g = inputs.from_edge_list(n, [(i, i + 1) for i in range(n - 1)])
+    for k in range(1, n + 1):
+        got = gpu_lib.group_closeness(g, 1.0, k)
+        S, f = oracle.greedy_group(g, 1.0, k)
+        assert sorted(got["group"]) == sorted(set(got["group"])) and len(got["group"]) == k
+        assert np.allclose(got["farness"], f, rtol=RTOL, atol=0.0)
+        _check_farness(g, 1.0, got)
+
+
+def test_larger_graph_farness(gpu_lib):
+    """n = 3000 (47 pivot blocks, a ragged last block): the greedy's f(S)
+    against a dense inverse of L* without S at the first and the last step."""
+    g = inputs.barabasi_albert(3000, 4, 7)
+    k = 12
+    got = gpu_lib.group_closeness(g, 1.0, k)
+    assert len(set(got["group"])) == k
+    for i in (0, k - 1):
+        ref = oracle.group_farness(g, 1.0, got["group"][:i + 1])
+        assert abs(got["farness"][i] - ref) <= RTOL * ref
+    d = np.diag(oracle.forest_matrix(g, 1.0))
+    assert got["group"][0] == int(np.argmin(d))
+    assert all(a > b for a, b in zip(got["farness"], got["farness"][1:]))
+
+
+def test_argument_errors(gpu_lib):
+    fc = gpu_lib
+    g = inputs.barabasi_albert(50, 2, 1)
+    for k in (0, 51):
+        with pytest.raises(fc.FCError) as e:
+            fc.group_closeness(g, 1.0, k)
+        assert e.value.code == fc.FC_ERR_ARG
+    with pytest.raises(fc.FCError) as e:
+        fc.group_closeness(g, 0.0, 2)
+    assert e.value.code == fc.FC_ERR_ARG
+    with pytest.raises(fc.FCError) as e:
+        fc.group_closeness(inputs.barabasi_albert(70_000, 1, 1), 1.0, 2)
+    assert e.value.code == fc.FC_ERR_UNSUPPORTED
