@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--sampler", default="auto", choices=["auto", "lane", "coop", "lds", "hyb"])
     ap.add_argument("--config", default="ba200k",
                     choices=["ba200k", "ba200k_w", "er1000", "grid1000", "rmat_batch", "rmat22",
-                             "solve", "rank"],
+                             "solve", "rank", "group"],
                     help="workload; the default is the headline configuration")
     ap.add_argument("--phase-timing", action="store_true",
                     help="report per-phase times of the workgroup sampler (adds clock reads)")
@@ -392,6 +392,37 @@ def other_config(args, fc, inputs, dev):
                     "kendall_ms": 1000 * dt_kt, "kendall_pairs_per_s": pairs / dt_kt,
                     "kendall_two_estimates_tau_b": kt["tau_b"],
                     "ground_truth_s": truth_s, "kt_vs_cg": quality})
+    elif args.config == "group":
+        # group forest closeness (Algorithm 2): one dense inverse (k = 1 times it
+        # alone), then one downdate pass over the n x n matrix per greedy step
+        g = inputs.barabasi_albert(20_000, 5, 0)
+        dg = fc.to_device(g, dev)
+        k = 50
+        t1, _ = _timed(lambda: fc.group_closeness(dg, 1.0, 1, device=dev, trusted=True), args.steps,
+                       args.warmup)
+        tk, out = _timed(lambda: fc.group_closeness(dg, 1.0, k, device=dev, trusted=True),
+                         args.steps, args.warmup)
+        N = (g.n + 63) // 64 * 64
+        flops = 2.0 * N ** 3  # blocked Gauss-Jordan: n^3 multiply-adds
+        step_s = (tk - t1) / (k - 1)
+        step_bytes = 16.0 * g.n * g.n  # read and write the n x n binary64 matrix
+        res.update({"metric": "greedy group forest closeness time (Algorithm 2)", "value": 1000 * tk,
+                    "unit": "ms", "higher_is_better": False,
+                    "config": {"workload": "ba_n20000_m5_alpha1_group_k50", "n": g.n, "m": g.m,
+                               "k": k},
+                    "group_head": out["group"][:8], "farness_first_last": [out["farness"][0],
+                                                                           out["farness"][-1]],
+                    "inverse": {"ms": 1000 * t1,
+                                "roofline": {"bound": "mfma", "achieved": flops / t1 / 1e12,
+                                             "peak": 78.6, "unit": "TFLOP/s",
+                                             "frac": flops / t1 / 1e12 / 78.6,
+                                             "algorithmic_flops": flops,
+                                             "note": "k = 1 call: build, inverse, change of ground, one norm pass"}},
+                    "greedy_step": {"ms": 1000 * step_s,
+                                    "roofline": {"bound": "hbm", "achieved": step_bytes / step_s / 1e9,
+                                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                                 "frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS,
+                                                 "algorithmic_bytes": step_bytes}}})
     elif args.config == "grid1000":
         g = inputs.grid_removed(1000, 1000, 0.12, 0)
         dg = fc.to_device(g, dev)
