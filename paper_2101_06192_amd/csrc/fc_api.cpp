@@ -765,7 +765,7 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->wthr,
                       &ctx->s_wdeg, &ctx->rk_key0, &ctx->rk_key1, &ctx->rk_val0, &ctx->rk_val1,
                       &ctx->rk_hist, &ctx->rk_thist, &ctx->rk_ra, &ctx->rk_rb, &ctx->g_mat,
-                      &ctx->g_vec, &ctx->g_part, &ctx->g_taken})
+                      &ctx->g_vec, &ctx->g_part, &ctx->g_taken, &ctx->g_scr})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

@@ -24,14 +24,14 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
     if ((rc = ensure(ctx, ctx->g_mat, sizeof(double) * N * static_cast<size_t>(N), "dense matrix")) ||
         (rc = ensure(ctx, ctx->g_vec, sizeof(double) * (4 * static_cast<size_t>(n) + 64 * 64 + 16),
                      "group vectors")) ||
+        (rc = ensure(ctx, ctx->g_scr, sizeof(double) * fc::group_scratch_doubles(N), "inverse scratch")) ||
         (rc = ensure(ctx, ctx->g_part, sizeof(double) * chunks * N, "column sums")) ||
         (rc = ensure(ctx, ctx->g_taken, n, "group flags")))
         return rc;
     double *A = static_cast<double *>(ctx->g_mat.ptr);
     double *vec = static_cast<double *>(ctx->g_vec.ptr);
     double *cv = vec, *rv = vec + n, *diag = vec + 2 * n, *gain = vec + 3 * n;
-    double *Dinv = vec + 4 * static_cast<size_t>(n);
-    double *scal = Dinv + 64 * 64;  // [0] trace, [1] pivot
+    double *scal = vec + 4 * static_cast<size_t>(n) + 64 * 64;  // [0] trace, [1] pivot
     unsigned long long *sel = reinterpret_cast<unsigned long long *>(scal + 4);
     double *part = static_cast<double *>(ctx->g_part.ptr);
     uint8_t *taken = static_cast<uint8_t *>(ctx->g_taken.ptr);
@@ -41,7 +41,8 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
     // minus a constant)
     FC_HIP(ctx, fc::launch_group_build(gv.row_ptr, gv.col_idx, gv.weights, n, alpha, A, ctx->stream),
            "dense build");
-    FC_HIP(ctx, fc::launch_group_invert(A, N, Dinv, ctx->stream), "dense inverse");
+    FC_HIP(ctx, fc::launch_group_invert(A, N, static_cast<double *>(ctx->g_scr.ptr), ctx->stream),
+           "dense inverse");
     FC_HIP(ctx, hipMemsetAsync(sel, 0xFF, 2 * sizeof(unsigned long long), ctx->stream), "memset");
     FC_HIP(ctx, fc::launch_group_first(A, n, N, diag, sel, ctx->stream), "first vertex");
     unsigned long long hsel[2];

@@ -39,7 +39,7 @@ struct fc_ctx {
     DevBuf weights, wsum, wthr;  // staged edge weights (host graphs), running row weight sums,
                                  // step thresholds
     DevBuf rk_key0, rk_key1, rk_val0, rk_val1, rk_hist, rk_thist, rk_ra, rk_rb;  // ranking output
-    DevBuf g_mat, g_vec, g_part, g_taken;  // group closeness: dense matrix, vectors, sums, flags
+    DevBuf g_mat, g_vec, g_part, g_taken, g_scr;  // group closeness: matrix, vectors, sums, flags, scratch
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler

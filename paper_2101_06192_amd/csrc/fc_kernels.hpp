@@ -290,15 +290,17 @@ hipError_t launch_kendall(const uint32_t *ra, const uint32_t *rb, uint32_t n,
                           unsigned long long *out, hipStream_t stream);
 
 // Group forest closeness (group.hip): dense N x N binary64 matrices,
-// N = group_dim(n) (n rounded up to 64), row-major.
+// N = group_dim(n) (n rounded up to 256), row-major.
 uint32_t group_dim(uint32_t n);
+size_t group_scratch_doubles(uint32_t N);  // scratch of launch_group_invert
 uint32_t group_chunks(uint32_t n);  // row chunks of the column sums
 // A = alpha L + I on the first n rows and columns (weighted when w is not
 // null), identity on the padding.
 hipError_t launch_group_build(const int32_t *row_ptr, const int32_t *col_idx, const double *w,
                               uint32_t n, double alpha, double *A, hipStream_t stream);
-// A <- A^{-1} in place (SPD; blocked Gauss-Jordan, Dinv: 64 x 64 scratch).
-hipError_t launch_group_invert(double *A, uint32_t N, double *Dinv, hipStream_t stream);
+// A <- A^{-1} in place (SPD; blocked Gauss-Jordan; scratch of
+// group_scratch_doubles(N) doubles).
+hipError_t launch_group_invert(double *A, uint32_t N, double *scratch, hipStream_t stream);
 // diag[v] = A[v][v]; sel[0] = min diagonal bits, sel[1] = smallest id with it
 // (sel preset to all ones by the caller).
 hipError_t launch_group_first(const double *A, uint32_t n, uint32_t N, double *diag,

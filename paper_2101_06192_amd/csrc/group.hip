@@ -5,12 +5,13 @@
 // step, adds the vertex v maximising |M e_v|^2 / M_vv and downdates
 // M <- M - M e_v e_v^T M / M_vv (row and column v become zero).
 //
-// Layout: one N x N row-major binary64 matrix, N = n rounded up to 64; the
+// Layout: one N x N row-major binary64 matrix, N = n rounded up to 256; the
 // padding is an identity block, never read by the greedy.  It first holds
-// alpha L + I, inverted in place by blocked Gauss-Jordan (64 x 64 pivot
-// blocks; the rank-64 trailing update on fp64 MFMA), i.e. Omega; then, in
-// place, the inverse of L* grounded at the first vertex v0, with slot v0
-// standing for u*.
+// alpha L + I, inverted in place by blocked Gauss-Jordan with 256-wide pivot
+// blocks (each pivot block inverted by the same method with 64-wide blocks in
+// a 256 x 256 scratch; the panels and the rank-256 trailing update are fp64
+// MFMA tile products), i.e. Omega; then, in place, the inverse of L*
+// grounded at the first vertex v0, with slot v0 standing for u*.
 #include "fc_kernels.hpp"
 
 namespace fc {
@@ -18,6 +19,7 @@ namespace fc {
 namespace {
 
 constexpr uint32_t kT = 64;        // tile edge
+constexpr uint32_t kB = 256;       // pivot block width of the outer Gauss-Jordan
 constexpr uint32_t kPad = kT + 1;  // LDS row stride (doubles): rows fall on different banks
 constexpr uint32_t kThreads = 256;
 
@@ -165,6 +167,89 @@ __global__ __launch_bounds__(kThreads) void gj_update_kernel(double *__restrict_
             for (uint32_t r = 0; r < 4; ++r)
                 A[static_cast<size_t>(i0 + q.qr + 16u * s + d_row(q.lane, r)) * N + j0 + q.qc +
                   16u * u + d_col(q.lane)] = acc[s][u][r];
+}
+
+// Tile product over K = kchunks x 64: out[ti, tj] = (load_c ? out[ti, tj] : 0)
+// + (negate_x ? -X : X)[ti, :] Y[:, tj], the K dimension streamed through LDS
+// 64 at a time (the accumulators stay in registers).  Tiles whose row tile is
+// in [si0, si1) or whose column tile is in [sj0, sj1) are skipped.
+struct GemmArgs {
+    const double *X;
+    const double *Y;
+    double *out;
+    uint32_t ldx, ldy, ldo, kchunks;
+    uint32_t si0, si1, sj0, sj1;
+    uint32_t load_c, negate_x;
+};
+
+__device__ __forceinline__ void stage_ld(const double *__restrict__ A, uint32_t ld, uint32_t r0,
+                                         uint32_t c0, double *S, bool negate) {
+    for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads) {
+        const uint32_t r = e / kT, c = e % kT;
+        const double x = A[static_cast<size_t>(r0 + r) * ld + c0 + c];
+        S[r * kPad + c] = negate ? -x : x;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
+    const uint32_t ti = blockIdx.y, tj = blockIdx.x;
+    if ((ti >= g.si0 && ti < g.si1) || (tj >= g.sj0 && tj < g.sj1)) return;
+    __shared__ double X[kT * kPad], Y[kT * kPad];
+    const Quad q = quad();
+    double4_t acc[2][2];
+    const uint32_t i0 = ti * kT, j0 = tj * kT;
+#pragma unroll
+    for (uint32_t s = 0; s < 2; ++s)
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                acc[s][u][r] = g.load_c ? g.out[static_cast<size_t>(i0 + q.qr + 16u * s + d_row(q.lane, r)) *
+                                                    g.ldo + j0 + q.qc + 16u * u + d_col(q.lane)]
+                                        : 0.0;
+    // software pipeline: chunk c + 1 is loaded into registers while the
+    // matrix cores work on chunk c from LDS
+    constexpr uint32_t kPer = kT * kT / kThreads;  // elements of a chunk per thread
+    double xr[kPer], yr[kPer];
+    const double sx = g.negate_x ? -1.0 : 1.0;
+    auto load = [&](uint32_t c) {
+#pragma unroll
+        for (uint32_t q2 = 0; q2 < kPer; ++q2) {
+            const uint32_t e = q2 * kThreads + threadIdx.x, r = e / kT, cc = e % kT;
+            xr[q2] = g.X[static_cast<size_t>(i0 + r) * g.ldx + c * kT + cc];
+            yr[q2] = g.Y[static_cast<size_t>(c * kT + r) * g.ldy + j0 + cc];
+        }
+    };
+    load(0);
+    for (uint32_t c = 0; c < g.kchunks; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (uint32_t q2 = 0; q2 < kPer; ++q2) {
+            const uint32_t e = q2 * kThreads + threadIdx.x, r = e / kT, cc = e % kT;
+            X[r * kPad + cc] = sx * xr[q2];
+            Y[r * kPad + cc] = yr[q2];
+        }
+        __syncthreads();
+        if (c + 1 < g.kchunks) load(c + 1);
+        tile_mma(X, Y, q.qr, q.qc, q.lane, acc);
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < 2; ++s)
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u)
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                g.out[static_cast<size_t>(i0 + q.qr + 16u * s + d_row(q.lane, r)) * g.ldo + j0 + q.qc +
+                      16u * u + d_col(q.lane)] = acc[s][u][r];
+}
+
+// dst[r][c] = src[r][c] for a rows x cols block (row strides lds, ldd).
+__global__ __launch_bounds__(kThreads) void copy_block_kernel(const double *__restrict__ src,
+                                                              uint32_t lds, double *__restrict__ dst,
+                                                              uint32_t ldd, uint32_t cols) {
+    const uint32_t r = blockIdx.y;
+    for (uint32_t c = blockIdx.x * kThreads + threadIdx.x; c < cols; c += gridDim.x * kThreads)
+        dst[static_cast<size_t>(r) * ldd + c] = src[static_cast<size_t>(r) * lds + c];
 }
 
 __global__ __launch_bounds__(kThreads) void gj_put_kernel(double *__restrict__ A, uint32_t N,
@@ -331,7 +416,10 @@ inline unsigned int blocks_for(uint32_t items) { return (items + kThreads - 1) /
 
 }  // namespace
 
-uint32_t group_dim(uint32_t n) { return (n + kT - 1) / kT * kT; }
+uint32_t group_dim(uint32_t n) { return (n + kB - 1) / kB * kB; }
+size_t group_scratch_doubles(uint32_t N) {
+    return static_cast<size_t>(kB) * kB + 2 * static_cast<size_t>(kB) * N + kT * kT;
+}
 uint32_t group_chunks(uint32_t n) { return (n + kChunk - 1) / kChunk; }
 
 hipError_t launch_group_build(const int32_t *row_ptr, const int32_t *col_idx, const double *w,
@@ -343,7 +431,10 @@ hipError_t launch_group_build(const int32_t *row_ptr, const int32_t *col_idx, co
     return hipGetLastError();
 }
 
-hipError_t launch_group_invert(double *A, uint32_t N, double *Dinv, hipStream_t stream) {
+namespace {
+
+// In-place Gauss-Jordan inverse with 64-wide pivot blocks (N a multiple of 64).
+void invert_64(double *A, uint32_t N, double *Dinv, hipStream_t stream) {
     const uint32_t nt = N / kT;
     for (uint32_t pt = 0; pt < nt; ++pt) {
         gj_pivot_kernel<<<1, kThreads, 0, stream>>>(A, N, pt * kT, Dinv);
@@ -351,6 +442,49 @@ hipError_t launch_group_invert(double *A, uint32_t N, double *Dinv, hipStream_t 
         gj_update_kernel<<<dim3(nt, nt), kThreads, 0, stream>>>(A, N, pt);
         gj_panel_kernel<<<nt, kThreads, 0, stream>>>(A, N, pt, Dinv, 1u);
         gj_put_kernel<<<1, kThreads, 0, stream>>>(A, N, pt, Dinv);
+    }
+}
+
+}  // namespace
+
+// Outer Gauss-Jordan over 256-wide pivot blocks P (rows and columns [p0, p0 + 256)):
+//   W = A[P, P]^{-1}                    (copy, then invert_64 on the 256 x 256 copy)
+//   R = W A[P, :]                       (row panel, out of place: 256 x N)
+//   A[i, j] -= A[i, P] R[:, j]          (i, j outside P; A[i, P] still the old panel)
+//   C = -A[:, P] W                      (column panel, out of place: N x 256)
+//   A[P, :] = R, A[:, P] = C, A[P, P] = W
+// Scratch: W (256 x 256), R (256 x N), C (N x 256), then a 64 x 64 block.
+hipError_t launch_group_invert(double *A, uint32_t N, double *scratch, hipStream_t stream) {
+    double *W = scratch, *R = W + kB * kB, *C = R + static_cast<size_t>(kB) * N;
+    double *D64 = C + static_cast<size_t>(N) * kB;
+    const uint32_t nt = N / kT, pb = kB / kT;
+    for (uint32_t p0 = 0; p0 < N; p0 += kB) {
+        const uint32_t pt0 = p0 / kT, pt1 = pt0 + pb;
+        copy_block_kernel<<<dim3(1, kB), kThreads, 0, stream>>>(A + static_cast<size_t>(p0) * N + p0, N,
+                                                                W, kB, kB);
+        invert_64(W, kB, D64, stream);
+        GemmArgs row{W, A + static_cast<size_t>(p0) * N, R, kB, N, N, pb, 0u, 0u, pt0, pt1, 0u, 0u};
+        gemm_kernel<<<dim3(nt, pb), kThreads, 0, stream>>>(row);
+        GemmArgs upd{A + p0, R, A, N, N, N, pb, pt0, pt1, pt0, pt1, 1u, 1u};
+        gemm_kernel<<<dim3(nt, nt), kThreads, 0, stream>>>(upd);
+        GemmArgs col{A + p0, W, C, N, kB, kB, pb, pt0, pt1, 0u, 0u, 0u, 1u};
+        gemm_kernel<<<dim3(pb, nt), kThreads, 0, stream>>>(col);
+        // write back: rows of P from R (outside P's columns), columns of P from C
+        // (outside P's rows), and W on the diagonal block
+        if (p0 > 0)
+            copy_block_kernel<<<dim3(4, kB), kThreads, 0, stream>>>(R, N, A + static_cast<size_t>(p0) * N,
+                                                                    N, p0);
+        if (p0 + kB < N)
+            copy_block_kernel<<<dim3(4, kB), kThreads, 0, stream>>>(
+                R + p0 + kB, N, A + static_cast<size_t>(p0) * N + p0 + kB, N, N - p0 - kB);
+        if (p0 > 0)
+            copy_block_kernel<<<dim3(1, p0), kThreads, 0, stream>>>(C, kB, A + p0, N, kB);
+        if (p0 + kB < N)
+            copy_block_kernel<<<dim3(1, N - p0 - kB), kThreads, 0, stream>>>(
+                C + static_cast<size_t>(p0 + kB) * kB, kB, A + static_cast<size_t>(p0 + kB) * N + p0, N,
+                kB);
+        copy_block_kernel<<<dim3(1, kB), kThreads, 0, stream>>>(W, kB, A + static_cast<size_t>(p0) * N + p0,
+                                                                N, kB);
     }
     return hipGetLastError();
 }
