@@ -9,6 +9,8 @@ benchmark times, on outputs the oracle can recompute one by one.
   within the Hoeffding radius.
 - 1000 x 1000 grid with 12% of the edges removed, 1024 trees at alpha = 1
   and 2: per-tree digests and walk steps of sampled trees against the oracle.
+- Weighted BA(200000, 5), 4096 trees: per-tree digests and steps of sampled
+  trees against the oracle.
 (BA(200000, 5) with 4096 trees is in test_gpu_parity.py.)
 """
 import sys
@@ -87,3 +89,24 @@ def test_grid_full_size_sampled(gpu_lib, alpha):
         assert got["tree_digests"][t] == ref.digests[0], t
         assert got["tree_steps"][t] == ref.steps[0], t
     assert int(got["root_counts"].astype(np.int64).sum()) == got["stats"]["roots"]
+
+
+def test_weighted_ba200k_full_size_sampled(gpu_lib):
+    """The weighted workload of the benchmark (BA(200000, 5), log-uniform
+    weights in [0.1, 10), alpha = 1, 4096 trees in one call, the LDS sampler
+    with first arrows drawn ahead): per-tree digests and steps of sampled trees
+    against the oracle, and the totals against the root counts."""
+    fc = gpu_lib
+    g = inputs.with_weights(inputs.barabasi_albert(200_000, 5, 0), 0)
+    dg = fc.to_device(g)
+    got = fc.sample(dg, alpha=1.0, seed=0, tree_begin=0, tree_count=4096, want_digests=True,
+                    want_steps=True)
+    st = got["stats"]
+    _say(f"weighted ba200k: sampler={st['sampler']} ms={st['ms_sample']:.1f} predraw={st['ms_predraw']:.1f}")
+    assert st["sampler"] == "wilson_lds" and st["ms_predraw"] > 0.0
+    for t in (0, 1, 2047, 4095):
+        ref = oracle.sample(g, 1.0, 0, t, 1)
+        assert got["tree_digests"][t] == ref.digests[0], t
+        assert got["tree_steps"][t] == ref.steps[0], t
+    assert int(got["root_counts"].astype(np.int64).sum()) == st["roots"]
+    assert int(got["tree_steps"].sum()) == st["walk_steps"]
