@@ -362,8 +362,17 @@ def other_config(args, fc, inputs, dev):
         other = fc.farness(dg, alpha=1.0, eps=0.1, delta=0.1, seed=1, device=dev, as_torch=True)
         dt_kt, kt = _timed(lambda: fc.kendall_tau(diag, other["diag"], device=dev), args.steps,
                            args.warmup)
+        fc.set_option("kendall_pairs", 1, dev)
+        dt_pairs, kt_pairs = _timed(lambda: fc.kendall_tau(diag, other["diag"], device=dev),
+                                    args.steps, args.warmup)
+        fc.set_option("kendall_pairs", 0, dev)
+        assert kt_pairs["counts"] == kt["counts"]
         n = g.n
         pairs = n * (n - 1) // 2
+        # the all-pairs kernel is VALU-bound: 10 instructions per pair (two
+        # differences, two v_med3_i32 signs, a product, three multiply-adds, loop
+        # share) against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 lane-ops
+        valu_peak = 256 * 4 * 16 * 2.4e9
         gs = inputs.barabasi_albert(20_000, 5, 0)
         dgs = fc.to_device(gs, dev)
         t0 = time.perf_counter()
@@ -389,7 +398,13 @@ def other_config(args, fc, inputs, dev):
                     "config": {"workload": "ba_n200000_m5_alpha1_eps0.1_rank_kendall", "n": n,
                                "kt_graph": "ba_n20000_m5_alpha1"},
                     "rank_ms": 1000 * dt_rank,
-                    "kendall_ms": 1000 * dt_kt, "kendall_pairs_per_s": pairs / dt_kt,
+                    "kendall_ms": 1000 * dt_kt,
+                    "kendall_all_pairs": {"ms": 1000 * dt_pairs, "pairs_per_s": pairs / dt_pairs,
+                                          "roofline": {"bound": "alu",
+                                                       "achieved": 10 * pairs / dt_pairs / 1e12,
+                                                       "peak": valu_peak / 1e12,
+                                                       "unit": "T int32 lane-ops/s",
+                                                       "frac": 10 * pairs / dt_pairs / valu_peak}},
                     "kendall_two_estimates_tau_b": kt["tau_b"],
                     "ground_truth_s": truth_s, "kt_vs_cg": quality})
     elif args.config == "group":

@@ -207,6 +207,9 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "max_draws"       cap on the arrows one vertex may draw in one tree, below each
  *                     sampler's own limit (0, the default: no extra cap); a call that
  *                     exceeds it returns FC_ERR_OVERFLOW (exercises that error path)
+ *   "kendall_pairs"   1: fc_kendall_tau compares all n(n-1)/2 pairs (tiled) instead of
+ *                     counting discordant pairs by a merge sort (0, the default); same
+ *                     counts, O(n^2) instead of O(n log^2 n) work
  * Returns FC_ERR_ARG for an unknown key or a value out of range. */
 FC_API int fc_set_option(fc_ctx *ctx, const char *key, int64_t value);
 
@@ -351,7 +354,10 @@ FC_API int fc_rank(fc_ctx *ctx, const double *score, int32_t n, int32_t descendi
  *           no NaN (FC_ERR_ARG).
  *   tau_b:  host double, or NULL.
  *   counts: host int64[5] = {n_c, n_d, n_a, n_b, n_ab}, or NULL.
- * The device compares all n(n-1)/2 pairs (tiled through LDS). */
+ * On the device: min-ranks of a and b by radix sort, ties from the sorted runs,
+ * pairs tied in both from a sort of the (rank a, rank b) pairs, discordant pairs
+ * as the strict inversions of rank b in that order, counted by a bottom-up merge
+ * sort (option "kendall_pairs": all pairs compared instead). */
 FC_API int fc_kendall_tau(fc_ctx *ctx, const double *a, const double *b, int32_t n,
                           double *tau_b, int64_t *counts);
 

@@ -764,7 +764,7 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->rl_base, &ctx->rl_inv, &ctx->rl_orig, &ctx->rl_vrec, &ctx->rl_adj,
                       &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->wthr,
                       &ctx->s_wdeg, &ctx->rk_key0, &ctx->rk_key1, &ctx->rk_val0, &ctx->rk_val1,
-                      &ctx->rk_hist, &ctx->rk_thist, &ctx->rk_ra, &ctx->rk_rb, &ctx->g_mat,
+                      &ctx->rk_hist, &ctx->rk_thist, &ctx->rk_ra, &ctx->rk_rb, &ctx->rk_s, &ctx->g_mat,
                       &ctx->g_vec, &ctx->g_part, &ctx->g_taken, &ctx->g_scr})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -807,6 +807,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "lds_wg_per_cu") {
         if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
         ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
+    } else if (k == "kendall_pairs") {
+        if (value < 0 || value > 1) return set_err(ctx, FC_ERR_ARG, "kendall_pairs must be 0 or 1");
+        ctx->kendall_pairs = value != 0;
     } else if (k == "predraw_mib") {
         if (value < 0 || value > (int64_t(1) << 22)) return set_err(ctx, FC_ERR_ARG, "predraw_mib");
         ctx->predraw_mib = static_cast<uint32_t>(value);

@@ -38,7 +38,7 @@ struct fc_ctx {
     DevBuf cpre;                                                  // LDS: pre-drawn tree words
     DevBuf weights, wsum, wthr;  // staged edge weights (host graphs), running row weight sums,
                                  // step thresholds
-    DevBuf rk_key0, rk_key1, rk_val0, rk_val1, rk_hist, rk_thist, rk_ra, rk_rb;  // ranking output
+    DevBuf rk_key0, rk_key1, rk_val0, rk_val1, rk_hist, rk_thist, rk_ra, rk_rb, rk_s;  // ranking
     DevBuf g_mat, g_vec, g_part, g_taken, g_scr;  // group closeness: matrix, vectors, sums, flags, scratch
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
@@ -59,6 +59,7 @@ struct fc_ctx {
     uint32_t lds_threads = 0;     // threads per workgroup of the LDS-counter sampler (0: by n)
     uint32_t lds_wg_per_cu = 0;   // its resident workgroups per CU (0: as many as fit)
     uint32_t predraw_mib = 32768;  // budget of pre-drawn first arrows (0: off)
+    bool kendall_pairs = false;   // Kendall's tau by all pairs instead of merge-sort counts
     double wall_khz = 100000.0;   // device wall clock rate
 };
 

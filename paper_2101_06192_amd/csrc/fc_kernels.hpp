@@ -280,9 +280,17 @@ hipError_t launch_radix_pass(const uint64_t *key, const int32_t *val, uint32_t n
                              unsigned int *thist, const unsigned int *base, uint64_t *okey,
                              int32_t *oval, hipStream_t stream);
 hipError_t launch_rank_of(const int32_t *order, uint32_t n, int32_t *rank, hipStream_t stream);
-// out[sval[i]] = the number of sorted keys below skey[i] (skey ascending).
+// out[sval[i]] = the number of sorted keys below skey[i] (skey ascending; out
+// may be null); *ties += pairs of equal keys.
 hipError_t launch_min_rank(const uint64_t *skey, const int32_t *sval, uint32_t n, uint32_t *out,
-                           hipStream_t stream);
+                           unsigned long long *ties, hipStream_t stream);
+// key[i] = ra[i] << 32 | rb[i], val[i] = i.
+hipError_t launch_pair_keys(const uint32_t *ra, const uint32_t *rb, uint32_t n, uint64_t *key,
+                            int32_t *val, hipStream_t stream);
+// *inv += strict inversions of s = rb[id[.]] (pairs p < q with s_p > s_q) by a
+// bottom-up merge sort (s and tmp: n scratch each).
+hipError_t launch_inversions(const uint32_t *rb, const int32_t *id, uint32_t n, uint32_t *s,
+                             uint32_t *tmp, unsigned long long *inv, hipStream_t stream);
 // Kendall pair counts of two rank vectors (< 2^31) over all pairs i < j
 // (n <= 65535 * 256): out[0] += sum of sign products, out[1..3] += pairs tied in
 // a, in b, in both (out zeroed by the caller; out[0] is two's complement).

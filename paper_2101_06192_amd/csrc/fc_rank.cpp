@@ -33,19 +33,22 @@ int ensure_sort(fc_ctx *ctx, size_t n) {
     return FC_OK;
 }
 
-// Stable sort of the scores' order-preserving keys with the indices as values
-// (rk_key0 / rk_val0 and rk_key1 / rk_val1 alternate); *keys and *vals point
-// at the sorted arrays.  FC_ERR_ARG when a score is NaN.
-int sort_scores(fc_ctx *ctx, const double *score, uint32_t n, bool descending,
-                const uint64_t **keys, const int32_t **vals) {
+// Stable sort of the keys in rk_key0 with the values in rk_val0 (rk_key0 /
+// rk_val0 and rk_key1 / rk_val1 alternate); *keys and *vals point at the
+// sorted arrays.  With score set, the keys are first made from the scores
+// (FC_ERR_ARG when a score is NaN); else rk_key0 / rk_val0 hold them already.
+int sort_keys(fc_ctx *ctx, const double *score, uint32_t n, bool descending,
+              const uint64_t **keys, const int32_t **vals) {
     unsigned int *hist = static_cast<unsigned int *>(ctx->rk_hist.ptr);
     unsigned int *base_d = hist + kHistWords;
     unsigned int *bad_d = hist + kFlagWord;
     FC_HIP(ctx, hipMemsetAsync(hist, 0, 4 * (kFlagWord + 1), ctx->stream), "memset counts");
-    FC_HIP(ctx, fc::launch_rank_keys(score, n, descending,
-                                     static_cast<uint64_t *>(ctx->rk_key0.ptr),
-                                     static_cast<int32_t *>(ctx->rk_val0.ptr), bad_d, ctx->stream),
-           "rank keys");
+    if (score)
+        FC_HIP(ctx, fc::launch_rank_keys(score, n, descending,
+                                         static_cast<uint64_t *>(ctx->rk_key0.ptr),
+                                         static_cast<int32_t *>(ctx->rk_val0.ptr), bad_d,
+                                         ctx->stream),
+               "rank keys");
     FC_HIP(ctx, fc::launch_digit_hist(static_cast<const uint64_t *>(ctx->rk_key0.ptr), n, hist,
                                       ctx->stream),
            "digit counts");
@@ -102,7 +105,7 @@ extern "C" int fc_rank(fc_ctx *ctx, const double *score, int32_t n, int32_t desc
     if ((rc = ensure_sort(ctx, static_cast<size_t>(n)))) return rc;
     const uint64_t *keys;
     const int32_t *sorted;
-    if ((rc = sort_scores(ctx, score, un, descending != 0, &keys, &sorted))) return rc;
+    if ((rc = sort_keys(ctx, score, un, descending != 0, &keys, &sorted))) return rc;
     if (order)
         FC_HIP(ctx, hipMemcpyAsync(order, sorted, 4 * static_cast<size_t>(n),
                                    hipMemcpyDeviceToDevice, ctx->stream),
@@ -121,40 +124,60 @@ extern "C" int fc_kendall_tau(fc_ctx *ctx, const double *a, const double *b, int
         return set_err(ctx, FC_ERR_UNSUPPORTED, "n must be <= 65535 * 256");
     if (n > 0 && (!a || !b)) return set_err(ctx, FC_ERR_ARG, "a and b must be device pointers");
     const uint32_t un = static_cast<uint32_t>(n);
+    // sums on the device: [0] n_c - n_d (pair kernel) or n_d (merge count),
+    // [1] tied in a, [2] tied in b, [3] tied in both
     unsigned long long out[4] = {0, 0, 0, 0};
+    const bool pairs = ctx->kendall_pairs;
     if (n > 0) {
         const size_t nn = static_cast<size_t>(n);
         if ((rc = ensure_sort(ctx, nn)) || (rc = ensure(ctx, ctx->rk_ra, 4 * nn, "ranks")) ||
-            (rc = ensure(ctx, ctx->rk_rb, 4 * nn, "ranks")))
+            (rc = ensure(ctx, ctx->rk_rb, 4 * nn, "ranks")) ||
+            (rc = ensure(ctx, ctx->rk_s, 8 * nn, "merge runs")))
             return rc;
-        // each vector's scores -> min-ranks (equal scores share a rank)
+        unsigned long long *out_d =
+            reinterpret_cast<unsigned long long *>(static_cast<unsigned int *>(ctx->rk_hist.ptr) +
+                                                   kOutWord);
+        // each vector's scores -> min-ranks (equal scores share a rank) and its ties
         const double *src[2] = {a, b};
         DevBuf *dst[2] = {&ctx->rk_ra, &ctx->rk_rb};
         for (int v = 0; v < 2; ++v) {
             const uint64_t *keys;
             const int32_t *ids;
-            if ((rc = sort_scores(ctx, src[v], un, false, &keys, &ids))) return rc;
+            if ((rc = sort_keys(ctx, src[v], un, false, &keys, &ids))) return rc;
+            if (v == 0) FC_HIP(ctx, hipMemsetAsync(out_d, 0, sizeof(out), ctx->stream), "memset sums");
             FC_HIP(ctx, fc::launch_min_rank(keys, ids, un, static_cast<uint32_t *>(dst[v]->ptr),
-                                            ctx->stream),
+                                            out_d + 1 + v, ctx->stream),
                    "min ranks");
         }
-        unsigned long long *out_d =
-            reinterpret_cast<unsigned long long *>(static_cast<unsigned int *>(ctx->rk_hist.ptr) +
-                                                   kOutWord);
-        FC_HIP(ctx, hipMemsetAsync(out_d, 0, sizeof(out), ctx->stream), "memset sums");
-        FC_HIP(ctx, fc::launch_kendall(static_cast<const uint32_t *>(ctx->rk_ra.ptr),
-                                       static_cast<const uint32_t *>(ctx->rk_rb.ptr), un, out_d,
-                                       ctx->stream),
-               "kendall");
+        const uint32_t *ra = static_cast<const uint32_t *>(ctx->rk_ra.ptr);
+        const uint32_t *rb = static_cast<const uint32_t *>(ctx->rk_rb.ptr);
+        if (pairs) {  // all n(n-1)/2 pairs compared (the definition, tiled)
+            FC_HIP(ctx, hipMemsetAsync(out_d, 0, sizeof(out), ctx->stream), "memset sums");
+            FC_HIP(ctx, fc::launch_kendall(ra, rb, un, out_d, ctx->stream), "kendall");
+        } else {
+            // pairs tied in both: equal (rank a, rank b); discordant pairs: strict
+            // inversions of rank b in the order of the (a, b) sort
+            FC_HIP(ctx, fc::launch_pair_keys(ra, rb, un, static_cast<uint64_t *>(ctx->rk_key0.ptr),
+                                             static_cast<int32_t *>(ctx->rk_val0.ptr), ctx->stream),
+                   "pair keys");
+            const uint64_t *keys;
+            const int32_t *ids;
+            if ((rc = sort_keys(ctx, nullptr, un, false, &keys, &ids))) return rc;
+            FC_HIP(ctx, fc::launch_min_rank(keys, ids, un, nullptr, out_d + 3, ctx->stream),
+                   "joint ties");
+            uint32_t *sbuf = static_cast<uint32_t *>(ctx->rk_s.ptr);
+            FC_HIP(ctx, fc::launch_inversions(rb, ids, un, sbuf, sbuf + nn, out_d, ctx->stream),
+                   "inversions");
+        }
         FC_HIP(ctx, hipMemcpyAsync(out, out_d, sizeof(out), hipMemcpyDeviceToHost, ctx->stream),
                "copy sums");
         FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "kendall");
     }
     const int64_t n0 = static_cast<int64_t>(n) * (n - 1) / 2;
-    const int64_t s = static_cast<int64_t>(out[0]);
     const int64_t ta = static_cast<int64_t>(out[1]), tb = static_cast<int64_t>(out[2]),
                   tab = static_cast<int64_t>(out[3]);
     const int64_t untied = n0 - ta - tb + tab;  // n_c + n_d
+    const int64_t s = pairs ? static_cast<int64_t>(out[0]) : untied - 2 * static_cast<int64_t>(out[0]);
     if (counts) {
         counts[0] = (untied + s) / 2;
         counts[1] = (untied - s) / 2;

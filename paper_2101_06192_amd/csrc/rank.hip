@@ -147,20 +147,97 @@ __global__ __launch_bounds__(kRankThreads) void rank_of_kernel(const int32_t *__
 // Min-rank of every key after the sort: the number of keys strictly below it
 // (equal keys share it), found by binary search in the sorted keys and
 // scattered to the key's original index.
+// Also adds sum over positions of (i - min-rank) into *ties: a run of t equal
+// keys contributes 0 + 1 + ... + (t - 1) = t(t - 1)/2, its tied pairs.
+__device__ __forceinline__ void block_add_u64(unsigned long long x, unsigned long long *out) {
+    __shared__ unsigned long long red[kRankThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (uint32_t w = 0; w < kRankThreads / 64; ++w) t += red[w];
+        if (t) atomicAdd(out, t);
+    }
+}
+
 __global__ __launch_bounds__(kRankThreads) void min_rank_kernel(const uint64_t *__restrict__ skey,
                                                                 const int32_t *__restrict__ sval,
                                                                 uint32_t n,
-                                                                uint32_t *__restrict__ out) {
+                                                                uint32_t *__restrict__ out,
+                                                                unsigned long long *__restrict__ ties) {
+    const uint32_t i = blockIdx.x * kRankThreads + threadIdx.x;
+    unsigned long long t = 0;
+    if (i < n) {
+        const uint64_t k = skey[i];
+        uint32_t lo = 0, hi = i;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (skey[mid] < k) lo = mid + 1;
+            else hi = mid;
+        }
+        if (out) out[sval[i]] = lo;
+        t = i - lo;
+    }
+    block_add_u64(t, ties);
+}
+
+// Composite keys (ra[i] << 32 | rb[i]) with the indices as values.
+__global__ __launch_bounds__(kRankThreads) void pair_keys_kernel(const uint32_t *__restrict__ ra,
+                                                                 const uint32_t *__restrict__ rb,
+                                                                 uint32_t n,
+                                                                 uint64_t *__restrict__ key,
+                                                                 int32_t *__restrict__ val) {
     const uint32_t i = blockIdx.x * kRankThreads + threadIdx.x;
     if (i >= n) return;
-    const uint64_t k = skey[i];
-    uint32_t lo = 0, hi = i;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (skey[mid] < k) lo = mid + 1;
-        else hi = mid;
+    key[i] = (static_cast<uint64_t>(ra[i]) << 32) | rb[i];
+    val[i] = static_cast<int32_t>(i);
+}
+
+// s[i] = rb[id[i]]: rank b in the order of the (a, b) sort.
+__global__ __launch_bounds__(kRankThreads) void gather_kernel(const uint32_t *__restrict__ rb,
+                                                              const int32_t *__restrict__ id,
+                                                              uint32_t n, uint32_t *__restrict__ s) {
+    const uint32_t i = blockIdx.x * kRankThreads + threadIdx.x;
+    if (i < n) s[i] = rb[id[i]];
+}
+
+// One level of a bottom-up merge sort of s with strict-inversion counts: runs
+// of `width` are sorted; each element finds its place in the merged run by
+// binary search in the sibling run (a left element after the right elements
+// below it, a right element after the left elements not above it, so equal
+// values keep their order), and a right element adds the left elements above
+// it to *inv (pairs p < q with s_p > s_q).
+__global__ __launch_bounds__(kRankThreads) void merge_level_kernel(const uint32_t *__restrict__ in,
+                                                                   uint32_t n, uint32_t width,
+                                                                   uint32_t *__restrict__ out,
+                                                                   unsigned long long *__restrict__ inv) {
+    const uint32_t i = blockIdx.x * kRankThreads + threadIdx.x;
+    unsigned long long c = 0;
+    if (i < n) {
+        const uint32_t x = in[i];
+        const uint32_t l0 = (i / (2 * width)) * (2 * width);
+        const uint32_t r0 = min(l0 + width, n), r1 = min(l0 + 2 * width, n);
+        if (i < r0) {  // left run: count right elements < x
+            uint32_t lo = r0, hi = r1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (in[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            out[l0 + (i - l0) + (lo - r0)] = x;
+        } else {  // right run: count left elements <= x
+            uint32_t lo = l0, hi = r0;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (in[mid] <= x) lo = mid + 1;
+                else hi = mid;
+            }
+            out[l0 + (i - r0) + (lo - l0)] = x;
+            c = r0 - lo;
+        }
     }
-    out[sval[i]] = lo;
+    block_add_u64(c, inv);
 }
 
 // Kendall pair counts on min-ranks (ties exactly where the scores tie).
@@ -280,9 +357,31 @@ hipError_t launch_rank_of(const int32_t *order, uint32_t n, int32_t *rank, hipSt
 }
 
 hipError_t launch_min_rank(const uint64_t *skey, const int32_t *sval, uint32_t n, uint32_t *out,
-                           hipStream_t stream) {
+                           unsigned long long *ties, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    min_rank_kernel<<<blocks_for(n, kRankThreads), kRankThreads, 0, stream>>>(skey, sval, n, out);
+    min_rank_kernel<<<blocks_for(n, kRankThreads), kRankThreads, 0, stream>>>(skey, sval, n, out, ties);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_keys(const uint32_t *ra, const uint32_t *rb, uint32_t n, uint64_t *key,
+                            int32_t *val, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    pair_keys_kernel<<<blocks_for(n, kRankThreads), kRankThreads, 0, stream>>>(ra, rb, n, key, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_inversions(const uint32_t *rb, const int32_t *id, uint32_t n, uint32_t *s,
+                             uint32_t *tmp, unsigned long long *inv, hipStream_t stream) {
+    if (n < 2) return hipSuccess;
+    gather_kernel<<<blocks_for(n, kRankThreads), kRankThreads, 0, stream>>>(rb, id, n, s);
+    uint32_t *a = s, *b = tmp;
+    for (uint32_t w = 1; w < n; w *= 2) {
+        merge_level_kernel<<<blocks_for(n, kRankThreads), kRankThreads, 0, stream>>>(a, n, w, b, inv);
+        uint32_t *t = a;
+        a = b;
+        b = t;
+        if (w > 0x7FFFFFFFu) break;
+    }
     return hipGetLastError();
 }
 

@@ -114,3 +114,50 @@ def test_ranking_of_the_estimate(gpu_lib):
     assert kt["tau_b"] == oracle.kendall_tau_b(d, truth)
     _say(f"ER(1000) tau=2000: KT of the estimate vs the dense ground truth {kt['tau_b']:.4f}")
     assert kt["tau_b"] > 0.8
+
+
+@pytest.mark.parametrize("n,kind", [(3, "ties"), (1000, "ties"), (20000, "random")])
+def test_kendall_pair_kernel_bit_exact(gpu_lib, n, kind):
+    """The tiled all-pairs kernel (option kendall_pairs) against the oracle."""
+    a = _scores(kind, n, n + 3)
+    b = a + _scores("ties", n, n + 4)
+    gpu_lib.set_option("kendall_pairs", 1)
+    try:
+        got = gpu_lib.kendall_tau(a, b)
+    finally:
+        gpu_lib.set_option("kendall_pairs", 0)
+    assert got["counts"] == oracle.kendall_counts(a, b)
+    t = oracle.kendall_tau_b(a, b)
+    assert (math.isnan(t) and math.isnan(got["tau_b"])) or got["tau_b"] == t
+
+
+@pytest.mark.parametrize("kind", ["random", "ties", "special"])
+def test_kendall_merge_equals_pairs_full_size(gpu_lib, kind):
+    """n = 200000, beyond the oracle's reach: the merge-sort counts equal the
+    all-pairs counts exactly."""
+    n = 200_000
+    a = _scores(kind, n, 21)
+    b = _scores(kind, n, 22) + (a if kind != "special" else 0.0)
+    merge = gpu_lib.kendall_tau(a, b)
+    gpu_lib.set_option("kendall_pairs", 1)
+    try:
+        pairs = gpu_lib.kendall_tau(a, b)
+    finally:
+        gpu_lib.set_option("kendall_pairs", 0)
+    assert merge["counts"] == pairs["counts"]
+    assert merge["tau_b"] == pairs["tau_b"]
+
+
+def test_kendall_merge_large_closed_forms(gpu_lib):
+    """n = 2^21 + 777 (22 merge levels, ragged runs): b = a and b = -a."""
+    n = (1 << 21) + 777
+    a = _scores("ties", n, 9)
+    _, cnt = np.unique(a, return_counts=True)
+    ties = int((cnt.astype(np.int64) * (cnt - 1) // 2).sum())
+    n0 = n * (n - 1) // 2
+    assert gpu_lib.kendall_tau(a, a)["counts"] == (n0 - ties, 0, ties, ties, ties)
+    assert gpu_lib.kendall_tau(a, -a)["counts"] == (0, n0 - ties, ties, ties, ties)
+    # a random permutation of 2^15 against the identity, no ties: the oracle's pairs
+    perm = np.random.default_rng(4).permutation(1 << 15).astype(np.float64)
+    ident = np.arange(1 << 15, dtype=np.float64)
+    assert gpu_lib.kendall_tau(ident, perm)["counts"] == oracle.kendall_counts(ident, perm)
