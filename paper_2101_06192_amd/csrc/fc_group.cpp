@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "fc_internal.hpp"
+#include "fc_group_kernels.hpp"
 
 using namespace fc_host;
 

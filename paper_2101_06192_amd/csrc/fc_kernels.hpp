@@ -264,69 +264,4 @@ hipError_t cg_inner(const CgWork &w, uint32_t max_iters, uint32_t poll, uint32_t
 // R64 = B - A X and |R_j|^2 into res_rr (and |B_j|^2 into res_bb).
 hipError_t cg_residual(const CgWork &w, bool with_b, hipStream_t stream);
 
-// Ranking output (rank.hip).  Keys: order-preserving uint64 of each score
-// (complemented when descending), val[i] = i when val is not null; *bad |= 1
-// when a score is NaN.
-hipError_t launch_rank_keys(const double *score, uint32_t n, bool descending, uint64_t *key,
-                            int32_t *val, unsigned int *bad, hipStream_t stream);
-// hist[p * 256 + d] += keys whose byte p is d (hist zeroed by the caller).
-hipError_t launch_digit_hist(const uint64_t *key, uint32_t n, unsigned int *hist,
-                             hipStream_t stream);
-// Tiles of the radix sort (thist holds 256 * rank_tiles(n) counters).
-uint32_t rank_tiles(uint32_t n);
-// One stable pass on byte shift / 8: (key, val) -> (okey, oval); base[d] =
-// keys whose byte is below d.
-hipError_t launch_radix_pass(const uint64_t *key, const int32_t *val, uint32_t n, uint32_t shift,
-                             unsigned int *thist, const unsigned int *base, uint64_t *okey,
-                             int32_t *oval, hipStream_t stream);
-hipError_t launch_rank_of(const int32_t *order, uint32_t n, int32_t *rank, hipStream_t stream);
-// out[sval[i]] = the number of sorted keys below skey[i] (skey ascending; out
-// may be null); *ties += pairs of equal keys.
-hipError_t launch_min_rank(const uint64_t *skey, const int32_t *sval, uint32_t n, uint32_t *out,
-                           unsigned long long *ties, hipStream_t stream);
-// key[i] = ra[i] << 32 | rb[i], val[i] = i.
-hipError_t launch_pair_keys(const uint32_t *ra, const uint32_t *rb, uint32_t n, uint64_t *key,
-                            int32_t *val, hipStream_t stream);
-// *inv += strict inversions of s = rb[id[.]] (pairs p < q with s_p > s_q) by a
-// bottom-up merge sort (s and tmp: n scratch each).
-hipError_t launch_inversions(const uint32_t *rb, const int32_t *id, uint32_t n, uint32_t *s,
-                             uint32_t *tmp, unsigned long long *inv, hipStream_t stream);
-// Kendall pair counts of two rank vectors (< 2^31) over all pairs i < j
-// (n <= 65535 * 256): out[0] += sum of sign products, out[1..3] += pairs tied in
-// a, in b, in both (out zeroed by the caller; out[0] is two's complement).
-hipError_t launch_kendall(const uint32_t *ra, const uint32_t *rb, uint32_t n,
-                          unsigned long long *out, hipStream_t stream);
-
-// Group forest closeness (group.hip): dense N x N binary64 matrices,
-// N = group_dim(n) (n rounded up to 256), row-major.
-uint32_t group_dim(uint32_t n);
-size_t group_scratch_doubles(uint32_t N);  // scratch of launch_group_invert
-uint32_t group_chunks(uint32_t n);  // row chunks of the column sums
-// A = alpha L + I on the first n rows and columns (weighted when w is not
-// null), identity on the padding.
-hipError_t launch_group_build(const int32_t *row_ptr, const int32_t *col_idx, const double *w,
-                              uint32_t n, double alpha, double *A, hipStream_t stream);
-// A <- A^{-1} in place (SPD; blocked Gauss-Jordan; scratch of
-// group_scratch_doubles(N) doubles).
-hipError_t launch_group_invert(double *A, uint32_t N, double *scratch, hipStream_t stream);
-// diag[v] = A[v][v]; sel[0] = min diagonal bits, sel[1] = smallest id with it
-// (sel preset to all ones by the caller).
-hipError_t launch_group_first(const double *A, uint32_t n, uint32_t N, double *diag,
-                              unsigned long long *sel, hipStream_t stream);
-// Omega -> inverse of L* grounded at v0, in place (slot v0 becomes u*); c: n scratch.
-hipError_t launch_group_reground(double *A, uint32_t n, uint32_t N, uint32_t v0, double *c,
-                                 hipStream_t stream);
-// *out = trace over the first n slots; *piv = A[v][v] when v < n.
-hipError_t launch_group_trace(const double *A, uint32_t n, uint32_t N, uint32_t v, double *out,
-                              double *piv, hipStream_t stream);
-// Column sums of squares per row chunk into part (chunks x N); with v < n
-// first the downdate by vertex v (pivot *piv; cv, rv: n scratch).
-hipError_t launch_group_colsq(double *A, uint32_t n, uint32_t N, uint32_t v, double *cv, double *rv,
-                              const double *piv, double *part, hipStream_t stream);
-// gain[j] = column sum / A[j][j] for j not taken (else -1); sel[0] = max gain
-// bits (preset 0), sel[1] = smallest id with it (preset all ones).
-hipError_t launch_group_argmax(const double *A, uint32_t n, uint32_t N, const double *part,
-                               const uint8_t *taken, double *gain, unsigned long long *sel,
-                               hipStream_t stream);
-
 }  // namespace fc

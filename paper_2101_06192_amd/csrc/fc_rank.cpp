@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "fc_internal.hpp"
+#include "fc_rank_kernels.hpp"
 
 using namespace fc_host;
 

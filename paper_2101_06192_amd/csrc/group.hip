@@ -12,7 +12,7 @@
 // a 256 x 256 scratch; the panels and the rank-256 trailing update are fp64
 // MFMA tile products), i.e. Omega; then, in place, the inverse of L*
 // grounded at the first vertex v0, with slot v0 standing for u*.
-#include "fc_kernels.hpp"
+#include "fc_group_kernels.hpp"
 
 namespace fc {
 

@@ -6,7 +6,7 @@
 // Omega_vv (Eq. "eq-fdistu-tr": farness grows with Omega_vv); the paper ranks
 // the vertices by the estimate and reports Kendall's rank correlation against
 // the ground truth (Section 6, "Vertex Ranking").
-#include "fc_kernels.hpp"
+#include "fc_rank_kernels.hpp"
 
 namespace fc {
 
