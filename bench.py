@@ -113,6 +113,9 @@ def main():
                     choices=["ba200k", "ba200k_w", "er1000", "grid1000", "rmat_batch", "rmat22",
                              "solve", "rank", "group"],
                     help="workload; the default is the headline configuration")
+    ap.add_argument("--lds-repop", type=int, default=None, choices=[0, 1, 2],
+                    help="LDS sampler: pop re-formed 2-cycles within their round "
+                         "(0 never, 1 weighted graphs, 2 always: the library default)")
     ap.add_argument("--phase-timing", action="store_true",
                     help="report per-phase times of the workgroup sampler (adds clock reads)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -141,6 +144,8 @@ def main():
     from paper_2101_06192_amd import inputs
 
     dev = torch.device("cuda:0")
+    if args.lds_repop is not None:
+        fc.set_option("lds_repop", args.lds_repop, dev)
     if args.config != "ba200k":
         other_config(args, fc, inputs, dev)
         return

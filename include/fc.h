@@ -207,6 +207,11 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "max_draws"       cap on the arrows one vertex may draw in one tree, below each
  *                     sampler's own limit (0, the default: no extra cap); a call that
  *                     exceeds it returns FC_ERR_OVERFLOW (exercises that error path)
+ *   "lds_repop"       LDS-counter sampler: a 2-cycle that the redrawn arrows of a round
+ *                     close again is popped in that same round (cycle popping may pop
+ *                     any cycle at any time: the same trees) instead of a round later
+ *                     with everything that hangs off it; 0 never, 1 weighted graphs
+ *                     only, 2 always (the default)
  *   "kendall_pairs"   1: fc_kendall_tau compares all n(n-1)/2 pairs (tiled) instead of
  *                     counting discordant pairs by a merge sort (0, the default); same
  *                     counts, O(n^2) instead of O(n log^2 n) work

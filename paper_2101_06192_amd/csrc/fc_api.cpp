@@ -204,6 +204,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     const uint32_t *wthr = nullptr;
     if ((rc = weight_tables(ctx, g, ctx->wsum, ctx->wthr, &wsum, &wthr))) return rc;
     const bool weighted = wsum != nullptr;
+    const bool repop = ctx->lds_repop == 2 || (ctx->lds_repop == 1 && weighted);
     FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, wsum, g.n, p->alpha, vrec, &sm->dmax,
                                       static_cast<uint32_t *>(ctx->iso.ptr), &sm->wtotal,
                                       ctx->stream),
@@ -417,7 +418,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             slots = std::min<size_t>(slots, tree_count);
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
             uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
-            const int fit = fc::lds_max_active(lds_threads, lds_words, weighted);
+            const int fit = fc::lds_max_active(lds_threads, lds_words, weighted, repop);
             if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
             else per_cu = 1;
             slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
@@ -595,7 +596,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             FC_HIP(ctx, fc::launch_lds_predraw(c, ctx->stream), "lds_predraw launch");
             FC_HIP(ctx, hipEventRecord(ctx->evm, ctx->stream), "event");
         }
-        FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, weighted, ctx->stream),
+        FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, weighted, repop, ctx->stream),
                "wilson_lds launch");
     } else if (use_coop) {
         FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, weighted,
@@ -807,6 +808,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "lds_wg_per_cu") {
         if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
         ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
+    } else if (k == "lds_repop") {
+        if (value < 0 || value > 2) return set_err(ctx, FC_ERR_ARG, "lds_repop must be 0, 1 or 2");
+        ctx->lds_repop = static_cast<uint32_t>(value);
     } else if (k == "kendall_pairs") {
         if (value < 0 || value > 1) return set_err(ctx, FC_ERR_ARG, "kendall_pairs must be 0 or 1");
         ctx->kendall_pairs = value != 0;

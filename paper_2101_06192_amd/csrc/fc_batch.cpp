@@ -37,6 +37,7 @@ struct Group {
     size_t ntab = 0, kk_words = 0;
     bool use_lds = false, lds_bits = false, in_bits = false, word32 = true;
     bool weighted = false;   // some job's graph carries edge weights
+    bool repop = false;      // re-formed 2-cycles popped within their round (LDS kernel)
     uint32_t lds_words = 0;  // dynamic LDS of the LDS-counter kernel (largest graph)
 };
 
@@ -87,7 +88,7 @@ hipError_t enqueue_group(const Group &g, const fc::CoopArgs &a, uint32_t threads
     hipError_t e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.small.ptr),
                                        sizeof(Small) / 8, 0ull, stream);
     if (e != hipSuccess) return e;
-    if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, g.weighted, stream);
+    if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, g.weighted, g.repop, stream);
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.kk.ptr), g.kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
     return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, g.weighted, stream);
@@ -118,7 +119,7 @@ int size_scratch(fc_ctx *ctx, Group &g, uint32_t slots) {
 
 uint32_t slots_for(const fc_ctx *ctx, const Group &g, uint32_t threads, uint32_t wg_per_cu) {
     const size_t n = g.n_max;
-    const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words, g.weighted)
+    const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words, g.weighted, g.repop)
                               : fc::coop_max_active(threads, g.lds_bits, g.in_bits, g.word32,
                                                     g.n_max, g.weighted);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
@@ -441,6 +442,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
             word_layout(static_cast<uint32_t>(b->jobs[j].graph.n), dmax[k], true, &ts, &w32);
             g.word32 = g.word32 && w32;
         }
+        g.repop = ctx->lds_repop == 2 || (ctx->lds_repop == 1 && g.weighted);
         g.lds_bits = !use_lds && ctx->coop_lds_bits &&
                      fc::coop_lds_bytes(g.n_max) + 1024u <= ctx->max_lds;
         g.in_bits = g.lds_bits && ctx->coop_in_bits &&

@@ -60,6 +60,7 @@ struct fc_ctx {
     uint32_t lds_wg_per_cu = 0;   // its resident workgroups per CU (0: as many as fit)
     uint32_t predraw_mib = 32768;  // budget of pre-drawn first arrows (0: off)
     bool kendall_pairs = false;   // Kendall's tau by all pairs instead of merge-sort counts
+    uint32_t lds_repop = 2;       // re-formed 2-cycle pops: 0 never, 1 weighted graphs, 2 always
     double wall_khz = 100000.0;   // device wall clock rate
 };
 

@@ -113,10 +113,14 @@ constexpr int kRC = 2;
 // (up to 64 kTailRegs entries).
 constexpr int kTailRegs = 6;
 
-template <bool kWeighted>
+// Passes of the re-formed 2-cycle pops per round (an optimisation that may
+// stop at any pass: the next round pops what is left).
+constexpr uint32_t kRepopPasses = 32;
+
+template <bool kWeighted, bool kRepop>
 __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_lds[];
-    __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev;
+    __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev, s_rp, s_rp_over;
     __shared__ uint64_t s_tail[64];
     __shared__ unsigned long long s_digest, s_roots;
     __shared__ unsigned long long s_ph[kPhCount + 1];
@@ -499,6 +503,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     wave_append_many<kR>(cyc, &s_cycles, n, &s_over, e, pop);
                 }
             }
+            const uint32_t u_hang = uniform(s_u);  // the sweep's entries (final since its barrier)
             __syncthreads();
             mark(kPhSplit);
             // pop every cycle: each cycle vertex draws its next arrow (in round 0
@@ -541,6 +546,87 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 wave_append_many<kRC>(Unext, &s_u, n, &s_over, w, live);
             }
             __syncthreads();
+            // Re-formed 2-cycles: a redrawn vertex u whose new arrow goes to an
+            // unsettled tg whose arrow goes back to u closes a cycle of the current
+            // arrows, which may be popped at once (any cycle may be popped at any
+            // time) instead of a round later with everything that hangs off it.
+            // The pair is popped by u's lane, or by the smaller id's when both were
+            // redrawn in the same pass.  In-arrow fields, all 0 here for unsettled
+            // vertices, mark "redrawn in this pass" (+1, cleared after the
+            // detection) and "popped again this round" (+2).  The popped vertices are
+            // already in the next list, with their old targets: a pass over that
+            // list re-reads the target of every entry marked +2 and clears the mark.
+            // A pass's pops go to one half of the dead peel buffer; a pass that
+            // would overflow it ends the loop.
+            if (kRepop) {
+                const uint32_t cap = n >> 1;
+                const uint64_t *cur = Unext + u_hang;
+                uint32_t ccur = min(uniform(s_u), n) - u_hang;
+                bool any = false;
+                for (uint32_t pass = 0; ccur > 0u && pass < kRepopPasses; ++pass) {
+                    uint64_t *nxt = peel + ((pass & 1u) ? cap : 0u);
+                    for (uint32_t i = tid; i < ccur; i += T) count_add(f_lo(cur[i]));
+                    if (tid == 0) {
+                        s_rp = 0;
+                        s_rp_over = 0;
+                    }
+                    __syncthreads();
+                    for (uint32_t base = wave_base; base < ccur; base += T) {
+                        const uint32_t i = base + lane;
+                        uint64_t e[2] = {0ull, 0ull};
+                        bool pp[2] = {false, false};
+                        if (i < ccur) {
+                            const uint32_t u = f_lo(cur[i]), tg = f_mid(cur[i]);
+                            if (tg < nl && !is_settled(tg) && f_lo(word[tg]) == u &&
+                                ((count_of(tg) & 1u) == 0u || u < tg)) {
+                                e[0] = pack(u, 0u, 0u);
+                                e[1] = pack(tg, 0u, 0u);
+                                pp[0] = pp[1] = true;
+                            }
+                        }
+                        wave_append_many<2>(nxt, &s_rp, cap, &s_rp_over, e, pp);
+                    }
+                    __syncthreads();
+                    for (uint32_t i = tid; i < ccur; i += T) (void)count_dec(f_lo(cur[i]));
+                    const uint32_t cn = uniform(s_rp);
+                    if (uniform(s_rp_over) != 0u || cn == 0u) break;
+                    for (uint32_t i = tid; i < cn; i += T) {
+                        const uint32_t v = f_lo(nxt[i]);
+                        const uint32_t k = f_k(word[v]);
+                        if (k >= min(kKMax, a.k_limit)) {  // count past the limit
+                            err |= kErrVisitOverflow;
+                            nxt[i] = pack(v, n, 0u);
+                            continue;
+                        }
+                        const uint64_t nw = draw<kWeighted>(job, load_vrec(job.vrec, v), a.key0,
+                                                            a.key1, k, t);
+                        word[v] = nw;
+                        if (f_lo(nw) == n) set_settled(v);
+                        nxt[i] = pack(v, f_lo(nw), 0u);
+                        if ((count_of(v) & 2u) == 0u) {  // first pop this round: mark it
+                            const Field f = field_of(C, v);
+                            atomicAdd(&s_lds[f.w], 2u << f.sh);
+                        }
+                    }
+                    draws += cn;
+                    any = true;
+                    cur = nxt;
+                    ccur = cn;
+                    __syncthreads();
+                }
+                if (any) {
+                    const uint32_t nu = min(uniform(s_u), n);
+                    for (uint32_t i = tid; i < nu; i += T) {
+                        const uint32_t v = f_lo(Unext[i]);
+                        if (count_of(v) & 2u) {
+                            Unext[i] = pack(v, f_lo(word[v]), 0u);
+                            const Field f = field_of(C, v);
+                            atomicAdd(&s_lds[f.w], 0u - (2u << f.sh));
+                        }
+                    }
+                }
+                __syncthreads();
+            }
             mark(kPhCycles);
             draws += ccount;
             ucount = min(uniform(s_u), n);
@@ -680,19 +766,29 @@ hipError_t launch_lds_predraw(const CoopArgs &a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+namespace {
+const void *lds_kernel_of(bool weighted, bool repop) {
+    if (weighted)
+        return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<true, true>)
+                     : reinterpret_cast<const void *>(&wilson_lds_kernel<true, false>);
+    return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<false, true>)
+                 : reinterpret_cast<const void *>(&wilson_lds_kernel<false, false>);
+}
+}  // namespace
+
 hipError_t lds_set_limit(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_lds_kernel<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(bytes));
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&wilson_lds_kernel<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    for (int m = 0; m < 4; ++m) {
+        const hipError_t e = hipFuncSetAttribute(lds_kernel_of(m & 1, m & 2),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(bytes));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted) {
+int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted, bool repop) {
     int blocks = 0;
-    const void *f = weighted ? reinterpret_cast<const void *>(&wilson_lds_kernel<true>)
-                             : reinterpret_cast<const void *>(&wilson_lds_kernel<false>);
+    const void *f = lds_kernel_of(weighted, repop);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, static_cast<int>(threads),
                                                      4u * static_cast<size_t>(lds_words)) !=
         hipSuccess)
@@ -701,11 +797,16 @@ int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted) {
 }
 
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
-                             bool weighted, hipStream_t stream) {
+                             bool weighted, bool repop, hipStream_t stream) {
     if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
     const size_t lds = 4u * static_cast<size_t>(lds_words);
-    if (weighted) wilson_lds_kernel<true><<<a.slots, threads, lds, stream>>>(a);
-    else wilson_lds_kernel<false><<<a.slots, threads, lds, stream>>>(a);
+    if (weighted) {
+        if (repop) wilson_lds_kernel<true, true><<<a.slots, threads, lds, stream>>>(a);
+        else wilson_lds_kernel<true, false><<<a.slots, threads, lds, stream>>>(a);
+    } else {
+        if (repop) wilson_lds_kernel<false, true><<<a.slots, threads, lds, stream>>>(a);
+        else wilson_lds_kernel<false, false><<<a.slots, threads, lds, stream>>>(a);
+    }
     return hipGetLastError();
 }
 

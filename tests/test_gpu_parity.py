@@ -574,3 +574,23 @@ def test_solve_argument_errors(gpu_lib):
     with pytest.raises(fc.FCError) as e:
         fc.solve(g, 1.0, np.ones((50, 2)), rtol=0.0)
     assert e.value.code == fc.FC_ERR_ARG
+
+
+@pytest.mark.parametrize("repop", [0, 2], ids=["repop_off", "repop_on"])
+@pytest.mark.parametrize("case", ["er1000", "ba20k", "grid", "rmat", "small"])
+def test_lds_repop_bit_exact(gpu_lib, repop, case):
+    """The LDS sampler with and without popping re-formed 2-cycles within their
+    round (option lds_repop): the same trees as the oracle, unweighted and
+    weighted."""
+    fc = gpu_lib
+    g = {"er1000": lambda: inputs.erdos_renyi(1000, 0.01, 0),
+         "ba20k": lambda: inputs.barabasi_albert(20_000, 5, 2),
+         "grid": lambda: inputs.grid_removed(60, 70, 0.12, 1),
+         "rmat": lambda: inputs.rmat(1 << 12, 8, 5),
+         "small": lambda: inputs.from_edge_list(4, [(0, 1), (1, 2), (2, 3), (0, 3)])}[case]()
+    fc.set_option("lds_repop", repop)
+    try:
+        for gg, alpha in ((g, 1.0), (inputs.with_weights(g, 7), 0.5)):
+            _compare(fc, gg, alpha, 3, 0, 40, per_tree=True, sampler="lds")
+    finally:
+        fc.set_option("lds_repop", 2)
