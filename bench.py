@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--lds-repop", type=int, default=None, choices=[0, 1, 2],
                     help="LDS sampler: pop re-formed 2-cycles within their round "
                          "(0 never, 1 weighted graphs, 2 always: the library default)")
+    ap.add_argument("--coop-repop", type=int, default=None, choices=[0, 1, 2],
+                    help="global-counter sampler: the same option (coop_repop)")
     ap.add_argument("--phase-timing", action="store_true",
                     help="report per-phase times of the workgroup sampler (adds clock reads)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -146,6 +148,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.lds_repop is not None:
         fc.set_option("lds_repop", args.lds_repop, dev)
+    if args.coop_repop is not None:
+        fc.set_option("coop_repop", args.coop_repop, dev)
     if args.config != "ba200k":
         other_config(args, fc, inputs, dev)
         return

@@ -212,6 +212,9 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *                     any cycle at any time: the same trees) instead of a round later
  *                     with everything that hangs off it; 0 never, 1 weighted graphs
  *                     only, 2 always (the default)
+ *   "coop_repop"      the same for the global-counter sampler (graphs whose counters do
+ *                     not fit LDS), with an LDS filter that flags the re-popped
+ *                     vertices; 0 never, 1 weighted graphs only, 2 always (the default)
  *   "kendall_pairs"   1: fc_kendall_tau compares all n(n-1)/2 pairs (tiled) instead of
  *                     counting discordant pairs by a merge sort (0, the default); same
  *                     counts, O(n^2) instead of O(n log^2 n) work

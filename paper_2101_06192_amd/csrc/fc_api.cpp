@@ -239,6 +239,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::LaneArgs a{};
     fc::CoopArgs c{};
     bool lds_bits = false, in_bits = false, word32 = false;
+    uint32_t repop_words = 0;  // global-counter sampler: re-pop filter words (0: off)
     bool use_lds = false, use_hyb = false;
     uint32_t lds_words = 0, lds_threads = 1024, hot = 0;
     uint32_t tshift = 32;
@@ -500,8 +501,22 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
 
         uint32_t per_cu = ctx->coop_wg_per_cu;
         const int fit = fc::coop_max_active(ctx->coop_threads, lds_bits, in_bits, word32,
-                                            static_cast<uint32_t>(g.n), weighted);
+                                            static_cast<uint32_t>(g.n), weighted, 0);
         if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
+        // the re-pop filter takes what LDS those workgroups leave free, up to 32 KiB
+        // (at least 256 B), without lowering the workgroups per CU
+        if (ctx->coop_repop == 2 || (ctx->coop_repop == 1 && weighted)) {
+            const size_t dyn = lds_bits ? (in_bits ? 2u : 1u) * fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) : 0u;
+            const size_t share = ctx->max_lds / per_cu;
+            const size_t room = std::min<size_t>(
+                32768u, share > dyn + kLdsStaticBytes ? share - dyn - kLdsStaticBytes : 0u);
+            for (uint32_t w = 64; 4u * w <= room; w <<= 1) repop_words = w;
+            while (repop_words && fit > 0 &&
+                   fc::coop_max_active(ctx->coop_threads, lds_bits, in_bits, word32,
+                                       static_cast<uint32_t>(g.n), weighted, repop_words) <
+                       static_cast<int>(per_cu))
+                repop_words = repop_words > 64 ? repop_words >> 1 : 0;
+        }
         slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
         if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
         if ((rc = ensure(ctx, ctx->cword, wbytes * static_cast<size_t>(g.n) * slots, "tree words")))
@@ -600,7 +615,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                "wilson_lds launch");
     } else if (use_coop) {
         FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, weighted,
-                                           ctx->stream),
+                                           repop_words, ctx->stream),
                "wilson_coop launch");
     } else
         FC_HIP(ctx, fc::launch_wilson_lane(a, ctx->stream), "wilson_lane launch");
@@ -811,6 +826,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "lds_repop") {
         if (value < 0 || value > 2) return set_err(ctx, FC_ERR_ARG, "lds_repop must be 0, 1 or 2");
         ctx->lds_repop = static_cast<uint32_t>(value);
+    } else if (k == "coop_repop") {
+        if (value < 0 || value > 2) return set_err(ctx, FC_ERR_ARG, "coop_repop must be 0, 1 or 2");
+        ctx->coop_repop = static_cast<uint32_t>(value);
     } else if (k == "kendall_pairs") {
         if (value < 0 || value > 1) return set_err(ctx, FC_ERR_ARG, "kendall_pairs must be 0 or 1");
         ctx->kendall_pairs = value != 0;

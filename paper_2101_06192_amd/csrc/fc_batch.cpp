@@ -91,7 +91,8 @@ hipError_t enqueue_group(const Group &g, const fc::CoopArgs &a, uint32_t threads
     if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, g.weighted, g.repop, stream);
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.kk.ptr), g.kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
-    return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, g.weighted, stream);
+    return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, g.weighted, 0u,
+                                  stream);
 }
 
 // Size a group's scratch for `slots` workgroups and point its arguments at it.
@@ -121,7 +122,7 @@ uint32_t slots_for(const fc_ctx *ctx, const Group &g, uint32_t threads, uint32_t
     const size_t n = g.n_max;
     const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words, g.weighted, g.repop)
                               : fc::coop_max_active(threads, g.lds_bits, g.in_bits, g.word32,
-                                                    g.n_max, g.weighted);
+                                                    g.n_max, g.weighted, 0u);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
     const size_t per_slot = g.use_lds ? (8 + 24 + 4) * n + 8
                                       : ((g.word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +

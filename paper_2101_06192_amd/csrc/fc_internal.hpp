@@ -61,6 +61,7 @@ struct fc_ctx {
     uint32_t predraw_mib = 32768;  // budget of pre-drawn first arrows (0: off)
     bool kendall_pairs = false;   // Kendall's tau by all pairs instead of merge-sort counts
     uint32_t lds_repop = 2;       // re-formed 2-cycle pops: 0 never, 1 weighted graphs, 2 always
+    uint32_t coop_repop = 2;      // the same for the global-counter sampler
     double wall_khz = 100000.0;   // device wall clock rate
 };
 

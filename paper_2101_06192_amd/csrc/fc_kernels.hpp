@@ -135,14 +135,16 @@ struct CoopArgs {
 // vertices with in-arrows.
 // weighted: some job carries running weight sums (the weighted instantiation
 // checks each job's pointer).
+// repop_words: 0, or a power of two: re-formed 2-cycles are popped within the
+// round that re-forms them, with an LDS filter of that many 32-bit words.
 hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
-                              bool word32, bool weighted, hipStream_t stream);
+                              bool word32, bool weighted, uint32_t repop_words, hipStream_t stream);
 // Allow up to `bytes` of dynamic LDS per workgroup for every variant (set once
 // per device to the device limit; launches pass what they need).
 hipError_t coop_set_lds_limit(size_t bytes);
 // Workgroups of the chosen variant that fit on one CU at once (0 if unknown).
 int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max,
-                    bool weighted);
+                    bool weighted, uint32_t repop_words);
 size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 
 // LDS-counter variant (n < 2^kRelabelIdBits): the per-tree arrays are word

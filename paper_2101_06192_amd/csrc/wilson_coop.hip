@@ -63,6 +63,26 @@ __device__ __forceinline__ void wave_append(uint64_t *__restrict__ list, uint32_
     }
 }
 
+// As wave_append, two items per lane (adjacent), dropping items at or past
+// `cap`; the tail still counts them, so a tail above `cap` reports the overflow.
+__device__ __forceinline__ void wave_append2(uint64_t *__restrict__ list, uint32_t *tail,
+                                             uint64_t a0, uint64_t a1, bool pred, uint32_t cap) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const uint32_t lane = __lane_id();
+    const uint32_t leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(tail, 2u * static_cast<uint32_t>(__popcll(mask)));
+    base = __shfl(base, leader, 64);
+    if (pred) {
+        const uint32_t i = base + 2u * static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
+        if (i + 1u < cap) {
+            list[i] = a0;
+            list[i + 1u] = a1;
+        }
+    }
+}
+
 // The per-tree arrays belong to one workgroup for the whole launch, so their
 // atomics only need workgroup scope (no cross-XCD coherence).
 template <typename W>
@@ -111,9 +131,9 @@ template <bool kLdsBits, typename W, bool kInBits, bool kWeighted>
 // At most 512 threads, and registers for six waves per SIMD (24 per CU):
 // the phases are latency bound, so resident waves matter more than unrolling.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6)))
-void wilson_coop_kernel(CoopArgs a) {
+void wilson_coop_kernel(CoopArgs a, uint32_t fwords) {
     extern __shared__ uint32_t s_dyn[];
-    __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev;
+    __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev, s_rp[2];
     __shared__ uint64_t s_tail[64];
     __shared__ unsigned long long s_digest, s_roots;
 
@@ -132,6 +152,10 @@ void wilson_coop_kernel(CoopArgs a) {
     uint32_t *__restrict__ lvl = a.levels + slot * (stride + 2);
     uint32_t *__restrict__ bits = kLdsBits ? s_dyn : a.bits + slot * bstride;
     uint32_t *__restrict__ inb = s_dyn + bstride;  // used only when kInBits
+    // re-pop filter (fwords > 0): one bit per vertex id modulo its size, set for
+    // vertices popped again within a round
+    uint32_t *__restrict__ filt = s_dyn + (kLdsBits ? (kInBits ? 2u : 1u) * bstride : 0u);
+    const uint32_t fmask = fwords * 32u - 1u;
     unsigned int err = 0;
     uint32_t epoch = 0;  // per-slot tree sequence number of this launch (kk was zeroed)
 
@@ -417,6 +441,13 @@ void wilson_coop_kernel(CoopArgs a) {
                 }
             }
             __syncthreads();
+            // the hanging vertices' entries end here; the redrawn ones follow
+            const uint32_t u_hang = uniform(s_u);
+            if (fwords) {  // every wave reads s_u before the redraw appends
+                if (tid == 0) s_rp[0] = s_rp[1] = 0u;
+                for (uint32_t i = tid; i < fwords; i += T) filt[i] = 0u;
+                __syncthreads();
+            }
             // pop every cycle: each cycle vertex draws its next arrow
             const uint32_t ccount = min(uniform(s_cycles), n);
             for (uint32_t base = wave_base; base < ccount; base += 2 * T) {
@@ -440,7 +471,8 @@ void wilson_coop_kernel(CoopArgs a) {
                         if (kInBits) clear_in(v[q]);
                         if (k[q] + 1u > a.k_limit) err |= kErrVisitOverflow;
                         kk[v[q]] = (static_cast<uint64_t>(epoch) << 32) | (k[q] + 1u);
-                        word[v[q]] = static_cast<W>(tg[q]);  // count back to 0 with it
+                        // count back to 0 with it, or 1 (redrawn in re-pop pass 0)
+                        word[v[q]] = static_cast<W>(tg[q]) | (fwords && tg[q] != n ? cnt_one : W(0));
                         if (tg[q] == n) set_settled(v[q]);
                     }
                 }
@@ -449,6 +481,90 @@ void wilson_coop_kernel(CoopArgs a) {
                     wave_append(Unext, &s_u, pair(v[q], tg[q]), v[q] < n && tg[q] != n);
             }
             __syncthreads();
+            // Re-formed 2-cycles: a redrawn vertex u whose new arrow goes to an
+            // unsettled tg whose arrow goes back to u closes a cycle of the current
+            // arrows, which may be popped at once (any cycle may be popped at any
+            // time) instead of a round later with everything that hangs off it.
+            // Passes repeat over the vertices just redrawn.  Their tree words carry
+            // an in-arrow count of 1 (set by the store of the new arrow) while the
+            // pass looks for pairs: a pair whose both ends were redrawn in the same
+            // pass is popped by the smaller id, any other by u's lane; a lane that
+            // finds no pair clears its own mark (the mark is read only through a
+            // word whose target matches, which that lane would have seen).  The
+            // popped vertices already sit in the next list with their old targets:
+            // the LDS filter flags their ids (modulo its size), and a pass over the
+            // list re-reads the word of every flagged entry.  A pass's pops go to one
+            // half of the dead peel buffer; one that would overflow it clears the
+            // marks and ends the loop, and so does the pass after the last allowed.
+            if (fwords) {
+                constexpr uint32_t kPasses = 32;
+                const uint32_t cap = n >> 1;
+                const uint64_t *cur = Unext + u_hang;
+                uint32_t ccur = min(uniform(s_u), n) - u_hang;
+                bool any = false;
+                for (uint32_t pass = 0; ccur > 0u; ++pass) {
+                    uint32_t *rp = &s_rp[pass & 1u];
+                    uint64_t *__restrict__ nxt = peel + ((pass & 1u) ? cap : 0u);
+                    const bool final = pass == kPasses;
+                    for (uint32_t base = wave_base; base < ccur; base += T) {
+                        const uint32_t i = base + lane;
+                        uint32_t u = n, tg = n;
+                        bool lead = false;
+                        if (i < ccur) {
+                            const uint64_t e = cur[i];
+                            u = lo32(e);
+                            tg = hi32(e);
+                            bool pp = false;
+                            if (!final && !is_settled(tg)) {
+                                const W w = word[tg];
+                                pp = target_of(w) == u;
+                                lead = pp && (cnt_of(w) == 0u || u < tg);
+                            }
+                            if (!pp && tg < n) word[u] = static_cast<W>(tg);
+                        }
+                        wave_append2(nxt, rp, pair(u, 0u), pair(tg, 0u), lead, cap);
+                    }
+                    __syncthreads();
+                    const uint32_t cn = uniform(*rp);
+                    if (cn > cap) {  // not every pop was listed: pop none, clear the marks
+                        for (uint32_t i = tid; i < ccur; i += T) {
+                            const uint64_t e = cur[i];
+                            if (hi32(e) < n) word[lo32(e)] = static_cast<W>(hi32(e));
+                        }
+                        __syncthreads();
+                        break;
+                    }
+                    if (cn == 0u) break;
+                    for (uint32_t i = tid; i < cn; i += T) {
+                        const uint32_t v = lo32(nxt[i]);
+                        uint32_t k = 1u;
+                        const uint64_t kv = kk[v];
+                        if (hi32(kv) == epoch) k = lo32(kv);
+                        if (k + 1u > a.k_limit) err |= kErrVisitOverflow;
+                        const uint32_t tg = draw<kWeighted>(job, a.key0, a.key1, v, k, t);
+                        kk[v] = (static_cast<uint64_t>(epoch) << 32) | (k + 1u);
+                        word[v] = static_cast<W>(tg) | (tg != n ? cnt_one : W(0));
+                        if (tg == n) set_settled(v);
+                        nxt[i] = pair(v, tg);
+                        atomicOr(&filt[(v & fmask) >> 5], 1u << (v & 31u));
+                    }
+                    if (tid == 0) s_rp[(pass + 1u) & 1u] = 0u;  // last read before the barrier above
+                    draws += cn;
+                    any = true;
+                    cur = nxt;
+                    ccur = cn;
+                    __syncthreads();
+                }
+                if (any) {
+                    const uint32_t nu = min(uniform(s_u), n);
+                    for (uint32_t i = tid; i < nu; i += T) {
+                        const uint32_t v = lo32(Unext[i]);
+                        if ((filt[(v & fmask) >> 5] >> (v & 31u)) & 1u)
+                            Unext[i] = pair(v, target_of(word[v]));
+                    }
+                }
+                __syncthreads();
+            }
             mark(kPhRedraw);
             draws += ccount;
             ucount = min(uniform(s_u), n);
@@ -514,9 +630,9 @@ void wilson_coop_kernel(CoopArgs a) {
 size_t coop_lds_bytes(uint32_t n) { return 4u * ((static_cast<size_t>(n) + 31u) >> 5); }
 
 template <bool kLds, typename W, bool kIn, bool kWt>
-hipError_t launch_one(const CoopArgs &a, uint32_t threads, hipStream_t stream) {
-    const size_t lds = kLds ? (kIn ? 2 : 1) * coop_lds_bytes(a.n_max) : 0;
-    wilson_coop_kernel<kLds, W, kIn, kWt><<<a.slots, threads, lds, stream>>>(a);
+hipError_t launch_one(const CoopArgs &a, uint32_t threads, uint32_t repop_words, hipStream_t stream) {
+    const size_t lds = (kLds ? (kIn ? 2 : 1) * coop_lds_bytes(a.n_max) : 0) + 4u * repop_words;
+    wilson_coop_kernel<kLds, W, kIn, kWt><<<a.slots, threads, lds, stream>>>(a, repop_words);
     return hipGetLastError();
 }
 
@@ -534,8 +650,8 @@ const void *kernel_of(bool lds_bits, bool in_bits, bool word32) {
 }
 
 int coop_max_active(uint32_t threads, bool lds_bits, bool in_bits, bool word32, uint32_t n_max,
-                    bool weighted) {
-    const size_t lds = lds_bits ? (in_bits ? 2 : 1) * coop_lds_bytes(n_max) : 0;
+                    bool weighted, uint32_t repop_words) {
+    const size_t lds = (lds_bits ? (in_bits ? 2 : 1) * coop_lds_bytes(n_max) : 0) + 4u * repop_words;
     const void *f = weighted ? kernel_of<true>(lds_bits, in_bits, word32)
                              : kernel_of<false>(lds_bits, in_bits, word32);
     int blocks = 0;
@@ -559,22 +675,23 @@ hipError_t coop_set_lds_limit(size_t bytes) {
 
 template <bool kWt>
 hipError_t launch_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
-                       bool word32, hipStream_t stream) {
+                       bool word32, uint32_t rw, hipStream_t stream) {
     if (lds_bits && in_bits)
-        return word32 ? launch_one<true, uint32_t, true, kWt>(a, threads, stream)
-                      : launch_one<true, unsigned long long, true, kWt>(a, threads, stream);
+        return word32 ? launch_one<true, uint32_t, true, kWt>(a, threads, rw, stream)
+                      : launch_one<true, unsigned long long, true, kWt>(a, threads, rw, stream);
     if (lds_bits)
-        return word32 ? launch_one<true, uint32_t, false, kWt>(a, threads, stream)
-                      : launch_one<true, unsigned long long, false, kWt>(a, threads, stream);
-    return word32 ? launch_one<false, uint32_t, false, kWt>(a, threads, stream)
-                  : launch_one<false, unsigned long long, false, kWt>(a, threads, stream);
+        return word32 ? launch_one<true, uint32_t, false, kWt>(a, threads, rw, stream)
+                      : launch_one<true, unsigned long long, false, kWt>(a, threads, rw, stream);
+    return word32 ? launch_one<false, uint32_t, false, kWt>(a, threads, rw, stream)
+                  : launch_one<false, unsigned long long, false, kWt>(a, threads, rw, stream);
 }
 
 hipError_t launch_wilson_coop(const CoopArgs &a, uint32_t threads, bool lds_bits, bool in_bits,
-                              bool word32, bool weighted, hipStream_t stream) {
+                              bool word32, bool weighted, uint32_t repop_words, hipStream_t stream) {
     if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
-    return weighted ? launch_coop<true>(a, threads, lds_bits, in_bits, word32, stream)
-                    : launch_coop<false>(a, threads, lds_bits, in_bits, word32, stream);
+    if (repop_words & (repop_words - 1u)) return hipErrorInvalidValue;  // a power of two or 0
+    return weighted ? launch_coop<true>(a, threads, lds_bits, in_bits, word32, repop_words, stream)
+                    : launch_coop<false>(a, threads, lds_bits, in_bits, word32, repop_words, stream);
 }
 
 }  // namespace fc

@@ -89,6 +89,19 @@ def test_grid_full_size_sampled(gpu_lib, alpha):
         assert got["tree_digests"][t] == ref.digests[0], t
         assert got["tree_steps"][t] == ref.steps[0], t
     assert int(got["root_counts"].astype(np.int64).sum()) == got["stats"]["roots"]
+    # popping re-formed 2-cycles within their round (the default) changes no tree:
+    # every digest, step count and root count equal with the option off (the
+    # re-pop filter's ids alias here: 10^6 vertices over 2^18 filter bits)
+    fc.set_option("coop_repop", 0)
+    try:
+        off = fc.sample(dg, alpha=alpha, seed=0, tree_begin=0, tree_count=1024, want_digests=True,
+                        want_steps=True, trusted=True)
+    finally:
+        fc.set_option("coop_repop", 2)
+    _say(f"grid alpha={alpha}: without re-pops ms={off['stats']['ms_sample']:.1f}")
+    assert np.array_equal(off["tree_digests"], got["tree_digests"])
+    assert np.array_equal(off["tree_steps"], got["tree_steps"])
+    assert np.array_equal(off["root_counts"], got["root_counts"])
 
 
 def test_weighted_ba200k_full_size_sampled(gpu_lib):

@@ -336,6 +336,35 @@ def test_auto_choice_prefers_lds_counters(gpu_lib):
     assert np.array_equal(got["tree_digests"], got2["tree_digests"])
 
 
+@pytest.mark.parametrize("repop", [0, 2], ids=["repop_off", "repop_on"])
+@pytest.mark.parametrize("case", ["ba20k", "grid", "matching", "path", "cycles", "w64"])
+def test_coop_repop_bit_exact(gpu_lib, repop, case):
+    """The global-counter sampler with and without popping re-formed 2-cycles
+    within their round (option coop_repop): the same trees as the oracle,
+    unweighted and weighted; a perfect matching has one count bit per word (the
+    pass mark then fills it), "w64" forces 64-bit words and a global settled
+    bitmap (the filter then sits alone in LDS)."""
+    fc = gpu_lib
+    g = {"ba20k": lambda: inputs.barabasi_albert(20_000, 3, 4),
+         "grid": lambda: inputs.grid_removed(90, 110, 0.12, 2),
+         "matching": lambda: inputs.from_edge_list(2000, [(2 * i, 2 * i + 1) for i in range(1000)]),
+         "path": lambda: inputs.from_edge_list(3000, [(i, i + 1) for i in range(2999)]),
+         "cycles": lambda: inputs.from_edge_list(
+             999, [(i, 3 * (i // 3) + (i + 1) % 3) for i in range(999)]),
+         "w64": lambda: inputs.barabasi_albert(5000, 4, 9)}[case]()
+    fc.set_option("coop_repop", repop)
+    if case == "w64":
+        fc.set_option("coop_word32", 0)
+        fc.set_option("coop_lds_bits", 0)
+    try:
+        for gg, alpha in ((g, 1.0), (inputs.with_weights(g, 7), 2.0)):
+            _compare(fc, gg, alpha, 3, 0, 40, per_tree=True, sampler="coop")
+    finally:
+        fc.set_option("coop_repop", 2)
+        fc.set_option("coop_word32", 1)
+        fc.set_option("coop_lds_bits", 1)
+
+
 @pytest.mark.parametrize("shape", [(64, 1, 1, 1, 1), (256, 3, 0, 1, 1), (448, 1, 1, 0, 0),
                                    (512, 2, 0, 0, 0), (512, 4, 1, 1, 0), (256, 2, 1, 0, 1)])
 def test_coop_launch_shapes_bit_exact(gpu_lib, shape):
@@ -368,6 +397,7 @@ def test_set_option_rejects_bad_values(gpu_lib):
                      ("lanes_per_wave", 65), ("nonsense", 1), ("coop_lds_bits", 2),
                      ("coop_lds_counts", 2), ("lds_threads", 1088), ("lds_threads", 96),
                      ("lds_wg_per_cu", -1), ("lds_wg_per_cu", 65), ("hyb_hot_cap", -1),
+                     ("coop_repop", 3), ("coop_repop", -1),
                      ("max_draws", -1),
                      ("max_draws", 1 << 31)):
         with pytest.raises(fc.FCError) as e:
