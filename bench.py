@@ -447,6 +447,17 @@ def other_config(args, fc, inputs, dev):
                                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                                  "frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS,
                                                  "algorithmic_bytes": step_bytes}}})
+        # the sizes of the paper's group experiment (two citation graphs of 2708 and
+        # 3327 vertices, k = 200, 400, 600), as seeded stand-ins of the same n and m
+        shapes = []
+        for name, gg in (("ba_n2708_m2", inputs.barabasi_albert(2708, 2, 0)),
+                         ("er_n3327_m4552", inputs.erdos_renyi(3327, 2 * 4552 / (3327 * 3326), 0))):
+            dgg = fc.to_device(gg, dev)
+            for kk in (200, 400, 600):
+                tt, _ = _timed(lambda: fc.group_closeness(dgg, 1.0, kk, device=dev, trusted=True),
+                               args.steps, args.warmup)
+                shapes.append({"graph": name, "n": gg.n, "m": gg.m, "k": kk, "ms": 1000 * tt})
+        res["paper_sizes"] = shapes
     elif args.config == "grid1000":
         g = inputs.grid_removed(1000, 1000, 0.12, 0)
         dg = fc.to_device(g, dev)

@@ -112,6 +112,33 @@ def test_larger_graph_farness(gpu_lib):
     assert all(a > b for a, b in zip(got["farness"], got["farness"][1:]))
 
 
+def test_paper_sized_greedy(gpu_lib):
+    """The size of the paper's group experiment (a 2708-vertex citation graph,
+    here a seeded BA stand-in with m = 2), k = 120: the oracle's greedy is
+    followed while both pick the same vertex; where they part, the two choices
+    must tie (their f(S + v) equal within the tolerance, by direct inversion).
+    f(S) of the device's own set is checked by direct inversion every 30 steps."""
+    g = inputs.barabasi_albert(2708, 2, 0)
+    k = 120
+    got = gpu_lib.group_closeness(g, 1.0, k)
+    S, f = oracle.greedy_group(g, 1.0, k)
+    G = got["group"]
+    assert len(set(G)) == k
+    j = 0
+    while j < k and G[j] == S[j]:
+        assert abs(got["farness"][j] - f[j]) <= RTOL * f[j], j
+        j += 1
+    _say(f"paper-sized greedy: same choices for {j} of {k} steps")
+    if j < k:
+        a = oracle.group_farness(g, 1.0, G[:j] + [G[j]])
+        b = oracle.group_farness(g, 1.0, G[:j] + [S[j]])
+        assert abs(a - b) <= RTOL * b, (j, G[j], S[j], a, b)
+    for i in range(0, k, 30):
+        ref = oracle.group_farness(g, 1.0, G[:i + 1])
+        assert abs(got["farness"][i] - ref) <= RTOL * ref, i
+    assert all(x > y for x, y in zip(got["farness"], got["farness"][1:]))
+
+
 def test_argument_errors(gpu_lib):
     fc = gpu_lib
     g = inputs.barabasi_albert(50, 2, 1)
