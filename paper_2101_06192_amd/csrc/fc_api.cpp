@@ -503,20 +503,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         const int fit = fc::coop_max_active(ctx->coop_threads, lds_bits, in_bits, word32,
                                             static_cast<uint32_t>(g.n), weighted, 0);
         if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
-        // the re-pop filter takes what LDS those workgroups leave free, up to 32 KiB
-        // (at least 256 B), without lowering the workgroups per CU
-        if (ctx->coop_repop == 2 || (ctx->coop_repop == 1 && weighted)) {
-            const size_t dyn = lds_bits ? (in_bits ? 2u : 1u) * fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) : 0u;
-            const size_t share = ctx->max_lds / per_cu;
-            const size_t room = std::min<size_t>(
-                32768u, share > dyn + kLdsStaticBytes ? share - dyn - kLdsStaticBytes : 0u);
-            for (uint32_t w = 64; 4u * w <= room; w <<= 1) repop_words = w;
-            while (repop_words && fit > 0 &&
-                   fc::coop_max_active(ctx->coop_threads, lds_bits, in_bits, word32,
-                                       static_cast<uint32_t>(g.n), weighted, repop_words) <
-                       static_cast<int>(per_cu))
-                repop_words = repop_words > 64 ? repop_words >> 1 : 0;
-        }
+        repop_words = coop_repop_words(ctx, ctx->coop_threads, per_cu, lds_bits, in_bits, word32,
+                                       static_cast<uint32_t>(g.n), weighted);
         slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
         if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
         if ((rc = ensure(ctx, ctx->cword, wbytes * static_cast<size_t>(g.n) * slots, "tree words")))
@@ -664,6 +652,27 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(
                std::chrono::steady_clock::now().time_since_epoch())
         .count();
+}
+
+uint32_t coop_repop_words(const fc_ctx *ctx, uint32_t threads, uint32_t per_cu, bool lds_bits,
+                          bool in_bits, bool word32, uint32_t n, bool weighted) {
+    if (!(ctx->coop_repop == 2 || (ctx->coop_repop == 1 && weighted))) return 0;
+    // what LDS per_cu workgroups leave free, up to 32 KiB (at least 256 B), without
+    // lowering the workgroups per CU
+    const int fit0 = fc::coop_max_active(threads, lds_bits, in_bits, word32, n, weighted, 0);
+    if (fit0 > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit0));
+    per_cu = std::max<uint32_t>(per_cu, 1);
+    const size_t dyn = lds_bits ? (in_bits ? 2u : 1u) * fc::coop_lds_bytes(n) : 0u;
+    const size_t share = ctx->max_lds / per_cu;
+    const size_t room =
+        std::min<size_t>(32768u, share > dyn + kLdsStaticBytes ? share - dyn - kLdsStaticBytes : 0u);
+    uint32_t words = 0;
+    for (uint32_t w = 64; 4u * w <= room; w <<= 1) words = w;
+    while (words && fit0 > 0 &&
+           fc::coop_max_active(threads, lds_bits, in_bits, word32, n, weighted, words) <
+               static_cast<int>(per_cu))
+        words = words > 64 ? words >> 1 : 0;
+    return words;
 }
 
 void word_layout(uint32_t n, uint32_t dmax, bool allow32, uint32_t *tshift, bool *word32) {

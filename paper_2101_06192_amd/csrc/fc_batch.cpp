@@ -38,6 +38,7 @@ struct Group {
     bool use_lds = false, lds_bits = false, in_bits = false, word32 = true;
     bool weighted = false;   // some job's graph carries edge weights
     bool repop = false;      // re-formed 2-cycles popped within their round (LDS kernel)
+    uint32_t repop_words = 0;  // the same, global-counter kernel: its LDS filter (set with the shape)
     uint32_t lds_words = 0;  // dynamic LDS of the LDS-counter kernel (largest graph)
 };
 
@@ -91,8 +92,8 @@ hipError_t enqueue_group(const Group &g, const fc::CoopArgs &a, uint32_t threads
     if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, g.weighted, g.repop, stream);
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.kk.ptr), g.kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
-    return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, g.weighted, 0u,
-                                  stream);
+    return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, g.weighted,
+                                  g.repop_words, stream);
 }
 
 // Size a group's scratch for `slots` workgroups and point its arguments at it.
@@ -118,12 +119,16 @@ int size_scratch(fc_ctx *ctx, Group &g, uint32_t slots) {
     return FC_OK;
 }
 
-uint32_t slots_for(const fc_ctx *ctx, const Group &g, uint32_t threads, uint32_t wg_per_cu) {
+// (also picks the re-pop filter of a global-counter group for this shape)
+uint32_t slots_for(const fc_ctx *ctx, Group &g, uint32_t threads, uint32_t wg_per_cu) {
     const size_t n = g.n_max;
     const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words, g.weighted, g.repop)
                               : fc::coop_max_active(threads, g.lds_bits, g.in_bits, g.word32,
                                                     g.n_max, g.weighted, 0u);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
+    g.repop_words = g.use_lds ? 0u
+                              : coop_repop_words(ctx, threads, wg_per_cu, g.lds_bits, g.in_bits,
+                                                 g.word32, g.n_max, g.weighted);
     const size_t per_slot = g.use_lds ? (8 + 24 + 4) * n + 8
                                       : ((g.word32 ? 4 : 8) + 8 + 24 + 4) * n + 8 +
                                             (g.lds_bits ? 0 : 4 * ((n + 31) / 32));

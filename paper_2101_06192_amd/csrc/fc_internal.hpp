@@ -111,5 +111,9 @@ uint32_t lds_threads_for(const fc_ctx *ctx, uint64_t trees, uint32_t lds_words);
 // Bits of the target field so that n < 2^tshift, and whether a 32-bit tree
 // word also holds an in-arrow count up to dmax.
 void word_layout(uint32_t n, uint32_t dmax, bool allow32, uint32_t *tshift, bool *word32);
+// Global-counter sampler: LDS words of the re-pop filter for a launch of
+// `threads` x `per_cu` workgroups (0 when the option is off or nothing fits).
+uint32_t coop_repop_words(const fc_ctx *ctx, uint32_t threads, uint32_t per_cu, bool lds_bits,
+                          bool in_bits, bool word32, uint32_t n, bool weighted);
 
 }  // namespace fc_host

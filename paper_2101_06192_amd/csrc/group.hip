@@ -182,15 +182,6 @@ struct GemmArgs {
     uint32_t load_c, negate_x;
 };
 
-__device__ __forceinline__ void stage_ld(const double *__restrict__ A, uint32_t ld, uint32_t r0,
-                                         uint32_t c0, double *S, bool negate) {
-    for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads) {
-        const uint32_t r = e / kT, c = e % kT;
-        const double x = A[static_cast<size_t>(r0 + r) * ld + c0 + c];
-        S[r * kPad + c] = negate ? -x : x;
-    }
-}
-
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
     const uint32_t ti = blockIdx.y, tj = blockIdx.x;
     if ((ti >= g.si0 && ti < g.si1) || (tj >= g.sj0 && tj < g.sj1)) return;
