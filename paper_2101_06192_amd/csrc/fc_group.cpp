@@ -23,7 +23,8 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
     const uint32_t N = fc::group_dim(n);
     const size_t chunks = fc::group_chunks(n);
     if ((rc = ensure(ctx, ctx->g_mat, sizeof(double) * N * static_cast<size_t>(N), "dense matrix")) ||
-        (rc = ensure(ctx, ctx->g_vec, sizeof(double) * (4 * static_cast<size_t>(n) + 64 * 64 + 16),
+        (rc = ensure(ctx, ctx->g_vec,
+                     sizeof(double) * (4 * static_cast<size_t>(n) + 64 * 64 + 16 + 2 * static_cast<size_t>(k)),
                      "group vectors")) ||
         (rc = ensure(ctx, ctx->g_scr, sizeof(double) * fc::group_scratch_doubles(N), "inverse scratch")) ||
         (rc = ensure(ctx, ctx->g_part, sizeof(double) * chunks * N, "column sums")) ||
@@ -31,9 +32,15 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
         return rc;
     double *A = static_cast<double *>(ctx->g_mat.ptr);
     double *vec = static_cast<double *>(ctx->g_vec.ptr);
-    double *cv = vec, *rv = vec + n, *diag = vec + 2 * n, *gain = vec + 3 * n;
+    double *cv = vec, *rv = vec + n, *diag = vec + 2 * n;
+    // per gain block (256 ids): largest gain's bits and its smallest id
+    unsigned long long *bmax = reinterpret_cast<unsigned long long *>(vec + 3 * n);
+    uint32_t *bid = reinterpret_cast<uint32_t *>(bmax + (n + 255) / 256);
     double *scal = vec + 4 * static_cast<size_t>(n) + 64 * 64;  // [0] trace, [1] pivot
     unsigned long long *sel = reinterpret_cast<unsigned long long *>(scal + 4);
+    uint32_t *bad = reinterpret_cast<uint32_t *>(scal + 6);
+    double *fout = scal + 16;                                     // f(S) of step s
+    int32_t *gout = reinterpret_cast<int32_t *>(fout + k);         // vertex of step s
     double *part = static_cast<double *>(ctx->g_part.ptr);
     uint8_t *taken = static_cast<uint8_t *>(ctx->g_taken.ptr);
 
@@ -62,25 +69,25 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
     FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "trace");
     group[0] = static_cast<int32_t>(v0);
     if (farness) farness[0] = tr;
-    for (int32_t s = 1; s < k; ++s) {
-        const unsigned long long init[2] = {0ull, ~0ull};
-        FC_HIP(ctx, hipMemcpyAsync(sel, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream), "copy");
-        FC_HIP(ctx, fc::launch_group_argmax(A, n, N, part, taken, gain, sel, ctx->stream), "argmax");
-        FC_HIP(ctx, hipMemcpyAsync(hsel, sel, sizeof(hsel), hipMemcpyDeviceToHost, ctx->stream), "copy");
-        FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "argmax");
-        if (hsel[1] >= n) return set_err(ctx, FC_ERR_HIP, "no candidate vertex (non-finite gains)");
-        const uint32_t v = static_cast<uint32_t>(hsel[1]);
-        group[s] = static_cast<int32_t>(v);
-        FC_HIP(ctx, hipMemsetAsync(taken + v, 1, 1, ctx->stream), "flag");
-        FC_HIP(ctx, fc::launch_group_trace(A, n, N, v, scal, scal + 1, ctx->stream), "pivot");
-        FC_HIP(ctx, fc::launch_group_colsq(A, n, N, v, cv, rv, scal + 1, part, ctx->stream),
-               "downdate");
-        if (farness) {
-            FC_HIP(ctx, fc::launch_group_trace(A, n, N, n, scal, scal + 1, ctx->stream), "trace");
-            FC_HIP(ctx, hipMemcpyAsync(&farness[s], scal, sizeof(double), hipMemcpyDeviceToHost,
-                                       ctx->stream), "copy");
-        }
-    }
+    if (k == 1) return FC_OK;
+    // the remaining steps run back to back on the device (each choice is read by
+    // the next step's kernels there); choices and f(S) come back once at the end
+    FC_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(uint32_t), ctx->stream), "memset");
+    for (int32_t s = 1; s < k; ++s)
+        FC_HIP(ctx, fc::launch_group_step(A, n, N, part, taken, bmax, bid, sel + 1, cv, rv, scal + 1,
+                                          gout, farness ? fout : nullptr, static_cast<uint32_t>(s),
+                                          bad, ctx->stream),
+               "greedy step");
+    uint32_t hbad = 0;
+    std::vector<int32_t> hg(static_cast<size_t>(k));
+    FC_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, ctx->stream), "copy");
+    FC_HIP(ctx, hipMemcpyAsync(hg.data() + 1, gout + 1, sizeof(int32_t) * (k - 1), hipMemcpyDeviceToHost,
+                               ctx->stream), "copy");
+    if (farness)
+        FC_HIP(ctx, hipMemcpyAsync(farness + 1, fout + 1, sizeof(double) * (k - 1), hipMemcpyDeviceToHost,
+                                   ctx->stream), "copy");
     FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "group closeness");
+    if (hbad) return set_err(ctx, FC_ERR_HIP, "no candidate vertex (non-finite gains)");
+    std::memcpy(group + 1, hg.data() + 1, sizeof(int32_t) * (k - 1));
     return FC_OK;
 }

@@ -34,10 +34,14 @@ hipError_t launch_group_trace(const double *A, uint32_t n, uint32_t N, uint32_t 
 // first the downdate by vertex v (pivot *piv; cv, rv: n scratch).
 hipError_t launch_group_colsq(double *A, uint32_t n, uint32_t N, uint32_t v, double *cv, double *rv,
                               const double *piv, double *part, hipStream_t stream);
-// gain[j] = column sum / A[j][j] for j not taken (else -1); sel[0] = max gain
-// bits (preset 0), sel[1] = smallest id with it (preset all ones).
-hipError_t launch_group_argmax(const double *A, uint32_t n, uint32_t N, const double *part,
-                               const uint8_t *taken, double *gain, unsigned long long *sel,
-                               hipStream_t stream);
+// One greedy step with no host round trip: the gains |M e_j|^2 / M_jj of the
+// vertices not taken, per-block maxima (bmax, bid: blocks of 256 ids), then on
+// the largest gain's smallest id v: taken[v] = 1, gout[s] = v, *piv = M[v][v],
+// *vsel = v, the downdate and the next column sums, and fout[s] = f(S) when
+// fout is not null.  No candidate: gout[s] = -1, *bad = 1, the matrix as it was.
+hipError_t launch_group_step(double *A, uint32_t n, uint32_t N, double *part, uint8_t *taken,
+                             unsigned long long *bmax, uint32_t *bid, unsigned long long *vsel,
+                             double *cv, double *rv, double *piv, int32_t *gout, double *fout,
+                             uint32_t s, uint32_t *bad, hipStream_t stream);
 
 }  // namespace fc

@@ -313,12 +313,22 @@ __global__ __launch_bounds__(kThreads) void reground_kernel(double *__restrict__
     *p = (o - ci - cj) + cvv;
 }
 
+// The vertex of a greedy step: the host's v, or the device's choice *vsel
+// (n when there is none: the step then changes nothing).
+__device__ __forceinline__ uint32_t step_vertex(uint32_t v, const unsigned long long *vsel, uint32_t n) {
+    if (!vsel) return v;
+    const unsigned long long x = *vsel;
+    return x < n ? static_cast<uint32_t>(x) : n;
+}
+
 __global__ __launch_bounds__(kThreads) void copy_col_kernel(const double *__restrict__ A, uint32_t n,
-                                                            uint32_t N, uint32_t v,
+                                                            uint32_t N, uint32_t v0,
+                                                            const unsigned long long *vsel,
                                                             double *__restrict__ col,
                                                             double *__restrict__ row) {
     const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
+    const uint32_t v = step_vertex(v0, vsel, n);
+    if (i >= n || v >= n) return;
     col[i] = A[static_cast<size_t>(i) * N + v];
     if (row) row[i] = A[static_cast<size_t>(v) * N + i];
 }
@@ -328,16 +338,18 @@ __global__ __launch_bounds__(kThreads) void copy_col_kernel(const double *__rest
 // whose row and column become zero.
 constexpr uint32_t kChunk = 64;
 __global__ __launch_bounds__(kThreads) void colsq_kernel(double *__restrict__ A, uint32_t n, uint32_t N,
-                                                         uint32_t v, const double *__restrict__ cv,
+                                                         uint32_t v0, const unsigned long long *vsel,
+                                                         const double *__restrict__ cv,
                                                          const double *__restrict__ rv,
                                                          const double *__restrict__ pivp,
                                                          double *__restrict__ part) {
     const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t c = blockIdx.y;
     if (j >= n) return;
+    const uint32_t v = step_vertex(v0, vsel, n);
     const uint32_t i0 = c * kChunk, i1 = min(n, i0 + kChunk);
     double s = 0.0;
-    if (cv) {
+    if (cv && v < n) {
         const double piv = *pivp;
         const double f = rv[j] / piv;
         for (uint32_t i = i0; i < i1; ++i) {
@@ -356,30 +368,104 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(double *__restrict__ A,
 }
 
 // gain[j] = |M e_j|^2 / M_jj for candidates (not taken, not the u* slot),
-// else -1; the chunk sums added in chunk order.
+// the chunk sums added in chunk order; per block, the largest candidate gain
+// as its binary64 bit pattern (0 with no candidate) in bmax[b] and the
+// smallest id of a candidate with that pattern and a gain >= 0 (none: all
+// ones, e.g. when the largest pattern is a NaN's) in bid[b].
 __global__ __launch_bounds__(kThreads) void gain_kernel(const double *__restrict__ A, uint32_t n,
                                                         uint32_t N, uint32_t chunks,
                                                         const double *__restrict__ part,
                                                         const uint8_t *__restrict__ taken,
-                                                        double *__restrict__ gain,
-                                                        unsigned long long *sel) {
-    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
-    if (j >= n) return;
-    double g = -1.0;
-    if (!taken[j]) {
-        double s = 0.0;
-        for (uint32_t c = 0; c < chunks; ++c) s += part[static_cast<size_t>(c) * N + j];
-        g = s / A[static_cast<size_t>(j) * N + j];
-        atomicMax(&sel[0], static_cast<unsigned long long>(__double_as_longlong(g)));
+                                                        unsigned long long *__restrict__ bmax,
+                                                        uint32_t *__restrict__ bid) {
+    __shared__ unsigned long long sk[kThreads];
+    __shared__ uint32_t si[kThreads];
+    const uint32_t t = threadIdx.x, j = blockIdx.x * kThreads + t;
+    unsigned long long key = 0ull;
+    bool ok = false;
+    if (j < n && !taken[j]) {
+        double sum = 0.0;
+        for (uint32_t c = 0; c < chunks; ++c) sum += part[static_cast<size_t>(c) * N + j];
+        const double g = sum / A[static_cast<size_t>(j) * N + j];
+        key = static_cast<unsigned long long>(__double_as_longlong(g));
+        ok = g >= 0.0;
     }
-    gain[j] = g;
+    sk[t] = key;
+    __syncthreads();
+    for (uint32_t h = kThreads / 2; h > 0; h >>= 1) {
+        if (t < h) sk[t] = max(sk[t], sk[t + h]);
+        __syncthreads();
+    }
+    const unsigned long long top = sk[0];
+    si[t] = ok && key == top ? j : ~0u;
+    __syncthreads();
+    for (uint32_t h = kThreads / 2; h > 0; h >>= 1) {
+        if (t < h) si[t] = min(si[t], si[t + h]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        bmax[blockIdx.x] = top;
+        bid[blockIdx.x] = si[0];
+    }
 }
-__global__ __launch_bounds__(kThreads) void argmax_id_kernel(const double *__restrict__ gain, uint32_t n,
-                                                             unsigned long long *sel) {
-    const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
-    if (j < n && gain[j] >= 0.0 &&
-        static_cast<unsigned long long>(__double_as_longlong(gain[j])) == sel[0])
-        atomicMin(&sel[1], static_cast<unsigned long long>(j));
+
+// The step's vertex from the gain blocks' results (every block of the next
+// kernel reduces them the same way): the smallest id among the largest
+// pattern, or n when there is none.
+__device__ uint32_t reduce_choice(const unsigned long long *__restrict__ bmax,
+                                  const uint32_t *__restrict__ bid, uint32_t nb, uint32_t n) {
+    __shared__ unsigned long long sk[kThreads];
+    __shared__ uint32_t si[kThreads];
+    const uint32_t t = threadIdx.x;
+    unsigned long long k = 0ull;
+    for (uint32_t b = t; b < nb; b += kThreads) k = max(k, bmax[b]);
+    sk[t] = k;
+    __syncthreads();
+    for (uint32_t h = kThreads / 2; h > 0; h >>= 1) {
+        if (t < h) sk[t] = max(sk[t], sk[t + h]);
+        __syncthreads();
+    }
+    const unsigned long long top = sk[0];
+    uint32_t id = ~0u;
+    for (uint32_t b = t; b < nb; b += kThreads)
+        if (bmax[b] == top) id = min(id, bid[b]);
+    si[t] = id;
+    __syncthreads();
+    for (uint32_t h = kThreads / 2; h > 0; h >>= 1) {
+        if (t < h) si[t] = min(si[t], si[t + h]);
+        __syncthreads();
+    }
+    const uint32_t v = si[0];
+    __syncthreads();  // the arrays are reused by a later call
+    return v < n ? v : n;
+}
+
+// Column v of the chosen vertex (and its row) copied out before the downdate,
+// v reduced from the gain blocks; block 0 also does the step's bookkeeping:
+// taken[v] = 1, gout[s] = v, *piv = M[v][v], *vout = v for the downdate
+// (all ones and *bad = 1 when there is no candidate).
+__global__ __launch_bounds__(kThreads) void choose_copy_kernel(
+    const double *__restrict__ A, uint32_t n, uint32_t N, const unsigned long long *__restrict__ bmax,
+    const uint32_t *__restrict__ bid, uint32_t nb, uint8_t *__restrict__ taken, int32_t *gout,
+    uint32_t s, double *piv, unsigned long long *vout, uint32_t *bad, double *__restrict__ col,
+    double *__restrict__ row) {
+    const uint32_t v = reduce_choice(bmax, bid, nb, n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (v < n) {
+            taken[v] = 1u;
+            gout[s] = static_cast<int32_t>(v);
+            *piv = A[static_cast<size_t>(v) * N + v];
+            *vout = v;
+        } else {
+            gout[s] = -1;
+            *bad = 1u;
+            *vout = ~0ull;
+        }
+    }
+    const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n || v >= n) return;
+    col[i] = A[static_cast<size_t>(i) * N + v];
+    row[i] = A[static_cast<size_t>(v) * N + i];
 }
 
 // tr(M) over the first n slots (one block, fixed order), into *out; also
@@ -490,7 +576,7 @@ hipError_t launch_group_first(const double *A, uint32_t n, uint32_t N, double *d
 
 hipError_t launch_group_reground(double *A, uint32_t n, uint32_t N, uint32_t v0, double *c,
                                  hipStream_t stream) {
-    copy_col_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, v0, c, nullptr);
+    copy_col_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, v0, nullptr, c, nullptr);
     reground_kernel<<<dim3(blocks_for(n), n), kThreads, 0, stream>>>(A, n, N, v0, c);
     return hipGetLastError();
 }
@@ -504,18 +590,23 @@ hipError_t launch_group_trace(const double *A, uint32_t n, uint32_t N, uint32_t 
 hipError_t launch_group_colsq(double *A, uint32_t n, uint32_t N, uint32_t v, double *cv, double *rv,
                               const double *piv, double *part, hipStream_t stream) {
     const bool down = v < n;
-    if (down) copy_col_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, v, cv, rv);
+    if (down) copy_col_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, v, nullptr, cv, rv);
     colsq_kernel<<<dim3(blocks_for(n), group_chunks(n)), kThreads, 0, stream>>>(
-        A, n, N, v, down ? cv : nullptr, down ? rv : nullptr, piv, part);
+        A, n, N, v, nullptr, down ? cv : nullptr, down ? rv : nullptr, piv, part);
     return hipGetLastError();
 }
 
-hipError_t launch_group_argmax(const double *A, uint32_t n, uint32_t N, const double *part,
-                               const uint8_t *taken, double *gain, unsigned long long *sel,
-                               hipStream_t stream) {
-    gain_kernel<<<blocks_for(n), kThreads, 0, stream>>>(A, n, N, group_chunks(n), part, taken, gain,
-                                                        sel);
-    argmax_id_kernel<<<blocks_for(n), kThreads, 0, stream>>>(gain, n, sel);
+hipError_t launch_group_step(double *A, uint32_t n, uint32_t N, double *part, uint8_t *taken,
+                             unsigned long long *bmax, uint32_t *bid, unsigned long long *vsel,
+                             double *cv, double *rv, double *piv, int32_t *gout, double *fout,
+                             uint32_t s, uint32_t *bad, hipStream_t stream) {
+    const uint32_t nb = blocks_for(n);
+    gain_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, group_chunks(n), part, taken, bmax, bid);
+    choose_copy_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, bmax, bid, nb, taken, gout, s, piv, vsel,
+                                                    bad, cv, rv);
+    colsq_kernel<<<dim3(nb, group_chunks(n)), kThreads, 0, stream>>>(A, n, N, n, vsel, cv, rv, piv,
+                                                                    part);
+    if (fout) trace_kernel<<<1, kThreads, 0, stream>>>(A, n, N, n, fout + s, nullptr);
     return hipGetLastError();
 }
 
