@@ -499,8 +499,9 @@ void wilson_coop_kernel(CoopArgs a, uint32_t fwords) {
             if (fwords) {
                 constexpr uint32_t kPasses = 32;
                 const uint32_t cap = n >> 1;
-                const uint64_t *cur = Unext + u_hang;
-                uint32_t ccur = min(uniform(s_u), n) - u_hang;
+                const uint32_t u_end = min(uniform(s_u), n), u_beg = min(u_hang, u_end);
+                const uint64_t *cur = Unext + u_beg;
+                uint32_t ccur = u_end - u_beg;
                 bool any = false;
                 for (uint32_t pass = 0; ccur > 0u; ++pass) {
                     uint32_t *rp = &s_rp[pass & 1u];

@@ -560,8 +560,9 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             // would overflow it ends the loop.
             if (kRepop) {
                 const uint32_t cap = n >> 1;
-                const uint64_t *cur = Unext + u_hang;
-                uint32_t ccur = min(uniform(s_u), n) - u_hang;
+                const uint32_t u_end = min(uniform(s_u), n), u_beg = min(u_hang, u_end);
+                const uint64_t *cur = Unext + u_beg;
+                uint32_t ccur = u_end - u_beg;
                 bool any = false;
                 for (uint32_t pass = 0; ccur > 0u && pass < kRepopPasses; ++pass) {
                     uint64_t *nxt = peel + ((pass & 1u) ? cap : 0u);
