@@ -72,33 +72,55 @@ __device__ __forceinline__ Quad quad() {
     return {32u * (w >> 1), 32u * (w & 1u), threadIdx.x & 63u};
 }
 
-// Pivot block inverse: D = A[p0.., p0..] (64 x 64, SPD) inverted in LDS by
-// Gauss-Jordan without pivoting, written to Dinv (64 x 64, row-major).
+// Pivot block inverse: D = A[p0.., p0..] (64 x 64, SPD) inverted by
+// Gauss-Jordan without pivoting, written to Dinv (64 x 64, row-major).  The
+// 256 threads hold the block in registers, a 4 x 4 sub-block each (thread
+// (ty, tx) = rows 4 ty.., columns 4 tx..); step p publishes row p and column p
+// (the multipliers, read before any row changes them) through LDS, double
+// buffered by the step's parity so that one barrier per step suffices, and row
+// p is scaled by the pivot's reciprocal.
 __global__ __launch_bounds__(kThreads) void gj_pivot_kernel(const double *__restrict__ A, uint32_t N,
                                                             uint32_t p0, double *__restrict__ Dinv) {
-    __shared__ double D[kT * kPad];
-    __shared__ double colp[kT];
-    stage(A, N, p0, p0, D, false);
-    __syncthreads();
+    __shared__ double rowp[2][kT], colp[2][kT];
+    const uint32_t tx = threadIdx.x & 15u, ty = threadIdx.x >> 4;
+    double d[4][4];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r)
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c)
+            d[r][c] = A[static_cast<size_t>(p0 + 4u * ty + r) * N + p0 + 4u * tx + c];
     for (uint32_t p = 0; p < kT; ++p) {
-        const double piv = D[p * kPad + p];
+        const uint32_t b = p & 1u, band = p >> 2, lp = p & 3u;
+        if (tx == band)
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) colp[b][4u * ty + r] = d[r][lp];
+        if (ty == band)
+#pragma unroll
+            for (uint32_t c = 0; c < 4; ++c) rowp[b][4u * tx + c] = d[lp][c];
         __syncthreads();
-        if (threadIdx.x < kT) {  // row p divided by the pivot (its own entry becomes 1 / piv)
-            const uint32_t j = threadIdx.x;
-            colp[j] = D[j * kPad + p];  // the multipliers, read before any row changes them
-            D[p * kPad + j] = (j == p ? 1.0 : D[p * kPad + j]) / piv;
+        const double inv = 1.0 / rowp[b][p];
+        double rp[4];
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c) {
+            const uint32_t j = 4u * tx + c;
+            rp[c] = (j == p ? 1.0 : rowp[b][j]) * inv;  // row p of the result
         }
-        __syncthreads();
-        for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads) {
-            const uint32_t i = e / kT, j = e % kT;
-            if (i == p) continue;
-            // column p of row i becomes -f / piv; the others subtract f * row p
-            D[i * kPad + j] = (j == p ? 0.0 : D[i * kPad + j]) - colp[i] * D[p * kPad + j];
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+            const uint32_t i = 4u * ty + r;
+            const double f = colp[b][i];
+#pragma unroll
+            for (uint32_t c = 0; c < 4; ++c) {
+                const uint32_t j = 4u * tx + c;
+                // column p of row i becomes -f / piv; the others subtract f * row p
+                d[r][c] = i == p ? rp[c] : (j == p ? 0.0 : d[r][c]) - f * rp[c];
+            }
         }
-        __syncthreads();
     }
-    for (uint32_t e = threadIdx.x; e < kT * kT; e += kThreads)
-        Dinv[e] = D[(e / kT) * kPad + e % kT];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r)
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c) Dinv[(4u * ty + r) * kT + 4u * tx + c] = d[r][c];
 }
 
 // Row panel: A[p-rows, j-tile] <- Dinv A[p-rows, j-tile] (j-tile != p);
