@@ -606,6 +606,31 @@ def test_solve_argument_errors(gpu_lib):
     assert e.value.code == fc.FC_ERR_ARG
 
 
+def _heavy_pairs_graph():
+    """BA(1800, 3) with unit weights and 100 separate pairs of weight 10^4:
+    a pair's walk bounces thousands of times, so its 2-cycle re-forms pass
+    after pass."""
+    ba = inputs.barabasi_albert(1800, 3, 11)
+    deg = np.diff(ba.row_ptr)
+    src = np.repeat(np.arange(ba.n), deg)
+    edges = [(int(a), int(b), 1.0) for a, b in zip(src, ba.col_idx) if a < b]
+    edges += [(1800 + 2 * i, 1801 + 2 * i, 1e4) for i in range(100)]
+    return inputs.from_weighted_edge_list(2000, edges, "ba1800_heavy_pairs")
+
+
+@pytest.mark.parametrize("sampler", ["lds", "coop"])
+def test_repop_overflow_and_pass_limit(gpu_lib, sampler):
+    """The re-pop's two exits besides running out of pairs: a perfect matching
+    at alpha = 100, where nearly every pair forms again, so a pass outgrows its
+    half of the peel buffer (the pass is dropped and its pairs wait for the next
+    round); and pairs of weight 10^4, which keep re-forming past the last
+    allowed pass.  Both give the oracle's trees."""
+    fc = gpu_lib
+    matching = inputs.from_edge_list(2000, [(2 * i, 2 * i + 1) for i in range(1000)], "matching2000")
+    _compare(fc, matching, 100.0, 5, 0, 12, per_tree=True, sampler=sampler)
+    _compare(fc, _heavy_pairs_graph(), 1.0, 6, 0, 12, per_tree=True, sampler=sampler)
+
+
 @pytest.mark.parametrize("repop", [0, 2], ids=["repop_off", "repop_on"])
 @pytest.mark.parametrize("case", ["er1000", "ba20k", "grid", "rmat", "small"])
 def test_lds_repop_bit_exact(gpu_lib, repop, case):
