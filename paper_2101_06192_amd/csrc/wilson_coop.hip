@@ -34,6 +34,8 @@
 //                          level boundaries (u32)
 //   settled  bit  LDS      one bit per vertex when n/8 bytes fit the LDS
 //                          budget, else a per-slot global bitmap
+//   filter   bit  LDS      re-pop filter (when re-formed 2-cycles are popped
+//                          within their round): one bit per id modulo its size
 #include "fc_kernels.hpp"
 
 namespace fc {
