@@ -211,7 +211,9 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *                     close again is popped in that same round (cycle popping may pop
  *                     any cycle at any time: the same trees) instead of a round later
  *                     with everything that hangs off it; 0 never, 1 weighted graphs
- *                     only, 2 always (the default)
+ *                     only, 2 always (the default; a batch created with
+ *                     FC_FLAG_AUTOTUNE then times each LDS launch group with and
+ *                     without the re-pops and keeps the faster: the trees are the same)
  *   "coop_repop"      the same for the global-counter sampler (graphs whose counters do
  *                     not fit LDS), with an LDS filter that flags the re-popped
  *                     vertices; 0 never, 1 weighted graphs only, 2 always (the default)

@@ -145,38 +145,64 @@ int autotune(fc_batch *b, Group &g) {
     int rc = FC_OK;
     static const uint32_t cand_coop[][2] = {{256, 3}, {256, 6}, {512, 2}, {512, 3}, {128, 12}};
     static const uint32_t cand_lds[][2] = {{256, 64}, {512, 64}, {1024, 64}, {256, 4}, {512, 2}};
-    std::vector<std::array<uint32_t, 2>> cand;
-    if (g.use_lds)
-        for (const auto &c : cand_lds) cand.push_back({c[0], c[1]});
-    else
-        for (const auto &c : cand_coop) cand.push_back({c[0], c[1]});
+    // (threads, workgroups per CU, re-pops): with the option at its default the
+    // LDS groups are timed with and without popping re-formed 2-cycles within
+    // their round (the same trees either way; it pays on BA and ER graphs, not on
+    // R-MAT batches)
+    std::vector<std::array<uint32_t, 3>> cand;
+    const bool tune_repop = g.use_lds && ctx->lds_repop == 2;
+    if (g.use_lds) {
+        for (const auto &c : cand_lds) {
+            cand.push_back({c[0], c[1], g.repop ? 1u : 0u});
+            if (tune_repop) cand.push_back({c[0], c[1], g.repop ? 0u : 1u});
+        }
+    } else {
+        for (const auto &c : cand_coop) cand.push_back({c[0], c[1], g.repop ? 1u : 0u});
+    }
     // throw-away job table: same graphs and records, outputs into one scratch R
     std::vector<fc::CoopJob> tab(g.ntab);
     FC_HIP(ctx, hipMemcpy(tab.data(), g.jobtab.ptr, sizeof(fc::CoopJob) * tab.size(),
                           hipMemcpyDeviceToHost), "read job table");
     if ((rc = ensure(ctx, g.scratch_r, 4 * static_cast<size_t>(g.n_max), "tuning outputs"))) return rc;
-    for (auto &j : tab) {
+    // the tuning sample: a sixteenth of every job's trees (at least one), so that
+    // every graph and alpha of the group is in it, not only the largest first jobs
+    std::vector<uint32_t> tmap;
+    for (size_t t = 0; t < tab.size(); ++t) {
+        fc::CoopJob &j = tab[t];
         j.root_counts = static_cast<uint32_t *>(g.scratch_r.ptr);
         j.visit_counts = nullptr;
         j.tree_digests = nullptr;
         j.tree_steps = nullptr;
         j.parents = nullptr;
         j.tree_visits = nullptr;
+        const uint32_t c = j.tree_count ? std::max<uint32_t>(1, j.tree_count / 16) : 0u;
+        j.first_item = static_cast<uint32_t>(tmap.size());
+        j.tree_count = c;
+        tmap.insert(tmap.end(), c, static_cast<uint32_t>(t));
     }
-    DevBuf tmp_tab;
-    if ((rc = ensure(ctx, tmp_tab, sizeof(fc::CoopJob) * tab.size(), "tuning job table"))) return rc;
-    const uint32_t prefix = std::min<uint32_t>(g.item_count,
-                                               std::max<uint32_t>(g.item_count / 16, 4096));
+    if (tmap.empty()) return FC_OK;
+    DevBuf tmp_tab, tmp_map;
+    if ((rc = ensure(ctx, tmp_tab, sizeof(fc::CoopJob) * tab.size(), "tuning job table")) ||
+        (rc = ensure(ctx, tmp_map, 4 * tmap.size(), "tuning item map"))) {
+        if (tmp_tab.ptr) (void)hipFree(tmp_tab.ptr);
+        return rc;
+    }
+    const uint32_t prefix = static_cast<uint32_t>(tmap.size());
     float best = 1e30f;
     uint32_t best_t = g.threads, best_w = g.wg_per_cu;
+    bool best_r = g.repop;
     hipError_t he = hipMemcpy(tmp_tab.ptr, tab.data(), sizeof(fc::CoopJob) * tab.size(),
                               hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+        he = hipMemcpy(tmp_map.ptr, tmap.data(), 4 * tmap.size(), hipMemcpyHostToDevice);
     if (he != hipSuccess) rc = hip_fail(ctx, he, "write tuning table");
     for (size_t c = 0; rc == FC_OK && c < cand.size(); ++c) {
+        g.repop = cand[c][2] != 0u;
         const uint32_t slots = slots_for(ctx, g, cand[c][0], cand[c][1]);
         if ((rc = size_scratch(ctx, g, slots))) break;
         fc::CoopArgs a = g.args;
         a.jobs = static_cast<const fc::CoopJob *>(tmp_tab.ptr);
+        a.item_job = static_cast<const uint32_t *>(tmp_map.ptr);
         a.item_count = prefix;
         if ((he = hipEventRecord(b->ev0, b->stream)) != hipSuccess ||
             (he = enqueue_group(g, a, cand[c][0], b->stream)) != hipSuccess ||
@@ -200,9 +226,12 @@ int autotune(fc_batch *b, Group &g) {
             best = ms;
             best_t = cand[c][0];
             best_w = cand[c][1];
+            best_r = cand[c][2] != 0u;
         }
     }
     if (tmp_tab.ptr) (void)hipFree(tmp_tab.ptr);
+    if (tmp_map.ptr) (void)hipFree(tmp_map.ptr);
+    g.repop = best_r;
     if (rc) return rc;
     g.threads = best_t;
     g.wg_per_cu = best_w;
