@@ -32,16 +32,17 @@ __device__ __forceinline__ uint32_t d_row(uint32_t lane, uint32_t r) { return (l
 __device__ __forceinline__ uint32_t d_col(uint32_t lane) { return lane & 15u; }
 
 // acc += X * Y over one wave's 32 x 32 quadrant (qr, qc) of a 64 x 64 tile,
-// X and Y 64 x 64 in LDS (row stride kPad).
+// X 64 x K (row stride XS) and Y K x 64 (row stride kPad) in LDS.
+template <uint32_t K = kT, uint32_t XS = kPad>
 __device__ __forceinline__ void tile_mma(const double *X, const double *Y, uint32_t qr,
                                          uint32_t qc, uint32_t lane, double4_t (&acc)[2][2]) {
     const uint32_t li = lane & 15u, lk = lane >> 4;
 #pragma unroll 4
-    for (uint32_t k0 = 0; k0 < kT; k0 += 4) {
+    for (uint32_t k0 = 0; k0 < K; k0 += 4) {
         double a[2], b[2];
 #pragma unroll
         for (uint32_t s = 0; s < 2; ++s) {
-            a[s] = X[(qr + 16u * s + li) * kPad + k0 + lk];
+            a[s] = X[(qr + 16u * s + li) * XS + k0 + lk];
             b[s] = Y[(k0 + lk) * kPad + qc + 16u * s + li];
         }
 #pragma unroll
@@ -191,10 +192,13 @@ __global__ __launch_bounds__(kThreads) void gj_update_kernel(double *__restrict_
                   16u * u + d_col(q.lane)] = acc[s][u][r];
 }
 
-// Tile product over K = kchunks x 64: out[ti, tj] = (load_c ? out[ti, tj] : 0)
+// Tile product over K = kchunks x kK: out[ti, tj] = (load_c ? out[ti, tj] : 0)
 // + (negate_x ? -X : X)[ti, :] Y[:, tj], the K dimension streamed through LDS
-// 64 at a time (the accumulators stay in registers).  Tiles whose row tile is
+// kK at a time (the accumulators stay in registers; 32-deep chunks keep the
+// LDS tiles and the prefetch registers small enough for four workgroups per CU).  Tiles whose row tile is
 // in [si0, si1) or whose column tile is in [sj0, sj1) are skipped.
+constexpr uint32_t kK = 32;         // K chunk of gemm_kernel
+constexpr uint32_t kPadK = kK + 1;  // its X tile's row stride (doubles)
 struct GemmArgs {
     const double *X;
     const double *Y;
@@ -204,10 +208,10 @@ struct GemmArgs {
     uint32_t load_c, negate_x;
 };
 
-__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void gemm_kernel(GemmArgs g) {
     const uint32_t ti = blockIdx.y, tj = blockIdx.x;
     if ((ti >= g.si0 && ti < g.si1) || (tj >= g.sj0 && tj < g.sj1)) return;
-    __shared__ double X[kT * kPad], Y[kT * kPad];
+    __shared__ double X[kT * kPadK], Y[kK * kPad];
     const Quad q = quad();
     double4_t acc[2][2];
     const uint32_t i0 = ti * kT, j0 = tj * kT;
@@ -222,15 +226,15 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
                                         : 0.0;
     // software pipeline: chunk c + 1 is loaded into registers while the
     // matrix cores work on chunk c from LDS
-    constexpr uint32_t kPer = kT * kT / kThreads;  // elements of a chunk per thread
+    constexpr uint32_t kPer = kT * kK / kThreads;  // elements of a chunk per thread
     double xr[kPer], yr[kPer];
     const double sx = g.negate_x ? -1.0 : 1.0;
     auto load = [&](uint32_t c) {
 #pragma unroll
         for (uint32_t q2 = 0; q2 < kPer; ++q2) {
-            const uint32_t e = q2 * kThreads + threadIdx.x, r = e / kT, cc = e % kT;
-            xr[q2] = g.X[static_cast<size_t>(i0 + r) * g.ldx + c * kT + cc];
-            yr[q2] = g.Y[static_cast<size_t>(c * kT + r) * g.ldy + j0 + cc];
+            const uint32_t e = q2 * kThreads + threadIdx.x;
+            xr[q2] = g.X[static_cast<size_t>(i0 + e / kK) * g.ldx + c * kK + e % kK];
+            yr[q2] = g.Y[static_cast<size_t>(c * kK + e / kT) * g.ldy + j0 + e % kT];
         }
     };
     load(0);
@@ -238,13 +242,13 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
         __syncthreads();
 #pragma unroll
         for (uint32_t q2 = 0; q2 < kPer; ++q2) {
-            const uint32_t e = q2 * kThreads + threadIdx.x, r = e / kT, cc = e % kT;
-            X[r * kPad + cc] = sx * xr[q2];
-            Y[r * kPad + cc] = yr[q2];
+            const uint32_t e = q2 * kThreads + threadIdx.x;
+            X[(e / kK) * kPadK + e % kK] = sx * xr[q2];
+            Y[(e / kT) * kPad + e % kT] = yr[q2];
         }
         __syncthreads();
         if (c + 1 < g.kchunks) load(c + 1);
-        tile_mma(X, Y, q.qr, q.qc, q.lane, acc);
+        tile_mma<kK, kPadK>(X, Y, q.qr, q.qc, q.lane, acc);
     }
 #pragma unroll
     for (uint32_t s = 0; s < 2; ++s)
@@ -562,11 +566,11 @@ hipError_t launch_group_invert(double *A, uint32_t N, double *scratch, hipStream
         copy_block_kernel<<<dim3(1, kB), kThreads, 0, stream>>>(A + static_cast<size_t>(p0) * N + p0, N,
                                                                 W, kB, kB);
         invert_64(W, kB, D64, stream);
-        GemmArgs row{W, A + static_cast<size_t>(p0) * N, R, kB, N, N, pb, 0u, 0u, pt0, pt1, 0u, 0u};
+        GemmArgs row{W, A + static_cast<size_t>(p0) * N, R, kB, N, N, kB / kK, 0u, 0u, pt0, pt1, 0u, 0u};
         gemm_kernel<<<dim3(nt, pb), kThreads, 0, stream>>>(row);
-        GemmArgs upd{A + p0, R, A, N, N, N, pb, pt0, pt1, pt0, pt1, 1u, 1u};
+        GemmArgs upd{A + p0, R, A, N, N, N, kB / kK, pt0, pt1, pt0, pt1, 1u, 1u};
         gemm_kernel<<<dim3(nt, nt), kThreads, 0, stream>>>(upd);
-        GemmArgs col{A + p0, W, C, N, kB, kB, pb, pt0, pt1, 0u, 0u, 0u, 1u};
+        GemmArgs col{A + p0, W, C, N, kB, kB, kB / kK, pt0, pt1, 0u, 0u, 0u, 1u};
         gemm_kernel<<<dim3(pb, nt), kThreads, 0, stream>>>(col);
         // write back: rows of P from R (outside P's columns), columns of P from C
         // (outside P's rows), and W on the diagonal block
