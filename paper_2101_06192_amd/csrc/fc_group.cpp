@@ -35,7 +35,8 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
     double *cv = vec, *rv = vec + n, *diag = vec + 2 * n;
     // per gain block (256 ids): largest gain's bits and its smallest id
     unsigned long long *bmax = reinterpret_cast<unsigned long long *>(vec + 3 * n);
-    uint32_t *bid = reinterpret_cast<uint32_t *>(bmax + (n + 255) / 256);
+    double *bdiag = vec + 3 * static_cast<size_t>(n) + (n + 255) / 256;
+    uint32_t *bid = reinterpret_cast<uint32_t *>(bdiag + (n + 255) / 256);
     double *scal = vec + 4 * static_cast<size_t>(n) + 64 * 64;  // [0] trace, [1] pivot
     unsigned long long *sel = reinterpret_cast<unsigned long long *>(scal + 4);
     uint32_t *bad = reinterpret_cast<uint32_t *>(scal + 6);
@@ -74,10 +75,12 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
     // the next step's kernels there); choices and f(S) come back once at the end
     FC_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(uint32_t), ctx->stream), "memset");
     for (int32_t s = 1; s < k; ++s)
-        FC_HIP(ctx, fc::launch_group_step(A, n, N, part, taken, bmax, bid, sel + 1, cv, rv, scal + 1,
-                                          gout, farness ? fout : nullptr, static_cast<uint32_t>(s),
-                                          bad, ctx->stream),
+        FC_HIP(ctx, fc::launch_group_step(A, n, N, part, taken, bmax, bid, bdiag, sel + 1, cv, rv,
+                                          scal + 1, gout, farness ? fout : nullptr,
+                                          static_cast<uint32_t>(s), bad, ctx->stream),
                "greedy step");
+    if (farness)  // f(S) after the last step
+        FC_HIP(ctx, fc::launch_group_trace(A, n, N, n, fout + (k - 1), nullptr, ctx->stream), "trace");
     uint32_t hbad = 0;
     std::vector<int32_t> hg(static_cast<size_t>(k));
     FC_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, ctx->stream), "copy");

@@ -34,14 +34,17 @@ hipError_t launch_group_trace(const double *A, uint32_t n, uint32_t N, uint32_t 
 // first the downdate by vertex v (pivot *piv; cv, rv: n scratch).
 hipError_t launch_group_colsq(double *A, uint32_t n, uint32_t N, uint32_t v, double *cv, double *rv,
                               const double *piv, double *part, hipStream_t stream);
-// One greedy step with no host round trip: the gains |M e_j|^2 / M_jj of the
-// vertices not taken, per-block maxima (bmax, bid: blocks of 256 ids), then on
-// the largest gain's smallest id v: taken[v] = 1, gout[s] = v, *piv = M[v][v],
-// *vsel = v, the downdate and the next column sums, and fout[s] = f(S) when
-// fout is not null.  No candidate: gout[s] = -1, *bad = 1, the matrix as it was.
+// One greedy step s >= 1 with no host round trip: the gains |M e_j|^2 / M_jj of
+// the vertices not taken, per-block maxima and diagonal sums (bmax, bid, bdiag:
+// blocks of 256 ids), then on the largest gain's smallest id v: taken[v] = 1,
+// gout[s] = v, *piv = M[v][v], *vsel = v, the downdate and the next column
+// sums.  With fout not null, fout[s - 1] = tr M as the step found it (f(S) of
+// step s - 1; the last step's f(S) is left to launch_group_trace).  No
+// candidate: gout[s] = -1, *bad = 1, the matrix as it was.
 hipError_t launch_group_step(double *A, uint32_t n, uint32_t N, double *part, uint8_t *taken,
-                             unsigned long long *bmax, uint32_t *bid, unsigned long long *vsel,
-                             double *cv, double *rv, double *piv, int32_t *gout, double *fout,
-                             uint32_t s, uint32_t *bad, hipStream_t stream);
+                             unsigned long long *bmax, uint32_t *bid, double *bdiag,
+                             unsigned long long *vsel, double *cv, double *rv, double *piv,
+                             int32_t *gout, double *fout, uint32_t s, uint32_t *bad,
+                             hipStream_t stream);
 
 }  // namespace fc

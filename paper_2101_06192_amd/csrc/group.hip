@@ -395,31 +395,39 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(double *__restrict__ A,
 
 // gain[j] = |M e_j|^2 / M_jj for candidates (not taken, not the u* slot),
 // the chunk sums added in chunk order; per block, the largest candidate gain
-// as its binary64 bit pattern (0 with no candidate) in bmax[b] and the
-// smallest id of a candidate with that pattern and a gain >= 0 (none: all
-// ones, e.g. when the largest pattern is a NaN's) in bid[b].
+// as its binary64 bit pattern (0 with no candidate) in bmax[b], the smallest
+// id of a candidate with that pattern and a gain >= 0 (none: all ones, e.g.
+// when the largest pattern is a NaN's) in bid[b], and the sum of its diagonal
+// entries (in a fixed order) in bdiag[b].
 __global__ __launch_bounds__(kThreads) void gain_kernel(const double *__restrict__ A, uint32_t n,
                                                         uint32_t N, uint32_t chunks,
                                                         const double *__restrict__ part,
                                                         const uint8_t *__restrict__ taken,
                                                         unsigned long long *__restrict__ bmax,
-                                                        uint32_t *__restrict__ bid) {
+                                                        uint32_t *__restrict__ bid,
+                                                        double *__restrict__ bdiag) {
     __shared__ unsigned long long sk[kThreads];
     __shared__ uint32_t si[kThreads];
+    __shared__ double sd[kThreads];
     const uint32_t t = threadIdx.x, j = blockIdx.x * kThreads + t;
     unsigned long long key = 0ull;
     bool ok = false;
+    const double djj = j < n ? A[static_cast<size_t>(j) * N + j] : 0.0;
     if (j < n && !taken[j]) {
         double sum = 0.0;
         for (uint32_t c = 0; c < chunks; ++c) sum += part[static_cast<size_t>(c) * N + j];
-        const double g = sum / A[static_cast<size_t>(j) * N + j];
+        const double g = sum / djj;
         key = static_cast<unsigned long long>(__double_as_longlong(g));
         ok = g >= 0.0;
     }
     sk[t] = key;
+    sd[t] = djj;
     __syncthreads();
     for (uint32_t h = kThreads / 2; h > 0; h >>= 1) {
-        if (t < h) sk[t] = max(sk[t], sk[t + h]);
+        if (t < h) {
+            sk[t] = max(sk[t], sk[t + h]);
+            sd[t] += sd[t + h];
+        }
         __syncthreads();
     }
     const unsigned long long top = sk[0];
@@ -432,6 +440,7 @@ __global__ __launch_bounds__(kThreads) void gain_kernel(const double *__restrict
     if (t == 0) {
         bmax[blockIdx.x] = top;
         bid[blockIdx.x] = si[0];
+        bdiag[blockIdx.x] = sd[0];
     }
 }
 
@@ -469,13 +478,20 @@ __device__ uint32_t reduce_choice(const unsigned long long *__restrict__ bmax,
 // Column v of the chosen vertex (and its row) copied out before the downdate,
 // v reduced from the gain blocks; block 0 also does the step's bookkeeping:
 // taken[v] = 1, gout[s] = v, *piv = M[v][v], *vout = v for the downdate
-// (all ones and *bad = 1 when there is no candidate).
+// (all ones and *bad = 1 when there is no candidate), and, when fout is not
+// null, fout[s - 1] = the sum of the blocks' diagonal sums (f(S) of step s - 1).
 __global__ __launch_bounds__(kThreads) void choose_copy_kernel(
     const double *__restrict__ A, uint32_t n, uint32_t N, const unsigned long long *__restrict__ bmax,
-    const uint32_t *__restrict__ bid, uint32_t nb, uint8_t *__restrict__ taken, int32_t *gout,
-    uint32_t s, double *piv, unsigned long long *vout, uint32_t *bad, double *__restrict__ col,
-    double *__restrict__ row) {
+    const uint32_t *__restrict__ bid, const double *__restrict__ bdiag, uint32_t nb,
+    uint8_t *__restrict__ taken, int32_t *gout, uint32_t s, double *piv, unsigned long long *vout,
+    uint32_t *bad, double *__restrict__ fout, double *__restrict__ col, double *__restrict__ row) {
     const uint32_t v = reduce_choice(bmax, bid, nb, n);
+    if (fout && blockIdx.x == 0 && threadIdx.x == 0) {
+        // tr M before this step's downdate: f(S) after the previous step
+        double tr = 0.0;
+        for (uint32_t b = 0; b < nb; ++b) tr += bdiag[b];
+        fout[s - 1] = tr;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (v < n) {
             taken[v] = 1u;
@@ -623,16 +639,17 @@ hipError_t launch_group_colsq(double *A, uint32_t n, uint32_t N, uint32_t v, dou
 }
 
 hipError_t launch_group_step(double *A, uint32_t n, uint32_t N, double *part, uint8_t *taken,
-                             unsigned long long *bmax, uint32_t *bid, unsigned long long *vsel,
-                             double *cv, double *rv, double *piv, int32_t *gout, double *fout,
-                             uint32_t s, uint32_t *bad, hipStream_t stream) {
+                             unsigned long long *bmax, uint32_t *bid, double *bdiag,
+                             unsigned long long *vsel, double *cv, double *rv, double *piv,
+                             int32_t *gout, double *fout, uint32_t s, uint32_t *bad,
+                             hipStream_t stream) {
     const uint32_t nb = blocks_for(n);
-    gain_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, group_chunks(n), part, taken, bmax, bid);
-    choose_copy_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, bmax, bid, nb, taken, gout, s, piv, vsel,
-                                                    bad, cv, rv);
+    gain_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, group_chunks(n), part, taken, bmax, bid,
+                                             bdiag);
+    choose_copy_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, bmax, bid, bdiag, nb, taken, gout, s,
+                                                    piv, vsel, bad, fout, cv, rv);
     colsq_kernel<<<dim3(nb, group_chunks(n)), kThreads, 0, stream>>>(A, n, N, n, vsel, cv, rv, piv,
                                                                     part);
-    if (fout) trace_kernel<<<1, kThreads, 0, stream>>>(A, n, N, n, fout + s, nullptr);
     return hipGetLastError();
 }
 
