@@ -251,6 +251,28 @@ FC_API int fc_sample(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
                      uint64_t *visit_counts, uint64_t *tree_digests, uint64_t *tree_steps,
                      int32_t *parents, uint32_t *tree_visits, fc_stats *stats);
 
+/* fc_sample for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, trees and outputs as fc_sample, but every
+ * buffer the call needs beyond its inputs and outputs (vertex records,
+ * relabelled ids, per-tree state, lists, counters) is carved from one static
+ * device array of the library, 64 MiB per device, held from the first
+ * fc_create on that device until the process ends; the call itself never
+ * allocates or frees device memory.
+ *   g: device-resident graph (g->mem = FC_MEM_DEVICE, else FC_ERR_ARG).
+ *   Trees in flight shrink to what the array holds; a graph whose per-graph
+ *   buffers and one tree's state do not fit gets FC_ERR_NOMEM (the message
+ *   names the buffer and the limit) and nothing is written to the outputs.
+ *   No first-arrow pre-draw (option "predraw_mib" is ignored).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap in time on one device (two host threads, two
+ * streams) race and must be serialised by the caller. */
+FC_API int fc_sample_noalloc(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
+                             uint32_t tree_begin, uint32_t tree_count, uint32_t *root_counts,
+                             uint64_t *visit_counts, uint64_t *tree_digests,
+                             uint64_t *tree_steps, int32_t *parents, uint32_t *tree_visits,
+                             fc_stats *stats);
+
 /* Algorithm 1, ApproxDiagForestMatrix(G, alpha, eps, delta): samples tau trees
  * (tree ids 0..tau-1) and writes diag_out[v] (double[n]):
  *   FC_EST_DIRECT:       R[v] / tau, an unbiased estimate of Omega_vv

@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
             "fc_tau": (ctypes.c_int, [i64, i64, f64, f64, f64, ctypes.POINTER(u32)]),
             "fc_thresholds": (ctypes.c_int, [vp, f64, i32, vp]),
             "fc_sample": (ctypes.c_int, [vp, gp, pp, u32, u32, vp, vp, vp, vp, vp, vp, sp]),
+            "fc_sample_noalloc": (ctypes.c_int, [vp, gp, pp, u32, u32, vp, vp, vp, vp, vp, vp, sp]),
             "fc_diag_estimate": (ctypes.c_int, [vp, gp, pp, vp, vp, sp]),
             "fc_farness": (ctypes.c_int, [vp, gp, pp, vp, vp, vp, vp, sp]),
             "fc_solve": (ctypes.c_int, [vp, gp, f64, vp, vp, i32, f64, i32, i32, i32,
@@ -284,6 +285,28 @@ def sample(g, alpha: float, seed: int = 0, tree_begin: int = 0, tree_count: int 
            want_tree_visits: bool = False, trusted: bool = False, as_torch: bool = False,
            root_counts=None, sampler=None) -> dict:
     """Sample trees [tree_begin, tree_begin + tree_count) (fc_sample)."""
+    return _sample("fc_sample", g, alpha, seed, tree_begin, tree_count, stream_id, device,
+                   want_visits, want_digests, want_steps, want_parents, want_tree_visits,
+                   trusted, as_torch, root_counts, sampler)
+
+
+def sample_noalloc(g, alpha: float, seed: int = 0, tree_begin: int = 0, tree_count: int = 1,
+                   stream_id: int = 0, device="cuda:0", want_visits: bool = False,
+                   want_digests: bool = False, want_steps: bool = False,
+                   want_parents: bool = False, want_tree_visits: bool = False,
+                   trusted: bool = False, as_torch: bool = False, root_counts=None,
+                   sampler=None) -> dict:
+    """As ``sample``, through fc_sample_noalloc: the library allocates no device
+    memory for the call (its scratch is the library's static device array; the
+    graph must be device-resident)."""
+    return _sample("fc_sample_noalloc", g, alpha, seed, tree_begin, tree_count, stream_id,
+                   device, want_visits, want_digests, want_steps, want_parents,
+                   want_tree_visits, trusted, as_torch, root_counts, sampler)
+
+
+def _sample(entry, g, alpha, seed, tree_begin, tree_count, stream_id, device, want_visits,
+            want_digests, want_steps, want_parents, want_tree_visits, trusted, as_torch,
+            root_counts, sampler) -> dict:
     import torch
     ctx = context(device)
     n = int(g.n)
@@ -297,9 +320,9 @@ def sample(g, alpha: float, seed: int = 0, tree_begin: int = 0, tree_count: int 
     gs = _graph_struct(g)
     ps = _params(alpha, seed=seed, stream_id=stream_id, trusted=trusted, sampler=sampler)
     st = fc_stats()
-    ctx.check(lib().fc_sample(ctx.handle, ctypes.byref(gs), ctypes.byref(ps), int(tree_begin),
-                              int(tree_count), _ptr(R), _ptr(V), _ptr(D), _ptr(S), _ptr(P),
-                              _ptr(TV), ctypes.byref(st)))
+    ctx.check(getattr(lib(), entry)(ctx.handle, ctypes.byref(gs), ctypes.byref(ps),
+                                    int(tree_begin), int(tree_count), _ptr(R), _ptr(V), _ptr(D),
+                                    _ptr(S), _ptr(P), _ptr(TV), ctypes.byref(st)))
     res = {"stats": st.as_dict()}
     res["root_counts"] = _out(R[:n], as_torch)
     if not as_torch:

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "fc_internal.hpp"
@@ -24,6 +25,42 @@ static_assert(sizeof(fc_graph) == 48, "fc_graph layout");
 static_assert(sizeof(fc_params) == 56, "fc_params layout");
 static_assert(sizeof(fc_stats) == 136, "fc_stats layout");
 static_assert(sizeof(fc_job) == 88, "fc_job layout");
+
+// Device scratch of fc_sample_noalloc: one array per device, loaded with the
+// code object and held until the process ends.  Host code never uses the
+// array's name as an address (on the host it is only a stand-in); it uses the
+// device address that hipGetSymbolAddress returns, taken once per device when
+// a context is created on it.
+static constexpr size_t kStaticScratchBytes = static_cast<size_t>(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (current), looked up once.
+void *scratch_of(int device, hipError_t *err) {
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        } else {
+            g_scratch_ptr[device] = p;
+        }
+    }
+    *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
+}  // namespace
 
 namespace fc_host {
 
@@ -40,6 +77,19 @@ int hip_fail(fc_ctx *ctx, hipError_t e, const char *what) {
 int ensure(fc_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
     if (bytes == 0) bytes = 16;
     if (b.bytes >= bytes) return FC_OK;
+    if (ctx->arena) {  // carve, 256-byte aligned; a buffer that must grow gets a new range
+        const size_t off = (ctx->arena_off + 255u) & ~static_cast<size_t>(255u);
+        if (off > ctx->arena_size || bytes > ctx->arena_size - off)
+            return set_err(ctx, FC_ERR_NOMEM,
+                           std::string("the static scratch (") +
+                               std::to_string(ctx->arena_size >> 20) + " MiB) cannot hold " +
+                               what + " (" + std::to_string(bytes) + " bytes with " +
+                               std::to_string(off) + " already in use by this call)");
+        b.ptr = ctx->arena + off;
+        b.bytes = bytes;
+        ctx->arena_off = off + bytes;
+        return FC_OK;
+    }
     if (b.ptr) {
         (void)hipStreamSynchronize(ctx->stream);
         (void)hipFree(b.ptr);
@@ -55,6 +105,13 @@ int ensure(fc_ctx *ctx, DevBuf &b, size_t bytes, const char *what) {
     }
     b.bytes = bytes;
     return FC_OK;
+}
+
+size_t state_budget_now(const fc_ctx *ctx) {
+    if (!ctx->arena) return ctx->state_budget;
+    // what is left, less the alignment of the per-slot buffers still to carve
+    const size_t used = ctx->arena_off + 8u * 256u;
+    return used < ctx->arena_size ? ctx->arena_size - used : 0u;
 }
 
 uint32_t env_u32(const char *name, uint32_t dflt) {
@@ -334,7 +391,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                                                 static_cast<fc::VRec *>(ctx->rl_vrec.ptr), ctx->stream),
                    "relabel records");
             const size_t per_slot = (8u + 4u + 8u + 24u + 4u) * n + 8u;
-            slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+            slots = std::max<size_t>(1, state_budget_now(ctx) / per_slot);
             slots = std::min<size_t>(slots, tree_count);
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
             const int fit = fc::hyb_max_active(lds_threads, lds_words, weighted);
@@ -415,7 +472,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                                                 static_cast<fc::VRec *>(ctx->rl_vrec.ptr), ctx->stream),
                    "relabel records");
             const size_t per_slot = (8u + 24u + 4u) * n + 8u;
-            slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+            slots = std::max<size_t>(1, state_budget_now(ctx) / per_slot);
             slots = std::min<size_t>(slots, tree_count);
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
             uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
@@ -494,7 +551,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
                   2 * fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) + 1024u <= ctx->max_lds;
         const size_t per_slot = (wbytes + 8u + 24u + 4u) * static_cast<size_t>(g.n) + 8u +
                                 (lds_bits ? 0u : 4u * nwords);
-        slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+        slots = std::max<size_t>(1, state_budget_now(ctx) / per_slot);
         slots = std::min<size_t>(slots, tree_count);
         // persistent workgroups: as many as requested per CU, but never more
         // than fit at once (a workgroup that starts late finds the queue empty)
@@ -560,7 +617,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     } else if (!use_coop) {
         // trees in flight: bounded by the tree count and by the state budget
         const size_t per_slot = sizeof(uint64_t) * static_cast<size_t>(g.n);
-        slots = std::max<size_t>(1, ctx->state_budget / per_slot);
+        slots = std::max<size_t>(1, state_budget_now(ctx) / per_slot);
         slots = std::min<size_t>(slots, tree_count);
         if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
         if ((rc = ensure(ctx, ctx->state, per_slot * slots, "per-tree state"))) return rc;
@@ -722,6 +779,12 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     if (hipSetDevice(hip_device) != hipSuccess) return FC_ERR_HIP;
     fc_ctx *ctx = new fc_ctx();
     ctx->device = hip_device;
+    {
+        // the static scratch of fc_sample_noalloc on this device (a failure here
+        // only disables that entry point; it reports the error)
+        hipError_t se = hipSuccess;
+        (void)scratch_of(hip_device, &se);
+    }
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
         hipEventCreate(&ctx->evm) != hipSuccess ||
@@ -913,6 +976,70 @@ int fc_sample(fc_ctx *ctx, const fc_graph *g, const fc_params *params, uint32_t 
                      tree_digests, tree_steps, parents, tree_visits, stats);
     if (stats) stats->ms_total = now_ms() - t0;
     return rc;
+}
+
+int fc_sample_noalloc(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
+                      uint32_t tree_begin, uint32_t tree_count, uint32_t *root_counts,
+                      uint64_t *visit_counts, uint64_t *tree_digests, uint64_t *tree_steps,
+                      int32_t *parents, uint32_t *tree_visits, fc_stats *stats) {
+    const double t0 = now_ms();
+    int rc = begin(ctx);
+    if (rc) return rc;
+    if ((rc = check_params(ctx, params))) return rc;
+    if ((rc = check_graph_args(ctx, g))) return rc;
+    if (g->mem != FC_MEM_DEVICE)
+        return set_err(ctx, FC_ERR_ARG, "fc_sample_noalloc needs a device-resident graph");
+    if (!root_counts && g->n > 0) return set_err(ctx, FC_ERR_ARG, "root_counts is NULL");
+    if (static_cast<uint64_t>(tree_begin) + tree_count > 0x100000000ull)
+        return set_err(ctx, FC_ERR_ARG, "tree ids must stay below 2^32");
+    hipError_t se = hipSuccess;
+    void *base = scratch_of(ctx->device, &se);
+    if (!base)
+        return set_err(ctx, FC_ERR_HIP, std::string("no static scratch on this device: ") +
+                                             hipGetErrorString(se));
+    // The call runs the ordinary sampling path on a shadow of the context whose
+    // buffers all come from the static scratch (ensure() carves them and never
+    // allocates); the shadow shares the context's stream, events and options.
+    fc_ctx sh;
+    sh.device = ctx->device;
+    sh.stream = ctx->stream;
+    sh.ev0 = ctx->ev0;
+    sh.ev1 = ctx->ev1;
+    sh.evm = ctx->evm;
+    sh.lanes_per_wave = ctx->lanes_per_wave;
+    sh.max_slots = ctx->max_slots;
+    sh.cu_count = ctx->cu_count;
+    sh.max_lds = ctx->max_lds;
+    sh.coop_threads = ctx->coop_threads;
+    sh.coop_wg_per_cu = ctx->coop_wg_per_cu;
+    sh.force_sampler = ctx->force_sampler;
+    sh.coop_lds_bits = ctx->coop_lds_bits;
+    sh.coop_word32 = ctx->coop_word32;
+    sh.coop_in_bits = ctx->coop_in_bits;
+    sh.phase_timing = ctx->phase_timing;
+    sh.max_draws = ctx->max_draws;
+    sh.hyb_hot_cap = ctx->hyb_hot_cap;
+    sh.coop_lds_counts = ctx->coop_lds_counts;
+    sh.lds_threads = ctx->lds_threads;
+    sh.lds_wg_per_cu = ctx->lds_wg_per_cu;
+    sh.predraw_mib = 0;  // every tree draws its own first arrows: no per-call pre-draw array
+    sh.kendall_pairs = ctx->kendall_pairs;
+    sh.lds_repop = ctx->lds_repop;
+    sh.coop_repop = ctx->coop_repop;
+    sh.wall_khz = ctx->wall_khz;
+    sh.arena = static_cast<char *>(base);
+    sh.arena_size = kStaticScratchBytes;
+    sh.arena_off = 0;
+    GraphView gv;
+    if ((rc = ensure(&sh, sh.small, sizeof(Small), "counters")) ||
+        (rc = prepare_graph(&sh, g, params->flags & FC_FLAG_TRUSTED_GRAPH, &gv)) ||
+        (rc = run_sampler(&sh, gv, params, tree_begin, tree_count, root_counts, visit_counts,
+                          tree_digests, tree_steps, parents, tree_visits, stats))) {
+        ctx->last_error = "fc_sample_noalloc: " + sh.last_error;
+        return rc;
+    }
+    if (stats) stats->ms_total = now_ms() - t0;
+    return FC_OK;
 }
 
 static int estimate_common(fc_ctx *ctx, const fc_graph *g, const fc_params *params,

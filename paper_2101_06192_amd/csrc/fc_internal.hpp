@@ -63,6 +63,10 @@ struct fc_ctx {
     uint32_t lds_repop = 2;       // re-formed 2-cycle pops: 0 never, 1 weighted graphs, 2 always
     uint32_t coop_repop = 2;      // the same for the global-counter sampler
     double wall_khz = 100000.0;   // device wall clock rate
+    // Arena mode (fc_sample_noalloc): every buffer of one call is carved from
+    // this device range instead of being allocated; null in ordinary contexts.
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_off = 0;
 };
 
 
@@ -82,8 +86,12 @@ constexpr uint32_t kPredrawMinVertices = 16384;
 
 int set_err(fc_ctx *ctx, int code, const std::string &msg);
 int hip_fail(fc_ctx *ctx, hipError_t e, const char *what);
-// Grow-only device buffer: (re)allocates when `bytes` exceeds its size.
+// Grow-only device buffer: (re)allocates when `bytes` exceeds its size; in
+// arena mode carves it from the context's arena instead (never allocates).
 int ensure(fc_ctx *ctx, DevBuf &b, size_t bytes, const char *what);
+// Bytes of per-tree state the sampler may use now: the context's budget, or
+// in arena mode what is left of the arena.
+size_t state_budget_now(const fc_ctx *ctx);
 uint32_t env_u32(const char *name, uint32_t dflt);
 bool valid_alpha(double a);
 
