@@ -143,7 +143,7 @@ def main():
     import torch
 
     import paper_2101_06192_amd as fc
-    from paper_2101_06192_amd import inputs
+    import inputs
 
     dev = torch.device("cuda:0")
     if args.lds_repop is not None:

@@ -101,10 +101,16 @@ extern "C" {
 #define FC_FLAG_SAMPLER_HYB 32  /* force the hybrid workgroup-per-tree sampler: counters and
                                    settled bits of the highest-degree vertices in LDS, the
                                    rest in global memory */
+#define FC_FLAG_SAMPLER_TILE 64 /* force the tile sampler: the tree's cycles are popped tile by
+                                   tile (tiles of consecutive ids, counters in LDS), the
+                                   cycles that cross tiles through the graph of the vertices
+                                   whose arrow leaves their tile */
 /* No sampler flag: a workgroup-per-tree sampler, with LDS counters whenever
- * one tree's counters and settled bitmap fit; else with global counters when
- * the settled bitmap alone fits in LDS; else the hybrid (option
- * "coop_lds_counts" = 0: global counters throughout).  The lane sampler runs
+ * one tree's counters and settled bitmap fit; else the tile sampler when at
+ * most a tenth of the CSR entries join ids of different tiles (option
+ * "tile_cross_permille"); else with global counters when the settled bitmap
+ * alone fits in LDS; else the hybrid (option "coop_lds_counts" = 0: global
+ * counters throughout).  The lane sampler runs
  * only on request.  All samplers produce identical results (same trees, same
  * counts). */
 
@@ -217,6 +223,15 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "coop_repop"      the same for the global-counter sampler (graphs whose counters do
  *                     not fit LDS), with an LDS filter that flags the re-popped
  *                     vertices; 0 never, 1 weighted graphs only, 2 always (the default)
+ *   "tile_size"       tile sampler: vertices per tile, a multiple of 64 up to 32704 (0, the
+ *                     default: the widest tile whose LDS arrays fit)
+ *   "tile_cross_permille"  the tile sampler is picked automatically when at most this many
+ *                     CSR entries per thousand join ids of different tiles (default 100)
+ *   "tile_threads"    threads per workgroup of the tile sampler (64..1024, multiple of 64;
+ *                     default 1024)
+ *   "tile_repop"      the tile sampler pops a 2-cycle that a round's new arrows close again
+ *                     within that round, inside the tile: 0 never, 1 weighted graphs only,
+ *                     2 always (the default)
  *   "kendall_pairs"   1: fc_kendall_tau compares all n(n-1)/2 pairs (tiled) instead of
  *                     counting discordant pairs by a merge sort (0, the default); same
  *                     counts, O(n^2) instead of O(n log^2 n) work

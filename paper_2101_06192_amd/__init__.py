@@ -39,8 +39,9 @@ FC_FLAG_SAMPLER_LANE = 2
 FC_FLAG_SAMPLER_COOP = 4
 FC_FLAG_SAMPLER_LDS = 16
 FC_FLAG_SAMPLER_HYB = 32
+FC_FLAG_SAMPLER_TILE = 64
 SAMPLERS = {None: 0, "auto": 0, "lane": FC_FLAG_SAMPLER_LANE, "coop": FC_FLAG_SAMPLER_COOP,
-            "lds": FC_FLAG_SAMPLER_LDS, "hyb": FC_FLAG_SAMPLER_HYB}
+            "lds": FC_FLAG_SAMPLER_LDS, "hyb": FC_FLAG_SAMPLER_HYB, "tile": FC_FLAG_SAMPLER_TILE}
 
 
 class FCError(RuntimeError):

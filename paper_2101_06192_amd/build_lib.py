@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["graph_prep.hip", "relabel.hip", "wilson_lane.hip", "wilson_coop.hip", "wilson_lds.hip", "wilson_hyb.hip", "finalize.hip", "cg.hip", "probe.hip", "rank.hip", "group.hip",
+SOURCES = ["graph_prep.hip", "relabel.hip", "wilson_lane.hip", "wilson_coop.hip", "wilson_lds.hip", "wilson_hyb.hip", "wilson_tile.hip", "finalize.hip", "cg.hip", "probe.hip", "rank.hip", "group.hip",
            "fc_api.cpp", "fc_batch.cpp", "fc_solve.cpp", "fc_rank.cpp", "fc_group.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -281,6 +281,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     else if (p->flags & FC_FLAG_SAMPLER_COOP) mode = 2;
     else if (p->flags & FC_FLAG_SAMPLER_LDS) mode = 3;
     else if (p->flags & FC_FLAG_SAMPLER_HYB) mode = 4;
+    else if (p->flags & FC_FLAG_SAMPLER_TILE) mode = 5;
     else mode = ctx->force_sampler;
     // automatically always a workgroup sampler: measured, the LDS-counter one beats
     // the lane-per-tree walk even with 2^18 trees of a 1000-vertex graph
@@ -297,7 +298,9 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::CoopArgs c{};
     bool lds_bits = false, in_bits = false, word32 = false;
     uint32_t repop_words = 0;  // global-counter sampler: re-pop filter words (0: off)
-    bool use_lds = false, use_hyb = false;
+    bool use_lds = false, use_hyb = false, use_tile = false;
+    fc::TileArgs ta{};
+    uint32_t tile_threads = 1024;
     uint32_t lds_words = 0, lds_threads = 1024, hot = 0;
     uint32_t tshift = 32;
     unsigned int dmax = 0;
@@ -335,12 +338,45 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         if (mode == 3 && !use_lds)
             return set_err(ctx, FC_ERR_UNSUPPORTED,
                            "the in-arrow counters of one tree do not fit in LDS");
+        // tile sampler: when the LDS-counter variant does not fit and most edges join
+        // ids of the same tile (graphs with local ids: grids, road networks)
+        if (!use_lds && (mode == 5 || (mode == 0 && ctx->coop_lds_counts)) && g.n >= 1) {
+            uint32_t B = ctx->tile_size;
+            if (B == 0) {  // the widest tile whose arrays fit in LDS
+                B = fc::kTileMax;
+                while (B > 64u && fc::tile_lds_bytes(B) + kLdsStaticBytes > ctx->max_lds) B -= 64u;
+            }
+            const uint32_t ntiles = static_cast<uint32_t>((static_cast<uint64_t>(g.n) + B - 1u) / B);
+            bool fits = fc::tile_lds_bytes(B) + kLdsStaticBytes <= ctx->max_lds;
+            bool local = mode == 5;
+            if (fits && !local && g.nnz > 0) {
+                FC_HIP(ctx, hipMemsetAsync(&sm->sum, 0, sizeof(unsigned long long), ctx->stream),
+                       "memset cross count");
+                FC_HIP(ctx, fc::launch_count_cross(g.row_ptr, g.col_idx, static_cast<uint32_t>(g.n),
+                                                   B, &sm->sum, ctx->stream),
+                       "count_cross");
+                unsigned long long cross = 0;
+                FC_HIP(ctx, hipMemcpyAsync(&cross, &sm->sum, sizeof(cross), hipMemcpyDeviceToHost,
+                                           ctx->stream), "copy cross count");
+                FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "count_cross");
+                local = static_cast<double>(cross) * 1000.0 <=
+                        static_cast<double>(ctx->tile_cross_permille) * static_cast<double>(g.nnz);
+            }
+            if (mode == 5 && !fits)
+                return set_err(ctx, FC_ERR_UNSUPPORTED, "the tile sampler's tile does not fit in LDS");
+            if (fits && local) {
+                use_tile = true;
+                ta.B = B;
+                ta.Bp = (B + 63u) & ~63u;
+                ta.ntiles = ntiles;
+            }
+        }
         // hybrid variant: the widest-class (highest-degree) prefix of the ids in LDS.
         // Automatically only where the global-counter variant cannot keep its
         // settled bitmap in LDS either (beyond that size the hybrid wins).
         const bool coop_bits_fit = fc::coop_lds_bytes(static_cast<uint32_t>(g.n)) + 1024u <= ctx->max_lds;
-        if (!use_lds && (mode == 4 || (mode == 0 && ctx->coop_lds_counts && !coop_bits_fit)) &&
-            g.n >= 1) {
+        if (!use_lds && !use_tile &&
+            (mode == 4 || (mode == 0 && ctx->coop_lds_counts && !coop_bits_fit)) && g.n >= 1) {
             if ((rc = ensure(ctx, ctx->rl_blk, 4u * fc::kRelabelClasses * nb, "class counts")) ||
                 (rc = ensure(ctx, ctx->rl_base, 4u * fc::kRelabelClasses * nb, "class offsets")))
                 return rc;
@@ -539,7 +575,85 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             c.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
         }
     }
-    if (use_coop && !use_lds && !use_hyb) {
+    size_t tile_lds = 0;
+    if (use_tile) {
+        kname = "wilson_tile";
+        const size_t n = static_cast<size_t>(g.n);
+        const size_t bw = (n + 31u) >> 5;
+        tile_threads = ctx->tile_threads;
+        // the exit and settled bitmaps share the tiles' LDS when n bits fit
+        const bool bits_lds = 4u * bw + kLdsStaticBytes <= ctx->max_lds;
+        tile_lds = std::max(fc::tile_lds_bytes(ta.B), bits_lds ? 4u * bw : 0u);
+        const int fit = fc::tile_max_active(tile_threads, tile_lds, weighted);
+        // first arrows of all trees drawn ahead when their targets fit the budget
+        const size_t pre_bytes = 4u * n * static_cast<size_t>(tree_count);
+        bool predraw = ctx->predraw_mib != 0 &&
+                       pre_bytes <= (static_cast<size_t>(ctx->predraw_mib) << 20);
+        if (predraw && ensure(ctx, ctx->cpre, pre_bytes, "pre-drawn targets") != FC_OK) {
+            predraw = false;
+            ctx->last_error.clear();
+        }
+        const size_t per_slot = (predraw ? 0u : 4u * n) + 8u * n + 2u * n + 4u * n * 3u + 12u * n +
+                                4u * (n + 2u) + 4u * ta.ntiles + (bits_lds ? 4u : 8u) * bw +
+                                10u * 256u;
+        slots = std::max<size_t>(1, state_budget_now(ctx) / per_slot);
+        slots = std::min<size_t>(slots, tree_count);
+        const uint32_t per_cu = fit > 0 ? static_cast<uint32_t>(fit) : 1u;
+        slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
+        if (ctx->max_slots) slots = std::min<size_t>(slots, ctx->max_slots);
+        if ((!predraw && (rc = ensure(ctx, ctx->cword, 4u * n * slots, "tree targets"))) ||
+            (rc = ensure(ctx, ctx->ckk, 8u * n * slots, "draw counts")) ||
+            (rc = ensure(ctx, ctx->t_ex, 2u * n * slots, "exits")) ||
+            (rc = ensure(ctx, ctx->t_exl, 4u * n * slots, "exit lists")) ||
+            (rc = ensure(ctx, ctx->t_pc, 4u * n * slots, "in-counts")) ||
+            (rc = ensure(ctx, ctx->t_sc, 4u * n * slots, "exit successors")) ||
+            (rc = ensure(ctx, ctx->t_ecnt, 4u * ta.ntiles * slots, "tile exit counts")) ||
+            (rc = ensure(ctx, ctx->t_bl, 12u * n * slots, "lists")) ||
+            (rc = ensure(ctx, ctx->clevels, 4u * (n + 2u) * slots, "levels")) ||
+            (rc = ensure(ctx, ctx->cbits, 4u * bw * slots, "settled bitmap")) ||
+            (!bits_lds && (rc = ensure(ctx, ctx->t_xb, 4u * bw * slots, "exit bitmap"))))
+            return rc;
+        FC_HIP(ctx, hipMemsetAsync(ctx->ckk.ptr, 0, 8u * n * slots, ctx->stream), "memset draw counts");
+        FC_HIP(ctx, hipMemsetAsync(ctx->t_pc.ptr, 0, 4u * n * slots, ctx->stream), "memset in-counts");
+        ta.vrec = vrec;
+        ta.col_idx = g.col_idx;
+        ta.wsum = wsum;
+        ta.wthr = wthr;
+        ta.n = static_cast<uint32_t>(g.n);
+        ta.tree_begin = tree_begin;
+        ta.tree_count = tree_count;
+        ta.stream_id = p->stream_id;
+        ta.key0 = static_cast<uint32_t>(p->seed);
+        ta.key1 = static_cast<uint32_t>(p->seed >> 32);
+        ta.slots = static_cast<uint32_t>(slots);
+        ta.k_limit = ctx->max_draws ? ctx->max_draws : 0x7FFFFFFFu;
+        ta.max_rounds = 0x40000000u;
+        ta.step_cap = step_cap;
+        ta.pre = predraw ? static_cast<uint32_t *>(ctx->cpre.ptr) : nullptr;
+        ta.tw = predraw ? nullptr : static_cast<uint32_t *>(ctx->cword.ptr);
+        ta.kk = static_cast<uint64_t *>(ctx->ckk.ptr);
+        ta.ex = static_cast<uint16_t *>(ctx->t_ex.ptr);
+        ta.exl = static_cast<uint32_t *>(ctx->t_exl.ptr);
+        ta.ecnt = static_cast<uint32_t *>(ctx->t_ecnt.ptr);
+        ta.pc = static_cast<uint32_t *>(ctx->t_pc.ptr);
+        ta.sc = static_cast<uint32_t *>(ctx->t_sc.ptr);
+        ta.bl = static_cast<uint32_t *>(ctx->t_bl.ptr);
+        ta.lv = static_cast<uint32_t *>(ctx->clevels.ptr);
+        ta.bits = static_cast<uint32_t *>(ctx->cbits.ptr);
+        ta.xb = bits_lds ? nullptr : static_cast<uint32_t *>(ctx->t_xb.ptr);
+        ta.bits_lds = bits_lds ? 1u : 0u;
+        ta.repop = (ctx->tile_repop == 2 || (ctx->tile_repop == 1 && weighted)) ? 1u : 0u;
+        ta.queue = &sm->queue;
+        ta.totals = &sm->totals;
+        ta.phase_ticks = ctx->phase_timing ? sm->phase_ticks : nullptr;
+        ta.root_counts = root_counts;
+        ta.visit_counts = reinterpret_cast<unsigned long long *>(visit_counts);
+        ta.tree_digests = reinterpret_cast<unsigned long long *>(tree_digests);
+        ta.tree_steps = reinterpret_cast<unsigned long long *>(tree_steps);
+        ta.parents = parents;
+        ta.tree_visits = tree_visits;
+    }
+    if (use_coop && !use_lds && !use_hyb && !use_tile) {
         // 32-bit tree words when target and in-arrow count both fit (the count of
         // a vertex never exceeds its degree)
         word_layout(static_cast<uint32_t>(g.n), dmax, ctx->coop_word32, &tshift, &word32);
@@ -648,7 +762,14 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     }
 
     FC_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
-    if (use_hyb) {
+    if (use_tile) {
+        if (ta.pre) {
+            FC_HIP(ctx, fc::launch_tile_predraw(ta, ctx->stream), "tile_predraw launch");
+            FC_HIP(ctx, hipEventRecord(ctx->evm, ctx->stream), "event");
+        }
+        FC_HIP(ctx, fc::launch_wilson_tile(ta, tile_threads, tile_lds, ctx->stream),
+               "wilson_tile launch");
+    } else if (use_hyb) {
         FC_HIP(ctx, fc::launch_wilson_hyb(c, lds_threads, lds_words, ctx->stream),
                "wilson_hyb launch");
     } else if (use_lds) {
@@ -687,13 +808,13 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         stats->digest_sum = tot.digest_sum;
         stats->ms_sample = ms;
         stats->ms_predraw = 0.0;
-        if (use_lds && c.pre) {
+        if ((use_lds && c.pre) || (use_tile && ta.pre)) {
             float pm = 0.f;
             (void)hipEventElapsedTime(&pm, ctx->ev0, ctx->evm);
             stats->ms_predraw = pm;
         }
         for (int i = 0; i < 8; ++i) stats->phase_ms[i] = 0.0;
-        if (use_coop && ctx->phase_timing) {
+        if ((use_coop || use_tile) && ctx->phase_timing) {
             unsigned long long ticks[8];
             FC_HIP(ctx, hipMemcpy(ticks, sm->phase_ticks, sizeof(ticks), hipMemcpyDeviceToHost),
                    "copy phase ticks");
@@ -815,7 +936,8 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
     // each launch passes what it uses
     if (fc::coop_set_lds_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess ||
         fc::lds_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess ||
-        fc::hyb_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess) {
+        fc::hyb_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess ||
+        fc::tile_set_limit(ctx->max_lds - kLdsStaticBytes) != hipSuccess) {
         (void)hipGetLastError();
         fc_destroy(ctx);
         return FC_ERR_HIP;
@@ -835,6 +957,7 @@ int fc_create(fc_ctx **out, int hip_device, void *hip_stream) {
         if (fs && !std::strcmp(fs, "coop")) ctx->force_sampler = 2;
         if (fs && !std::strcmp(fs, "lds")) ctx->force_sampler = 3;
         if (fs && !std::strcmp(fs, "hyb")) ctx->force_sampler = 4;
+        if (fs && !std::strcmp(fs, "tile")) ctx->force_sampler = 5;
     }
     *out = ctx;
     return FC_OK;
@@ -853,7 +976,8 @@ int fc_destroy(fc_ctx *ctx) {
                       &ctx->iso, &ctx->corigt, &ctx->cpre, &ctx->weights, &ctx->wsum, &ctx->wthr,
                       &ctx->s_wdeg, &ctx->rk_key0, &ctx->rk_key1, &ctx->rk_val0, &ctx->rk_val1,
                       &ctx->rk_hist, &ctx->rk_thist, &ctx->rk_ra, &ctx->rk_rb, &ctx->rk_s, &ctx->g_mat,
-                      &ctx->g_vec, &ctx->g_part, &ctx->g_taken, &ctx->g_scr})
+                      &ctx->g_vec, &ctx->g_part, &ctx->g_taken, &ctx->g_scr, &ctx->t_ex, &ctx->t_exl,
+                      &ctx->t_ecnt, &ctx->t_pc, &ctx->t_sc, &ctx->t_bl, &ctx->t_xb})
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -922,6 +1046,19 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "max_slots") {
         if (value < 0 || value > 0x7FFFFFFF) return set_err(ctx, FC_ERR_ARG, "max_slots");
         ctx->max_slots = static_cast<uint32_t>(value);
+    } else if (k == "tile_size") {
+        if (value < 0 || value > fc::kTileMax || value % 64)
+            return set_err(ctx, FC_ERR_ARG, "tile_size must be 0 or a multiple of 64 up to 32704");
+        ctx->tile_size = static_cast<uint32_t>(value);
+    } else if (k == "tile_cross_permille") {
+        if (value < 0 || value > 1000) return set_err(ctx, FC_ERR_ARG, "tile_cross_permille");
+        ctx->tile_cross_permille = static_cast<uint32_t>(value);
+    } else if (k == "tile_repop") {
+        if (value < 0 || value > 2) return set_err(ctx, FC_ERR_ARG, "tile_repop must be 0, 1 or 2");
+        ctx->tile_repop = static_cast<uint32_t>(value);
+    } else if (k == "tile_threads") {
+        if (value < 64 || value > 1024 || value % 64) return set_err(ctx, FC_ERR_ARG, "tile_threads");
+        ctx->tile_threads = static_cast<uint32_t>(value);
     } else {
         return set_err(ctx, FC_ERR_ARG, "unknown option " + k);
     }
@@ -1026,6 +1163,10 @@ int fc_sample_noalloc(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
     sh.kendall_pairs = ctx->kendall_pairs;
     sh.lds_repop = ctx->lds_repop;
     sh.coop_repop = ctx->coop_repop;
+    sh.tile_size = ctx->tile_size;
+    sh.tile_cross_permille = ctx->tile_cross_permille;
+    sh.tile_threads = ctx->tile_threads;
+    sh.tile_repop = ctx->tile_repop;
     sh.wall_khz = ctx->wall_khz;
     sh.arena = static_cast<char *>(base);
     sh.arena_size = kStaticScratchBytes;

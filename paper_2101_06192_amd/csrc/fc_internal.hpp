@@ -40,6 +40,7 @@ struct fc_ctx {
                                  // step thresholds
     DevBuf rk_key0, rk_key1, rk_val0, rk_val1, rk_hist, rk_thist, rk_ra, rk_rb, rk_s;  // ranking
     DevBuf g_mat, g_vec, g_part, g_taken, g_scr;  // group closeness: matrix, vectors, sums, flags, scratch
+    DevBuf t_ex, t_exl, t_ecnt, t_pc, t_sc, t_bl, t_xb;  // tile sampler (exits, counts, lists)
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
     size_t state_budget = 0;      // bytes of per-tree state the sampler may use
     uint32_t lanes_per_wave = 64; // active lanes per wave in the lane sampler
@@ -62,6 +63,11 @@ struct fc_ctx {
     bool kendall_pairs = false;   // Kendall's tau by all pairs instead of merge-sort counts
     uint32_t lds_repop = 2;       // re-formed 2-cycle pops: 0 never, 1 weighted graphs, 2 always
     uint32_t coop_repop = 2;      // the same for the global-counter sampler
+    uint32_t tile_size = 0;       // tile sampler: vertices per tile (0: the widest that fits LDS)
+    uint32_t tile_cross_permille = 100;  // picked automatically when at most this share (per
+                                         // mille) of the CSR entries cross tiles
+    uint32_t tile_threads = 1024; // threads per workgroup of the tile sampler
+    uint32_t tile_repop = 2;      // tile sampler's re-formed 2-cycle pops: 0 never, 1 weighted, 2 always
     double wall_khz = 100000.0;   // device wall clock rate
     // Arena mode (fc_sample_noalloc): every buffer of one call is carved from
     // this device range instead of being allocated; null in ordinary contexts.

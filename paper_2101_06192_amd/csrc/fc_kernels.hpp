@@ -222,6 +222,62 @@ hipError_t launch_relabel_graph(const int32_t *row_ptr, const int32_t *col_idx, 
 hipError_t launch_relabel_vrec(const VRec *vrec, const uint32_t *inv, uint32_t n, VRec *vrec_r,
                                hipStream_t stream);
 
+// Tile sampler (graphs whose ids are local): one workgroup per tree pops the
+// cycles inside each tile of B consecutive ids with LDS counters, finds the
+// cycles that cross tiles on the functional graph of the exit vertices, and
+// finishes the few vertices whose exit does not reach u* with global counters.
+constexpr uint32_t kTileMax = 32704;  // largest tile: local ids and codes fit 15 bits
+struct TileArgs {
+    const VRec *vrec;          // records of G* (original ids)
+    const int32_t *col_idx;
+    const double *wsum;        // running weight sums per CSR entry (weighted graph), or null
+    const uint32_t *wthr;      // step thresholds per CSR entry (with wsum)
+    uint32_t n;
+    uint32_t B;                // tile size (vertices), 1..kTileMax
+    uint32_t Bp;               // B rounded up to a multiple of 64
+    uint32_t ntiles;           // ceil(n / B)
+    uint32_t tree_begin, tree_count, stream_id, key0, key1;
+    uint32_t slots;            // workgroups (trees in flight)
+    uint32_t k_limit;          // largest per-vertex draw count in one tree
+    uint32_t max_rounds;       // bound on popping rounds per tile and in the residual
+    unsigned long long step_cap;  // per-tree bound on draws
+    uint32_t *pre;             // tree_count * n first-arrow targets drawn ahead, or null
+    uint32_t *tw;              // slots * n targets (when pre is null)
+    uint64_t *kk;              // slots * n (epoch << 32) | draws; zeroed per launch
+    uint16_t *ex;              // slots * n tile-local exit, or 0x7FFF (reaches u* in the tile)
+    uint32_t *exl;             // slots * n per-tile exit lists (tile * B offsets)
+    uint32_t *ecnt;            // slots * ntiles exits per tile
+    uint32_t *pc;              // slots * n in-counts; zeroed per launch
+    uint32_t *sc;              // slots * n exit-graph successors
+    uint32_t *bl;              // slots * 3 n lists
+    uint32_t *lv;              // slots * (n + 2) peel level bounds
+    uint32_t *bits;            // slots * ceil(n / 32) settled bitmap (residual rounds)
+    uint32_t *xb;              // slots * ceil(n / 32) exits that reach u*, or null: in LDS
+    uint32_t bits_lds;         // 1: the residual rounds use a copy of bits in LDS
+    uint32_t repop;            // 1: pop re-formed 2-cycles within the tile round that re-forms them
+    unsigned int *queue;
+    Totals *totals;
+    unsigned long long *phase_ticks;  // 8 tick sums: tile loads, counts, peels, pops, exits,
+                                      // exit graph, residual, output
+    uint32_t *root_counts;
+    unsigned long long *visit_counts;
+    unsigned long long *tree_digests;
+    unsigned long long *tree_steps;
+    int32_t *parents;
+    uint32_t *tree_visits;
+};
+// lds: dynamic LDS bytes, at least tile_lds_bytes(B) and, with xb null or
+// bits_lds set, a bitmap of n bits (4 ceil(n / 32)).
+hipError_t launch_wilson_tile(const TileArgs &a, uint32_t threads, size_t lds, hipStream_t stream);
+// First arrow of every vertex in every tree of the call: a.pre[item * n + v].
+hipError_t launch_tile_predraw(const TileArgs &a, hipStream_t stream);
+hipError_t tile_set_limit(size_t bytes);
+int tile_max_active(uint32_t threads, size_t lds, bool weighted);
+size_t tile_lds_bytes(uint32_t B);  // LDS of one tile's arrays
+// *out += CSR entries whose ends lie in different tiles of B ids.
+hipError_t launch_count_cross(const int32_t *row_ptr, const int32_t *col_idx, uint32_t n,
+                              uint32_t B, unsigned long long *out, hipStream_t stream);
+
 // p[0..count) = value (a kernel, so that it can sit in a captured HIP graph).
 hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long value,
                            hipStream_t stream);

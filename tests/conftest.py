@@ -18,7 +18,7 @@ def _ensure_built():
     point compiles everything; tests just load what exists)."""
     need = [
         os.path.join(ROOT, "oracle", "liboracle.so"),
-        os.path.join(ROOT, "paper_2101_06192_amd", "inputs", "libgraphgen.so"),
+        os.path.join(ROOT, "inputs", "libgraphgen.so"),
         os.path.join(ROOT, "paper_2101_06192_amd", "libfc.so"),
     ]
     if not all(os.path.exists(p) for p in need):

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 pytestmark = pytest.mark.gpu
 

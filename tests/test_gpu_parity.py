@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -22,7 +22,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-SAMPLERS = ["lane", "coop", "lds", "hyb"]
+SAMPLERS = ["lane", "coop", "lds", "hyb", "tile"]
 
 
 def _compare(fc, g, alpha, seed, t0, count, stream=0, per_tree=True, sampler="lane"):
@@ -228,16 +228,24 @@ def test_draw_limit_reports_overflow(gpu_lib, sampler):
 
 def test_lds_sampler_rejects_graphs_too_large_and_auto_falls_back(gpu_lib):
     """10^6 vertices need at least 610 KiB of 4-bit counters: forcing the
-    LDS-counter sampler fails cleanly, the automatic choice uses global
-    counters."""
+    LDS-counter sampler fails cleanly; the automatic choice is the tile
+    sampler (the grid's row-major ids keep 98% of the edges inside a tile),
+    or global counters when no share of crossing edges is accepted."""
     fc = gpu_lib
     g = inputs.grid_removed(1000, 1000, 0.12, 0)
     with pytest.raises(fc.FCError) as e:
         fc.sample(g, alpha=1.0, seed=0, tree_begin=0, tree_count=2, sampler="lds")
     assert e.value.code == fc.FC_ERR_UNSUPPORTED
-    got = fc.sample(g, alpha=1.0, seed=0, tree_begin=0, tree_count=2, want_digests=True)
-    assert got["stats"]["sampler"] == "wilson_coop"
     ref = oracle.sample(g, 1.0, 0, 0, 2, per_tree=False)
+    got = fc.sample(g, alpha=1.0, seed=0, tree_begin=0, tree_count=2, want_digests=True)
+    assert got["stats"]["sampler"] == "wilson_tile"
+    assert np.array_equal(got["tree_digests"], ref.digests)
+    fc.set_option("tile_cross_permille", 0)
+    try:
+        got = fc.sample(g, alpha=1.0, seed=0, tree_begin=0, tree_count=2, want_digests=True)
+    finally:
+        fc.set_option("tile_cross_permille", 100)
+    assert got["stats"]["sampler"] == "wilson_coop"
     assert np.array_equal(got["tree_digests"], ref.digests)
 
 

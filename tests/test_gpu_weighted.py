@@ -12,11 +12,11 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 pytestmark = pytest.mark.gpu
 
-SAMPLERS = ["lane", "coop", "lds", "hyb"]
+SAMPLERS = ["lane", "coop", "lds", "hyb", "tile"]
 
 
 def _say(msg):

@@ -4,7 +4,7 @@ for the paper's datasets and have no external reference values."""
 import numpy as np
 import pytest
 
-from paper_2101_06192_amd import inputs
+import inputs
 
 
 def _check_simple_symmetric(g):

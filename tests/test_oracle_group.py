@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 
 def _three_regular():

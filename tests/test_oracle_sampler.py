@@ -18,7 +18,7 @@ import pytest
 from scipy import stats
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 
 def _is_spanning_tree(g, parent):

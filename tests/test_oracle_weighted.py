@@ -20,7 +20,7 @@ import pytest
 from scipy import stats
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 
 def test_unit_weights_are_the_unweighted_sampler():

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 
 class _Arrows:

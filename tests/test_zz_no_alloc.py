@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2101_06192_amd import inputs
+import inputs
 
 pytestmark = pytest.mark.gpu
 
