@@ -49,6 +49,9 @@ def _load():
         lib.gg_uniforms.argtypes = [ctypes.c_int64, ctypes.c_uint64, f64p]
         lib.gg_normals.restype = None
         lib.gg_normals.argtypes = [ctypes.c_int64, ctypes.c_uint64, f64p]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.gg_csr.restype = ctypes.c_int64
+        lib.gg_csr.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i64p, i32p, i64p]
         _lib = lib
     return _lib
 
@@ -84,7 +87,29 @@ class CSRGraph:
 
 
 def csr_from_edges(n: int, us: np.ndarray, vs: np.ndarray, name: str = "") -> CSRGraph:
-    """Symmetrise, drop self-loops and duplicates, sort rows."""
+    """Symmetrise, drop self-loops and duplicates, sort rows (in C: a count, a
+    scatter and a sort of every row)."""
+    lib = _load()
+    us = np.ascontiguousarray(us, dtype=np.int32)
+    vs = np.ascontiguousarray(vs, dtype=np.int32)
+    m = int(us.shape[0])
+    raw = ctypes.c_int64(0)
+    if lib.gg_csr(int(n), m, _p32(us), _p32(vs), None, None, ctypes.byref(raw)) < 0:
+        raise ValueError("edge endpoint out of range")
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.empty(max(raw.value, 1), dtype=np.int32)
+    nnz = lib.gg_csr(int(n), m, _p32(us), _p32(vs),
+                     row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p32(col),
+                     ctypes.byref(raw))
+    if nnz < 0:
+        raise MemoryError("CSR construction failed")
+    if nnz >= 2**31:
+        raise ValueError("graph too large for int32 CSR")
+    return CSRGraph(n, row_ptr.astype(np.int32), np.ascontiguousarray(col[:nnz]), name)
+
+
+def csr_from_edges_numpy(n: int, us: np.ndarray, vs: np.ndarray, name: str = "") -> CSRGraph:
+    """The same CSR as csr_from_edges, with numpy (kept to check it)."""
     us = np.asarray(us, dtype=np.int64)
     vs = np.asarray(vs, dtype=np.int64)
     keep = us != vs

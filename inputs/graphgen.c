@@ -214,3 +214,58 @@ void gg_normals(int64_t count, uint64_t seed, double *out) {
         if (i + 1 < count) out[i + 1] = rad * sin(two_pi * u2);
     }
 }
+
+/*
+ * Simple symmetric CSR from an undirected edge list: both directions of every
+ * edge u != v, rows sorted ascending, duplicates dropped.  Pass 1 (row_ptr and
+ * col_idx NULL) returns the number of directed entries before deduplication in
+ * *raw and fills nothing; pass 2 fills row_ptr (n + 1 entries, int64) and
+ * col_idx (room for *raw entries) and returns the final entry count.  Returns
+ * -1 on an id out of [0, n) or a failed allocation.
+ */
+static int gg_cmp_i32(const void *a, const void *b) {
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int64_t gg_csr(int32_t n, int64_t m, const int32_t *us, const int32_t *vs, int64_t *row_ptr,
+               int32_t *col_idx, int64_t *raw) {
+    int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!deg) return -1;
+    for (int64_t i = 0; i < m; ++i) {
+        const int32_t u = us[i], v = vs[i];
+        if (u < 0 || v < 0 || u >= n || v >= n) { free(deg); return -1; }
+        if (u == v) continue;
+        ++deg[u];
+        ++deg[v];
+    }
+    int64_t total = 0;
+    for (int32_t v = 0; v < n; ++v) total += deg[v];
+    *raw = total;
+    if (!row_ptr || !col_idx) { free(deg); return total; }
+    /* scatter into rows (deg becomes the fill cursor) */
+    int64_t *start = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!start) { free(deg); return -1; }
+    start[0] = 0;
+    for (int32_t v = 0; v < n; ++v) start[v + 1] = start[v] + deg[v];
+    for (int32_t v = 0; v < n; ++v) deg[v] = start[v];
+    for (int64_t i = 0; i < m; ++i) {
+        const int32_t u = us[i], v = vs[i];
+        if (u == v) continue;
+        col_idx[deg[u]++] = v;
+        col_idx[deg[v]++] = u;
+    }
+    /* sort and deduplicate each row, compacting in place */
+    int64_t out = 0;
+    row_ptr[0] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const int64_t a = start[v], b = start[v + 1];
+        qsort(col_idx + a, (size_t)(b - a), sizeof(int32_t), gg_cmp_i32);
+        for (int64_t e = a; e < b; ++e)
+            if (e == a || col_idx[e] != col_idx[e - 1]) col_idx[out++] = col_idx[e];
+        row_ptr[v + 1] = out;
+    }
+    free(start);
+    free(deg);
+    return out;
+}
