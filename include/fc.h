@@ -217,9 +217,10 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *                     close again is popped in that same round (cycle popping may pop
  *                     any cycle at any time: the same trees) instead of a round later
  *                     with everything that hangs off it; 0 never, 1 weighted graphs
- *                     only, 2 always (the default; a batch created with
- *                     FC_FLAG_AUTOTUNE then times each LDS launch group with and
- *                     without the re-pops and keeps the faster: the trees are the same)
+ *                     only, 2 always, 3 (the default) always, except that a batch
+ *                     created with FC_FLAG_AUTOTUNE times each LDS launch group with
+ *                     and without the re-pops and keeps the faster (the trees are the
+ *                     same either way)
  *   "coop_repop"      the same for the global-counter sampler (graphs whose counters do
  *                     not fit LDS), with an LDS filter that flags the re-popped
  *                     vertices; 0 never, 1 weighted graphs only, 2 always (the default)
@@ -335,8 +336,12 @@ typedef struct fc_batch fc_batch;
  * distinct graph (unless FC_FLAG_TRUSTED_GRAPH), builds each job's vertex
  * records of G*, orders the work items (trees) largest graph first, sizes
  * the per-slot scratch for the largest graph, optionally autotunes the
- * launch shape (FC_FLAG_AUTOTUNE; results do not depend on it) and captures
- * the sampling launch as a HIP graph.  The job array is copied; the graphs
+ * launch shape (FC_FLAG_AUTOTUNE; results do not depend on it: each candidate
+ * shape is warmed up on a few trees, then timed twice on a thirty-second of
+ * every job's trees, best of two; the choice is kept per device and job
+ * shapes, so a batch created again with the same graph sizes, alphas, tree
+ * counts and options is not timed again) and captures the sampling launch as
+ * a HIP graph.  The job array is copied; the graphs
  * and output buffers it points to must stay valid until fc_batch_destroy.
  * Returns FC_ERR_ARG for a job with a host graph, alpha <= 0, a NULL
  * root_counts, or more than 2^32 - 1 trees in total. */

@@ -261,7 +261,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     const uint32_t *wthr = nullptr;
     if ((rc = weight_tables(ctx, g, ctx->wsum, ctx->wthr, &wsum, &wthr))) return rc;
     const bool weighted = wsum != nullptr;
-    const bool repop = ctx->lds_repop == 2 || (ctx->lds_repop == 1 && weighted);
+    const bool repop = ctx->lds_repop >= 2 || (ctx->lds_repop == 1 && weighted);
     FC_HIP(ctx, fc::launch_build_vrec(g.row_ptr, wsum, g.n, p->alpha, vrec, &sm->dmax,
                                       static_cast<uint32_t *>(ctx->iso.ptr), &sm->wtotal,
                                       ctx->stream),
@@ -1020,7 +1020,7 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
         if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
         ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
     } else if (k == "lds_repop") {
-        if (value < 0 || value > 2) return set_err(ctx, FC_ERR_ARG, "lds_repop must be 0, 1 or 2");
+        if (value < 0 || value > 3) return set_err(ctx, FC_ERR_ARG, "lds_repop must be 0, 1, 2 or 3");
         ctx->lds_repop = static_cast<uint32_t>(value);
     } else if (k == "coop_repop") {
         if (value < 0 || value > 2) return set_err(ctx, FC_ERR_ARG, "coop_repop must be 0, 1 or 2");

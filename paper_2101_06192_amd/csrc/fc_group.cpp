@@ -90,7 +90,8 @@ extern "C" int fc_group_closeness(fc_ctx *ctx, const fc_graph *g, double alpha, 
         FC_HIP(ctx, hipMemcpyAsync(farness + 1, fout + 1, sizeof(double) * (k - 1), hipMemcpyDeviceToHost,
                                    ctx->stream), "copy");
     FC_HIP(ctx, hipStreamSynchronize(ctx->stream), "group closeness");
-    if (hbad) return set_err(ctx, FC_ERR_HIP, "no candidate vertex (non-finite gains)");
+    if (hbad & 2u) return set_err(ctx, FC_ERR_HIP, "a greedy step met a NaN gain (non-finite entries in the inverse)");
+    if (hbad) return set_err(ctx, FC_ERR_HIP, "a greedy step found no candidate vertex");
     std::memcpy(group + 1, hg.data() + 1, sizeof(int32_t) * (k - 1));
     return FC_OK;
 }

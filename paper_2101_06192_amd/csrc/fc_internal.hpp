@@ -61,7 +61,8 @@ struct fc_ctx {
     uint32_t lds_wg_per_cu = 0;   // its resident workgroups per CU (0: as many as fit)
     uint32_t predraw_mib = 32768;  // budget of pre-drawn first arrows (0: off)
     bool kendall_pairs = false;   // Kendall's tau by all pairs instead of merge-sort counts
-    uint32_t lds_repop = 2;       // re-formed 2-cycle pops: 0 never, 1 weighted graphs, 2 always
+    uint32_t lds_repop = 3;       // re-formed 2-cycle pops: 0 never, 1 weighted graphs, 2 always,
+                                  // 3 always, and timed both ways by batch autotuning
     uint32_t coop_repop = 2;      // the same for the global-counter sampler
     uint32_t tile_size = 0;       // tile sampler: vertices per tile (0: the widest that fits LDS)
     uint32_t tile_cross_permille = 100;  // picked automatically when at most this share (per

@@ -393,19 +393,28 @@ __global__ __launch_bounds__(kThreads) void colsq_kernel(double *__restrict__ A,
     part[static_cast<size_t>(c) * N + j] = s;
 }
 
+// Order-preserving 64-bit key of a non-NaN binary64 value (-0 taken as +0):
+// keys compare as the values do, and every key is above 0, the key of "no
+// candidate".
+__device__ __forceinline__ unsigned long long gain_key(double g) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(g + 0.0));
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
 // gain[j] = |M e_j|^2 / M_jj for candidates (not taken, not the u* slot),
-// the chunk sums added in chunk order; per block, the largest candidate gain
-// as its binary64 bit pattern (0 with no candidate) in bmax[b], the smallest
-// id of a candidate with that pattern and a gain >= 0 (none: all ones, e.g.
-// when the largest pattern is a NaN's) in bid[b], and the sum of its diagonal
-// entries (in a fixed order) in bdiag[b].
+// the chunk sums added in chunk order; per block, the largest candidate
+// gain's key (0 with no candidate) in bmax[b], the smallest id of a
+// candidate with that key (none: all ones) in bid[b], and the sum of its
+// diagonal entries (in a fixed order) in bdiag[b].  Gains are >= 0 in exact
+// arithmetic; a rounded negative one still competes by its value.  A NaN gain
+// (non-finite entries in M) sets bit 1 of *bad.
 __global__ __launch_bounds__(kThreads) void gain_kernel(const double *__restrict__ A, uint32_t n,
                                                         uint32_t N, uint32_t chunks,
                                                         const double *__restrict__ part,
                                                         const uint8_t *__restrict__ taken,
                                                         unsigned long long *__restrict__ bmax,
                                                         uint32_t *__restrict__ bid,
-                                                        double *__restrict__ bdiag) {
+                                                        double *__restrict__ bdiag, uint32_t *bad) {
     __shared__ unsigned long long sk[kThreads];
     __shared__ uint32_t si[kThreads];
     __shared__ double sd[kThreads];
@@ -417,8 +426,12 @@ __global__ __launch_bounds__(kThreads) void gain_kernel(const double *__restrict
         double sum = 0.0;
         for (uint32_t c = 0; c < chunks; ++c) sum += part[static_cast<size_t>(c) * N + j];
         const double g = sum / djj;
-        key = static_cast<unsigned long long>(__double_as_longlong(g));
-        ok = g >= 0.0;
+        if (g == g) {
+            key = gain_key(g);
+            ok = true;
+        } else {
+            atomicOr(bad, 2u);
+        }
     }
     sk[t] = key;
     sd[t] = djj;
@@ -478,7 +491,7 @@ __device__ uint32_t reduce_choice(const unsigned long long *__restrict__ bmax,
 // Column v of the chosen vertex (and its row) copied out before the downdate,
 // v reduced from the gain blocks; block 0 also does the step's bookkeeping:
 // taken[v] = 1, gout[s] = v, *piv = M[v][v], *vout = v for the downdate
-// (all ones and *bad = 1 when there is no candidate), and, when fout is not
+// (all ones and bit 0 of *bad set when there is no candidate), and, when fout is not
 // null, fout[s - 1] = the sum of the blocks' diagonal sums (f(S) of step s - 1).
 __global__ __launch_bounds__(kThreads) void choose_copy_kernel(
     const double *__restrict__ A, uint32_t n, uint32_t N, const unsigned long long *__restrict__ bmax,
@@ -500,7 +513,7 @@ __global__ __launch_bounds__(kThreads) void choose_copy_kernel(
             *vout = v;
         } else {
             gout[s] = -1;
-            *bad = 1u;
+            atomicOr(bad, 1u);
             *vout = ~0ull;
         }
     }
@@ -645,7 +658,7 @@ hipError_t launch_group_step(double *A, uint32_t n, uint32_t N, double *part, ui
                              hipStream_t stream) {
     const uint32_t nb = blocks_for(n);
     gain_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, group_chunks(n), part, taken, bmax, bid,
-                                             bdiag);
+                                             bdiag, bad);
     choose_copy_kernel<<<nb, kThreads, 0, stream>>>(A, n, N, bmax, bid, bdiag, nb, taken, gout, s,
                                                     piv, vsel, bad, fout, cv, rv);
     colsq_kernel<<<dim3(nb, group_chunks(n)), kThreads, 0, stream>>>(A, n, N, n, vsel, cv, rv, piv,

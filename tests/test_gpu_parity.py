@@ -538,6 +538,36 @@ def test_batch_graph_replays_and_autotune(gpu_lib, counters):
         b.close()
 
 
+def test_batch_autotune_cached_and_repop_values(gpu_lib):
+    """A batch created again with the same job shapes takes the cached launch
+    shape (the same shape string, the same trees); every lds_repop value,
+    tuned (3) or fixed (0, 1, 2), gives the eager trees."""
+    fc = gpu_lib
+    gs = _batch_graphs()[:3]
+    dgs = [fc.to_device(g) for g in gs]
+    jobs = [{"graph": dg, "alpha": 2.0, "stream_id": i, "tree_count": 40, "digests": True}
+            for i, dg in enumerate(dgs)]
+    eager = [fc.sample(dg, alpha=2.0, seed=3, tree_count=40, stream_id=i, want_digests=True)
+             for i, dg in enumerate(dgs)]
+    try:
+        for repop in (3, 2, 1, 0):
+            fc.set_option("lds_repop", repop)
+            shapes = []
+            for _ in range(2):
+                b = fc.Batch(jobs, seed=3, autotune=True)
+                shapes.append(b.run()["sampler"])
+                for i in range(len(jobs)):
+                    got = b.result(i)
+                    assert np.array_equal(got["tree_digests"], eager[i]["tree_digests"]), (repop, i)
+                    assert np.array_equal(got["root_counts"], eager[i]["root_counts"]), (repop, i)
+                b.close()
+            assert shapes[0] == shapes[1], shapes
+        with pytest.raises(fc.FCError):
+            fc.set_option("lds_repop", 4)
+    finally:
+        fc.set_option("lds_repop", 3)
+
+
 def test_batch_rejects_host_graphs_and_bad_alpha(gpu_lib):
     fc = gpu_lib
     g = inputs.erdos_renyi(30, 0.2, 1)
@@ -656,4 +686,4 @@ def test_lds_repop_bit_exact(gpu_lib, repop, case):
         for gg, alpha in ((g, 1.0), (inputs.with_weights(g, 7), 0.5)):
             _compare(fc, gg, alpha, 3, 0, 40, per_tree=True, sampler="lds")
     finally:
-        fc.set_option("lds_repop", 2)
+        fc.set_option("lds_repop", 3)
