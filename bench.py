@@ -649,6 +649,9 @@ def _short(name):
 
 
 def _matches(name, kernels):
+    """One of this library's kernels (namespace fc), by short name."""
+    if "fc::" not in name:
+        return False
     short = _short(name)
     return any(short == k or short.startswith(k + "<") for k in kernels)
 

@@ -13,6 +13,9 @@ def test_short_names_and_matching():
     assert bench._matches(n, ["wilson_lds_kernel"])
     assert not bench._matches(n, ["wilson_lds"])
     assert not bench._matches("fc::lds_predraw_kernel<false>(x)", ["wilson_lds_kernel"])
+    # another library's kernel of the same short name is not ours
+    assert not bench._matches("void at::native::reduce_kernel<128, 4>(x)", ["reduce_kernel"])
+    assert bench._matches("fc::(anonymous namespace)::reduce_kernel(double*)", ["reduce_kernel"])
 
 
 def test_dispatch_counters_sum_per_dispatch():
