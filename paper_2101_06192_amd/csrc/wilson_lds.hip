@@ -541,7 +541,8 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                         word[v[q]] = w[q];
                         if (!live[q]) set_settled(v[q]);
                     }
-                    w[q] = pack(v[q], f_lo(w[q]), 0u);
+                    // (the entry carries the new draw count for the re-pop passes)
+                    w[q] = pack(v[q], f_lo(w[q]), f_k(w[q]));
                 }
                 wave_append_many<kRC>(Unext, &s_u, n, &s_over, w, live);
             }
@@ -556,6 +557,9 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             // detection) and "popped again this round" (+2).  The popped vertices are
             // already in the next list, with their old targets: a pass over that
             // list re-reads the target of every entry marked +2 and clears the mark.
+            // The pass lists carry each vertex's draw count (from its new word, or
+            // from the partner's word read for the detection), so a redraw reads
+            // no tree word.
             // A pass's pops go to one half of the dead peel buffer; a pass that
             // would overflow it ends the loop.
             if (kRepop) {
@@ -577,12 +581,16 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                         uint64_t e[2] = {0ull, 0ull};
                         bool pp[2] = {false, false};
                         if (i < ccur) {
-                            const uint32_t u = f_lo(cur[i]), tg = f_mid(cur[i]);
-                            if (tg < nl && !is_settled(tg) && f_lo(word[tg]) == u &&
-                                ((count_of(tg) & 1u) == 0u || u < tg)) {
-                                e[0] = pack(u, 0u, 0u);
-                                e[1] = pack(tg, 0u, 0u);
-                                pp[0] = pp[1] = true;
+                            const uint64_t c = cur[i];
+                            const uint32_t u = f_lo(c), tg = f_mid(c);
+                            if (tg < nl && !is_settled(tg)) {
+                                const uint64_t wt = word[tg];
+                                if (f_lo(wt) == u && ((count_of(tg) & 1u) == 0u || u < tg)) {
+                                    // both ends with their draw counts so far
+                                    e[0] = pack(u, 0u, f_k(c));
+                                    e[1] = pack(tg, 0u, f_k(wt));
+                                    pp[0] = pp[1] = true;
+                                }
                             }
                         }
                         wave_append_many<2>(nxt, &s_rp, cap, &s_rp_over, e, pp);
@@ -593,7 +601,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                     if (uniform(s_rp_over) != 0u || cn == 0u) break;
                     for (uint32_t i = tid; i < cn; i += T) {
                         const uint32_t v = f_lo(nxt[i]);
-                        const uint32_t k = f_k(word[v]);
+                        const uint32_t k = f_k(nxt[i]);
                         if (k >= min(kKMax, a.k_limit)) {  // count past the limit
                             err |= kErrVisitOverflow;
                             nxt[i] = pack(v, n, 0u);
@@ -603,7 +611,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                                                             a.key1, k, t);
                         word[v] = nw;
                         if (f_lo(nw) == n) set_settled(v);
-                        nxt[i] = pack(v, f_lo(nw), 0u);
+                        nxt[i] = pack(v, f_lo(nw), f_k(nw));
                         if ((count_of(v) & 2u) == 0u) {  // first pop this round: mark it
                             const Field f = field_of(C, v);
                             atomicAdd(&s_lds[f.w], 2u << f.sh);

@@ -1,0 +1,27 @@
+"""The committed oracle fixtures are what their scripts say: the R-MAT 2^22
+CG ground truth holds 64 distinct non-isolated vertices whose Omega_vv lies in
+the interval every Omega_vv must (1 / (1 + alpha d_v) <= Omega_vv <= 1)."""
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_rmat22_cg64_fixture_shape_and_bounds():
+    vs, deg, om = [], [], []
+    with open(os.path.join(HERE, "golden", "rmat22_cg64.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            a, b, c = line.split()
+            vs.append(int(a))
+            deg.append(int(b))
+            om.append(float.fromhex(c))
+    vs, deg, om = np.array(vs), np.array(deg), np.array(om)
+    assert vs.size == 64 and np.unique(vs).size == 64 and (np.diff(vs) > 0).all()
+    assert (vs >= 0).all() and (vs < 1 << 22).all()
+    assert (deg >= 1).all()
+    alpha = 1.0
+    assert (om >= 1.0 / (1.0 + alpha * deg) - 1e-9).all()
+    assert (om < 1.0).all()

@@ -424,8 +424,9 @@ def test_rmat_heavy_tail_bit_exact(gpu_lib, sampler):
 
 def test_ba200k_full_run_sampled(gpu_lib):
     """The benchmark's configuration (BA(200000, 5), alpha = 1, 4096 trees):
-    per-tree digests of a spread of tree ids recomputed one by one by the
-    oracle, exact totals, and the estimate against CG on sampled vertices."""
+    per-tree digests and steps of trees 0..63 and of a spread of later tree
+    ids recomputed by the oracle, exact totals, and the estimate against CG on
+    sampled vertices."""
     fc = gpu_lib
     g = inputs.barabasi_albert(200_000, 5, 0)
     dg = fc.to_device(g)
@@ -434,7 +435,12 @@ def test_ba200k_full_run_sampled(gpu_lib):
     _say(f"full run sampler={got['stats']['sampler']} ms={got['stats']['ms_sample']:.1f}")
     # the benchmark's launch: LDS counters, first arrows drawn ahead
     assert got["stats"]["sampler"] == "wilson_lds" and got["stats"]["ms_predraw"] > 0.0
-    for t in (0, 1, 777, 2048, 4095):
+    # every tree of the first 64 (a quarter of the trees the first wave of
+    # workgroups samples), then a spread of later ones
+    ref = oracle.sample(g, 1.0, 0, 0, 64)
+    assert np.array_equal(got["tree_digests"][:64], ref.digests)
+    assert np.array_equal(got["tree_steps"][:64], ref.steps)
+    for t in (777, 2048, 4095):
         ref = oracle.sample(g, 1.0, 0, t, 1)
         assert got["tree_digests"][t] == ref.digests[0], t
         assert got["tree_steps"][t] == ref.steps[0], t
