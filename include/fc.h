@@ -233,6 +233,9 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "tile_repop"      the tile sampler pops a 2-cycle that a round's new arrows close again
  *                     within that round, inside the tile: 0 never, 1 weighted graphs only,
  *                     2 always (the default)
+ *   "tile_bits_lds"   1 (default): the tile sampler keeps its exit and settled bitmaps
+ *                     (n bits each) in LDS when they fit; 0: in global memory, so that a
+ *                     small tile_size leaves room for several workgroups per CU
  *   "kendall_pairs"   1: fc_kendall_tau compares all n(n-1)/2 pairs (tiled) instead of
  *                     counting discordant pairs by a merge sort (0, the default); same
  *                     counts, O(n^2) instead of O(n log^2 n) work

@@ -582,7 +582,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
         const size_t bw = (n + 31u) >> 5;
         tile_threads = ctx->tile_threads;
         // the exit and settled bitmaps share the tiles' LDS when n bits fit
-        const bool bits_lds = 4u * bw + kLdsStaticBytes <= ctx->max_lds;
+        const bool bits_lds = ctx->tile_bits_lds && 4u * bw + kLdsStaticBytes <= ctx->max_lds;
         tile_lds = std::max(fc::tile_lds_bytes(ta.B), bits_lds ? 4u * bw : 0u);
         const int fit = fc::tile_max_active(tile_threads, tile_lds, weighted);
         // first arrows of all trees drawn ahead when their targets fit the budget
@@ -1053,6 +1053,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "tile_cross_permille") {
         if (value < 0 || value > 1000) return set_err(ctx, FC_ERR_ARG, "tile_cross_permille");
         ctx->tile_cross_permille = static_cast<uint32_t>(value);
+    } else if (k == "tile_bits_lds") {
+        if (value < 0 || value > 1) return set_err(ctx, FC_ERR_ARG, "tile_bits_lds must be 0 or 1");
+        ctx->tile_bits_lds = static_cast<uint32_t>(value);
     } else if (k == "tile_repop") {
         if (value < 0 || value > 2) return set_err(ctx, FC_ERR_ARG, "tile_repop must be 0, 1 or 2");
         ctx->tile_repop = static_cast<uint32_t>(value);
@@ -1167,6 +1170,7 @@ int fc_sample_noalloc(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
     sh.tile_cross_permille = ctx->tile_cross_permille;
     sh.tile_threads = ctx->tile_threads;
     sh.tile_repop = ctx->tile_repop;
+    sh.tile_bits_lds = ctx->tile_bits_lds;
     sh.wall_khz = ctx->wall_khz;
     sh.arena = static_cast<char *>(base);
     sh.arena_size = kStaticScratchBytes;

@@ -69,6 +69,7 @@ struct fc_ctx {
                                          // mille) of the CSR entries cross tiles
     uint32_t tile_threads = 1024; // threads per workgroup of the tile sampler
     uint32_t tile_repop = 2;      // tile sampler's re-formed 2-cycle pops: 0 never, 1 weighted, 2 always
+    uint32_t tile_bits_lds = 1;   // tile sampler's exit and settled bitmaps in LDS when they fit (0: global)
     double wall_khz = 100000.0;   // device wall clock rate
     // Arena mode (fc_sample_noalloc): every buffer of one call is carved from
     // this device range instead of being allocated; null in ordinary contexts.

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
     // s_lc: three rotating tail counters, so that one barrier per peel level
     // suffices (level k appends with counter (k + 1) % 3 while thread 0 clears
     // counter (k + 2) % 3, which everyone read a level ago)
-    __shared__ uint32_t s_item, s_u, s_c, s_over, s_rover, s_nlev, s_pos, s_lc[3];
+    __shared__ uint32_t s_item, s_u, s_c, s_over, s_rover, s_nlev, s_pos, s_nc, s_lc[3];
     __shared__ uint32_t s_tail[64];
     __shared__ unsigned long long s_digest, s_roots, s_draws;
     __shared__ unsigned long long s_ph[kPhNum + 1];
@@ -209,35 +209,31 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
             return tg;
         };
 
-        // -------------------------------------------------------------------
-        // 1. tiles: their own cycles, then every vertex's exit
-        // -------------------------------------------------------------------
-        for (uint32_t tile = 0; tile < ntiles && !(err & kErrStepCap); ++tile) {
-            const uint32_t lo = tile * B;
-            const uint32_t b = min(B, n - lo);
-            __syncthreads();
-            {
-                constexpr int kL = 8;  // loads in flight per thread
-                for (uint32_t i0 = tid; i0 < b; i0 += kL * T) {
-                    uint32_t tg[kL];
-#pragma unroll
-                    for (int q = 0; q < kL; ++q) {
-                        const uint32_t i = i0 + q * T;
-                        tg[q] = i < b ? tw[lo + i] : n;
-                    }
-#pragma unroll
-                    for (int q = 0; q < kL; ++q) {
-                        const uint32_t i = i0 + q * T;
-                        if (i < b) {
-                            const uint32_t code = tg[q] == n ? kRoot : (tg[q] - lo < b ? tg[q] - lo : kExt);
-                            lt[i] = static_cast<uint16_t>(code);
-                            st16[i] = static_cast<uint16_t>(code == kRoot ? kSettled
-                                                            : code == kExt ? i : kUnres);
-                        }
-                    }
-                }
-            }
-            mark(kPhLoad);
+        // Cycle popping inside a vertex set held in LDS (a tile, or the
+        // residual): set vertex i is global id vid(i); an arrow's target becomes
+        // a set-local code: kRoot when it reaches u* (u* itself, or a vertex
+        // settled before), kExt for a vertex of another tile, else its local id.
+        // Rounds until every vertex of the set is resolved (settled, or its
+        // exit known).
+        // (the residual set: its id list and a list buffer apart from it and bP)
+        uint32_t *res_list = bU, *res_l0 = bN;
+        auto pop_rounds = [&](uint32_t b, uint32_t lo, bool res, int ph_count, int ph_peel,
+                              int ph_pop) {
+            auto vid = [&](uint32_t i) -> uint32_t { return res ? res_list[i] : lo + i; };
+            auto code_of = [&](uint32_t tg) -> uint32_t {
+                if (tg == n) return kRoot;
+                if (res) return ((gbits[tg >> 5] >> (tg & 31u)) & 1u) ? kRoot : sc[tg];
+                return tg - lo < b ? tg - lo : kExt;
+            };
+            // After the first round (which scans the whole set) only the vertices
+            // left hanging off a cycle by the sweep and the cycle vertices
+            // themselves can be unresolved: each round lists them (global, per
+            // slot, in lists the tiles do not use otherwise), and later rounds
+            // scan that list instead of the set.
+            uint32_t *Lcur = res ? res_l0 : bN + lo;
+            uint32_t *Lnext = res ? bP : bP + lo;
+            uint32_t lcount = 0;
+            bool full = true;
             uint32_t rounds = 0;
             for (;;) {
                 if (++rounds > a.max_rounds || s_over) {
@@ -249,12 +245,15 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                 if (tid == 0) {
                     s_u = 0;
                     s_c = 0;
+                    s_nc = 0;
                     s_lc[0] = 0;
                     s_lc[1] = 0;
                 }
                 __syncthreads();
+                const uint32_t scan = full ? b : lcount;  // candidates: the set, or the list
                 uint32_t mine = 0;
-                for (uint32_t i = tid; i < b; i += T) {
+                for (uint32_t j = tid; j < scan; j += T) {
+                    const uint32_t i = full ? j : Lcur[j];
                     if (st_get(i) & kUnres) {
                         ++mine;
                         const uint32_t tg = lt[i];
@@ -264,16 +263,21 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                 wave_count(&s_u, mine);
                 __syncthreads();
                 const uint32_t ucount = uniform(s_u);
-                if (ucount == 0) break;  // every vertex of the tile resolved
+                if (ucount == 0) break;  // every vertex of the set resolved
                 // peel level 0: unresolved with no in-arrow (level k appends
                 // with counter (k + 1) % 3)
-                for (uint32_t i = wave_base; i < b; i += T) {
-                    const uint32_t li = i + lane;
-                    const bool leaf = li < b && st_get(li) == kUnres;
+                for (uint32_t j = wave_base; j < scan; j += T) {
+                    const uint32_t lj = j + lane;
+                    uint32_t li = 0;
+                    bool leaf = false;
+                    if (lj < scan) {
+                        li = full ? lj : Lcur[lj];
+                        leaf = st_get(li) == kUnres;
+                    }
                     wave_push<uint16_t>(tp, 0u, &s_lc[0], Bp, &s_over, static_cast<uint16_t>(li), leaf);
                 }
                 __syncthreads();
-                mark(kPhCount);
+                mark(ph_count);
                 uint32_t plo = 0, phi = min(uniform(s_lc[0]), b), nlev = 0;
                 if (tid == 0) lv_set(0, 0);
                 while (phi - plo > 64u) {
@@ -363,23 +367,30 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                     }
                     __syncthreads();
                 }
-                mark(kPhPeel);
+                mark(ph_peel);
                 if (peeled == ucount) break;  // no cycle: every unresolved vertex resolved
-                // pop the tile's cycles: unresolved vertices with an in-arrow left
+                // pop the set's cycles: unresolved vertices with an in-arrow left
                 // (exactly one, from the cycle) draw their next arrow.  They are
                 // listed first (the peel order is spent), so that the draws'
                 // global loads go out together.
-                for (uint32_t i = wave_base; i < b; i += T) {
-                    const uint32_t li = i + lane;
-                    bool cyc = false;
-                    if (li < b) {
+                // The same scan lists every vertex still unresolved (hanging off a
+                // cycle, or on one) for the next round: no other can be then.
+                for (uint32_t j = wave_base; j < scan; j += T) {
+                    const uint32_t lj = j + lane;
+                    uint32_t li = 0;
+                    bool cyc = false, unres = false;
+                    if (lj < scan) {
+                        li = full ? lj : Lcur[lj];
                         const uint32_t s = st_get(li);
-                        cyc = (s & kUnres) && (s & kCountMask);
+                        unres = (s & kUnres) != 0u;
+                        cyc = unres && (s & kCountMask);
                     }
                     wave_push<uint16_t>(tp, 0u, &s_c, Bp, &s_over, static_cast<uint16_t>(li), cyc);
+                    wave_push<uint32_t>(Lnext, 0u, &s_nc, b, &s_over, li, unres);
                 }
                 __syncthreads();
                 const uint32_t npop = min(uniform(s_c), b);
+                const uint32_t next_count = min(uniform(s_nc), b);
                 // with the re-pops, vertices redrawn to an unresolved target carry
                 // the mark "redrawn in this pass" (count 1) into the first pass
                 const uint32_t half = Bp >> 1;
@@ -388,8 +399,8 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                 if (tid == 0) s_lc[0] = 0;  // the first pass's tail (the peel's counters are spent)
                 for (uint32_t j = tid; j < npop; j += T) {
                     const uint32_t i = tp[j];
-                    const uint32_t tg = pop(lo + i);
-                    const uint32_t code = tg == n ? kRoot : (tg - lo < b ? tg - lo : kExt);
+                    const uint32_t tg = pop(vid(i));
+                    const uint32_t code = code_of(tg);
                     lt[i] = static_cast<uint16_t>(code);
                     st16[i] = static_cast<uint16_t>(code == kRoot ? kSettled : code == kExt ? i : fresh);
                 }
@@ -440,8 +451,8 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                         if (nn == 0u || nn > half) break;
                         for (uint32_t j = tid; j < nn; j += T) {
                             const uint32_t i = tp[nxt + j];
-                            const uint32_t tg = pop(lo + i);
-                            const uint32_t code = tg == n ? kRoot : (tg - lo < b ? tg - lo : kExt);
+                            const uint32_t tg = pop(vid(i));
+                            const uint32_t code = code_of(tg);
                             lt[i] = static_cast<uint16_t>(code);
                             st16[i] = static_cast<uint16_t>(code == kRoot ? kSettled
                                                             : code == kExt ? i : kUnres | 1u);
@@ -452,8 +463,45 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                         ncur = nn;
                     }
                 }
-                mark(kPhPop);
+                mark(ph_pop);
+                uint32_t *const spent = Lcur;
+                Lcur = Lnext;
+                Lnext = spent;
+                lcount = next_count;
+                full = false;
             }
+        };
+
+        // -------------------------------------------------------------------
+        // 1. tiles: their own cycles, then every vertex's exit
+        // -------------------------------------------------------------------
+        for (uint32_t tile = 0; tile < ntiles && !(err & kErrStepCap); ++tile) {
+            const uint32_t lo = tile * B;
+            const uint32_t b = min(B, n - lo);
+            __syncthreads();
+            {
+                constexpr int kL = 8;  // loads in flight per thread
+                for (uint32_t i0 = tid; i0 < b; i0 += kL * T) {
+                    uint32_t tg[kL];
+#pragma unroll
+                    for (int q = 0; q < kL; ++q) {
+                        const uint32_t i = i0 + q * T;
+                        tg[q] = i < b ? tw[lo + i] : n;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kL; ++q) {
+                        const uint32_t i = i0 + q * T;
+                        if (i < b) {
+                            const uint32_t code = tg[q] == n ? kRoot : (tg[q] - lo < b ? tg[q] - lo : kExt);
+                            lt[i] = static_cast<uint16_t>(code);
+                            st16[i] = static_cast<uint16_t>(code == kRoot ? kSettled
+                                                            : code == kExt ? i : kUnres);
+                        }
+                    }
+                }
+            }
+            mark(kPhLoad);
+            pop_rounds(b, lo, false, kPhCount, kPhPeel, kPhPop);
             if (err & kErrStepCap) break;
             // every vertex's exit, and the tile's exit list
             if (tid == 0) s_c = 0;
@@ -591,14 +639,37 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                 }
             }
             __syncthreads();
-            if (a.bits_lds) {  // the residual rounds test the bitmap in LDS
+            uint32_t ucount = min(uniform(s_u), n);
+            if (ucount > B && a.bits_lds) {  // the global rounds test the bitmap in LDS
                 for (uint32_t i = tid; i < nw; i += T) s_dyn[i] = gbits[i];
                 __syncthreads();
             }
-            uint32_t ucount = min(uniform(s_u), n);
             uint32_t *U = bU, *Un = bN;
             uint32_t rounds = 0;
             while (ucount > 0) {
+                if (ucount <= B) {
+                    // What is left fits the tiles' LDS arrays: pop it as one more
+                    // set, its vertices numbered in list order (sc, spent since the
+                    // exit graph, maps an id to that number); targets settled
+                    // before count as u*.
+                    if (rounds > 0 && a.bits_lds) {  // the settled bitmap back to global
+                        for (uint32_t i = tid; i < nw; i += T) gbits[i] = s_dyn[i];
+                        __syncthreads();
+                    }
+                    for (uint32_t i = tid; i < ucount; i += T) sc[U[i]] = i;
+                    __syncthreads();
+                    for (uint32_t i = tid; i < ucount; i += T) {
+                        const uint32_t tg = tw[U[i]];
+                        const uint32_t code =
+                            tg == n || ((gbits[tg >> 5] >> (tg & 31u)) & 1u) ? kRoot : sc[tg];
+                        lt[i] = static_cast<uint16_t>(code);
+                        st16[i] = static_cast<uint16_t>(code == kRoot ? kSettled : kUnres);
+                    }
+                    res_list = U;
+                    res_l0 = U == bU ? bN : bU;
+                    pop_rounds(ucount, 0u, true, kPhResidual, kPhResidual, kPhResidual);
+                    break;
+                }
                 if (++rounds > a.max_rounds || s_over) {
                     err |= kErrStepCap;
                     break;

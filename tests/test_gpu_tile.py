@@ -68,6 +68,25 @@ def test_nonlocal_graphs_bit_exact(gpu_lib, tile):
     _compare(fc, inputs.rmat(4096, 8, 7), 10.0, 2, 0, 16, tile)
 
 
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_global_bitmaps_and_narrow_workgroups(gpu_lib, threads):
+    """Option tile_bits_lds = 0 keeps the exit and settled bitmaps in global
+    memory (several workgroups per CU with small tiles); narrower workgroups.
+    Small tiles give residual sets larger than a tile, which start with the
+    global rounds and finish in LDS once they fit."""
+    fc = gpu_lib
+    fc.set_option("tile_bits_lds", 0)
+    fc.set_option("tile_threads", threads)
+    try:
+        _compare(fc, inputs.grid_removed(60, 70, 0.12, 0), 2.0, 1, 3, 48, 128)
+        _compare(fc, inputs.erdos_renyi(1000, 0.01, 0), 1.0, 0, 0, 32, 64)
+    finally:
+        fc.set_option("tile_bits_lds", 1)
+        fc.set_option("tile_threads", 1024)
+    with pytest.raises(fc.FCError):
+        fc.set_option("tile_bits_lds", 2)
+
+
 def test_weighted_grid_bit_exact(gpu_lib):
     g = inputs.with_weights(inputs.grid_removed(50, 40, 0.12, 3), 5)
     _compare(gpu_lib, g, 1.0, 4, 0, 32, 128)
