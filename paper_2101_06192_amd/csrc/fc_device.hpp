@@ -63,6 +63,16 @@ __device__ __forceinline__ VRec load_vrec(const VRec *__restrict__ vrec, uint32_
     return {static_cast<int32_t>(q.x), q.y, q.z, q.w};
 }
 
+// Makes all four words of a record live at this point (call it where the draw
+// starts).  Left alone, the compiler fetches each field where it is first used
+// -- the flag word, the threshold after Philox, start and degree behind the
+// root test -- each fetch waiting for the one before: up to four round trips
+// to memory per draw instead of one 16-byte load.  (An empty asm statement: it
+// only keeps the values in registers; it reads and writes no memory.)
+__device__ __forceinline__ void hold_vrec(VRec &r) {
+    asm volatile("" : "+v"(r.start), "+v"(r.deg), "+v"(r.thr), "+v"(r.always_root));
+}
+
 
 // Weighted step (Section 2's non-negative edge weights; a walk leaves v along
 // an edge with probability proportional to its weight).  With S[0..deg) the

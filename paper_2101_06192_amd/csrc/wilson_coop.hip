@@ -117,7 +117,8 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgc
 template <bool kWeighted>
 __device__ __forceinline__ uint32_t draw(const CoopJob &j, uint32_t key0, uint32_t key1,
                                          uint32_t v, uint32_t k, uint32_t t) {
-    const VRec r = load_vrec(j.vrec, v);
+    VRec r = load_vrec(j.vrec, v);
+    hold_vrec(r);
     if (r.always_root) return j.n;  // the arrow is u* whatever the Philox words are
     const Philox4 x = philox4x32_10(v, k, t, j.stream_id, key0, key1);
     return arrow_target<kWeighted>(r, x.x0, x.x1, j.col_idx, j.wsum, j.wthr, j.n);

@@ -78,8 +78,9 @@ __device__ __forceinline__ Field hot_field(const HotClasses c, uint32_t x) {
 // internal | original target (u* = n in both).  kWeighted: the job carries
 // running weight sums (weighted step).
 template <bool kWeighted>
-__device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32_t key0,
+__device__ __forceinline__ uint64_t draw(const CoopJob &j, VRec r, uint32_t key0,
                                          uint32_t key1, uint32_t k, uint32_t t) {
+    hold_vrec(r);
     if (r.always_root >> 31) return pair(j.n, j.n);
     const uint32_t orig = r.always_root & 0x7FFFFFFFu;
     const Philox4 x = philox4x32_10(orig, k, t, j.stream_id, key0, key1);
@@ -442,20 +443,22 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             for (uint32_t base = wave_base; base < ccount; base += kRD * T) {
                 uint32_t v[kRD], k[kRD];
                 uint64_t w[kRD];
+                VRec r[kRD] = {};
 #pragma unroll
                 for (int q = 0; q < kRD; ++q) {
                     const uint32_t i = base + q * T + lane;
                     v[q] = i < ccount ? lo32(cyc[i]) : n;
                     k[q] = 1u;
                     if (v[q] < n) {
+                        // (the record is loaded beside the draw count, not after it)
+                        r[q] = load_vrec(job.vrec, v[q]);
                         const uint64_t kv = kk[v[q]];
                         if (hi32(kv) == epoch) k[q] = lo32(kv);
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < kRD; ++q)
-                    w[q] = v[q] < n ? draw<kWeighted>(job, load_vrec(job.vrec, v[q]), a.key0,
-                                                      a.key1, k[q], t)
+                    w[q] = v[q] < n ? draw<kWeighted>(job, r[q], a.key0, a.key1, k[q], t)
                                     : pair(n, n);
 #pragma unroll
                 for (int q = 0; q < kRD; ++q) {

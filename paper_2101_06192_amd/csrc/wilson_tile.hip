@@ -66,16 +66,6 @@ constexpr uint32_t kLvLds = 2048;       // peel level bounds kept in LDS per rou
 enum Phase : int { kPhLoad = 0, kPhCount, kPhPeel, kPhPop, kPhExits, kPhExit, kPhResidual,
                    kPhOutput, kPhNum };
 
-// Makes all four words of a record live at this point.  Left alone, the
-// compiler fetches each field where it is first used in tile_draw -- the flag
-// word, the threshold after Philox, start and degree behind the root test --
-// each fetch waiting for the one before: up to four round trips to memory per
-// redraw instead of one 16-byte load.  (An empty asm statement: it only keeps
-// the values in registers; it reads and writes no memory.)
-__device__ __forceinline__ void hold_vrec(VRec &r) {
-    asm volatile("" : "+v"(r.start), "+v"(r.deg), "+v"(r.thr), "+v"(r.always_root));
-}
-
 // One arrow of v in tree t with draw index k (original ids; kWeighted: the
 // graph may carry running weight sums).
 template <bool kWeighted>
