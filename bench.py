@@ -1001,6 +1001,13 @@ def main():
                                  kernels_ms=kernels, random_access_ceiling=ceiling),
         "cpu_baseline": cpu,
     }
+    if traffic and ceiling:
+        # the measured line traffic against the line rate of independent random
+        # loads over 4 GiB (each fetches a whole 128-byte line): how close the
+        # kernel runs to what the memory system gives random gathers
+        line_rate = ceiling["random_loads_per_s"] * 128.0
+        line["roofline"]["random_line_ceiling_gbs"] = line_rate / 1e9
+        line["roofline"]["random_line_ceiling_frac"] = traffic / (ms_kernel / 1000.0) / line_rate
     if args.phase_timing:
         line["phase_ms_per_workgroup"] = _phases(st)
     line["launches"] = {"step": {"kernel_ms": ms_kernel, "algorithmic_bytes": alg_bytes}}

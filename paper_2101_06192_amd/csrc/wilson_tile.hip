@@ -376,6 +376,13 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                 // global loads go out together.
                 // The same scan lists every vertex still unresolved (hanging off a
                 // cycle, or on one) for the next round: no other can be then.
+                // When every thread scans at most one entry, a cycle vertex is
+                // popped right there (the cycles are disjoint: popping them all at
+                // once is popping them one after another), saving a barrier and
+                // overlapping the draws with the scan.
+                const uint32_t half = Bp >> 1;
+                const bool inline_pop = scan <= T && scan <= half;
+                if (tid == 0) s_lc[0] = 0;  // the first re-pop pass's tail (the peel's counters are spent)
                 for (uint32_t j = wave_base; j < scan; j += T) {
                     const uint32_t lj = j + lane;
                     uint32_t li = 0;
@@ -388,24 +395,32 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
                     }
                     wave_push<uint16_t>(tp, 0u, &s_c, Bp, &s_over, static_cast<uint16_t>(li), cyc);
                     wave_push<uint32_t>(Lnext, 0u, &s_nc, b, &s_over, li, unres);
+                    if (inline_pop && cyc) {  // (npop <= half here: the re-pops run when enabled)
+                        const uint32_t tg = pop(vid(li));
+                        const uint32_t code = code_of(tg);
+                        lt[li] = static_cast<uint16_t>(code);
+                        st16[li] = static_cast<uint16_t>(code == kRoot ? kSettled
+                                                         : code == kExt ? li
+                                                         : a.repop ? kUnres | 1u : kUnres);
+                    }
                 }
                 __syncthreads();
                 const uint32_t npop = min(uniform(s_c), b);
                 const uint32_t next_count = min(uniform(s_nc), b);
                 // with the re-pops, vertices redrawn to an unresolved target carry
                 // the mark "redrawn in this pass" (count 1) into the first pass
-                const uint32_t half = Bp >> 1;
                 const bool repop = a.repop && npop <= half;
                 const uint32_t fresh = repop ? kUnres | 1u : kUnres;
-                if (tid == 0) s_lc[0] = 0;  // the first pass's tail (the peel's counters are spent)
-                for (uint32_t j = tid; j < npop; j += T) {
-                    const uint32_t i = tp[j];
-                    const uint32_t tg = pop(vid(i));
-                    const uint32_t code = code_of(tg);
-                    lt[i] = static_cast<uint16_t>(code);
-                    st16[i] = static_cast<uint16_t>(code == kRoot ? kSettled : code == kExt ? i : fresh);
+                if (!inline_pop) {
+                    for (uint32_t j = tid; j < npop; j += T) {
+                        const uint32_t i = tp[j];
+                        const uint32_t tg = pop(vid(i));
+                        const uint32_t code = code_of(tg);
+                        lt[i] = static_cast<uint16_t>(code);
+                        st16[i] = static_cast<uint16_t>(code == kRoot ? kSettled : code == kExt ? i : fresh);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
                 if (tid == 0) s_draws += npop;
                 // Re-formed 2-cycles: a redrawn vertex u whose new arrow goes to an
                 // unresolved t whose arrow comes back to u closes a cycle of the

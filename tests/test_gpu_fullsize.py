@@ -9,8 +9,10 @@ benchmark times, on outputs the oracle can recompute one by one.
   vertices (a committed fixture) within the Hoeffding radius.
 - The solve workload, BA(2000000, 8) with Gaussian right-hand sides, both
   precisions against the oracle's binary64 CG, column by column.
-- 1000 x 1000 grid with 12% of the edges removed, 1024 trees at alpha = 1
-  and 2: per-tree digests and walk steps of sampled trees against the oracle.
+- 1000 x 1000 grid with 12% of the edges removed, 1024 trees at alpha = 0.5,
+  1 and 2: digests and walk steps of trees 0..15 and 1023 against the oracle,
+  the estimate against the oracle's CG on 64 vertices (a committed fixture),
+  and all 1024 trees against the global-counter sampler.
 - Weighted BA(200000, 5), 4096 trees: per-tree digests and steps of sampled
   trees against the oracle.
 (BA(200000, 5) with 4096 trees is in test_gpu_parity.py.)
@@ -83,19 +85,28 @@ def test_rmat22_digests_and_estimate(gpu_lib):
     assert err.max() < radius
 
 
-def _golden_cg64():
+def _golden(name, alpha=None):
+    """(vertices, degrees, Omega_vv) of a CG fixture; rows may start with alpha."""
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat22_cg64.txt")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     vs, deg, om = [], [], []
     with open(path) as f:
         for line in f:
             if line.startswith("#") or not line.strip():
                 continue
-            a, b, c = line.split()
-            vs.append(int(a))
-            deg.append(int(b))
-            om.append(float.fromhex(c))
+            parts = line.split()
+            if len(parts) == 4:
+                if alpha is None or float(parts[0]) != alpha:
+                    continue
+                parts = parts[1:]
+            vs.append(int(parts[0]))
+            deg.append(int(parts[1]))
+            om.append(float.fromhex(parts[2]))
     return np.array(vs), np.array(deg), np.array(om)
+
+
+def _golden_cg64():
+    return _golden("rmat22_cg64.txt")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
@@ -132,7 +143,8 @@ def test_solve_ba2m_against_oracle_cg(gpu_lib, precision):
 def test_grid_full_size_sampled(gpu_lib, alpha):
     """The road-like workload in the benchmark's launch (1000 x 1000 grid, 12%
     of edges removed, 1024 trees in one call, the automatic choice: the tile
-    sampler): trees 0..7 and 1023 against the oracle one by one; all 1024
+    sampler): trees 0..15 and 1023 against the oracle; the estimate against
+    the oracle's CG on 64 vertices; all 1024
     trees' digests, steps and root counts against the global-counter sampler
     with and without its re-pops (three schedules, one set of trees)."""
     fc = gpu_lib
@@ -142,13 +154,21 @@ def test_grid_full_size_sampled(gpu_lib, alpha):
                     want_steps=True, trusted=True)
     _say(f"grid alpha={alpha}: sampler={got['stats']['sampler']} ms={got['stats']['ms_sample']:.1f}")
     assert got["stats"]["sampler"] == "wilson_tile"
-    ref = oracle.sample(g, alpha, 0, 0, 8)
-    assert np.array_equal(got["tree_digests"][:8], ref.digests)
-    assert np.array_equal(got["tree_steps"][:8], ref.steps)
+    ref = oracle.sample(g, alpha, 0, 0, 16)
+    assert np.array_equal(got["tree_digests"][:16], ref.digests)
+    assert np.array_equal(got["tree_steps"][:16], ref.steps)
     ref = oracle.sample(g, alpha, 0, 1023, 1)
     assert got["tree_digests"][1023] == ref.digests[0]
     assert got["tree_steps"][1023] == ref.steps[0]
     assert int(got["root_counts"].astype(np.int64).sum()) == got["stats"]["roots"]
+    # the estimate against the oracle's CG on 64 seeded vertices (a committed
+    # fixture written by tests/golden/make_grid_cg64.py), within the Hoeffding
+    # radius at delta = 1e-6 over 64 vertices with 1024 trees
+    vs, deg, om = _golden("grid_cg64.txt", alpha)
+    assert np.array_equal(np.diff(g.row_ptr)[vs], deg)
+    err = np.abs(got["root_counts"][vs].astype(np.float64) / 1024 - om)
+    _say(f"grid alpha={alpha}: 64 CG vertices, max |estimate - Omega_vv| = {err.max():.4f}")
+    assert err.max() < np.sqrt(np.log(2 * 64 / 1e-6) / (2 * 1024))
     for repop in (2, 0):
         fc.set_option("coop_repop", repop)
         try:
