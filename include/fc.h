@@ -343,8 +343,9 @@ typedef struct fc_batch fc_batch;
  * shape is warmed up on a few trees, then timed twice on a thirty-second of
  * every job's trees, best of two; the choice is kept per device and job
  * shapes, so a batch created again with the same graph sizes, alphas, tree
- * counts and options is not timed again) and captures the sampling launch as
- * a HIP graph.  The job array is copied; the graphs
+ * counts and options is not timed again; with the environment variable
+ * FC_TUNE_CACHE naming a file, choices are also appended there and read back
+ * by later processes) and captures the sampling launch as a HIP graph.  The job array is copied; the graphs
  * and output buffers it points to must stay valid until fc_batch_destroy.
  * Returns FC_ERR_ARG for a job with a host graph, alpha <= 0, a NULL
  * root_counts, or more than 2^32 - 1 trees in total. */

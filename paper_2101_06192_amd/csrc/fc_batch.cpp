@@ -16,8 +16,11 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <numeric>
 #include <utility>
@@ -147,6 +150,45 @@ using TuneKey = std::vector<uint64_t>;
 std::mutex g_tune_mu;
 std::map<TuneKey, std::array<uint32_t, 3>> g_tune_cache;
 
+// The on-disk form of the cache (environment variable FC_TUNE_CACHE: a file
+// of lines "key threads wg_per_cu repop", the key a comma-separated list of
+// the device's CU count and LDS size and the group's shape words).  Read when
+// a key is missing from the process's cache; a tuned choice is appended.
+std::string key_text(const fc_ctx *ctx, const TuneKey &k) {
+    std::ostringstream os;
+    os << ctx->cu_count << ',' << ctx->max_lds;
+    for (uint64_t x : k) os << ',' << std::hex << x << std::dec;
+    return os.str();
+}
+
+bool disk_lookup(const fc_ctx *ctx, const TuneKey &k, std::array<uint32_t, 3> *out) {
+    const char *path = std::getenv("FC_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    const std::string want = key_text(ctx, k);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {  // the last line for a key wins
+        std::istringstream is(line);
+        std::string key;
+        uint32_t t = 0, w = 0, r = 0;
+        if ((is >> key >> t >> w >> r) && key == want && t >= 64 && t <= 1024 && t % 64 == 0 && w >= 1 &&
+            w <= 64 && r <= 1) {
+            *out = {t, w, r};
+            found = true;
+        }
+    }
+    return found;
+}
+
+void disk_store(const fc_ctx *ctx, const TuneKey &k, const std::array<uint32_t, 3> &c) {
+    const char *path = std::getenv("FC_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key_text(ctx, k) << ' ' << c[0] << ' ' << c[1] << ' ' << c[2] << '\n';
+}
+
 TuneKey tune_key(const fc_batch *b, const Group &g) {
     const fc_ctx *ctx = b->ctx;
     TuneKey k = {static_cast<uint64_t>(ctx->device), g.use_lds, g.n_max, g.lds_words, g.weighted,
@@ -173,10 +215,14 @@ int autotune(fc_batch *b, Group &g) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            g.threads = it->second[0];
-            g.wg_per_cu = it->second[1];
-            g.repop = it->second[2] != 0u;
+        std::array<uint32_t, 3> c{};
+        const bool hit = it != g_tune_cache.end() || disk_lookup(ctx, key, &c);
+        if (hit) {
+            if (it != g_tune_cache.end()) c = it->second;
+            else g_tune_cache[key] = c;
+            g.threads = c[0];
+            g.wg_per_cu = c[1];
+            g.repop = c[2] != 0u;
             return FC_OK;
         }
     }
@@ -280,6 +326,7 @@ int autotune(fc_batch *b, Group &g) {
     g.wg_per_cu = best_w;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = {best_t, best_w, best_r ? 1u : 0u};
+    disk_store(ctx, key, g_tune_cache[key]);
     return FC_OK;
 }
 

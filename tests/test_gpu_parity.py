@@ -574,6 +574,47 @@ def test_batch_autotune_cached_and_repop_values(gpu_lib):
         fc.set_option("lds_repop", 3)
 
 
+_TUNE_CHILD = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import paper_2101_06192_amd as fc
+import inputs
+gs = [inputs.rmat(n, 8, 40 + i) for i, n in enumerate((700, 1500, 2900))]
+dgs = [fc.to_device(g) for g in gs]
+jobs = [{"graph": dg, "alpha": 0.7, "stream_id": i, "tree_count": 37, "digests": True}
+        for i, dg in enumerate(dgs)]
+b = fc.Batch(jobs, seed=11, autotune=True)
+st = b.run()
+d = [int(x) for i in range(len(jobs)) for x in b.result(i)["tree_digests"]]
+print(st["sampler"], sum(d) % (1 << 61))
+b.close()
+"""
+
+
+def test_batch_tune_cache_on_disk(gpu_lib, tmp_path):
+    """FC_TUNE_CACHE: a process appends its tuned choice to the file; a later
+    process with the same job shapes reads it back instead of tuning (nothing
+    appended) and samples the same trees."""
+    import os
+    import subprocess
+    import sys as _sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = tmp_path / "tune.txt"
+    env = dict(os.environ, FC_TUNE_CACHE=str(path))
+    outs = []
+    for _ in range(2):
+        r = subprocess.run([_sys.executable, "-c", _TUNE_CHILD, root], env=env, capture_output=True,
+                           text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(r.stdout.strip().splitlines()[-1])
+        if len(outs) == 1:
+            lines = path.read_text().splitlines()
+            assert len(lines) >= 1
+    assert path.read_text().splitlines() == lines  # read back, not tuned again
+    assert outs[0] == outs[1]
+
+
 def test_batch_rejects_host_graphs_and_bad_alpha(gpu_lib):
     fc = gpu_lib
     g = inputs.erdos_renyi(30, 0.2, 1)
