@@ -11,17 +11,20 @@
 //    targets; an arrow to u* or out of the tile ends a path there.  Round
 //    after round, the cycles that lie inside the tile are found (in-arrow
 //    counts in LDS, Kahn peel, reverse sweep) and popped, until none is
-//    left.  Every vertex of the tile then has an exit: the last tile vertex on
-//    its path (whose arrow leaves the tile), or "settled" when the path
-//    reaches u* inside the tile.
+//    left; after the first round only the vertices still unresolved are
+//    scanned (they are listed each round).  Every vertex of the tile then
+//    has an exit: the last tile vertex on its path (whose arrow leaves the
+//    tile), or "settled" when the path reaches u* inside the tile.
 // 2. Exit graph.  On the exit vertices the map u -> ex[target(u)] is a
 //    functional graph whose cycles are exactly the arrows' cycles that cross
 //    tiles.  A Kahn peel over the exits (global counters; only exits take
 //    part) and a reverse sweep find which exits reach u*.
 // 3. Residual.  A vertex is settled exactly when its exit is.  The few
 //    vertices that are not (on a crossing cycle or hanging off one) finish
-//    with the ordinary round-synchronous popping: a settled bitmap (LDS when
-//    it fits), global in-arrow counters and lists, only for them.
+//    as one more LDS set like a tile (numbered in list order, a target
+//    settled before counting as u*) once they fit the tile arrays; until
+//    then, with the ordinary round-synchronous popping: a settled bitmap (LDS
+//    when it fits), global in-arrow counters and lists, only for them.
 // No global atomic touches a vertex outside the exit graph and the residual.
 //
 // LDS during the tiles:
@@ -41,7 +44,8 @@
 //   exl    u32  each tile's exit vertices, at offset tile * B; ecnt[tile]
 //   pc, sc u32  in-counts (exit graph, residual; zero between uses) and exit
 //               successors
-//   bl     u32  lists: exits / residual, next residual, peel order
+//   bl     u32  lists: exits / residual, next residual, peel order (during
+//               the tiles: each round's unresolved vertices, two lists)
 //   lv     u32  peel level bounds
 //   xb          exits whose chain reaches u* (LDS when n/8 bytes fit)
 //   bits        settled bitmap of the residual rounds (copied into LDS when it
