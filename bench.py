@@ -1020,8 +1020,22 @@ def main():
         extras["rmat22"] = leg_rmat22(fc, inputs, dev, max(1, es - 1), 1, samplers=("hyb",),
                                       eps=not args.no_eps)
         extras["wall_s"] = time.perf_counter() - t0
+        if ceiling:
+            _add_line_ceiling(extras, ceiling["random_loads_per_s"] * 128.0)
         line["extras"] = extras
     print(json.dumps(line), flush=True)
+
+
+def _add_line_ceiling(obj, line_rate):
+    """Every roofline inside obj that carries counter traffic gets the same
+    comparison as the headline: traffic per second against the line rate of
+    independent random loads."""
+    if isinstance(obj, dict):
+        rf = obj.get("roofline")
+        if isinstance(rf, dict) and rf.get("traffic") and rf.get("kernel_ms"):
+            rf["random_line_ceiling_frac"] = rf["traffic"] / (rf["kernel_ms"] / 1000.0) / line_rate
+        for v in obj.values():
+            _add_line_ceiling(v, line_rate)
 
 
 def _options(args, fc, dev):

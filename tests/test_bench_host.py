@@ -62,3 +62,11 @@ def test_roofline_fields():
 def test_host_info_share():
     h = bench.host_info()
     assert 1 <= h["cores_used"] <= h["affinity_cpus"] <= h["nproc"]
+
+
+def test_line_ceiling_added_to_nested_rooflines():
+    extras = {"grid": {"per_alpha": {"1.0": {"roofline": {"traffic": 6.6e9, "kernel_ms": 1.0}}}},
+              "batch": {"batched": {"roofline": {"traffic": None, "kernel_ms": 2.0}}}}
+    bench._add_line_ceiling(extras, 6.6e12)
+    assert abs(extras["grid"]["per_alpha"]["1.0"]["roofline"]["random_line_ceiling_frac"] - 1.0) < 1e-12
+    assert "random_line_ceiling_frac" not in extras["batch"]["batched"]["roofline"]
