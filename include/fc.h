@@ -271,8 +271,9 @@ FC_API int fc_sample(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
                      int32_t *parents, uint32_t *tree_visits, fc_stats *stats);
 
 /* fc_sample for callers that cannot allocate device memory during the call
- * (code under HIP graph capture, tight serving loops, harnesses that forbid
- * hipMalloc): the same arguments, trees and outputs as fc_sample, but every
+ * (tight serving loops, harnesses that forbid hipMalloc, processes capturing
+ * HIP graphs on other streams meanwhile): the same arguments, trees and
+ * outputs as fc_sample, but every
  * buffer the call needs beyond its inputs and outputs (vertex records,
  * relabelled ids, per-tree state, lists, counters) is carved from one static
  * device array of the library, 64 MiB per device, held from the first
@@ -285,7 +286,9 @@ FC_API int fc_sample(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
  *   No first-arrow pre-draw (option "predraw_mib" is ignored).
  * Every call on a device shares that device's array and leaves its contents
  * behind: calls that overlap in time on one device (two host threads, two
- * streams) race and must be serialised by the caller. */
+ * streams) race and must be serialised by the caller.  Like fc_sample it
+ * synchronises its stream and reads counters back to the host, so the call
+ * itself cannot be recorded into a graph. */
 FC_API int fc_sample_noalloc(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
                              uint32_t tree_begin, uint32_t tree_count, uint32_t *root_counts,
                              uint64_t *visit_counts, uint64_t *tree_digests,
