@@ -136,14 +136,39 @@ def _src_path(name):
     return None
 
 
+def code_tokens(text: str) -> str:
+    """C/C++ source without its comments and with whitespace runs collapsed:
+    what a profile depends on (a comment or layout edit leaves the hash alone)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":  # string or character literal, kept whole
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_hash(sources) -> str:
-    """sha256[:16] over the named sources and every local header they include,
-    in name order."""
+    """sha256[:16] over the code (comments and layout dropped) of the named
+    sources and every local header they include, in name order."""
     h = hashlib.sha256()
     for name in hashed_files(sources):
         h.update(name.encode())
-        with open(_src_path(name), "rb") as f:
-            h.update(f.read())
+        with open(_src_path(name), encoding="utf-8", errors="replace") as f:
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 

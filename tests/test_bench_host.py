@@ -70,3 +70,11 @@ def test_line_ceiling_added_to_nested_rooflines():
     bench._add_line_ceiling(extras, 6.6e12)
     assert abs(extras["grid"]["per_alpha"]["1.0"]["roofline"]["random_line_ceiling_frac"] - 1.0) < 1e-12
     assert "random_line_ceiling_frac" not in extras["batch"]["batched"]["roofline"]
+
+
+def test_code_tokens_ignore_comments_and_layout():
+    a = "int f(int x) {  // add one\n    return x + 1; /* done */ }\n"
+    b = "int f(int x)\n{\n    return x + 1;\n}\n"
+    assert bench.code_tokens(a) == bench.code_tokens(b)
+    assert bench.code_tokens('const char *s = "a // b";') == 'const char *s = "a // b";'
+    assert bench.code_tokens("x = 1; // c") != bench.code_tokens("x = 2; // c")
