@@ -1044,6 +1044,9 @@ def main():
         extras["rmat_batch"] = leg_batch(fc, inputs, dev, es, 1, side=not args.no_side)
         extras["rmat22"] = leg_rmat22(fc, inputs, dev, max(1, es - 1), 1, samplers=("hyb",),
                                       eps=not args.no_eps)
+        extras["ba200k_w"] = leg_weighted(fc, inputs, dev, es, 1, eps=not args.no_eps)
+        extras["er1000"] = leg_er1000(fc, inputs, dev, es, 1, samplers=("auto",))
+        extras["solve"] = leg_solve(fc, inputs, dev, es, 1)
         extras["wall_s"] = time.perf_counter() - t0
         if ceiling:
             _add_line_ceiling(extras, ceiling["random_loads_per_s"] * 128.0)

@@ -202,3 +202,25 @@ def test_weighted_ba200k_full_size_sampled(gpu_lib):
         assert got["tree_steps"][t] == ref.steps[0], t
     assert int(got["root_counts"].astype(np.int64).sum()) == st["roots"]
     assert int(got["tree_steps"].sum()) == st["walk_steps"]
+
+
+def test_weighted_grid_full_size_tile(gpu_lib):
+    """The tile sampler on the 1000 x 1000 grid with log-uniform edge weights in
+    [0.1, 10) (alpha = 1, 64 trees, the automatic choice): trees 0..7 against
+    the oracle, all 64 trees' digests, steps and root counts against the
+    global-counter sampler."""
+    fc = gpu_lib
+    g = inputs.with_weights(inputs.grid_removed(1000, 1000, 0.12, 0), 3)
+    dg = fc.to_device(g)
+    got = fc.sample(dg, alpha=1.0, seed=2, tree_begin=0, tree_count=64, want_digests=True,
+                    want_steps=True, trusted=True)
+    _say(f"weighted grid: sampler={got['stats']['sampler']} ms={got['stats']['ms_sample']:.1f}")
+    assert got["stats"]["sampler"] == "wilson_tile"
+    ref = oracle.sample(g, 1.0, 2, 0, 8)
+    assert np.array_equal(got["tree_digests"][:8], ref.digests)
+    assert np.array_equal(got["tree_steps"][:8], ref.steps)
+    other = fc.sample(dg, alpha=1.0, seed=2, tree_begin=0, tree_count=64, want_digests=True,
+                      want_steps=True, trusted=True, sampler="coop")
+    assert np.array_equal(other["tree_digests"], got["tree_digests"])
+    assert np.array_equal(other["tree_steps"], got["tree_steps"])
+    assert np.array_equal(other["root_counts"], got["root_counts"])
