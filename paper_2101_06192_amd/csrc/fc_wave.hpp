@@ -8,6 +8,11 @@ namespace fc {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// x of lane i (i uniform across the wave; a scalar read, no LDS round trip).
+__device__ __forceinline__ uint32_t lane_of(uint32_t x, int32_t i) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), i));
+}
+
 // Order this wave's LDS accesses before and after (single-wave phases).
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

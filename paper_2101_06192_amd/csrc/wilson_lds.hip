@@ -52,6 +52,10 @@ constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
 constexpr uint32_t kKShift = 2 * kIdBits;
 constexpr uint32_t kKMax = (1u << (64 - kKShift)) - 1u;  // largest draw count a word holds
 
+// Makes x live at this point: its first use is here, not earlier (an empty
+// asm statement; it reads and writes no memory).
+__device__ __forceinline__ void hold_u64(uint64_t &x) { asm volatile("" : "+v"(x)); }
+
 // list entry / tree word fields
 __device__ __forceinline__ uint32_t f_lo(uint64_t w) { return static_cast<uint32_t>(w) & kIdMask; }
 __device__ __forceinline__ uint32_t f_mid(uint64_t w) {
@@ -121,7 +125,6 @@ template <bool kWeighted, bool kRepop>
 __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
     extern __shared__ uint32_t s_lds[];
     __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev, s_rp, s_rp_over;
-    __shared__ uint64_t s_tail[64];
     __shared__ unsigned long long s_digest, s_roots;
     __shared__ unsigned long long s_ph[kPhCount + 1];
 
@@ -348,43 +351,44 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             }
             // No level is larger than the one before it (a peeled vertex frees at
             // most its own target), so once a level fits in one wave, wave 0 peels
-            // the rest alone, without workgroup barriers: the frontier stays in
-            // registers (compacted through LDS) and is also appended to the list
-            // for the sweep.
+            // the rest alone, without workgroup barriers.  Each lane frees at most
+            // one vertex per level, so the frontier stays in the lanes that freed
+            // it (no compaction); it is also appended to the list for the sweep.
             const uint32_t tail0 = nlev;
             mark(kPhPeel);
             if (lo < hi) {
                 if (wave_base == 0) {
-                    uint32_t cnt = hi - lo, pos = hi, nl = nlev;
-                    uint64_t it = lane < cnt ? peel[lo + lane] : 0ull;
-                    while (cnt > 0) {
-                        if (lane == 0) lvl[nl + 1] = pos;
+                    uint32_t pos = hi, lv = nlev;  // lv: the level being peeled
+                    bool have = lane < hi - lo;
+                    uint64_t it = have ? peel[lo + lane] : 0ull;
+                    hold_u64(it);  // waited for here, not at every level's start
+                    const uint64_t below = (1ull << lane) - 1ull;
+                    while (__ballot(have) != 0ull) {
                         const uint32_t tg = f_mid(it);
+                        // the target's word is loaded (by every lane, in bounds)
+                        // before its count is known to drop to 0, and first used
+                        // after the two LDS accesses, which its load then overlaps
+                        uint64_t wt = word[have && tg < nl ? tg : 0u];
+                        if (lane == 0) lvl[lv + 1] = pos;
                         bool push = false;
-                        if (lane < cnt && !is_settled(tg)) push = count_dec(tg) == 1u;
-                        const uint64_t nx = push ? pack(tg, f_lo(word[tg]), 0u) : 0ull;
+                        if (have && !is_settled(tg)) push = count_dec(tg) == 1u;
+                        hold_u64(wt);
+                        const uint64_t nx = push ? pack(tg, f_lo(wt), 0u) : 0ull;
                         const uint64_t mask = __ballot(push);
                         const uint32_t m = static_cast<uint32_t>(__popcll(mask));
                         if (pos + m > n) {
                             if (lane == 0) s_over = 1u;
                             break;
                         }
-                        if (push) {
-                            const uint32_t r =
-                                static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
-                            s_tail[r] = nx;
-                            peel[pos + r] = nx;
-                        }
-                        wave_sync();
-                        it = lane < m ? s_tail[lane] : 0ull;
-                        wave_sync();
+                        if (push) peel[pos + static_cast<uint32_t>(__popcll(mask & below))] = nx;
+                        it = nx;
+                        have = push;
                         pos += m;
-                        cnt = m;
-                        ++nl;
+                        ++lv;
                     }
                     if (lane == 0) {
                         s_p = pos;
-                        s_nlev = nl;
+                        s_nlev = lv;
                     }
                 }
                 __syncthreads();
@@ -410,47 +414,71 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             // others hang off a cycle, keep their arrow and go to the next
             // unsettled list.  The narrow tail levels first, by wave 0 alone
             // (level boundaries fetched 63 at a time), then the wide ones.
+            // The tail's list tail is kept in a register (s_u is 0 and no other
+            // wave appends until the barrier after it).  The tail levels are
+            // taken in windows of consecutive levels with at most 64 kTailRegs
+            // entries: a window's entries are loaded into registers at once
+            // (entry A + 64 q + lane in buf[q]), its levels settled with LDS
+            // accesses only, and its hanging entries appended after it (a load
+            // or store inside the level loop would make each level wait for the
+            // level before's store: loads and stores share one counter).
             if (wave_base == 0 && nlev > tail0) {
+                uint32_t ut = 0;
+                const uint64_t below = (1ull << lane) - 1ull;
                 for (int32_t top = static_cast<int32_t>(nlev) - 1; top >= static_cast<int32_t>(tail0);
                      top -= 63) {
                     const int32_t li = top + 1 - static_cast<int32_t>(lane);  // lane j: lvl[top + 1 - j]
                     const uint32_t bnd = li >= static_cast<int32_t>(tail0) ? lvl[li] : 0u;
                     const int32_t levels = min(63, top - static_cast<int32_t>(tail0) + 1);
-                    // the batch's entries [A, B): in registers when they fit (entry
-                    // A + 64 s + lane in buf[s]), so each level waits for no load
-                    const uint32_t B = __shfl(bnd, 0, 64), A = __shfl(bnd, levels, 64);
-                    const bool inreg = B - A <= 64u * kTailRegs;
-                    uint64_t buf[kTailRegs];
+                    for (int32_t j = 0; j < levels;) {
+                        // levels j .. je - 1 of the batch (level j has at most 64
+                        // entries, so the window holds at least one level)
+                        const uint32_t B = lane_of(bnd, j);
+                        const int32_t ln = static_cast<int32_t>(lane);
+                        const uint64_t fit =
+                            __ballot(ln > j && ln <= levels && B - bnd <= 64u * kTailRegs);
+                        const int32_t je = fit ? 63 - __builtin_clzll(fit) : j + 1;
+                        const uint32_t A = lane_of(bnd, je);
+                        uint64_t buf[kTailRegs];
 #pragma unroll
-                    for (int q = 0; q < kTailRegs; ++q) {
-                        const uint32_t i = A + 64u * q + lane;
-                        buf[q] = inreg && i < B ? peel[i] : pack(n, n, 0u);
-                    }
-                    for (int32_t j = 0; j < levels; ++j) {
-                        const uint32_t a1 = __shfl(bnd, j, 64), a0 = __shfl(bnd, j + 1, 64);
-                        uint64_t p = pack(n, n, 0u);
-                        bool own = false;
-                        if (inreg) {  // a level has at most 64 entries: one per lane at most
+                        for (int q = 0; q < kTailRegs; ++q) {
+                            const uint32_t i = A + 64u * q + lane;
+                            buf[q] = i < B ? peel[i] : 0ull;
+                        }
+                        uint32_t hm = 0;  // bit q: buf[q] hangs
+                        for (; j < je; ++j) {
+                            const uint32_t a1 = lane_of(bnd, j), a0 = lane_of(bnd, j + 1);
+                            // a level has at most 64 entries: one per lane at most
+                            uint64_t p = 0;
+                            int sel = -1;
 #pragma unroll
                             for (int q = 0; q < kTailRegs; ++q) {
                                 const uint32_t i = A + 64u * q + lane;
                                 if (i >= a0 && i < a1) {
                                     p = buf[q];
-                                    own = true;
+                                    sel = q;
                                 }
                             }
-                        } else if (lane < a1 - a0) {
-                            p = peel[a0 + lane];
-                            own = true;
+                            if (sel >= 0) {
+                                if (is_settled(f_mid(p))) set_settled(f_lo(p));
+                                else hm |= 1u << sel;
+                            }
                         }
-                        bool hang = false;
-                        if (own) {
-                            if (is_settled(f_mid(p))) set_settled(f_lo(p));
-                            else hang = true;
+#pragma unroll
+                        for (int q = 0; q < kTailRegs; ++q) {
+                            const bool hang = (hm >> q) & 1u;
+                            const uint64_t mask = __ballot(hang);
+                            if (hang) {
+                                const uint32_t at = ut + static_cast<uint32_t>(__popcll(mask & below));
+                                if (at < n) Unext[at] = buf[q];
+                            }
+                            ut += static_cast<uint32_t>(__popcll(mask));
                         }
-                        wave_append(Unext, &s_u, n, &s_over, p, hang);
-                        wave_sync();
                     }
+                }
+                if (lane == 0) {
+                    s_u = ut;
+                    if (ut > n) s_over = 1u;
                 }
             }
             __syncthreads();
