@@ -19,6 +19,14 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Workgroup barrier that orders LDS accesses only: global stores issued before
+// it are not waited for (use it where they are read only after a full barrier).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Appends R items per lane (item[q] where pred[q]) to a list whose tail
 // counter lives in LDS, with one LDS atomic per wave: item q of every lane
 // goes after items 0..q-1 of all the wave's lanes.  Entries past `cap` are

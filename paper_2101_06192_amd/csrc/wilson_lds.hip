@@ -113,6 +113,9 @@ constexpr int kR = 8;
 constexpr int kRP = 4;  // wide peel levels (each item may add a random load)
 constexpr int kRD = 2;
 constexpr int kRC = 2;
+// Middle peel levels (more than one wave's worth, at most kSlots per thread)
+// keep their entries in registers.
+constexpr int kSlots = 2;
 // Registers per lane that hold a batch of narrow peel levels for the sweep
 // (up to 64 kTailRegs entries).
 constexpr int kTailRegs = 6;
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
             mark(kPhLevel0);
             uint32_t lo = 0, hi = min(uniform(s_p), n), nlev = 0;
             if (tid == 0) lvl[0] = 0;
-            while (hi - lo > 64u) {
+            while (hi - lo > kSlots * T) {
                 if (tid == 0) lvl[nlev + 1] = hi;
                 // (the level's entries are loaded one iteration ahead; entries
                 // appended meanwhile lie beyond hi)
@@ -348,6 +351,63 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 lo = hi;
                 hi = min(uniform(s_p), n);
                 __syncthreads();  // every wave has read s_p before the next level appends
+            }
+            // Levels of at most kSlots entries per thread (and more than one
+            // wave's worth): the frontier stays in registers, in the threads that
+            // freed it, so no level reloads its entries from the list, and the
+            // barriers between levels order LDS accesses only (the list and the
+            // level bounds are read after the full barrier that ends this part).
+            // Each pushed entry's target word is loaded right away, a level ahead
+            // of its use, so that the load overlaps the appends and barriers.
+            const uint32_t tA = nlev;
+            if (hi - lo > 64u) {
+                uint64_t it[kSlots], wt[kSlots];
+                bool have[kSlots];
+#pragma unroll
+                for (int q = 0; q < kSlots; ++q) {
+                    const uint32_t i = lo + q * T + tid;
+                    have[q] = i < hi;
+                    it[q] = have[q] ? peel[i] : 0ull;
+                }
+#pragma unroll
+                for (int q = 0; q < kSlots; ++q) {
+                    const uint32_t tg = f_mid(it[q]);
+                    wt[q] = word[have[q] && tg < nl ? tg : 0u];
+                }
+                for (;;) {
+                    if (tid == 0) lvl[nlev + 1] = hi;
+                    bool push[kSlots];
+#pragma unroll
+                    for (int q = 0; q < kSlots; ++q) {
+                        const uint32_t tg = f_mid(it[q]);
+                        push[q] = false;
+                        if (have[q] && !is_settled(tg)) push[q] = count_dec(tg) == 1u;
+                    }
+                    uint64_t nx[kSlots];
+#pragma unroll
+                    for (int q = 0; q < kSlots; ++q) {
+                        hold_u64(wt[q]);
+                        nx[q] = push[q] ? pack(f_mid(it[q]), f_lo(wt[q]), 0u) : 0ull;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kSlots; ++q) {
+                        const uint32_t tg = f_mid(nx[q]);
+                        wt[q] = word[push[q] && tg < nl ? tg : 0u];
+                    }
+                    wave_append_many<kSlots>(peel, &s_p, n, &s_over, nx, push);
+                    lds_barrier();
+                    ++nlev;
+                    lo = hi;
+                    hi = min(uniform(s_p), n);
+                    lds_barrier();  // every wave has read s_p before the next level appends
+#pragma unroll
+                    for (int q = 0; q < kSlots; ++q) {
+                        it[q] = nx[q];
+                        have[q] = push[q];
+                    }
+                    if (hi - lo <= 64u) break;
+                }
+                __syncthreads();  // the list's entries are read below
             }
             // No level is larger than the one before it (a peeled vertex frees at
             // most its own target), so once a level fits in one wave, wave 0 peels
@@ -482,7 +542,53 @@ __global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
                 }
             }
             __syncthreads();
-            for (int32_t Lv = static_cast<int32_t>(tail0) - 1; Lv >= 0; --Lv) {
+            // the middle levels [tA, tail0): at most kSlots entries per thread;
+            // each thread loads its entries of the next level while it settles
+            // the current one, and the barriers between levels order LDS only
+            // (the next unsettled list is read after a full barrier)
+            if (tail0 > tA) {
+                const int32_t ta = static_cast<int32_t>(tA);
+                for (int32_t top = static_cast<int32_t>(tail0) - 1; top >= ta; top -= 63) {
+                    const int32_t li = top + 1 - static_cast<int32_t>(lane);  // lane j: lvl[top + 1 - j]
+                    const uint32_t bnd = li >= ta ? lvl[li] : 0u;
+                    const int32_t levels = min(63, top - ta + 1);
+                    // level top - j: [bnd of lane j + 1, bnd of lane j)
+                    uint64_t p[kSlots];
+                    {
+                        const uint32_t a1 = lane_of(bnd, 0), a0 = lane_of(bnd, 1);
+#pragma unroll
+                        for (int q = 0; q < kSlots; ++q) {
+                            const uint32_t i = a0 + q * T + tid;
+                            p[q] = i < a1 ? peel[i] : pack(n, n, 0u);
+                        }
+                    }
+                    for (int32_t j = 0; j < levels; ++j) {
+                        uint64_t cur[kSlots];
+#pragma unroll
+                        for (int q = 0; q < kSlots; ++q) cur[q] = p[q];
+                        if (j + 1 < levels) {
+                            const uint32_t a1 = lane_of(bnd, j + 1), a0 = lane_of(bnd, j + 2);
+#pragma unroll
+                            for (int q = 0; q < kSlots; ++q) {
+                                const uint32_t i = a0 + q * T + tid;
+                                p[q] = i < a1 ? peel[i] : pack(n, n, 0u);
+                            }
+                        }
+                        bool hang[kSlots];
+#pragma unroll
+                        for (int q = 0; q < kSlots; ++q) {
+                            hang[q] = false;
+                            if (f_lo(cur[q]) < n) {
+                                if (is_settled(f_mid(cur[q]))) set_settled(f_lo(cur[q]));
+                                else hang[q] = true;
+                            }
+                        }
+                        wave_append_many<kSlots>(Unext, &s_u, n, &s_over, cur, hang);
+                        lds_barrier();
+                    }
+                }
+            }
+            for (int32_t Lv = static_cast<int32_t>(tA) - 1; Lv >= 0; --Lv) {
                 const uint32_t a0 = uniform(lvl[Lv]), a1 = uniform(lvl[Lv + 1]);
                 for (uint32_t base = a0 + wave_base; base < a1; base += kR * T) {
                     uint64_t p[kR];
