@@ -224,6 +224,11 @@ FC_API int fc_set_stream(fc_ctx *ctx, void *hip_stream);
  *   "coop_repop"      the same for the global-counter sampler (graphs whose counters do
  *                     not fit LDS), with an LDS filter that flags the re-popped
  *                     vertices; 0 never, 1 weighted graphs only, 2 always (the default)
+ *   "lds_lean"        LDS-counter sampler, workgroups of at most 512 threads: 1 runs the
+ *                     lean register shape (fewer loads in flight per lane, six waves per
+ *                     SIMD instead of four); 0 (the default) the full one.  A batch created
+ *                     with FC_FLAG_AUTOTUNE times both shapes and keeps the faster (the
+ *                     trees are the same either way)
  *   "tile_size"       tile sampler: vertices per tile, a multiple of 64 up to 32704 (0, the
  *                     default: the widest tile whose LDS arrays fit)
  *   "tile_cross_permille"  the tile sampler is picked automatically when at most this many

@@ -302,6 +302,7 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
     fc::TileArgs ta{};
     uint32_t tile_threads = 1024;
     uint32_t lds_words = 0, lds_threads = 1024, hot = 0;
+    bool lds_lean = false;  // LDS-counter sampler: the lean register shape
     uint32_t tshift = 32;
     unsigned int dmax = 0;
     if (use_coop) {
@@ -512,7 +513,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             slots = std::min<size_t>(slots, tree_count);
             lds_threads = lds_threads_for(ctx, tree_count, lds_words);
             uint32_t per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
-            const int fit = fc::lds_max_active(lds_threads, lds_words, weighted, repop);
+            lds_lean = ctx->lds_lean && lds_threads <= 512u;
+            const int fit = fc::lds_max_active(lds_threads, lds_words, weighted, repop, lds_lean);
             if (fit > 0) per_cu = std::min<uint32_t>(per_cu, static_cast<uint32_t>(fit));
             else per_cu = 1;
             slots = std::min<size_t>(slots, static_cast<size_t>(ctx->cu_count) * per_cu);
@@ -777,7 +779,8 @@ int run_sampler(fc_ctx *ctx, const GraphView &g, const fc_params *p, uint32_t tr
             FC_HIP(ctx, fc::launch_lds_predraw(c, ctx->stream), "lds_predraw launch");
             FC_HIP(ctx, hipEventRecord(ctx->evm, ctx->stream), "event");
         }
-        FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, weighted, repop, ctx->stream),
+        FC_HIP(ctx, fc::launch_wilson_lds(c, lds_threads, lds_words, weighted, repop, lds_lean,
+                                             ctx->stream),
                "wilson_lds launch");
     } else if (use_coop) {
         FC_HIP(ctx, fc::launch_wilson_coop(c, ctx->coop_threads, lds_bits, in_bits, word32, weighted,
@@ -1019,6 +1022,9 @@ int fc_set_option(fc_ctx *ctx, const char *key, int64_t value) {
     } else if (k == "lds_wg_per_cu") {
         if (value < 0 || value > 64) return set_err(ctx, FC_ERR_ARG, "lds_wg_per_cu");
         ctx->lds_wg_per_cu = static_cast<uint32_t>(value);
+    } else if (k == "lds_lean") {
+        if (value < 0 || value > 1) return set_err(ctx, FC_ERR_ARG, "lds_lean must be 0 or 1");
+        ctx->lds_lean = static_cast<uint32_t>(value);
     } else if (k == "lds_repop") {
         if (value < 0 || value > 3) return set_err(ctx, FC_ERR_ARG, "lds_repop must be 0, 1, 2 or 3");
         ctx->lds_repop = static_cast<uint32_t>(value);
@@ -1165,6 +1171,7 @@ int fc_sample_noalloc(fc_ctx *ctx, const fc_graph *g, const fc_params *params,
     sh.predraw_mib = 0;  // every tree draws its own first arrows: no per-call pre-draw array
     sh.kendall_pairs = ctx->kendall_pairs;
     sh.lds_repop = ctx->lds_repop;
+    sh.lds_lean = ctx->lds_lean;
     sh.coop_repop = ctx->coop_repop;
     sh.tile_size = ctx->tile_size;
     sh.tile_cross_permille = ctx->tile_cross_permille;

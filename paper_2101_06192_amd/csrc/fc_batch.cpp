@@ -43,6 +43,7 @@ struct Group {
     bool use_lds = false, lds_bits = false, in_bits = false, word32 = true;
     bool weighted = false;   // some job's graph carries edge weights
     bool repop = false;      // re-formed 2-cycles popped within their round (LDS kernel)
+    bool lean = false;       // LDS kernel: the lean register shape (at most 512 threads)
     uint32_t repop_words = 0;  // the same, global-counter kernel: its LDS filter (set with the shape)
     uint32_t lds_words = 0;  // dynamic LDS of the LDS-counter kernel (largest graph)
 };
@@ -94,7 +95,8 @@ hipError_t enqueue_group(const Group &g, const fc::CoopArgs &a, uint32_t threads
     hipError_t e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.small.ptr),
                                        sizeof(Small) / 8, 0ull, stream);
     if (e != hipSuccess) return e;
-    if (g.use_lds) return fc::launch_wilson_lds(a, threads, g.lds_words, g.weighted, g.repop, stream);
+    if (g.use_lds)
+        return fc::launch_wilson_lds(a, threads, g.lds_words, g.weighted, g.repop, g.lean, stream);
     e = fc::launch_fill_u64(static_cast<unsigned long long *>(g.kk.ptr), g.kk_words, 0ull, stream);
     if (e != hipSuccess) return e;
     return fc::launch_wilson_coop(a, threads, g.lds_bits, g.in_bits, g.word32, g.weighted,
@@ -127,7 +129,7 @@ int size_scratch(fc_ctx *ctx, Group &g, uint32_t slots) {
 // (also picks the re-pop filter of a global-counter group for this shape)
 uint32_t slots_for(const fc_ctx *ctx, Group &g, uint32_t threads, uint32_t wg_per_cu) {
     const size_t n = g.n_max;
-    const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words, g.weighted, g.repop)
+    const int fit = g.use_lds ? fc::lds_max_active(threads, g.lds_words, g.weighted, g.repop, g.lean)
                               : fc::coop_max_active(threads, g.lds_bits, g.in_bits, g.word32,
                                                     g.n_max, g.weighted, 0u);
     if (fit > 0) wg_per_cu = std::min<uint32_t>(wg_per_cu, static_cast<uint32_t>(fit));
@@ -148,10 +150,10 @@ uint32_t slots_for(const fc_ctx *ctx, Group &g, uint32_t threads, uint32_t wg_pe
 // options) takes the earlier choice without timing anything.
 using TuneKey = std::vector<uint64_t>;
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<uint32_t, 3>> g_tune_cache;
+std::map<TuneKey, std::array<uint32_t, 4>> g_tune_cache;
 
 // The on-disk form of the cache (environment variable FC_TUNE_CACHE: a file
-// of lines "key threads wg_per_cu repop", the key a comma-separated list of
+// of lines "key threads wg_per_cu repop lean", the key a comma-separated list of
 // the device's CU count and LDS size and the group's shape words).  Read when
 // a key is missing from the process's cache; a tuned choice is appended.
 std::string key_text(const fc_ctx *ctx, const TuneKey &k) {
@@ -161,7 +163,7 @@ std::string key_text(const fc_ctx *ctx, const TuneKey &k) {
     return os.str();
 }
 
-bool disk_lookup(const fc_ctx *ctx, const TuneKey &k, std::array<uint32_t, 3> *out) {
+bool disk_lookup(const fc_ctx *ctx, const TuneKey &k, std::array<uint32_t, 4> *out) {
     const char *path = std::getenv("FC_TUNE_CACHE");
     if (!path || !*path) return false;
     std::ifstream f(path);
@@ -172,21 +174,21 @@ bool disk_lookup(const fc_ctx *ctx, const TuneKey &k, std::array<uint32_t, 3> *o
     while (std::getline(f, line)) {  // the last line for a key wins
         std::istringstream is(line);
         std::string key;
-        uint32_t t = 0, w = 0, r = 0;
-        if ((is >> key >> t >> w >> r) && key == want && t >= 64 && t <= 1024 && t % 64 == 0 && w >= 1 &&
-            w <= 64 && r <= 1) {
-            *out = {t, w, r};
+        uint32_t t = 0, w = 0, r = 0, l = 0;
+        if ((is >> key >> t >> w >> r >> l) && key == want && t >= 64 && t <= 1024 && t % 64 == 0 &&
+            w >= 1 && w <= 64 && r <= 1 && l <= 1 && (l == 0 || t <= 512)) {
+            *out = {t, w, r, l};
             found = true;
         }
     }
     return found;
 }
 
-void disk_store(const fc_ctx *ctx, const TuneKey &k, const std::array<uint32_t, 3> &c) {
+void disk_store(const fc_ctx *ctx, const TuneKey &k, const std::array<uint32_t, 4> &c) {
     const char *path = std::getenv("FC_TUNE_CACHE");
     if (!path || !*path) return;
     std::ofstream f(path, std::ios::app);
-    if (f) f << key_text(ctx, k) << ' ' << c[0] << ' ' << c[1] << ' ' << c[2] << '\n';
+    if (f) f << key_text(ctx, k) << ' ' << c[0] << ' ' << c[1] << ' ' << c[2] << ' ' << c[3] << '\n';
 }
 
 TuneKey tune_key(const fc_batch *b, const Group &g) {
@@ -215,7 +217,7 @@ int autotune(fc_batch *b, Group &g) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        std::array<uint32_t, 3> c{};
+        std::array<uint32_t, 4> c{};
         const bool hit = it != g_tune_cache.end() || disk_lookup(ctx, key, &c);
         if (hit) {
             if (it != g_tune_cache.end()) c = it->second;
@@ -223,24 +225,30 @@ int autotune(fc_batch *b, Group &g) {
             g.threads = c[0];
             g.wg_per_cu = c[1];
             g.repop = c[2] != 0u;
+            g.lean = c[3] != 0u;
             return FC_OK;
         }
     }
     static const uint32_t cand_coop[][2] = {{256, 3}, {256, 6}, {512, 2}, {512, 3}, {128, 12}};
-    static const uint32_t cand_lds[][2] = {{256, 64}, {512, 64}, {1024, 64}, {256, 4}, {512, 2}};
-    // (threads, workgroups per CU, re-pops): with option lds_repop = 3 the LDS
-    // groups are timed with and without popping re-formed 2-cycles within their
-    // round (the same trees either way; it pays on BA and ER graphs, not on
+    // (threads, workgroups per CU, lean register shape) for the LDS kernel: the
+    // lean shape holds fewer loads in flight per lane but fits six waves per SIMD
+    // instead of four, which pays where trees are latency-bound (small graphs,
+    // large alpha)
+    static const uint32_t cand_lds[][3] = {{256, 64, 0}, {512, 64, 0}, {1024, 64, 0}, {256, 4, 0},
+                                           {512, 2, 0},  {256, 64, 1}, {512, 64, 1}};
+    // (threads, workgroups per CU, re-pops, lean): with option lds_repop = 3 the
+    // LDS groups are timed with and without popping re-formed 2-cycles within
+    // their round (the same trees either way; it pays on BA and ER graphs, not on
     // R-MAT batches); 0, 1 and 2 keep the re-pops as the option says
-    std::vector<std::array<uint32_t, 3>> cand;
+    std::vector<std::array<uint32_t, 4>> cand;
     const bool tune_repop = g.use_lds && ctx->lds_repop == 3;
     if (g.use_lds) {
         for (const auto &c : cand_lds) {
-            cand.push_back({c[0], c[1], g.repop ? 1u : 0u});
-            if (tune_repop) cand.push_back({c[0], c[1], g.repop ? 0u : 1u});
+            cand.push_back({c[0], c[1], g.repop ? 1u : 0u, c[2]});
+            if (tune_repop) cand.push_back({c[0], c[1], g.repop ? 0u : 1u, c[2]});
         }
     } else {
-        for (const auto &c : cand_coop) cand.push_back({c[0], c[1], g.repop ? 1u : 0u});
+        for (const auto &c : cand_coop) cand.push_back({c[0], c[1], g.repop ? 1u : 0u, 0u});
     }
     // throw-away job table: same graphs and records, outputs into one scratch R
     std::vector<fc::CoopJob> tab(g.ntab);
@@ -274,7 +282,7 @@ int autotune(fc_batch *b, Group &g) {
     const uint32_t prefix = static_cast<uint32_t>(tmap.size());
     float best = 1e30f;
     uint32_t best_t = g.threads, best_w = g.wg_per_cu;
-    bool best_r = g.repop;
+    bool best_r = g.repop, best_l = g.lean;
     hipError_t he = hipMemcpy(tmp_tab.ptr, tab.data(), sizeof(fc::CoopJob) * tab.size(),
                               hipMemcpyHostToDevice);
     if (he == hipSuccess)
@@ -282,6 +290,7 @@ int autotune(fc_batch *b, Group &g) {
     if (he != hipSuccess) rc = hip_fail(ctx, he, "write tuning table");
     for (size_t c = 0; rc == FC_OK && c < cand.size(); ++c) {
         g.repop = cand[c][2] != 0u;
+        g.lean = cand[c][3] != 0u;
         const uint32_t slots = slots_for(ctx, g, cand[c][0], cand[c][1]);
         if ((rc = size_scratch(ctx, g, slots))) break;
         fc::CoopArgs a = g.args;
@@ -316,16 +325,18 @@ int autotune(fc_batch *b, Group &g) {
             best_t = cand[c][0];
             best_w = cand[c][1];
             best_r = cand[c][2] != 0u;
+            best_l = cand[c][3] != 0u;
         }
     }
     if (tmp_tab.ptr) (void)hipFree(tmp_tab.ptr);
     if (tmp_map.ptr) (void)hipFree(tmp_map.ptr);
     g.repop = best_r;
+    g.lean = best_l;
     if (rc) return rc;
     g.threads = best_t;
     g.wg_per_cu = best_w;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {best_t, best_w, best_r ? 1u : 0u};
+    g_tune_cache[key] = {best_t, best_w, best_r ? 1u : 0u, best_l ? 1u : 0u};
     disk_store(ctx, key, g_tune_cache[key]);
     return FC_OK;
 }
@@ -641,6 +652,7 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
         if (use_lds) {
             g.threads = lds_threads_for(ctx, g.item_count, g.lds_words);
             g.wg_per_cu = ctx->lds_wg_per_cu ? ctx->lds_wg_per_cu : 64u;
+            g.lean = ctx->lds_lean && g.threads <= 512u;
         } else {
             g.threads = ctx->coop_threads;
             g.wg_per_cu = ctx->coop_wg_per_cu;

@@ -64,6 +64,8 @@ struct fc_ctx {
     uint32_t lds_repop = 3;       // re-formed 2-cycle pops: 0 never, 1 weighted graphs, 2 always,
                                   // 3 always, and timed both ways by batch autotuning
     uint32_t coop_repop = 2;      // the same for the global-counter sampler
+    uint32_t lds_lean = 0;        // LDS-counter sampler: the lean register shape for workgroups
+                                  // of at most 512 threads (batch autotuning times both)
     uint32_t tile_size = 0;       // tile sampler: vertices per tile (0: the widest that fits LDS)
     uint32_t tile_cross_permille = 100;  // picked automatically when at most this share (per
                                          // mille) of the CSR entries cross tiles

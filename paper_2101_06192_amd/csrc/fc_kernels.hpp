@@ -153,16 +153,18 @@ size_t coop_lds_bytes(uint32_t n);  // dynamic LDS of the settled bitmap
 // live in LDS.
 // weighted: some job carries running weight sums (the weighted instantiation
 // checks each job's pointer); repop: re-formed 2-cycles are popped within the
-// round that re-forms them.
+// round that re-forms them; lean (workgroups of at most 512 threads, ignored
+// above): the shape with fewer items in flight per lane and fewer registers,
+// six waves per SIMD instead of four.
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
-                             bool weighted, bool repop, hipStream_t stream);
+                             bool weighted, bool repop, bool lean, hipStream_t stream);
 hipError_t lds_set_limit(size_t bytes);  // as coop_set_lds_limit, for the LDS-counter kernel
 // First arrow of every non-isolated vertex in every tree of a single-job LDS
 // launch (a.single, items [0, a.item_count)): a.pre[item * a.n_max + v] = the
 // tree word the LDS kernel's first round would write.  Vertex-major, so the
 // relabelled records and adjacency are read once per vertex tile for many trees.
 hipError_t launch_lds_predraw(const CoopArgs &a, hipStream_t stream);
-int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted, bool repop);
+int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted, bool repop, bool lean);
 
 // Hybrid variant (ids widest class first: 32-bit fields end at e3, 16-bit at
 // e2, 8-bit at e1, then 4-bit): LDS fields and settled bits of ids [0, hot).

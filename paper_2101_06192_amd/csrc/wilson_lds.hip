@@ -108,24 +108,33 @@ __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32
 }
 
 // Items per lane per pass iteration (independent loads in flight per lane):
-// streaming passes, and passes that also draw arrows (more registers each).
-constexpr int kR = 8;
-constexpr int kRP = 4;  // wide peel levels (each item may add a random load)
-constexpr int kRD = 2;
-constexpr int kRC = 2;
-// Middle peel levels (more than one wave's worth, at most kSlots per thread)
-// keep their entries in registers.
-constexpr int kSlots = 2;
-// Registers per lane that hold a batch of narrow peel levels for the sweep
-// (up to 64 kTailRegs entries).
-constexpr int kTailRegs = 6;
+// streaming passes (R), wide peel levels, where each item may add a random
+// load (RP), passes that also draw arrows (RD, RC: more registers each);
+// middle peel levels (more than one wave's worth, at most Slots per thread)
+// keep their entries in registers; registers per lane that hold a window of
+// narrow peel levels for the sweep (up to 64 TailRegs entries).  The lean
+// shape (workgroups of at most 512 threads) holds fewer, so that its
+// registers leave room for six waves per SIMD instead of four.
+template <bool kLean> struct LdsShape {
+    static constexpr int R = 8, RP = 4, RD = 2, RC = 2, Slots = 2, TailRegs = 6;
+};
+template <> struct LdsShape<true> {
+    static constexpr int R = 2, RP = 2, RD = 1, RC = 1, Slots = 1, TailRegs = 3;
+};
 
 // Passes of the re-formed 2-cycle pops per round (an optimisation that may
 // stop at any pass: the next round pops what is left).
 constexpr uint32_t kRepopPasses = 32;
 
-template <bool kWeighted, bool kRepop>
-__global__ __launch_bounds__(1024) void wilson_lds_kernel(CoopArgs a) {
+template <bool kWeighted, bool kRepop, bool kLean>
+__global__ __launch_bounds__(kLean ? 512 : 1024) __attribute__((amdgpu_waves_per_eu(kLean ? 6 : 1)))
+void wilson_lds_kernel(CoopArgs a) {
+    constexpr int kR = LdsShape<kLean>::R;
+    constexpr int kRP = LdsShape<kLean>::RP;
+    constexpr int kRD = LdsShape<kLean>::RD;
+    constexpr int kRC = LdsShape<kLean>::RC;
+    constexpr int kSlots = LdsShape<kLean>::Slots;
+    constexpr int kTailRegs = LdsShape<kLean>::TailRegs;
     extern __shared__ uint32_t s_lds[];
     __shared__ uint32_t s_item, s_u, s_p, s_cycles, s_over, s_nlev, s_rp, s_rp_over;
     __shared__ unsigned long long s_digest, s_roots;
@@ -910,18 +919,25 @@ hipError_t launch_lds_predraw(const CoopArgs &a, hipStream_t stream) {
 }
 
 namespace {
-const void *lds_kernel_of(bool weighted, bool repop) {
+const void *lds_kernel_of(bool weighted, bool repop, bool lean) {
+    if (lean) {
+        if (weighted)
+            return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<true, true, true>)
+                         : reinterpret_cast<const void *>(&wilson_lds_kernel<true, false, true>);
+        return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<false, true, true>)
+                     : reinterpret_cast<const void *>(&wilson_lds_kernel<false, false, true>);
+    }
     if (weighted)
-        return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<true, true>)
-                     : reinterpret_cast<const void *>(&wilson_lds_kernel<true, false>);
-    return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<false, true>)
-                 : reinterpret_cast<const void *>(&wilson_lds_kernel<false, false>);
+        return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<true, true, false>)
+                     : reinterpret_cast<const void *>(&wilson_lds_kernel<true, false, false>);
+    return repop ? reinterpret_cast<const void *>(&wilson_lds_kernel<false, true, false>)
+                 : reinterpret_cast<const void *>(&wilson_lds_kernel<false, false, false>);
 }
 }  // namespace
 
 hipError_t lds_set_limit(size_t bytes) {
-    for (int m = 0; m < 4; ++m) {
-        const hipError_t e = hipFuncSetAttribute(lds_kernel_of(m & 1, m & 2),
+    for (int m = 0; m < 8; ++m) {
+        const hipError_t e = hipFuncSetAttribute(lds_kernel_of(m & 1, m & 2, m & 4),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(bytes));
         if (e != hipSuccess) return e;
@@ -929,9 +945,9 @@ hipError_t lds_set_limit(size_t bytes) {
     return hipSuccess;
 }
 
-int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted, bool repop) {
+int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted, bool repop, bool lean) {
     int blocks = 0;
-    const void *f = lds_kernel_of(weighted, repop);
+    const void *f = lds_kernel_of(weighted, repop, lean && threads <= 512u);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, static_cast<int>(threads),
                                                      4u * static_cast<size_t>(lds_words)) !=
         hipSuccess)
@@ -940,17 +956,12 @@ int lds_max_active(uint32_t threads, uint32_t lds_words, bool weighted, bool rep
 }
 
 hipError_t launch_wilson_lds(const CoopArgs &a, uint32_t threads, uint32_t lds_words,
-                             bool weighted, bool repop, hipStream_t stream) {
+                             bool weighted, bool repop, bool lean, hipStream_t stream) {
     if (a.n_max == 0 || a.item_count == 0 || a.slots == 0) return hipSuccess;
     const size_t lds = 4u * static_cast<size_t>(lds_words);
-    if (weighted) {
-        if (repop) wilson_lds_kernel<true, true><<<a.slots, threads, lds, stream>>>(a);
-        else wilson_lds_kernel<true, false><<<a.slots, threads, lds, stream>>>(a);
-    } else {
-        if (repop) wilson_lds_kernel<false, true><<<a.slots, threads, lds, stream>>>(a);
-        else wilson_lds_kernel<false, false><<<a.slots, threads, lds, stream>>>(a);
-    }
-    return hipGetLastError();
+    const void *f = lds_kernel_of(weighted, repop, lean && threads <= 512u);
+    void *args[] = {const_cast<CoopArgs *>(&a)};
+    return hipLaunchKernel(f, dim3(a.slots), dim3(threads), args, lds, stream);
 }
 
 }  // namespace fc

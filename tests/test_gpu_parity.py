@@ -615,6 +615,45 @@ def test_batch_tune_cache_on_disk(gpu_lib, tmp_path):
     assert outs[0] == outs[1]
 
 
+@pytest.mark.parametrize("weighted", [False, True], ids=["unweighted", "weighted"])
+@pytest.mark.parametrize("repop", [2, 0], ids=["repop", "no_repop"])
+def test_lds_lean_shape_bit_exact(gpu_lib, weighted, repop):
+    """The LDS sampler's lean register shape (option lds_lean, 256- and 512-thread
+    workgroups): every tree against the oracle on an R-MAT graph at alpha = 10
+    (long peel chains: the single-wave and middle levels) and on a BA graph; then
+    an untuned batch in the lean shape against the eager runs."""
+    fc = gpu_lib
+    gs = [inputs.rmat(3000, 8, 7), inputs.barabasi_albert(20_000, 5, 3)]
+    if weighted:
+        gs = [inputs.with_weights(g, 5) for g in gs]
+    try:
+        fc.set_option("lds_repop", repop)
+        fc.set_option("lds_lean", 1)
+        for threads, g, alpha, count in ((256, gs[0], 10.0, 40), (512, gs[1], 1.0, 24)):
+            fc.set_option("lds_threads", threads)
+            _compare(fc, g, alpha, 77, 5, count, stream=2, per_tree=False, sampler="lds")
+        fc.set_option("lds_threads", 256)
+        dgs = [fc.to_device(g) for g in gs]
+        jobs = [{"graph": dg, "alpha": a, "stream_id": i, "tree_count": 30, "digests": True}
+                for i, dg in enumerate(dgs) for a in (1.0, 10.0)]
+        b = fc.Batch(jobs, seed=9)
+        st = b.run()
+        _say(f"lean batch: {st['sampler']}")
+        for i, j in enumerate(jobs):
+            one = fc.sample(j["graph"], alpha=j["alpha"], seed=9, tree_count=30,
+                            stream_id=j["stream_id"], want_digests=True, sampler="coop")
+            got = b.result(i)
+            assert np.array_equal(got["tree_digests"], one["tree_digests"]), i
+            assert np.array_equal(got["root_counts"], one["root_counts"]), i
+        b.close()
+        with pytest.raises(fc.FCError):
+            fc.set_option("lds_lean", 2)
+    finally:
+        fc.set_option("lds_lean", 0)
+        fc.set_option("lds_threads", 0)
+        fc.set_option("lds_repop", 3)
+
+
 def test_batch_rejects_host_graphs_and_bad_alpha(gpu_lib):
     fc = gpu_lib
     g = inputs.erdos_renyi(30, 0.2, 1)
