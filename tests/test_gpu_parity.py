@@ -109,6 +109,33 @@ def test_small_and_degenerate_graphs(gpu_lib, case, sampler):
         _compare(gpu_lib, g, alpha, 1234567890123, 17, 97, stream=3, sampler=sampler)
 
 
+@pytest.mark.parametrize("shape", ["full", "lean"])
+@pytest.mark.parametrize("case", ["path5000", "bundle200x100"])
+def test_long_peel_chains_bit_exact(gpu_lib, case, shape):
+    """Arrow forests with thousands of peel levels (alpha = 50: roots are rare):
+    a path of 5000 vertices (single-wave levels in many 63-level batches and
+    register windows) and 200 disjoint paths of 100 vertices (about 200 entries
+    per level: the register-held middle levels for a hundred levels), in both
+    register shapes of the LDS sampler, against the oracle."""
+    fc = gpu_lib
+    if case == "path5000":
+        g = inputs.from_edge_list(5000, [(i, i + 1) for i in range(4999)], case)
+    else:
+        g = inputs.from_edge_list(20_000, [(100 * p + i, 100 * p + i + 1) for p in range(200)
+                                           for i in range(99)], case)
+    try:
+        if shape == "lean":
+            fc.set_option("lds_lean", 1)
+            fc.set_option("lds_threads", 256)
+        for repop in (3, 0):
+            fc.set_option("lds_repop", repop)
+            _compare(fc, g, 50.0, 31, 0, 12, per_tree=False, sampler="lds")
+    finally:
+        fc.set_option("lds_lean", 0)
+        fc.set_option("lds_threads", 0)
+        fc.set_option("lds_repop", 3)
+
+
 def test_empty_graph_and_zero_trees(gpu_lib):
     fc = gpu_lib
     g0 = inputs.from_edge_list(0, [])
