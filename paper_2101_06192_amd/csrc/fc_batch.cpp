@@ -554,11 +554,13 @@ int fc_batch_create(fc_ctx *ctx, const fc_job *jobs, int32_t n_jobs, uint64_t se
                                            vr + voff[k], b->stream), "relabel records");
     }
 
-    // launch groups: with LDS counters, jobs whose fields take at most a quarter
-    // of the LDS form the narrow group; everything else is one group
+    // launch groups: with LDS counters, jobs whose fields take at most a third
+    // of the LDS form the narrow group (three workgroups per CU fit, as many as
+    // the lean shape's registers allow at 512 threads); everything else is one
+    // group
     for (size_t k = 0; k < order.size(); ++k) {
         const bool narrow = use_lds && 4u * static_cast<size_t>(gwords[gof[k]]) + kLdsStaticBytes <=
-                                           ctx->max_lds / 4;
+                                           ctx->max_lds / 3;
         b->grp[narrow ? 1 : 0].jobs.push_back(order[k]);
     }
     if (b->grp[0].jobs.empty()) std::swap(b->grp[0].jobs, b->grp[1].jobs);

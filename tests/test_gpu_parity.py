@@ -487,9 +487,9 @@ def _batch_graphs():
     sizes = inputs.rmat_batch_sizes(6, 5, lo_exp=7.0, hi_exp=12.0)
     gs = [inputs.rmat(nn, 8, 100 + i) for i, nn in enumerate(sizes)]
     gs.append(inputs.barabasi_albert(5000, 3, 2))
-    # 80000 vertices need more than a quarter of the LDS for their counters:
+    # 100000 vertices need more than a third of the LDS for their counters:
     # with LDS counters the batch runs as two launch groups
-    gs.append(inputs.barabasi_albert(80_000, 3, 4))
+    gs.append(inputs.barabasi_albert(100_000, 3, 4))
     gs.append(inputs.grid_removed(40, 50, 0.12, 1))
     gs.append(inputs.from_edge_list(3, [(0, 1)], "edge_plus_isolated"))
     return gs
