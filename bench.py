@@ -905,7 +905,8 @@ def main():
     ap.add_argument("--take-profiles", default=None, metavar="STEMS",
                     help="comma-separated workloads (or 'all') to run under rocprofv3; "
                          "summaries go to --profile-out")
-    ap.add_argument("--profile-out", default=os.path.join(ROOT, "gpurun_out", "profiles"))
+    ap.add_argument("--profile-out", default=os.path.join(ROOT, "profile_runs"),
+                    help="directory for the summaries and the raw rocprofv3 output")
     args = ap.parse_args()
     if args.take_profiles:
         stems = list(PROFILE_SPECS) if args.take_profiles == "all" else args.take_profiles.split(",")
