@@ -582,28 +582,43 @@ void wilson_coop_kernel(CoopArgs a, uint32_t fwords) {
         // the tree: top arrows; R, digest, optional per-tree dumps
         unsigned long long my_digest = 0, my_roots = 0;
         const bool want_k = job.visit_counts || job.tree_visits;
-        for (uint32_t v = tid; v < n; v += T) {
-            const uint32_t tg = target_of(word[v]);
-            my_digest += mix64((static_cast<unsigned long long>(v) << 32) | tg);
-            // isolated vertices (bitmap from the vertex records) are roots in every
-            // tree: their root and draw counts for all the job's trees are added at
-            // once, by the workgroup that samples its first tree
-            const bool iso = job.iso && ((job.iso[v >> 5] >> (v & 31u)) & 1u);
-            if (tg == n) {
-                ++my_roots;
-                if (!iso) atomicAdd(&job.root_counts[v], 1u);
-                else if (ti == 0) atomicAdd(&job.root_counts[v], job.tree_count);
+        constexpr int kO = 8;  // vertices whose loads each thread keeps in flight
+        for (uint32_t base = tid; base < n; base += kO * T) {
+            uint32_t tgs[kO], isw[kO];
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                tgs[q] = v < n ? target_of(word[v]) : 0u;
+                isw[q] = v < n && job.iso ? job.iso[v >> 5] : 0u;
             }
-            if (job.parents) job.parents[static_cast<size_t>(ti) * n + v] = static_cast<int32_t>(tg);
-            if (want_k) {
-                const uint64_t kv = kk[v];
-                const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
-                if (job.visit_counts) {
-                    if (!iso) atomicAdd(&job.visit_counts[v], static_cast<unsigned long long>(k));
-                    else if (ti == 0)
-                        atomicAdd(&job.visit_counts[v], static_cast<unsigned long long>(job.tree_count));
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                if (v >= n) continue;
+                const uint32_t tg = tgs[q];
+                my_digest += mix64((static_cast<unsigned long long>(v) << 32) | tg);
+                // isolated vertices (bitmap from the vertex records) are roots in
+                // every tree: their root and draw counts for all the job's trees
+                // are added at once, by the workgroup that samples its first tree
+                const bool iso = (isw[q] >> (v & 31u)) & 1u;
+                if (tg == n) {
+                    ++my_roots;
+                    if (!iso) atomicAdd(&job.root_counts[v], 1u);
+                    else if (ti == 0) atomicAdd(&job.root_counts[v], job.tree_count);
                 }
-                if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + v] = k;
+                if (job.parents)
+                    job.parents[static_cast<size_t>(ti) * n + v] = static_cast<int32_t>(tg);
+                if (want_k) {
+                    const uint64_t kv = kk[v];
+                    const uint32_t k = hi32(kv) == epoch ? lo32(kv) : 1u;
+                    if (job.visit_counts) {
+                        if (!iso) atomicAdd(&job.visit_counts[v], static_cast<unsigned long long>(k));
+                        else if (ti == 0)
+                            atomicAdd(&job.visit_counts[v],
+                                      static_cast<unsigned long long>(job.tree_count));
+                    }
+                    if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + v] = k;
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1) {

@@ -497,7 +497,7 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
 
         unsigned long long my_digest = 0, my_roots = 0;
         const bool want_k = job.visit_counts || job.tree_visits;
-        constexpr int kO = 4;
+        constexpr int kO = 8;  // vertices whose loads each thread keeps in flight
         for (uint32_t base = tid; base < nl; base += kO * T) {
             uint32_t tgs[kO], ovs[kO], otgs[kO];
 #pragma unroll
@@ -529,16 +529,27 @@ __global__ __launch_bounds__(1024) void wilson_hyb_kernel(CoopArgs a) {
             }
         }
         // isolated vertices: per-tree digest terms; totals once per job
-        for (uint32_t v = nl + tid; v < n; v += T) {
-            const uint32_t ov = job.orig[v];
-            my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | n);
-            ++my_roots;
-            if (job.parents) job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(n);
-            if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = 1u;
-            if (ti == 0) {
-                atomicAdd(&job.root_counts[ov], job.tree_count);
-                if (job.visit_counts)
-                    atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(job.tree_count));
+        for (uint32_t base = nl + tid; base < n; base += kO * T) {
+            uint32_t ovs[kO];
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                ovs[q] = v < n ? job.orig[v] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                if (base + q * T >= n) continue;
+                const uint32_t ov = ovs[q];
+                my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | n);
+                ++my_roots;
+                if (job.parents)
+                    job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(n);
+                if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = 1u;
+                if (ti == 0) {
+                    atomicAdd(&job.root_counts[ov], job.tree_count);
+                    if (job.visit_counts)
+                        atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(job.tree_count));
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1) {

@@ -112,14 +112,15 @@ __device__ __forceinline__ uint64_t draw(const CoopJob &j, const VRec &r, uint32
 // load (RP), passes that also draw arrows (RD, RC: more registers each);
 // middle peel levels (more than one wave's worth, at most Slots per thread)
 // keep their entries in registers; registers per lane that hold a window of
-// narrow peel levels for the sweep (up to 64 TailRegs entries).  The lean
+// narrow peel levels for the sweep (up to 64 TailRegs entries); vertices per
+// thread whose loads the output pass keeps in flight (O).  The lean
 // shape (workgroups of at most 512 threads) holds fewer, so that its
 // registers leave room for six waves per SIMD instead of four.
 template <bool kLean> struct LdsShape {
-    static constexpr int R = 8, RP = 4, RD = 2, RC = 2, Slots = 2, TailRegs = 6;
+    static constexpr int R = 8, RP = 4, RD = 2, RC = 2, Slots = 2, TailRegs = 6, O = 8;
 };
 template <> struct LdsShape<true> {
-    static constexpr int R = 2, RP = 2, RD = 1, RC = 1, Slots = 1, TailRegs = 3;
+    static constexpr int R = 2, RP = 2, RD = 1, RC = 1, Slots = 1, TailRegs = 3, O = 4;
 };
 
 // Passes of the re-formed 2-cycle pops per round (an optimisation that may
@@ -791,7 +792,7 @@ void wilson_lds_kernel(CoopArgs a) {
 
         unsigned long long my_digest = 0, my_roots = 0;
         const bool want_k = job.visit_counts || job.tree_visits;
-        constexpr int kO = 4;
+        constexpr int kO = LdsShape<kLean>::O;
         for (uint32_t base = tid; base < nl; base += kO * T) {
             uint64_t ws[kO];
             uint32_t ovs[kO];
@@ -825,16 +826,27 @@ void wilson_lds_kernel(CoopArgs a) {
         // isolated vertices: a root after one draw in every tree.  Their digest
         // terms are added per tree; their root and draw counts for all the job's
         // trees at once, by the workgroup that samples its first tree.
-        for (uint32_t v = nl + tid; v < n; v += T) {
-            const uint32_t ov = job.orig[v];
-            my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | n);
-            ++my_roots;
-            if (job.parents) job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(n);
-            if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = 1u;
-            if (ti == 0) {
-                atomicAdd(&job.root_counts[ov], job.tree_count);
-                if (job.visit_counts)
-                    atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(job.tree_count));
+        for (uint32_t base = nl + tid; base < n; base += kO * T) {
+            uint32_t ovs[kO];
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                ovs[q] = v < n ? job.orig[v] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                if (base + q * T >= n) continue;
+                const uint32_t ov = ovs[q];
+                my_digest += mix64((static_cast<unsigned long long>(ov) << 32) | n);
+                ++my_roots;
+                if (job.parents)
+                    job.parents[static_cast<size_t>(ti) * n + ov] = static_cast<int32_t>(n);
+                if (job.tree_visits) job.tree_visits[static_cast<size_t>(ti) * n + ov] = 1u;
+                if (ti == 0) {
+                    atomicAdd(&job.root_counts[ov], job.tree_count);
+                    if (job.visit_counts)
+                        atomicAdd(&job.visit_counts[ov], static_cast<unsigned long long>(job.tree_count));
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1) {

@@ -798,19 +798,32 @@ __global__ __launch_bounds__(1024) void wilson_tile_kernel(TileArgs a) {
         // the tree: top arrows; R, digest, optional per-tree dumps
         unsigned long long my_digest = 0, my_roots = 0;
         const bool want_k = a.visit_counts || a.tree_visits;
-        for (uint32_t v = tid; v < n; v += T) {
-            const uint32_t tg = tw[v];
-            my_digest += mix64((static_cast<unsigned long long>(v) << 32) | tg);
-            if (tg == n) {
-                ++my_roots;
-                atomicAdd(&a.root_counts[v], 1u);
+        constexpr int kO = 16;  // targets whose loads each thread keeps in flight
+        for (uint32_t base = tid; base < n; base += kO * T) {
+            uint32_t tgs[kO];
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                tgs[q] = v < n ? tw[v] : 0u;
             }
-            if (a.parents) a.parents[static_cast<size_t>(item) * nn + v] = static_cast<int32_t>(tg);
-            if (want_k) {
-                const uint64_t kv = kk[v];
-                const uint32_t k = static_cast<uint32_t>(kv >> 32) == epoch ? static_cast<uint32_t>(kv) : 1u;
-                if (a.visit_counts) atomicAdd(&a.visit_counts[v], static_cast<unsigned long long>(k));
-                if (a.tree_visits) a.tree_visits[static_cast<size_t>(item) * nn + v] = k;
+#pragma unroll
+            for (int q = 0; q < kO; ++q) {
+                const uint32_t v = base + q * T;
+                if (v >= n) continue;
+                const uint32_t tg = tgs[q];
+                my_digest += mix64((static_cast<unsigned long long>(v) << 32) | tg);
+                if (tg == n) {
+                    ++my_roots;
+                    atomicAdd(&a.root_counts[v], 1u);
+                }
+                if (a.parents) a.parents[static_cast<size_t>(item) * nn + v] = static_cast<int32_t>(tg);
+                if (want_k) {
+                    const uint64_t kv = kk[v];
+                    const uint32_t k =
+                        static_cast<uint32_t>(kv >> 32) == epoch ? static_cast<uint32_t>(kv) : 1u;
+                    if (a.visit_counts) atomicAdd(&a.visit_counts[v], static_cast<unsigned long long>(k));
+                    if (a.tree_visits) a.tree_visits[static_cast<size_t>(item) * nn + v] = k;
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
